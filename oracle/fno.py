@@ -1,0 +1,108 @@
+"""NumPy forward pass of the subdomain Fourier neural operator (oracle).
+
+Test infrastructure only.  Architecture (Fig. 2 of the paper without the
+modulation path and low-rank R, which the plain 4-layer configuration does
+not use): lift (1x1) -> L Fourier blocks -> project (1x1, 1x1).
+
+Each Fourier block computes  u <- act(W u + b + F^-1(R . F(u)))  where F is the
+2D DFT of each channel truncated to the low modes, R a complex channel mix per
+kept mode, W a 1x1 channel mix and act the leaky ReLU (identity after the
+last block).  Conventions, shared with the weights file:
+
+* arrays are [channel][y][x]; the tile is Lx x Ly cells;
+* forward DFT  X[kx,ky] = sum_{x,y} u[y,x] exp(-2 pi i (kx x/Lx + ky y/Ly)),
+  kept modes kx in {0..m-1} U {Lx-m..Lx-1} (stored in that order), ky in {0..m-1};
+* inverse  u[y,x] = 1/(Lx Ly) sum_{kept} c_ky Re(X[kx,ky] exp(+2 pi i (...)))
+  with c_0 = 1 and c_ky = 2 for ky >= 1 (real-signal Hermitian completion);
+* spectral mix  Y[o,kx,ky] = sum_i X[i,kx,ky] R[kx,ky,i,o];
+* input channels: Re v/s, Im v/s (s = rms of v over the tile), (eps-1)/11,
+  k0 h sqrt(eps), Re/Im(1/s_x), Re/Im(1/s_y), interface-ring mask;
+* output e = (o_0 + i o_1) * s.
+
+Arithmetic is float64 on float32 weights.  Parity of the trained behaviour is
+unpinned (no values printed in the paper); the forward map itself is pinned
+in the tests.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LEAKY = 0.01
+
+
+def leaky(x):
+    return np.where(x >= 0, x, LEAKY * x)
+
+
+def kept_kx(Lx, m):
+    return np.concatenate([np.arange(m), np.arange(Lx - m, Lx)])
+
+
+def dft_truncated(u, m):
+    """u [C][Ly][Lx] real -> X [C][2m][m] complex (kx major, ky minor)."""
+    C, Ly, Lx = u.shape
+    kx = kept_kx(Lx, m)
+    ky = np.arange(m)
+    Ex = np.exp(-2j * np.pi * np.outer(np.arange(Lx), kx) / Lx)     # [x][kx]
+    Ey = np.exp(-2j * np.pi * np.outer(np.arange(Ly), ky) / Ly)     # [y][ky]
+    X = np.zeros((C, 2 * m, m), dtype=np.complex128)
+    for c in range(C):
+        X[c] = Ex.T @ u[c].T @ Ey          # sum_x sum_y Ex[x,kx] u[y,x] Ey[y,ky]
+    return X
+
+
+def idft_truncated(X, Lx, Ly, m):
+    """X [C][2m][m] -> u [C][Ly][Lx] real, Hermitian completion along ky."""
+    C = X.shape[0]
+    kx = kept_kx(Lx, m)
+    ky = np.arange(m)
+    cky = np.where(ky == 0, 1.0, 2.0)
+    Ex = np.exp(2j * np.pi * np.outer(kx, np.arange(Lx)) / Lx)      # [kx][x]
+    Ey = np.exp(2j * np.pi * np.outer(ky, np.arange(Ly)) / Ly)      # [ky][y]
+    out = np.zeros((C, Ly, Lx))
+    for c in range(C):
+        full = Ey.T @ (X[c] * cky[None, :]).T @ Ex                 # [y][x]
+        out[c] = full.real / (Lx * Ly)
+    return out
+
+
+def fourier_block(u, R, W, bias, m, act=True):
+    """One block: act(W u + b + F^-1(R . F(u))).  R [2m][m][Cin][Cout] complex."""
+    C, Ly, Lx = u.shape
+    X = dft_truncated(u, m)
+    Y = np.einsum("ikq,kqio->okq", X, R)
+    spec = idft_truncated(Y, Lx, Ly, m)
+    pw = np.einsum("oi,iyx->oyx", W, u) + bias[:, None, None]
+    out = pw + spec
+    return leaky(out) if act else out
+
+
+def build_inputs(v, eps, k0h, inv_sx, inv_sy, ring_mask):
+    """The 9 input channels for a local residual v [Ly][Lx] (complex)."""
+    s = np.sqrt(np.mean(np.abs(v) ** 2))
+    vn = v / s if s > 0 else v * 0
+    Ly, Lx = v.shape
+    ch = [vn.real, vn.imag, (eps - 1.0) / 11.0, k0h * np.sqrt(eps),
+          np.broadcast_to(inv_sx.real[None, :], (Ly, Lx)),
+          np.broadcast_to(inv_sx.imag[None, :], (Ly, Lx)),
+          np.broadcast_to(inv_sy.real[:, None], (Ly, Lx)),
+          np.broadcast_to(inv_sy.imag[:, None], (Ly, Lx)),
+          ring_mask.astype(np.float64)]
+    return np.stack(ch).astype(np.float64), s
+
+
+def fno_forward(weights, v, eps, k0h, inv_sx, inv_sy, ring_mask):
+    """Apply the network to one local residual v [Ly][Lx]; returns e [Ly][Lx] complex."""
+    wt = {k: np.asarray(a, dtype=np.float64) if not np.iscomplexobj(a) else np.asarray(a, np.complex128)
+          for k, a in weights.items()}
+    m = int(weights["modes"])
+    nl = int(weights["layers"])
+    x, s = build_inputs(v, eps, k0h, inv_sx, inv_sy, ring_mask)
+    if s == 0:
+        return np.zeros_like(v, dtype=np.complex128)
+    u = np.einsum("oi,iyx->oyx", wt["lift_w"], x) + wt["lift_b"][:, None, None]
+    for l in range(nl):
+        u = fourier_block(u, wt[f"R{l}"], wt[f"W{l}"], wt[f"b{l}"], m, act=(l < nl - 1))
+    p = leaky(np.einsum("oi,iyx->oyx", wt["proj1_w"], u) + wt["proj1_b"][:, None, None])
+    o = np.einsum("oi,iyx->oyx", wt["proj2_w"], p) + wt["proj2_b"][:, None, None]
+    return (o[0] + 1j * o[1]) * s

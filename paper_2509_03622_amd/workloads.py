@@ -1,0 +1,121 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws inputs (permittivity maps, source placements, partition
+lists); it holds none of the method's arithmetic, so both the HIP path and the
+CPU oracle can take their inputs from it.  Each generator uses
+``numpy.random.default_rng(seed)`` with a fixed draw order.
+
+The paper trains and tests on Gaussian-random-field and Voronoi permittivity
+maps in [1, 8] with line sources (Methods, training data generation); those
+datasets are not available, so these stand-ins keep the shapes, contrast and
+structure of the benchmark problems instead: piecewise-constant blocks and
+rectangles of permittivity in [1, 12], point sources, a PML on every side.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+H = 0.05          # cell size in wavelength units (20 cells per vacuum wavelength at lambda = 1)
+NPML = 12
+PML_M = 2
+PML_LNR = -30.0
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    eps: np.ndarray                  # [ny][nx] float32
+    wavelengths: list
+    sources: list                    # list of (ix, iy)
+    core_x: list
+    core_y: list
+    overlap: int = 8
+    k_coarse: int = 0
+    k_trial: int = 8
+    h: float = H
+    npml: int = NPML
+    pml_m: int = PML_M
+    pml_lnR: float = PML_LNR
+    notes: dict = field(default_factory=dict)
+
+    def J(self):
+        """Current density [n_src][ny][nx] complex64, one unit cell per source."""
+        J = np.zeros((len(self.sources), self.ny, self.nx), dtype=np.complex64)
+        for s, (ix, iy) in enumerate(self.sources):
+            J[s, iy, ix] = 1.0
+        return J
+
+
+def small_rectangles(seed=1):
+    """128 x 128, eps = 1 plus 6 rectangles in [2, 12], 2 x 2 cores of 64, 1 wavelength."""
+    rng = np.random.default_rng(seed)
+    n = 128
+    eps = np.ones((n, n), dtype=np.float64)
+    for _ in range(6):
+        w, hh = rng.integers(4, 25, 2)
+        x0 = rng.integers(14, n - 14 - w + 1)
+        y0 = rng.integers(14, n - 14 - hh + 1)
+        val = rng.uniform(2, 12)
+        eps[y0:y0 + hh, x0:x0 + w] = val
+    return Workload("rect128_2x2_lu", n, n, eps.astype(np.float32), [1.0], [(n // 2, n // 2)],
+                    [64, 64], [64, 64])
+
+
+def block_eps(rng, nx, ny, block):
+    vals = rng.uniform(1, 12, (ny // block, nx // block))
+    return np.kron(vals, np.ones((block, block)))
+
+
+def blocks_512(seed=2):
+    """512 x 512, 16-cell blocks in [1, 12], 8 x 8 cores of 64, 4 wavelengths, one coarse basis each."""
+    rng = np.random.default_rng(seed)
+    n = 512
+    eps = block_eps(rng, n, n, 16)
+    return Workload("blocks512_8x8_4wl_2level", n, n, eps.astype(np.float32), [0.8, 1.0, 1.2, 1.5],
+                    [(n // 2, n // 2)], [64] * 8, [64] * 8, k_coarse=1)
+
+
+def blocks_1024(seed=3):
+    """1024 x 1024, 64-cell blocks in [1, 12], 16 x 16 cores of 64, wavelength 1."""
+    rng = np.random.default_rng(seed)
+    n = 1024
+    eps = block_eps(rng, n, n, 64)
+    return Workload("blocks1024_16x16", n, n, eps.astype(np.float32), [1.0],
+                    [(n // 2, n // 2)], [64] * 16, [64] * 16, k_coarse=1)
+
+
+def uneven_2048x1536(seed=4, n_src=32):
+    """2048 x 1536, 16-cell blocks, mixed 64/96 cores, 32 sources x 2 wavelengths."""
+    rng = np.random.default_rng(seed)
+    nx, ny = 2048, 1536
+    eps = block_eps(rng, nx, ny, 16)
+    src = []
+    for _ in range(n_src):
+        ix = int(rng.integers(20, 2028))
+        iy = int(rng.integers(20, 1516))
+        src.append((ix, iy))
+    return Workload("uneven2048x1536_64rhs", nx, ny, eps.astype(np.float32), [1.0, 1.2], src,
+                    [96] + [64] * 29 + [96], [96] + [64] * 21 + [96])
+
+
+def random_small(seed, nx, ny, core_x, core_y, wavelengths=(1.0,), n_src=1, k_coarse=0,
+                 overlap=8, npml=NPML, block=8):
+    """Small random test problem: blocks of eps in [1, 12], random source cells."""
+    rng = np.random.default_rng(seed)
+    eps = np.kron(rng.uniform(1, 12, (ny // block, nx // block)), np.ones((block, block)))
+    src = [(int(rng.integers(npml + 2, nx - npml - 2)), int(rng.integers(npml + 2, ny - npml - 2)))
+           for _ in range(n_src)]
+    return Workload(f"random{nx}x{ny}_s{seed}", nx, ny, eps.astype(np.float32), list(wavelengths), src,
+                    list(core_x), list(core_y), overlap=overlap, k_coarse=k_coarse, npml=npml)
+
+
+WORKLOADS = {
+    "rect128": small_rectangles,
+    "blocks512": blocks_512,
+    "blocks1024": blocks_1024,
+    "uneven2048": uneven_2048x1536,
+}
