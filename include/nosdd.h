@@ -1,0 +1,188 @@
+/*
+ * nosdd.h -- C ABI of libnosdd: two-level Schwarz flexible-GMRES solver for
+ * 2D E_z FDFD (Helmholtz) problems with UPML, on one AMD Instinct MI355X.
+ *
+ * The problem statement follows the paper's two-level Schwarz algorithm
+ * (Algorithm 3 inputs: permittivity map, source, PML, subdomain partition,
+ * coarse-space size, subdomain solver, subdomain and global thresholds):
+ *
+ *   curl curl E - k0^2 eps E = -i omega J            (Eq. 1, E_z form)
+ *   d_n E + i k E = g  on subdomain interfaces       (Eq. 2, Robin data,
+ *                                                    exp(+i omega t) convention)
+ *
+ * Units are normalised (c = eps0 = mu0 = 1), so omega = k0 = 2 pi / wavelength,
+ * and the grid spacing h is in the same length unit as the wavelengths.
+ *
+ * Layout conventions used by every call:
+ *   - a scalar field on the grid is [ny][nx], row-major, x fastest;
+ *   - complex values are interleaved (re, im) single precision (nosdd_c32);
+ *   - a batch of right-hand sides is [n_wl][n_src][ny][nx]: RHS index
+ *     r = wl * n_src + src.
+ *
+ * Ownership: the caller owns every buffer it passes.  The library copies eps
+ * at problem_create and never keeps a caller pointer after a call returns.
+ * Library objects are released only by their *_destroy call.
+ *
+ * Errors: a negative status is a failure; output buffers are then
+ * unspecified and nosdd_last_error() describes the failure.  A positive
+ * status (NOSDD_NOT_CONVERGED) is a warning: outputs are valid.
+ *
+ * Threading: one host thread at a time per context.  All GPU work of a
+ * context is issued on one HIP stream (the caller's, or the library's own).
+ */
+#ifndef NOSDD_H
+#define NOSDD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } nosdd_c32;
+
+typedef enum {
+    NOSDD_OK = 0,
+    NOSDD_NOT_CONVERGED = 1,    /* tolerance not reached within max_iters; outputs valid */
+    NOSDD_EINVAL = -1,          /* invalid argument (null pointer, size, option)         */
+    NOSDD_ENOMEM = -2,          /* device or host allocation failed                      */
+    NOSDD_EHIP = -3,            /* HIP runtime error                                     */
+    NOSDD_EPARTITION = -4,      /* partition does not fit the grid / PML                 */
+    NOSDD_EBREAKDOWN = -5,      /* Krylov breakdown before any progress                  */
+    NOSDD_ENONFINITE = -6,      /* NaN or Inf met in a residual                          */
+    NOSDD_ENOWEIGHTS = -7,      /* neural subdomain solver requested without weights     */
+    NOSDD_ESTATE = -8           /* call out of order (e.g. solve before setup)           */
+} nosdd_status;
+
+typedef struct nosdd_ctx nosdd_ctx;
+typedef struct nosdd_problem nosdd_problem;
+
+/* Grid: nx * ny cells of size h; a PML of npml cells on every side with
+ * conductivity profile sigma(d) = sigma_max d^pml_m and ideal reflection
+ * exp(pml_lnR) (Methods, UPML equations).  Defaults used by the benchmarks:
+ * h = 0.05, npml = 12, pml_m = 2, pml_lnR = -30. */
+typedef struct {
+    int nx, ny;
+    double h;
+    int npml;
+    int pml_m;
+    double pml_lnR;
+} nosdd_grid;
+
+/* Rectangular partition (Methods, "partitioner"): core widths core_x[ncx]
+ * (sum = nx) and heights core_y[ncy] (sum = ny) tile the grid; every core is
+ * extended by overlap/2 cells across each side that is not on the global
+ * boundary.  overlap must be even and >= 2, overlap/2 + 1 <= every core, and
+ * no interface may lie inside the PML of its normal direction
+ * (NOSDD_EPARTITION otherwise). */
+typedef struct {
+    const int *core_x;
+    int ncx;
+    const int *core_y;
+    int ncy;
+    int overlap;
+} nosdd_partition;
+
+/* Subdomain solver and coarse space (Algorithm 3 set-up block).
+ * sub_solver: 0 = exact subdomain LU (block-tridiagonal factorisation),
+ *             1 = per-subdomain flexible GMRES preconditioned by the Fourier
+ *                 neural operator read from nn_weights (Algorithm 1 inference).
+ * k_coarse:   coarse basis functions per subdomain (0 = one-level).
+ * k_trial:    pseudo-plane-wave probes per subdomain (>= k_coarse; 8 if 0).
+ * inner_max, inner_tol: inner FGMRES step limit and relative threshold
+ *             (NN solver only). */
+typedef struct {
+    int sub_solver;
+    int k_coarse;
+    int k_trial;
+    const char *nn_weights;
+    int inner_max;
+    float inner_tol;
+} nosdd_setup_opts;
+
+/* Outer flexible GMRES(restart) on A x = b, right-preconditioned by the
+ * two-level Schwarz sweep.  Stops when ||b - A x|| / ||b|| <= tol (checked on
+ * an explicit residual) or after max_iters preconditioner applications.
+ * x0 (nullable) is an initial guess laid out like E_out. */
+typedef struct {
+    double tol;
+    int restart;
+    int max_iters;
+    const nosdd_c32 *x0;
+} nosdd_solve_opts;
+
+/* Create a context on HIP device hip_device.  hip_stream is a hipStream_t
+ * (nullable: the library creates its own default-priority stream). */
+nosdd_status nosdd_ctx_create(int hip_device, void *hip_stream, nosdd_ctx **out);
+void nosdd_ctx_destroy(nosdd_ctx *ctx);                /* NULL is accepted */
+/* Message of the last failure on this context; owned by the context and
+ * valid until the next call on it.  Never NULL. */
+const char *nosdd_last_error(const nosdd_ctx *ctx);
+
+/* Create a problem: eps is a host [ny][nx] real permittivity map (copied);
+ * wavelengths[n_wl] are solved together, one operator per wavelength. */
+nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *grid, const float *eps,
+                                  const nosdd_partition *part, const double *wavelengths,
+                                  int n_wl, nosdd_problem **out);
+/* Build every per-wavelength subdomain factorisation, the coarse space and,
+ * for sub_solver = 1, load the network.  Must precede any solve. */
+nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *opts);
+void nosdd_problem_destroy(nosdd_problem *p);          /* NULL is accepted */
+
+/* Solve for n_src current densities J[n_src][ny][nx] (host) at every
+ * wavelength.  Outputs (host): E_out[n_wl][n_src][ny][nx];
+ * resid_hist[n_wl][n_src][max_iters] relative residual estimate after each
+ * preconditioner application, -1 padded (nullable); iters[n_wl][n_src]
+ * preconditioner applications (nullable); final_resid[n_wl][n_src] explicit
+ * relative residual (nullable). */
+nosdd_status nosdd_solve(nosdd_problem *p, const nosdd_c32 *J, int n_src,
+                         const nosdd_solve_opts *opts, nosdd_c32 *E_out, float *resid_hist,
+                         int *iters, float *final_resid);
+/* Same as nosdd_solve, but J, x0 and E_out are device pointers, ordered on
+ * the context stream; resid_hist, iters and final_resid stay host pointers.
+ * This is the call whose time the benchmark reports (inputs resident in HBM). */
+nosdd_status nosdd_solve_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src,
+                                const nosdd_solve_opts *opts, nosdd_c32 *E_dev, float *resid_hist,
+                                int *iters, float *final_resid);
+
+/* ---- Steps of one Schwarz sweep, exposed for testing and composition. ----
+ * All vectors are device pointers on the context stream, laid out
+ * [n_wl][n_src][ny][nx]; n_src is the number of vectors per wavelength. */
+
+/* y = A x, or y = b - A x when b is not NULL (Eq. 1 operator with UPML). */
+nosdd_status nosdd_apply_operator(nosdd_problem *p, const nosdd_c32 *x, const nosdd_c32 *b,
+                                  nosdd_c32 *y, int n_src);
+/* One-level restricted additive Schwarz sweep with Robin transmission:
+ * z = sum_i Rt_i^T B_i^-1 R_i v  (gather across overlaps, exact subdomain
+ * solve, core-only scatter).  Equivalent to one boundary-update step of the
+ * paper's domain-decomposition loop applied to the residual v. */
+nosdd_status nosdd_schwarz_sweep(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *z, int n_src);
+/* Full two-level preconditioner: z = z1 + Phi c, Az = A z1 + W c with
+ * c = G^-1 W^H (v - A z1) (coarse correction, FP64 solve). Az nullable. */
+nosdd_status nosdd_precond_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *z, nosdd_c32 *Az,
+                                 int n_src);
+/* Exact local solves on subdomain-local vectors: for tile t (index ty*ncx+tx)
+ * and wavelength wl, u = B_{t,wl}^-1 rhs.  rhs and u are
+ * [n_wl][n_tiles][ly_t][lx_t] packed in tile order (tile sizes differ; use
+ * nosdd_tile_info for offsets), one vector per (wl, tile). */
+nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32 *u);
+/* Robin traces g_p(x) = (x_q - x_p)/h + i kappa_p (x_q + x_p)/2 on every
+ * interface-ring entry of every tile, for one global field per wavelength.
+ * g is [n_wl][n_entries]; entry order per tile: counter-clockwise ring walk
+ * from the lower-left node, bottom/right/top/left at corners. */
+nosdd_status nosdd_robin_trace(nosdd_problem *p, const nosdd_c32 *x, nosdd_c32 *g);
+
+/* Geometry queries (host). info[10] = {x0, x1, y0, y1, cx0, cx1, cy0, cy1,
+ * local_offset (cells, within one wavelength's packed local vector),
+ * trace_offset (entries)}.  Totals: n_tiles, local cells per wavelength,
+ * trace entries per wavelength. */
+nosdd_status nosdd_tile_info(const nosdd_problem *p, int tile, long long info[10]);
+nosdd_status nosdd_sizes(const nosdd_problem *p, int *n_tiles, long long *local_cells,
+                         long long *trace_entries, int *n_coarse);
+
+/* Timing of the last solve (ms, GPU events): setup, total solve, iterations. */
+nosdd_status nosdd_last_timing(const nosdd_problem *p, double *setup_ms, double *solve_ms,
+                               int *outer_iters);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NOSDD_H */

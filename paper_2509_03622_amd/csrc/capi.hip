@@ -1,0 +1,1079 @@
+// libnosdd host runtime and C ABI (declared in include/nosdd.h).
+//
+// Owns the device memory plan of a problem (permittivity, per-wavelength
+// stencil coefficients, subdomain factors, coarse basis, Krylov workspace) and
+// drives right-preconditioned flexible GMRES(restart) on the global FDFD
+// system, one Schwarz sweep (all subdomains x all RHS in one launch) per
+// preconditioner application.  The host only reads back one small status
+// array per outer iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nosdd.h"
+#include "common.h"
+
+using namespace nosdd;
+using cd = std::complex<double>;
+
+struct nosdd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+};
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n) {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n ? n : 16);
+        if (e == hipSuccess) bytes = n;
+        return e;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct Workspace {
+    int n_rhs = 0, m = 0, max_iters = 0, nblk = 0;
+    long long N = 0;
+    DevBuf x, b, V, Z, w, scratch, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, nw_re, bnorm2, bnorm, beta2, iters,
+        kcyc, active, want, reorth, inv_h, flags, hist, cd_, cc_;
+};
+
+}  // namespace
+
+struct nosdd_problem {
+    nosdd_ctx *ctx = nullptr;
+    int nx = 0, ny = 0, npml = 0, pml_m = 2;
+    double h = 0.05, lnR = -30.0;
+    std::vector<float> eps;
+    std::vector<double> wl;
+    std::vector<int> core_x, core_y;
+    int ncx = 0, ncy = 0, overlap = 0, ext = 0;
+    std::vector<TileDesc> tiles;
+    std::vector<std::vector<int4>> tile_entries;     // (p, q, side, 0) linear cell indices
+    long long loc_total = 0, dinv_wl_stride = 0;
+    int bmax = 0;
+    std::vector<std::vector<cd>> coefd;             // per wl: cxm|cxp|cym|cyp
+    DevBuf d_eps, d_coef, d_coefd, d_k0sq, d_k0f, d_k0, d_tiles, d_dinv, d_entries, d_tox, d_toy;
+    int n_entries = 0;
+    // coarse space
+    int kc = 0, ktrial = 8, n_c = 0;
+    long long box_wl_stride = 0;
+    DevBuf d_phi, d_W, d_GinvT;
+    bool setup_done = false;
+    int sub_solver = 0;
+    Workspace ws;
+    double setup_ms = 0.0, solve_ms = 0.0;
+    int last_iters = 0;
+};
+
+namespace {
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            (ctx)->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " #expr;   \
+            return e_ == hipErrorOutOfMemory ? NOSDD_ENOMEM : NOSDD_EHIP;                    \
+        }                                                                                    \
+    } while (0)
+
+nosdd_status fail(nosdd_ctx *ctx, nosdd_status s, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+// ---------------------------------------------------------------- PML / stencil
+// s(q) = 1 - i sigma_hat d(q)^m,  sigma_hat = (m+1)(-lnR) / (2 k0 npml h),
+// d(q) = clip(max(npml - 1/2 - q, q - (n - npml - 1/2)) / npml, 0, 1).
+cd stretch(double q, int n, int npml, int m, double sh) {
+    if (npml == 0) return cd(1.0, 0.0);
+    double d = std::max(npml - 0.5 - q, q - (n - npml - 0.5)) / npml;
+    d = std::min(1.0, std::max(0.0, d));
+    return cd(1.0, -sh * std::pow(d, m));
+}
+
+std::vector<cd> axis_coefs(int n, int npml, int m, double lnR, double k0, double h) {
+    const double sh = npml ? (m + 1) * (-lnR) / (2.0 * k0 * npml * h) : 0.0;
+    std::vector<cd> out(2 * n);
+    for (int i = 0; i < n; ++i) {
+        const cd sc = stretch(i, n, npml, m, sh);
+        const cd sm = stretch(i - 0.5, n, npml, m, sh);
+        const cd sp = stretch(i + 0.5, n, npml, m, sh);
+        out[i] = -1.0 / (sm * sc * h * h);        // coupling to i-1
+        out[n + i] = -1.0 / (sp * sc * h * h);    // coupling to i+1
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------- small dense FP64 linear algebra
+// Hermitian eigen-decomposition by cyclic Jacobi rotations (n <= 64).
+void herm_eig(int n, std::vector<cd> A, std::vector<double> &w, std::vector<cd> &V) {
+    V.assign((size_t)n * n, cd(0, 0));
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    double nrm = 0;
+    for (auto &a : A) nrm += std::norm(a);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += std::norm(A[(size_t)p * n + q]);
+        if (off <= 1e-30 * nrm) break;
+        for (int p = 0; p < n; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const cd apq = A[(size_t)p * n + q];
+                const double a = std::abs(apq);
+                if (a == 0.0) continue;
+                const cd ph = apq / a;                      // e^{i phi}
+                const double al = A[(size_t)p * n + p].real(), be = A[(size_t)q * n + q].real();
+                const double th = 0.5 * std::atan2(2.0 * a, be - al);
+                const double c = std::cos(th), s = std::sin(th);
+                const cd em = std::conj(ph);                // e^{-i phi}
+                // A <- A J (columns p, q)
+                for (int i = 0; i < n; ++i) {
+                    const cd xp = A[(size_t)i * n + p], xq = A[(size_t)i * n + q];
+                    A[(size_t)i * n + p] = c * xp - s * em * xq;
+                    A[(size_t)i * n + q] = s * xp + c * em * xq;
+                    const cd vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
+                    V[(size_t)i * n + p] = c * vp - s * em * vq;
+                    V[(size_t)i * n + q] = s * vp + c * em * vq;
+                }
+                // A <- J^H A (rows p, q)
+                for (int j = 0; j < n; ++j) {
+                    const cd xp = A[(size_t)p * n + j], xq = A[(size_t)q * n + j];
+                    A[(size_t)p * n + j] = c * xp - s * ph * xq;
+                    A[(size_t)q * n + j] = s * xp + c * ph * xq;
+                }
+            }
+        }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i].real();
+}
+
+// Explicit inverse of a Hermitian positive-definite matrix through its Cholesky factor.
+bool hpd_inverse(int n, const std::vector<cd> &G, std::vector<cd> &Ginv) {
+    std::vector<cd> L((size_t)n * n, cd(0, 0));
+    for (int j = 0; j < n; ++j) {
+        double d = G[(size_t)j * n + j].real();
+        for (int k = 0; k < j; ++k) d -= std::norm(L[(size_t)j * n + k]);
+        if (!(d > 0.0)) return false;
+        const double ljj = std::sqrt(d);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            cd s = G[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * std::conj(L[(size_t)j * n + k]);
+            L[(size_t)i * n + j] = s / ljj;
+        }
+    }
+    // Li = L^-1 (lower triangular)
+    std::vector<cd> Li((size_t)n * n, cd(0, 0));
+    for (int c = 0; c < n; ++c) {
+        Li[(size_t)c * n + c] = 1.0 / L[(size_t)c * n + c];
+        for (int i = c + 1; i < n; ++i) {
+            cd s = 0;
+            for (int k = c; k < i; ++k) s += L[(size_t)i * n + k] * Li[(size_t)k * n + c];
+            Li[(size_t)i * n + c] = -s / L[(size_t)i * n + i];
+        }
+    }
+    // Ginv = Li^H Li
+    Ginv.assign((size_t)n * n, cd(0, 0));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            cd s = 0;
+            for (int k = std::max(i, j); k < n; ++k) s += std::conj(Li[(size_t)k * n + i]) * Li[(size_t)k * n + j];
+            Ginv[(size_t)i * n + j] = s;
+        }
+    return true;
+}
+
+// ---------------------------------------------------------------- geometry helpers
+void ring_nodes(const TileDesc &t, std::vector<std::pair<int, int>> &nodes) {
+    nodes.clear();
+    for (int x = t.x0; x < t.x1; ++x) nodes.push_back({x, t.y0});
+    for (int y = t.y0 + 1; y < t.y1; ++y) nodes.push_back({t.x1 - 1, y});
+    for (int x = t.x1 - 2; x >= t.x0; --x) nodes.push_back({x, t.y1 - 1});
+    for (int y = t.y1 - 2; y > t.y0; --y) nodes.push_back({t.x0, y});
+}
+
+// trace entries of a tile (p, q linear; z = side bit; w = ring node index)
+void trace_entries(const TileDesc &t, int nx, std::vector<int4> &out) {
+    std::vector<std::pair<int, int>> nodes;
+    ring_nodes(t, nodes);
+    out.clear();
+    for (int r = 0; r < (int)nodes.size(); ++r) {
+        const int x = nodes[r].first, y = nodes[r].second;
+        const int p = y * nx + x;
+        if ((t.iface & SIDE_BOTTOM) && y == t.y0) out.push_back(make_int4(p, p - nx, SIDE_BOTTOM, r));
+        if ((t.iface & SIDE_RIGHT) && x == t.x1 - 1) out.push_back(make_int4(p, p + 1, SIDE_RIGHT, r));
+        if ((t.iface & SIDE_TOP) && y == t.y1 - 1) out.push_back(make_int4(p, p + nx, SIDE_TOP, r));
+        if ((t.iface & SIDE_LEFT) && x == t.x0) out.push_back(make_int4(p, p - 1, SIDE_LEFT, r));
+    }
+}
+
+__global__ void make_rhs_kernel(const float2 *J, float2 *b, const float *k0, long long N, int n_src) {
+    const int r = blockIdx.y;
+    const int wl = r / n_src, s = r - wl * n_src;
+    const float om = k0[wl];
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+        const float2 j = J[s * N + n];
+        b[r * N + n] = make_float2(om * j.y, -om * j.x);    // -i omega J
+    }
+}
+
+__global__ void fill_f32_kernel(float *p, long long n, float v) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+long long grid_blocks(long long N) { return std::min<long long>(1024, (N + 255) / 256); }
+
+nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
+    Workspace &w = p->ws;
+    nosdd_ctx *ctx = p->ctx;
+    const long long N = (long long)p->nx * p->ny;
+    const int nblk = (int)std::max<long long>(1, std::min<long long>(1024, (N + 2047) / 2048));
+    w.n_rhs = n_rhs;
+    w.m = m;
+    w.max_iters = max_iters;
+    w.N = N;
+    w.nblk = nblk;
+    const size_t vec = (size_t)n_rhs * N * sizeof(float2);
+    HIPCHK(ctx, w.x.ensure(vec));
+    HIPCHK(ctx, w.b.ensure(vec));
+    HIPCHK(ctx, w.w.ensure(vec));
+    HIPCHK(ctx, w.V.ensure(vec * (m + 1)));
+    HIPCHK(ctx, w.Z.ensure(vec * m));
+    HIPCHK(ctx, w.scratch.ensure((size_t)n_rhs * p->loc_total * sizeof(float2)));
+    HIPCHK(ctx, w.partial.ensure((size_t)n_rhs * nblk * 33 * sizeof(double2)));
+    const size_t hsz = (size_t)n_rhs * (m + 1) * m * sizeof(float2);
+    HIPCHK(ctx, w.H.ensure(hsz));
+    HIPCHK(ctx, w.H2.ensure(hsz));
+    HIPCHK(ctx, w.cs.ensure((size_t)n_rhs * m * sizeof(float)));
+    HIPCHK(ctx, w.sn.ensure((size_t)n_rhs * m * sizeof(float2)));
+    HIPCHK(ctx, w.gam.ensure((size_t)n_rhs * (m + 1) * sizeof(float2)));
+    HIPCHK(ctx, w.y.ensure((size_t)n_rhs * m * sizeof(float2)));
+    for (DevBuf *d : {&w.nw_pre, &w.nw_post, &w.nw_re, &w.bnorm2, &w.beta2})
+        HIPCHK(ctx, d->ensure((size_t)n_rhs * sizeof(double)));
+    for (DevBuf *d : {&w.bnorm, &w.inv_h}) HIPCHK(ctx, d->ensure((size_t)n_rhs * sizeof(float)));
+    for (DevBuf *d : {&w.iters, &w.kcyc, &w.active, &w.want, &w.reorth, &w.flags})
+        HIPCHK(ctx, d->ensure((size_t)n_rhs * sizeof(int)));
+    HIPCHK(ctx, w.hist.ensure((size_t)n_rhs * std::max(1, max_iters) * sizeof(float)));
+    const int nc = std::max(1, p->n_c);
+    HIPCHK(ctx, w.cd_.ensure((size_t)n_rhs * nc * sizeof(double2)));
+    HIPCHK(ctx, w.cc_.ensure((size_t)n_rhs * nc * sizeof(float2)));
+    return NOSDD_OK;
+}
+
+// z = M^-1 v (two-level), wout = A z.  v, z, wout: [n_rhs][N].
+void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2 *wout, int n_src, int n_rhs,
+             const int *active) {
+    Workspace &w = p->ws;
+    const long long N = (long long)p->nx * p->ny;
+    launch_bt_solve(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src, p->d_dinv.as<float2>(),
+                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, w.scratch.as<float2>(),
+                    p->loc_total, active, 0, p->bmax);
+    if (wout == nullptr) return;
+    launch_stencil(s, z, nullptr, wout, p->d_eps.as<float>(), p->d_coef.as<float2>(), p->d_k0sq.as<float>(), p->nx,
+                   p->ny, n_rhs, n_src, active);
+    if (p->n_c > 0) {
+        launch_coarse_dot(s, p->d_tiles.as<TileDesc>(), nullptr, p->n_c, p->kc, p->d_W.as<float2>(), p->box_wl_stride,
+                          0, v, wout, p->nx, N, n_rhs, n_src, active, w.cd_.as<double2>());
+        launch_coarse_solve(s, p->d_GinvT.as<double2>(), p->n_c, w.cd_.as<double2>(), w.cc_.as<float2>(), n_rhs,
+                            n_src, active);
+        launch_coarse_update(s, p->d_tiles.as<TileDesc>(), p->ncx, p->ncy, p->d_tox.as<int>(), p->d_toy.as<int>(),
+                             p->kc, p->d_phi.as<float2>(), p->d_W.as<float2>(), p->box_wl_stride, 0,
+                             w.cc_.as<float2>(), p->n_c, z, wout, p->nx, p->ny, n_rhs, n_src, active);
+    }
+}
+
+// ---------------------------------------------------------------- coarse set-up
+nosdd_status coarse_setup(nosdd_problem *p) {
+    nosdd_ctx *ctx = p->ctx;
+    hipStream_t s = ctx->stream;
+    const int nt = (int)p->tiles.size();
+    const int K = std::max(p->ktrial, p->kc);
+    const int kc = p->kc;
+    const int nwl = (int)p->wl.size();
+    const int nx = p->nx, ny = p->ny;
+    const double h = p->h;
+    p->n_c = nt * kc;
+    // box geometry
+    long long box_total = 0;
+    for (auto &t : p->tiles) {
+        t.bx0 = std::max(t.cx0 - 1, 0);
+        t.by0 = std::max(t.cy0 - 1, 0);
+        t.bw = std::min(t.cx1 + 1, nx) - t.bx0;
+        t.bh = std::min(t.cy1 + 1, ny) - t.by0;
+        t.box_off = (int)box_total;
+        box_total += (long long)kc * t.bw * t.bh;
+    }
+    p->box_wl_stride = box_total;
+    HIPCHK(ctx, hipMemcpyAsync(p->d_tiles.p, p->tiles.data(), p->tiles.size() * sizeof(TileDesc),
+                               hipMemcpyHostToDevice, s));
+    // probe Robin data per (wl, probe), injected into packed local vectors
+    const long long LT = p->loc_total;
+    std::vector<std::vector<cd>> Xt((size_t)nwl * nt);
+    std::vector<float2> rhs((size_t)nwl * K * LT, make_float2(0.f, 0.f));
+    for (int wi = 0; wi < nwl; ++wi) {
+        const double k0 = 2.0 * M_PI / p->wl[wi];
+        const auto &cf = p->coefd[wi];
+        for (int ti = 0; ti < nt; ++ti) {
+            const TileDesc &t = p->tiles[ti];
+            const auto &ent = p->tile_entries[ti];
+            const int ne = (int)ent.size();
+            std::vector<std::pair<int, int>> nodes;
+            ring_nodes(t, nodes);
+            std::vector<double> kap(nodes.size());
+            for (size_t r = 0; r < nodes.size(); ++r)
+                kap[r] = k0 * std::sqrt((double)p->eps[(size_t)nodes[r].second * nx + nodes[r].first]);
+            std::vector<cd> Xe((size_t)ne * K);
+            for (int l = 0; l < K; ++l) {
+                const double th = 2.0 * M_PI * l / K;
+                const double dx = std::cos(th), dy = std::sin(th);
+                std::vector<double> phi(nodes.size(), 0.0);
+                for (size_t r = 0; r + 1 < nodes.size(); ++r) {
+                    const double sx = nodes[r + 1].first - nodes[r].first, sy = nodes[r + 1].second - nodes[r].second;
+                    phi[r + 1] = phi[r] + h * 0.5 * (kap[r] + kap[r + 1]) * (dx * sx + dy * sy);
+                }
+                for (int e = 0; e < ne; ++e) Xe[(size_t)e * K + l] = std::exp(cd(0.0, -phi[ent[e].w]));
+            }
+            // modified Gram-Schmidt over the columns
+            for (int l = 0; l < K; ++l) {
+                for (int q = 0; q < l; ++q) {
+                    cd dot = 0;
+                    for (int e = 0; e < ne; ++e) dot += std::conj(Xe[(size_t)e * K + q]) * Xe[(size_t)e * K + l];
+                    for (int e = 0; e < ne; ++e) Xe[(size_t)e * K + l] -= dot * Xe[(size_t)e * K + q];
+                }
+                double nr = 0;
+                for (int e = 0; e < ne; ++e) nr += std::norm(Xe[(size_t)e * K + l]);
+                nr = std::sqrt(nr);
+                for (int e = 0; e < ne; ++e) Xe[(size_t)e * K + l] /= nr;
+            }
+            // inj(g)_p = -a_pq tau_p g_p
+            for (int e = 0; e < ne; ++e) {
+                const int pc = ent[e].x, px = pc % nx, py = pc / nx;
+                cd apq;
+                switch (ent[e].z) {
+                    case SIDE_LEFT: apq = cf[px]; break;
+                    case SIDE_RIGHT: apq = cf[nx + px]; break;
+                    case SIDE_BOTTOM: apq = cf[2 * nx + py]; break;
+                    default: apq = cf[2 * nx + ny + py]; break;
+                }
+                const double kp = k0 * std::sqrt((double)p->eps[pc]);
+                const cd tau = h / cd(1.0, 0.5 * kp * h);
+                const long long li = t.loc_off + (long long)(py - t.y0) * (t.x1 - t.x0) + (px - t.x0);
+                for (int l = 0; l < K; ++l) {
+                    const cd v = -apq * tau * Xe[(size_t)e * K + l];
+                    float2 &dst = rhs[((size_t)wi * K + l) * LT + li];
+                    dst.x += (float)v.real();
+                    dst.y += (float)v.imag();
+                }
+            }
+            Xt[(size_t)wi * nt + ti] = std::move(Xe);
+        }
+    }
+    // batched homogeneous probe solves on the GPU: F = B^-1 inj(X)
+    DevBuf d_rhs, d_F, d_scr;
+    const size_t bytes = rhs.size() * sizeof(float2);
+    HIPCHK(ctx, d_rhs.ensure(bytes));
+    HIPCHK(ctx, d_F.ensure(bytes));
+    HIPCHK(ctx, d_scr.ensure(bytes));
+    HIPCHK(ctx, hipMemcpyAsync(d_rhs.p, rhs.data(), bytes, hipMemcpyHostToDevice, s));
+    launch_bt_solve(s, p->d_tiles.as<TileDesc>(), nt, nwl * K, K, p->d_dinv.as<float2>(), p->dinv_wl_stride,
+                    p->d_coef.as<float2>(), nx, ny, d_rhs.as<float2>(), LT, d_F.as<float2>(), LT,
+                    d_scr.as<float2>(), LT, nullptr, 3, p->bmax);
+    std::vector<float2> F(rhs.size());
+    HIPCHK(ctx, hipMemcpyAsync(F.data(), d_F.p, bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+
+    // per tile: neighbour traces, SVD (through Y^H Y), basis fields, W = A Phi
+    std::vector<float2> phi_h((size_t)nwl * box_total), W_h((size_t)nwl * box_total);
+    std::vector<std::vector<cd>> Wd((size_t)nwl * nt);   // FP64 W boxes for G
+    const int nc = p->n_c;
+    std::vector<double2> ginv_dev((size_t)nwl * nc * nc);
+    for (int wi = 0; wi < nwl; ++wi) {
+        const double k0 = 2.0 * M_PI / p->wl[wi];
+        const auto &cf = p->coefd[wi];
+        const cd *cxm = cf.data(), *cxp = cf.data() + nx, *cym = cf.data() + 2 * nx, *cyp = cf.data() + 2 * nx + ny;
+        for (int ti = 0; ti < nt; ++ti) {
+            const TileDesc &t = p->tiles[ti];
+            const int lx = t.x1 - t.x0;
+            auto Fv = [&](int l, int x, int y) -> cd {
+                const float2 f = F[((size_t)wi * K + l) * LT + t.loc_off + (long long)(y - t.y0) * lx + (x - t.x0)];
+                return cd(f.x, f.y);
+            };
+            // rows of Y: traces on neighbours' ring entries lying inside this tile
+            std::vector<cd> Y;
+            int nrows = 0;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (!dx && !dy) continue;
+                    const int ntx = (ti % p->ncx) + dx, nty = (ti / p->ncx) + dy;
+                    if (ntx < 0 || ntx >= p->ncx || nty < 0 || nty >= p->ncy) continue;
+                    const int tj = nty * p->ncx + ntx;
+                    for (const int4 &e : p->tile_entries[tj]) {
+                        const int px = e.x % nx, py = e.x / nx, qx = e.y % nx, qy = e.y / nx;
+                        if (px < t.x0 || px >= t.x1 || py < t.y0 || py >= t.y1) continue;
+                        if (qx < t.x0 || qx >= t.x1 || qy < t.y0 || qy >= t.y1) continue;
+                        const double kp = k0 * std::sqrt((double)p->eps[e.x]);
+                        for (int l = 0; l < K; ++l) {
+                            const cd up = Fv(l, px, py), uq = Fv(l, qx, qy);
+                            Y.push_back((uq - up) / h + cd(0.0, 0.5 * kp) * (uq + up));
+                        }
+                        ++nrows;
+                    }
+                }
+            // right singular vectors of Y = eigenvectors of Y^H Y, by decreasing eigenvalue
+            std::vector<cd> YhY((size_t)K * K, cd(0, 0));
+            for (int rr = 0; rr < nrows; ++rr)
+                for (int a = 0; a < K; ++a)
+                    for (int bb = 0; bb < K; ++bb)
+                        YhY[(size_t)a * K + bb] += std::conj(Y[(size_t)rr * K + a]) * Y[(size_t)rr * K + bb];
+            std::vector<double> ev;
+            std::vector<cd> Vv;
+            herm_eig(K, YhY, ev, Vv);
+            std::vector<int> order(K);
+            for (int i = 0; i < K; ++i) order[i] = i;
+            std::stable_sort(order.begin(), order.end(), [&](int a, int bb) { return ev[a] > ev[bb]; });
+            // basis fields on the core, stored on the box (core grown by one cell)
+            const int bw = t.bw, bh = t.bh;
+            std::vector<cd> phib((size_t)kc * bw * bh, cd(0, 0)), wb((size_t)kc * bw * bh, cd(0, 0));
+            for (int l = 0; l < kc; ++l) {
+                const int col = order[l];
+                for (int y = t.cy0; y < t.cy1; ++y)
+                    for (int x = t.cx0; x < t.cx1; ++x) {
+                        cd v = 0;
+                        for (int q = 0; q < K; ++q) v += Fv(q, x, y) * Vv[(size_t)q * K + col];
+                        phib[(size_t)l * bw * bh + (size_t)(y - t.by0) * bw + (x - t.bx0)] = v;
+                    }
+                auto ph = [&](int x, int y) -> cd {
+                    if (x < t.cx0 || x >= t.cx1 || y < t.cy0 || y >= t.cy1) return cd(0, 0);
+                    return phib[(size_t)l * bw * bh + (size_t)(y - t.by0) * bw + (x - t.bx0)];
+                };
+                for (int y = t.by0; y < t.by0 + bh; ++y)
+                    for (int x = t.bx0; x < t.bx0 + bw; ++x) {
+                        const cd dg = -(cxm[x] + cxp[x] + cym[y] + cyp[y]) - k0 * k0 * (double)p->eps[(size_t)y * nx + x];
+                        cd v = dg * ph(x, y);
+                        if (x > 0) v += cxm[x] * ph(x - 1, y);
+                        if (x + 1 < nx) v += cxp[x] * ph(x + 1, y);
+                        if (y > 0) v += cym[y] * ph(x, y - 1);
+                        if (y + 1 < ny) v += cyp[y] * ph(x, y + 1);
+                        wb[(size_t)l * bw * bh + (size_t)(y - t.by0) * bw + (x - t.bx0)] = v;
+                    }
+            }
+            for (size_t e = 0; e < phib.size(); ++e) {
+                phi_h[(size_t)wi * box_total + t.box_off + e] = make_float2((float)phib[e].real(), (float)phib[e].imag());
+                W_h[(size_t)wi * box_total + t.box_off + e] = make_float2((float)wb[e].real(), (float)wb[e].imag());
+            }
+            Wd[(size_t)wi * nt + ti] = std::move(wb);
+        }
+        // G = W^H W over overlapping boxes (neighbouring tiles only)
+        std::vector<cd> G((size_t)nc * nc, cd(0, 0));
+        for (int ti = 0; ti < nt; ++ti) {
+            const TileDesc &a = p->tiles[ti];
+            for (int tj = 0; tj < nt; ++tj) {
+                const TileDesc &bt = p->tiles[tj];
+                if (std::abs(ti % p->ncx - tj % p->ncx) > 1 || std::abs(ti / p->ncx - tj / p->ncx) > 1) continue;
+                const int x0 = std::max(a.bx0, bt.bx0), x1 = std::min(a.bx0 + a.bw, bt.bx0 + bt.bw);
+                const int y0 = std::max(a.by0, bt.by0), y1 = std::min(a.by0 + a.bh, bt.by0 + bt.bh);
+                if (x0 >= x1 || y0 >= y1) continue;
+                const auto &wa = Wd[(size_t)wi * nt + ti], &wbb = Wd[(size_t)wi * nt + tj];
+                for (int la = 0; la < kc; ++la)
+                    for (int lb = 0; lb < kc; ++lb) {
+                        cd s = 0;
+                        for (int y = y0; y < y1; ++y)
+                            for (int x = x0; x < x1; ++x)
+                                s += std::conj(wa[(size_t)la * a.bw * a.bh + (size_t)(y - a.by0) * a.bw + (x - a.bx0)]) *
+                                     wbb[(size_t)lb * bt.bw * bt.bh + (size_t)(y - bt.by0) * bt.bw + (x - bt.bx0)];
+                        G[(size_t)(ti * kc + la) * nc + (tj * kc + lb)] = s;
+                    }
+            }
+        }
+        std::vector<cd> Gi;
+        if (!hpd_inverse(nc, G, Gi)) return fail(ctx, NOSDD_EBREAKDOWN, "coarse matrix G = W^H W is not positive definite");
+        for (int j = 0; j < nc; ++j)
+            for (int i = 0; i < nc; ++i) {
+                const cd g = Gi[(size_t)i * nc + j];
+                ginv_dev[(size_t)wi * nc * nc + (size_t)j * nc + i] = make_double2(g.real(), g.imag());
+            }
+    }
+    HIPCHK(ctx, p->d_phi.ensure(phi_h.size() * sizeof(float2)));
+    HIPCHK(ctx, p->d_W.ensure(W_h.size() * sizeof(float2)));
+    HIPCHK(ctx, p->d_GinvT.ensure(ginv_dev.size() * sizeof(double2)));
+    HIPCHK(ctx, hipMemcpyAsync(p->d_phi.p, phi_h.data(), phi_h.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(p->d_W.p, W_h.data(), W_h.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(p->d_GinvT.p, ginv_dev.data(), ginv_dev.size() * sizeof(double2), hipMemcpyHostToDevice,
+                               s));
+    std::vector<int> tox(nx), toy(ny);
+    for (int i = 0, acc = 0; i < p->ncx; ++i) {
+        for (int x = 0; x < p->core_x[i]; ++x) tox[acc + x] = i;
+        acc += p->core_x[i];
+    }
+    for (int i = 0, acc = 0; i < p->ncy; ++i) {
+        for (int y = 0; y < p->core_y[i]; ++y) toy[acc + y] = i;
+        acc += p->core_y[i];
+    }
+    HIPCHK(ctx, p->d_tox.ensure(nx * sizeof(int)));
+    HIPCHK(ctx, p->d_toy.ensure(ny * sizeof(int)));
+    HIPCHK(ctx, hipMemcpyAsync(p->d_tox.p, tox.data(), nx * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(p->d_toy.p, toy.data(), ny * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return NOSDD_OK;
+}
+
+nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const nosdd_solve_opts *o, const float2 *x0_dev,
+                        float2 *E_dev, float *resid_hist, int *iters_out, float *final_out) {
+    nosdd_ctx *ctx = p->ctx;
+    hipStream_t s = ctx->stream;
+    const int nwl = (int)p->wl.size();
+    const int n_rhs = nwl * n_src;
+    const int m = o->restart;
+    const long long N = (long long)p->nx * p->ny;
+    nosdd_status st = ensure_ws(p, n_rhs, m, o->max_iters);
+    if (st != NOSDD_OK) return st;
+    Workspace &w = p->ws;
+    const int nblk = w.nblk;
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    HIPCHK(ctx, hipEventRecord(e0, s));
+
+    float2 *x = w.x.as<float2>(), *b = w.b.as<float2>(), *V = w.V.as<float2>(), *Z = w.Z.as<float2>(),
+           *wv = w.w.as<float2>();
+    const long long vstride = (long long)n_rhs * N;
+    hipLaunchKernelGGL(make_rhs_kernel, dim3((unsigned)grid_blocks(N), n_rhs), dim3(256), 0, s, J_dev, b,
+                       p->d_k0f.as<float>(), N, n_src);
+    if (x0_dev)
+        HIPCHK(ctx, hipMemcpyAsync(x, x0_dev, vstride * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    else
+        HIPCHK(ctx, hipMemsetAsync(x, 0, vstride * sizeof(float2), s));
+    HIPCHK(ctx, hipMemsetAsync(w.iters.p, 0, n_rhs * sizeof(int), s));
+    {
+        const long long nh = (long long)n_rhs * std::max(1, o->max_iters);
+        hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)grid_blocks(nh)), dim3(256), 0, s, w.hist.as<float>(), nh,
+                           -1.0f);
+    }
+    // ||b||
+    launch_dots(s, V, vstride, 0, b, N, n_rhs, nullptr, w.partial.as<double2>(), nblk);
+    launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, nullptr, w.bnorm2.as<double>());
+    std::vector<double> bn2(n_rhs), beta2(n_rhs);
+    HIPCHK(ctx, hipMemcpyAsync(bn2.data(), w.bnorm2.p, n_rhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    std::vector<float> bnorm(n_rhs);
+    for (int r = 0; r < n_rhs; ++r) bnorm[r] = (float)std::sqrt(bn2[r]);
+    HIPCHK(ctx, hipMemcpyAsync(w.bnorm.p, bnorm.data(), n_rhs * sizeof(float), hipMemcpyHostToDevice, s));
+
+    GivensArgs ga;
+    ga.H = w.H.as<float2>();
+    ga.ldh = m;
+    ga.m = m;
+    ga.cs = w.cs.as<float>();
+    ga.sn = w.sn.as<float2>();
+    ga.gam = w.gam.as<float2>();
+    ga.nw_pre = w.nw_pre.as<double>();
+    ga.nw_post = w.nw_post.as<double>();
+    ga.nw_reorth = w.nw_re.as<double>();
+    ga.reorth = w.reorth.as<int>();
+    ga.bnorm = w.bnorm.as<float>();
+    ga.tol = (float)o->tol;
+    ga.active = w.active.as<int>();
+    ga.iters = w.iters.as<int>();
+    ga.kcyc = w.kcyc.as<int>();
+    ga.max_iters = o->max_iters;
+    ga.hist = w.hist.as<float>();
+    ga.hist_ld = std::max(1, o->max_iters);
+    ga.inv_h = w.inv_h.as<float>();
+    ga.flags = w.flags.as<int>();
+
+    std::vector<int> iters(n_rhs, 0), want(n_rhs), act(n_rhs);
+    std::vector<double> final_res(n_rhs, 0.0);
+    int *h_act = nullptr;
+    HIPCHK(ctx, hipHostMalloc((void **)&h_act, n_rhs * sizeof(int) * 2, hipHostMallocDefault));
+    nosdd_status result = NOSDD_OK;
+    int total_outer = 0;
+    for (;;) {
+        // explicit residual r = b - A x into w, beta^2
+        launch_stencil(s, x, b, wv, p->d_eps.as<float>(), p->d_coef.as<float2>(), p->d_k0sq.as<float>(), p->nx,
+                       p->ny, n_rhs, n_src, nullptr);
+        launch_dots(s, V, vstride, 0, wv, N, n_rhs, nullptr, w.partial.as<double2>(), nblk);
+        launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, nullptr, w.beta2.as<double>());
+        HIPCHK(ctx, hipMemcpyAsync(beta2.data(), w.beta2.p, n_rhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipMemcpyAsync(iters.data(), w.iters.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        int any = 0;
+        for (int r = 0; r < n_rhs; ++r) {
+            const double rel = bn2[r] > 0 ? std::sqrt(beta2[r] / bn2[r]) : 0.0;
+            final_res[r] = rel;
+            if (!std::isfinite(rel)) return fail(ctx, NOSDD_ENONFINITE, "non-finite residual");
+            want[r] = (rel > o->tol && iters[r] < o->max_iters && bn2[r] > 0) ? 1 : 0;
+            any |= want[r];
+        }
+        if (!any) break;
+        HIPCHK(ctx, hipMemcpyAsync(w.want.p, want.data(), n_rhs * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(ctx, hipMemsetAsync(w.kcyc.p, 0, n_rhs * sizeof(int), s));
+        HIPCHK(ctx, hipMemsetAsync(w.active.p, 0, n_rhs * sizeof(int), s));
+        HIPCHK(ctx, hipMemsetAsync(w.H.p, 0, (size_t)n_rhs * (m + 1) * m * sizeof(float2), s));
+        launch_start_cycle(s, V, wv, w.beta2.as<double>(), w.bnorm.as<float>(), w.gam.as<float2>(), m,
+                           w.kcyc.as<int>(), w.active.as<int>(), w.want.as<int>(), N, n_rhs);
+        const int *active = w.active.as<int>();
+        for (int j = 0; j < m; ++j) {
+            float2 *Vj = V + j * vstride, *Vn = V + (j + 1) * vstride, *Zj = Z + j * vstride;
+            precond(p, s, Vj, Zj, wv, n_src, n_rhs, active);
+            // classical Gram-Schmidt against V_0..V_j, selective second pass
+            launch_dots(s, V, vstride, j + 1, wv, N, n_rhs, active, w.partial.as<double2>(), nblk);
+            launch_reduce_dots(s, w.partial.as<double2>(), nblk, j + 1, n_rhs, active, w.H.as<float2>(), m, m, j, 0,
+                               w.nw_pre.as<double>());
+            launch_update(s, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, m, j, nullptr,
+                          w.partial.as<double2>(), nblk);
+            launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, active, w.nw_post.as<double>());
+            launch_dgks(s, w.nw_pre.as<double>(), w.nw_post.as<double>(), w.reorth.as<int>(), active, n_rhs);
+            const int *ro = w.reorth.as<int>();
+            launch_dots(s, V, vstride, j + 1, Vn, N, n_rhs, ro, w.partial.as<double2>(), nblk);
+            launch_reduce_dots(s, w.partial.as<double2>(), nblk, j + 1, n_rhs, ro, w.H2.as<float2>(), m, m, j, 0,
+                               nullptr);
+            launch_update(s, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, m, j, nullptr,
+                          w.partial.as<double2>(), nblk);
+            launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, ro, w.nw_re.as<double>());
+            launch_hadd(s, w.H.as<float2>(), w.H2.as<float2>(), m, j, j + 1, ro, n_rhs);
+            launch_givens(s, ga, j, n_rhs);
+            launch_scale(s, Vn, N, n_rhs, active, w.inv_h.as<float>());
+            ++total_outer;
+            HIPCHK(ctx, hipMemcpyAsync(h_act, w.active.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(ctx, hipStreamSynchronize(s));
+            int live = 0;
+            for (int r = 0; r < n_rhs; ++r) live |= h_act[r];
+            if (!live) break;
+        }
+        launch_backsolve(s, w.H.as<float2>(), m, m, w.gam.as<float2>(), w.kcyc.as<int>(), w.y.as<float2>(), n_rhs);
+        launch_xupdate(s, x, Z, vstride, w.y.as<float2>(), m, w.kcyc.as<int>(), N, n_rhs);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    if (E_dev) HIPCHK(ctx, hipMemcpyAsync(E_dev, x, vstride * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    HIPCHK(ctx, hipEventRecord(e1, s));
+    HIPCHK(ctx, hipMemcpyAsync(iters.data(), w.iters.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (resid_hist && o->max_iters > 0)
+        HIPCHK(ctx, hipMemcpyAsync(resid_hist, w.hist.p, (size_t)n_rhs * std::max(1, o->max_iters) * sizeof(float),
+                                   hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipHostFree(h_act);
+    p->solve_ms = ms;
+    p->last_iters = total_outer;
+    for (int r = 0; r < n_rhs; ++r) {
+        if (iters_out) iters_out[r] = iters[r];
+        if (final_out) final_out[r] = (float)final_res[r];
+        if (final_res[r] > o->tol) result = NOSDD_NOT_CONVERGED;
+    }
+    return result;
+}
+
+nosdd_status check_problem(nosdd_problem *p, bool need_setup) {
+    if (!p) return NOSDD_EINVAL;
+    if (need_setup && !p->setup_done) return fail(p->ctx, NOSDD_ESTATE, "nosdd_problem_setup has not been called");
+    if (hipSetDevice(p->ctx->device) != hipSuccess) return fail(p->ctx, NOSDD_EHIP, "hipSetDevice failed");
+    return NOSDD_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+nosdd_status nosdd_ctx_create(int hip_device, void *hip_stream, nosdd_ctx **out) {
+    if (!out) return NOSDD_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return NOSDD_EINVAL;
+    if (hipSetDevice(hip_device) != hipSuccess) return NOSDD_EHIP;
+    nosdd_ctx *c = new nosdd_ctx();
+    c->device = hip_device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
+            delete c;
+            return NOSDD_EHIP;
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return NOSDD_OK;
+}
+
+void nosdd_ctx_destroy(nosdd_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->own_stream && ctx->stream) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamDestroy(ctx->stream);
+    }
+    delete ctx;
+}
+
+const char *nosdd_last_error(const nosdd_ctx *ctx) {
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const float *eps, const nosdd_partition *part,
+                                  const double *wavelengths, int n_wl, nosdd_problem **out) {
+    if (!ctx) return NOSDD_EINVAL;
+    if (!out || !g || !eps || !part || !wavelengths || n_wl <= 0) return fail(ctx, NOSDD_EINVAL, "null argument or n_wl <= 0");
+    *out = nullptr;
+    if (g->nx < 4 || g->ny < 4 || !(g->h > 0) || g->npml < 0 || 2 * g->npml >= std::min(g->nx, g->ny) || g->pml_m < 0)
+        return fail(ctx, NOSDD_EINVAL, "invalid grid");
+    for (int i = 0; i < n_wl; ++i)
+        if (!(wavelengths[i] > 0)) return fail(ctx, NOSDD_EINVAL, "wavelengths must be positive");
+    if (!part->core_x || !part->core_y || part->ncx <= 0 || part->ncy <= 0)
+        return fail(ctx, NOSDD_EPARTITION, "empty partition");
+    if (part->overlap < 2 || part->overlap % 2) return fail(ctx, NOSDD_EPARTITION, "overlap must be even and >= 2");
+    long long sx = 0, sy = 0;
+    int minc = 1 << 30;
+    for (int i = 0; i < part->ncx; ++i) {
+        if (part->core_x[i] <= 0) return fail(ctx, NOSDD_EPARTITION, "core sizes must be positive");
+        sx += part->core_x[i];
+        minc = std::min(minc, part->core_x[i]);
+    }
+    for (int i = 0; i < part->ncy; ++i) {
+        if (part->core_y[i] <= 0) return fail(ctx, NOSDD_EPARTITION, "core sizes must be positive");
+        sy += part->core_y[i];
+        minc = std::min(minc, part->core_y[i]);
+    }
+    if (sx != g->nx || sy != g->ny) return fail(ctx, NOSDD_EPARTITION, "core sizes must sum to the grid size");
+    const int ext = part->overlap / 2;
+    const int ntile = part->ncx * part->ncy;
+    if (ntile > 1 && ext + 1 > minc) return fail(ctx, NOSDD_EPARTITION, "overlap/2 + 1 exceeds a core");
+    for (int i = 0; i < g->nx * g->ny; ++i)
+        if (!(std::isfinite(eps[i]))) return fail(ctx, NOSDD_EINVAL, "eps must be finite");
+
+    nosdd_problem *p = new nosdd_problem();
+    p->ctx = ctx;
+    p->nx = g->nx;
+    p->ny = g->ny;
+    p->h = g->h;
+    p->npml = g->npml;
+    p->pml_m = g->pml_m;
+    p->lnR = g->pml_lnR;
+    p->eps.assign(eps, eps + (size_t)g->nx * g->ny);
+    p->wl.assign(wavelengths, wavelengths + n_wl);
+    p->core_x.assign(part->core_x, part->core_x + part->ncx);
+    p->core_y.assign(part->core_y, part->core_y + part->ncy);
+    p->ncx = part->ncx;
+    p->ncy = part->ncy;
+    p->overlap = part->overlap;
+    p->ext = ext;
+    // tiles
+    long long loc = 0, dinv = 0;
+    int cy = 0;
+    for (int ty = 0; ty < p->ncy; ++ty) {
+        int cx = 0;
+        for (int tx = 0; tx < p->ncx; ++tx) {
+            TileDesc t{};
+            t.cx0 = cx;
+            t.cx1 = cx + p->core_x[tx];
+            t.cy0 = cy;
+            t.cy1 = cy + p->core_y[ty];
+            t.iface = (ty > 0 ? SIDE_BOTTOM : 0) | (tx < p->ncx - 1 ? SIDE_RIGHT : 0) |
+                      (ty < p->ncy - 1 ? SIDE_TOP : 0) | (tx > 0 ? SIDE_LEFT : 0);
+            t.x0 = (t.iface & SIDE_LEFT) ? t.cx0 - ext : t.cx0;
+            t.x1 = (t.iface & SIDE_RIGHT) ? t.cx1 + ext : t.cx1;
+            t.y0 = (t.iface & SIDE_BOTTOM) ? t.cy0 - ext : t.cy0;
+            t.y1 = (t.iface & SIDE_TOP) ? t.cy1 + ext : t.cy1;
+            const int n = p->npml;
+            auto bad_x = [&](int xb) { return xb < n || xb > p->nx - n - 1; };
+            auto bad_y = [&](int yb) { return yb < n || yb > p->ny - n - 1; };
+            if (((t.iface & SIDE_LEFT) && bad_x(t.x0)) || ((t.iface & SIDE_RIGHT) && bad_x(t.x1 - 1)) ||
+                ((t.iface & SIDE_BOTTOM) && bad_y(t.y0)) || ((t.iface & SIDE_TOP) && bad_y(t.y1 - 1))) {
+                delete p;
+                return fail(ctx, NOSDD_EPARTITION, "a subdomain interface lies inside the PML of its normal direction");
+            }
+            const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
+            t.tr = lx > ly ? 1 : 0;
+            t.b = std::min(lx, ly);
+            t.nb = std::max(lx, ly);
+            if (t.b % 2 || t.b > 72) {
+                delete p;
+                return fail(ctx, NOSDD_EPARTITION, "extended subdomains need an even short side of at most 72 cells");
+            }
+            t.loc_off = loc;
+            loc += (long long)lx * ly;
+            t.dinv_off = dinv;
+            dinv += (long long)t.nb * t.b * t.b;
+            p->bmax = std::max(p->bmax, t.b);
+            p->tiles.push_back(t);
+            cx += p->core_x[tx];
+        }
+        cy += p->core_y[ty];
+    }
+    p->loc_total = loc;
+    p->dinv_wl_stride = dinv;
+    for (auto &t : p->tiles) {
+        std::vector<int4> e;
+        trace_entries(t, p->nx, e);
+        t.tr_off = p->n_entries;
+        t.n_tr = (int)e.size();
+        p->n_entries += t.n_tr;
+        p->tile_entries.push_back(e);
+    }
+    // coefficients
+    const int nx = p->nx, ny = p->ny;
+    std::vector<float2> cf((size_t)n_wl * 2 * (nx + ny));
+    std::vector<double2> cdv((size_t)n_wl * 2 * (nx + ny));
+    std::vector<float> k0sq(n_wl), k0f(n_wl);
+    std::vector<double> k0d(n_wl);
+    for (int w = 0; w < n_wl; ++w) {
+        const double k0 = 2.0 * M_PI / p->wl[w];
+        k0d[w] = k0;
+        k0f[w] = (float)k0;
+        k0sq[w] = (float)(k0 * k0);
+        auto ax = axis_coefs(nx, p->npml, p->pml_m, p->lnR, k0, p->h);
+        auto ay = axis_coefs(ny, p->npml, p->pml_m, p->lnR, k0, p->h);
+        std::vector<cd> all(2 * (nx + ny));
+        for (int i = 0; i < 2 * nx; ++i) all[i] = ax[i];
+        for (int i = 0; i < 2 * ny; ++i) all[2 * nx + i] = ay[i];
+        for (size_t i = 0; i < all.size(); ++i) {
+            cf[(size_t)w * all.size() + i] = make_float2((float)all[i].real(), (float)all[i].imag());
+            cdv[(size_t)w * all.size() + i] = make_double2(all[i].real(), all[i].imag());
+        }
+        p->coefd.push_back(all);
+    }
+    std::vector<int4> ents;
+    for (auto &e : p->tile_entries) ents.insert(ents.end(), e.begin(), e.end());
+    hipStream_t s = ctx->stream;
+    auto up = [&](DevBuf &d, const void *src, size_t bytes) -> hipError_t {
+        hipError_t e = d.ensure(bytes);
+        if (e != hipSuccess) return e;
+        return bytes ? hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = up(p->d_eps, p->eps.data(), p->eps.size() * sizeof(float));
+    if (e == hipSuccess) e = up(p->d_coef, cf.data(), cf.size() * sizeof(float2));
+    if (e == hipSuccess) e = up(p->d_coefd, cdv.data(), cdv.size() * sizeof(double2));
+    if (e == hipSuccess) e = up(p->d_k0sq, k0sq.data(), k0sq.size() * sizeof(float));
+    if (e == hipSuccess) e = up(p->d_k0f, k0f.data(), k0f.size() * sizeof(float));
+    if (e == hipSuccess) e = up(p->d_k0, k0d.data(), k0d.size() * sizeof(double));
+    if (e == hipSuccess) e = up(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(TileDesc));
+    if (e == hipSuccess) e = up(p->d_entries, ents.data(), ents.size() * sizeof(int4));
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        ctx->err = std::string("HIP error during problem_create: ") + hipGetErrorString(e);
+        delete p;
+        return e == hipErrorOutOfMemory ? NOSDD_ENOMEM : NOSDD_EHIP;
+    }
+    *out = p;
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
+    nosdd_status st = check_problem(p, false);
+    if (st) return st;
+    nosdd_ctx *ctx = p->ctx;
+    if (!o) return fail(ctx, NOSDD_EINVAL, "null options");
+    if (o->sub_solver != 0 && o->sub_solver != 1) return fail(ctx, NOSDD_EINVAL, "sub_solver must be 0 or 1");
+    if (o->k_coarse < 0 || o->k_trial < 0) return fail(ctx, NOSDD_EINVAL, "negative coarse size");
+    if (o->sub_solver == 1 && (!o->nn_weights || !o->nn_weights[0]))
+        return fail(ctx, NOSDD_ENOWEIGHTS, "neural subdomain solver requested without a weights file");
+    if (o->sub_solver == 1) return fail(ctx, NOSDD_EINVAL, "neural subdomain solver is not available in this build");
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    HIPCHK(ctx, hipEventRecord(e0, s));
+    const int nwl = (int)p->wl.size();
+    HIPCHK(ctx, p->d_dinv.ensure((size_t)nwl * p->dinv_wl_stride * sizeof(float2)));
+    launch_bt_factor(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, p->d_eps.as<float>(), nullptr,
+                     p->d_coefd.as<double>(), p->d_k0.as<double>(), p->h, p->nx, p->ny, p->d_dinv.as<float2>(),
+                     p->dinv_wl_stride, p->bmax);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    p->kc = (p->tiles.size() > 1) ? o->k_coarse : 0;
+    p->ktrial = o->k_trial > 0 ? o->k_trial : 8;
+    p->n_c = 0;
+    if (p->kc > 0) {
+        if (p->kc > std::max(p->ktrial, p->kc) || std::max(p->ktrial, p->kc) > 64)
+            return fail(ctx, NOSDD_EINVAL, "k_trial must be at most 64");
+        st = coarse_setup(p);
+        if (st) return st;
+    }
+    HIPCHK(ctx, hipEventRecord(e1, s));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->setup_ms = ms;
+    p->sub_solver = o->sub_solver;
+    p->setup_done = true;
+    return NOSDD_OK;
+}
+
+void nosdd_problem_destroy(nosdd_problem *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    delete p;
+}
+
+static nosdd_status validate_solve(nosdd_problem *p, const void *J, int n_src, const nosdd_solve_opts *o, const void *E) {
+    nosdd_status st = check_problem(p, true);
+    if (st) return st;
+    if (!J || !o || !E || n_src <= 0) return fail(p->ctx, NOSDD_EINVAL, "null argument or n_src <= 0");
+    if (o->restart < 1 || o->restart > 31) return fail(p->ctx, NOSDD_EINVAL, "restart must be in [1, 31]");
+    if (o->max_iters < 0 || !(o->tol > 0)) return fail(p->ctx, NOSDD_EINVAL, "invalid tolerance or max_iters");
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_solve_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src, const nosdd_solve_opts *o,
+                                nosdd_c32 *E_dev, float *resid_hist, int *iters, float *final_resid) {
+    nosdd_status st = validate_solve(p, J_dev, n_src, o, E_dev);
+    if (st) return st;
+    return solve_impl(p, (const float2 *)J_dev, n_src, o, (const float2 *)o->x0, (float2 *)E_dev, resid_hist, iters,
+                      final_resid);
+}
+
+nosdd_status nosdd_solve(nosdd_problem *p, const nosdd_c32 *J, int n_src, const nosdd_solve_opts *o, nosdd_c32 *E_out,
+                         float *resid_hist, int *iters, float *final_resid) {
+    nosdd_status st = validate_solve(p, J, n_src, o, E_out);
+    if (st) return st;
+    nosdd_ctx *ctx = p->ctx;
+    hipStream_t s = ctx->stream;
+    const long long N = (long long)p->nx * p->ny;
+    const int n_rhs = (int)p->wl.size() * n_src;
+    DevBuf dJ, dE, dx0;
+    HIPCHK(ctx, dJ.ensure((size_t)n_src * N * sizeof(float2)));
+    HIPCHK(ctx, dE.ensure((size_t)n_rhs * N * sizeof(float2)));
+    HIPCHK(ctx, hipMemcpyAsync(dJ.p, J, (size_t)n_src * N * sizeof(float2), hipMemcpyHostToDevice, s));
+    nosdd_solve_opts od = *o;
+    if (o->x0) {
+        HIPCHK(ctx, dx0.ensure((size_t)n_rhs * N * sizeof(float2)));
+        HIPCHK(ctx, hipMemcpyAsync(dx0.p, o->x0, (size_t)n_rhs * N * sizeof(float2), hipMemcpyHostToDevice, s));
+        od.x0 = (const nosdd_c32 *)dx0.p;
+    }
+    st = solve_impl(p, dJ.as<float2>(), n_src, &od, (const float2 *)od.x0, dE.as<float2>(), resid_hist, iters,
+                    final_resid);
+    if (st < 0) return st;
+    HIPCHK(ctx, hipMemcpyAsync(E_out, dE.p, (size_t)n_rhs * N * sizeof(float2), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return st;
+}
+
+nosdd_status nosdd_apply_operator(nosdd_problem *p, const nosdd_c32 *x, const nosdd_c32 *b, nosdd_c32 *y, int n_src) {
+    nosdd_status st = check_problem(p, false);
+    if (st) return st;
+    if (!x || !y || n_src <= 0) return fail(p->ctx, NOSDD_EINVAL, "null argument or n_src <= 0");
+    launch_stencil(p->ctx->stream, (const float2 *)x, (const float2 *)b, (float2 *)y, p->d_eps.as<float>(),
+                   p->d_coef.as<float2>(), p->d_k0sq.as<float>(), p->nx, p->ny, (int)p->wl.size() * n_src, n_src,
+                   nullptr);
+    HIPCHK(p->ctx, hipGetLastError());
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_schwarz_sweep(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *z, int n_src) {
+    nosdd_status st = check_problem(p, true);
+    if (st) return st;
+    if (!v || !z || n_src <= 0) return fail(p->ctx, NOSDD_EINVAL, "null argument or n_src <= 0");
+    const int n_rhs = (int)p->wl.size() * n_src;
+    DevBuf scr;
+    HIPCHK(p->ctx, scr.ensure((size_t)n_rhs * p->loc_total * sizeof(float2)));
+    const long long N = (long long)p->nx * p->ny;
+    launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src,
+                    p->d_dinv.as<float2>(), p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny,
+                    (const float2 *)v, N, (float2 *)z, N, scr.as<float2>(), p->loc_total, nullptr, 0, p->bmax);
+    HIPCHK(p->ctx, hipGetLastError());
+    HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_precond_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *z, nosdd_c32 *Az, int n_src) {
+    nosdd_status st = check_problem(p, true);
+    if (st) return st;
+    if (!v || !z || n_src <= 0) return fail(p->ctx, NOSDD_EINVAL, "null argument or n_src <= 0");
+    const int n_rhs = (int)p->wl.size() * n_src;
+    st = ensure_ws(p, n_rhs, std::max(1, p->ws.m), std::max(1, p->ws.max_iters));
+    if (st) return st;
+    const long long N = (long long)p->nx * p->ny;
+    DevBuf tmp;
+    float2 *w = (float2 *)Az;
+    if (!w) {
+        HIPCHK(p->ctx, tmp.ensure((size_t)n_rhs * N * sizeof(float2)));
+        w = tmp.as<float2>();
+    }
+    precond(p, p->ctx->stream, (const float2 *)v, (float2 *)z, w, n_src, n_rhs, nullptr);
+    HIPCHK(p->ctx, hipGetLastError());
+    HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32 *u) {
+    nosdd_status st = check_problem(p, true);
+    if (st) return st;
+    if (!rhs || !u) return fail(p->ctx, NOSDD_EINVAL, "null argument");
+    const int nwl = (int)p->wl.size();
+    DevBuf scr;
+    HIPCHK(p->ctx, scr.ensure((size_t)nwl * p->loc_total * sizeof(float2)));
+    launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, 1, p->d_dinv.as<float2>(),
+                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, (const float2 *)rhs, p->loc_total,
+                    (float2 *)u, p->loc_total, scr.as<float2>(), p->loc_total, nullptr, 3, p->bmax);
+    HIPCHK(p->ctx, hipGetLastError());
+    HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_robin_trace(nosdd_problem *p, const nosdd_c32 *x, nosdd_c32 *g) {
+    nosdd_status st = check_problem(p, false);
+    if (st) return st;
+    if (!x || !g) return fail(p->ctx, NOSDD_EINVAL, "null argument");
+    launch_robin_trace(p->ctx->stream, p->d_entries.as<int4>(), p->n_entries, p->d_eps.as<float>(), p->d_k0f.as<float>(),
+                       (float)p->h, p->nx, p->ny, (const float2 *)x, (float2 *)g, (int)p->wl.size(), 1);
+    HIPCHK(p->ctx, hipGetLastError());
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_tile_info(const nosdd_problem *p, int tile, long long info[10]) {
+    if (!p || !info || tile < 0 || tile >= (int)p->tiles.size()) return NOSDD_EINVAL;
+    const TileDesc &t = p->tiles[tile];
+    const long long v[10] = {t.x0, t.x1, t.y0, t.y1, t.cx0, t.cx1, t.cy0, t.cy1, t.loc_off, t.tr_off};
+    for (int i = 0; i < 10; ++i) info[i] = v[i];
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_sizes(const nosdd_problem *p, int *n_tiles, long long *local_cells, long long *trace_entries,
+                         int *n_coarse) {
+    if (!p) return NOSDD_EINVAL;
+    if (n_tiles) *n_tiles = (int)p->tiles.size();
+    if (local_cells) *local_cells = p->loc_total;
+    if (trace_entries) *trace_entries = p->n_entries;
+    if (n_coarse) *n_coarse = p->n_c;
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_last_timing(const nosdd_problem *p, double *setup_ms, double *solve_ms, int *outer_iters) {
+    if (!p) return NOSDD_EINVAL;
+    if (setup_ms) *setup_ms = p->setup_ms;
+    if (solve_ms) *solve_ms = p->solve_ms;
+    if (outer_iters) *outer_iters = p->last_iters;
+    return NOSDD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Coarse-space correction of the two-level preconditioner (volume form of the
+// paper's coarse normal equations, Methods two-level subsection):
+//   t = v - A z1,  d = W^H t,  c = G^-1 d,  z = z1 + Phi c,  A z = A z1 + W c,
+// with Phi the basis fields (each supported on one subdomain core), W = A Phi
+// (supported on the core grown by one cell, the "box") and G = W^H W.
+// d and c are accumulated / solved in FP64 (G^-1 is applied as a dense FP64
+// product: G is small, n_sub * k_coarse, and its explicit inverse is formed at
+// set-up from a Cholesky factorisation in FP64).
+#include "common.h"
+
+namespace nosdd {
+
+// d[r][col] = sum_box conj(W[wl][col]) (v - w1)   -- one workgroup per (col, rhs)
+__global__ __launch_bounds__(256) void coarse_dot_kernel(const TileDesc *__restrict__ tiles, int kc,
+                                                         const float2 *__restrict__ Wbox, long long wl_stride,
+                                                         const float2 *__restrict__ v, const float2 *__restrict__ w1,
+                                                         int nx, long long N, int n_src, int n_c,
+                                                         const int *__restrict__ active, double2 *__restrict__ d) {
+    __shared__ double2 red[4];
+    const int col = blockIdx.x, r = blockIdx.y;
+    if (active && !active[r]) return;
+    const int wl = r / n_src;
+    const TileDesc t = tiles[col / kc];
+    const int l = col - (col / kc) * kc;
+    const float2 *Wc = Wbox + wl * wl_stride + t.box_off + (long long)l * t.bw * t.bh;
+    const float2 *vr = v + r * N, *wr = w1 + r * N;
+    double sx = 0.0, sy = 0.0;
+    const int nbox = t.bw * t.bh;
+    for (int e = threadIdx.x; e < nbox; e += 256) {
+        const int by = e / t.bw, bx = e - by * t.bw;
+        const long long g = (long long)(t.by0 + by) * nx + (t.bx0 + bx);
+        const float2 tv = csub(vr[g], wr[g]);
+        const float2 wv = Wc[e];
+        sx += (double)wv.x * tv.x + (double)wv.y * tv.y;
+        sy += (double)wv.x * tv.y - (double)wv.y * tv.x;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sx += __shfl_down(sx, off, 64);
+        sy += __shfl_down(sy, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double2(sx, sy);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double2 s = red[0];
+        for (int i = 1; i < 4; ++i) s = zadd(s, red[i]);
+        d[(long long)r * n_c + col] = s;
+    }
+}
+
+void launch_coarse_dot(hipStream_t s, const TileDesc *tiles, const int *col_tile, int n_c, int kc, const float2 *Wbox,
+                       long long box_wl_stride, int unused, const float2 *v, const float2 *w1, int nx, long long N,
+                       int n_rhs, int n_src, const int *active, double2 *d) {
+    (void)col_tile;
+    (void)unused;
+    hipLaunchKernelGGL(coarse_dot_kernel, dim3(n_c, n_rhs), dim3(256), 0, s, tiles, kc, Wbox, box_wl_stride, v, w1, nx,
+                       N, n_src, n_c, active, d);
+}
+
+// c[r] = Ginv[wl] d[r] in FP64 (GinvT[wl][j][i] = Ginv[i][j], coalesced over i)
+__global__ __launch_bounds__(256) void coarse_solve_kernel(const double2 *__restrict__ GinvT, int n_c,
+                                                           const double2 *__restrict__ d, float2 *__restrict__ c,
+                                                           int n_src, const int *__restrict__ active) {
+    const int r = blockIdx.y;
+    if (active && !active[r]) return;
+    const int wl = r / n_src;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_c) return;
+    const double2 *G = GinvT + (long long)wl * n_c * n_c;
+    const double2 *dr = d + (long long)r * n_c;
+    double sx = 0.0, sy = 0.0;
+    for (int j = 0; j < n_c; ++j) {
+        const double2 g = G[(long long)j * n_c + i];
+        const double2 dv = dr[j];
+        sx += g.x * dv.x - g.y * dv.y;
+        sy += g.x * dv.y + g.y * dv.x;
+    }
+    c[(long long)r * n_c + i] = make_float2((float)sx, (float)sy);
+}
+
+void launch_coarse_solve(hipStream_t s, const double2 *GinvT, int n_c, const double2 *d, float2 *c, int n_rhs,
+                         int n_src, const int *active) {
+    hipLaunchKernelGGL(coarse_solve_kernel, dim3((n_c + 255) / 256, n_rhs), dim3(256), 0, s, GinvT, n_c, d, c, n_src,
+                       active);
+}
+
+__device__ __forceinline__ float2 box_sum(const TileDesc &t, const float2 *base, int kc, const float2 *cc, int x,
+                                          int y) {
+    const int e = (y - t.by0) * t.bw + (x - t.bx0);
+    const long long colstride = (long long)t.bw * t.bh;
+    float2 s = make_float2(0.f, 0.f);
+    for (int l = 0; l < kc; ++l) s = cfma(s, cc[l], base[t.box_off + l * colstride + e]);
+    return s;
+}
+
+// z += Phi c (owner core), w += W c (owner box and the four side neighbours' boxes)
+__global__ __launch_bounds__(256) void coarse_update_kernel(const TileDesc *__restrict__ tiles, int ncx, int ncy,
+                                                            const int *__restrict__ tile_of_x,
+                                                            const int *__restrict__ tile_of_y, int kc,
+                                                            const float2 *__restrict__ Phibox,
+                                                            const float2 *__restrict__ Wbox, long long wl_stride,
+                                                            const float2 *__restrict__ c, int n_c, float2 *__restrict__ z,
+                                                            float2 *__restrict__ w, int nx, int ny, int n_src,
+                                                            const int *__restrict__ active) {
+    const int r = blockIdx.z;
+    if (active && !active[r]) return;
+    const int wl = r / n_src;
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= nx || y >= ny) return;
+    const int tx = tile_of_x[x], ty = tile_of_y[y];
+    const TileDesc t = tiles[ty * ncx + tx];
+    const float2 *cr = c + (long long)r * n_c;
+    const float2 *Pb = Phibox + wl * wl_stride;
+    const float2 *Wb = Wbox + wl * wl_stride;
+    const long long g = (long long)r * nx * ny + (long long)y * nx + x;
+    const int own = ty * ncx + tx;
+    z[g] = cadd(z[g], box_sum(t, Pb, kc, cr + own * kc, x, y));
+    float2 acc = box_sum(t, Wb, kc, cr + own * kc, x, y);
+    if (x == t.cx0 && tx > 0) {
+        const int nb = ty * ncx + tx - 1;
+        acc = cadd(acc, box_sum(tiles[nb], Wb, kc, cr + nb * kc, x, y));
+    }
+    if (x == t.cx1 - 1 && tx + 1 < ncx) {
+        const int nb = ty * ncx + tx + 1;
+        acc = cadd(acc, box_sum(tiles[nb], Wb, kc, cr + nb * kc, x, y));
+    }
+    if (y == t.cy0 && ty > 0) {
+        const int nb = (ty - 1) * ncx + tx;
+        acc = cadd(acc, box_sum(tiles[nb], Wb, kc, cr + nb * kc, x, y));
+    }
+    if (y == t.cy1 - 1 && ty + 1 < ncy) {
+        const int nb = (ty + 1) * ncx + tx;
+        acc = cadd(acc, box_sum(tiles[nb], Wb, kc, cr + nb * kc, x, y));
+    }
+    w[g] = cadd(w[g], acc);
+}
+
+void launch_coarse_update(hipStream_t s, const TileDesc *tiles, int ncx, int ncy, const int *tile_of_x,
+                          const int *tile_of_y, int kc, const float2 *Phibox, const float2 *Wbox,
+                          long long box_wl_stride, long long box_total, const float2 *c, int n_c, float2 *z, float2 *w,
+                          int nx, int ny, int n_rhs, int n_src, const int *active) {
+    (void)box_total;
+    dim3 grid((nx + 63) / 64, (ny + 3) / 4, n_rhs);
+    hipLaunchKernelGGL(coarse_update_kernel, grid, dim3(64, 4), 0, s, tiles, ncx, ncy, tile_of_x, tile_of_y, kc, Phibox,
+                       Wbox, box_wl_stride, c, n_c, z, w, nx, ny, n_src, active);
+}
+
+}  // namespace nosdd

@@ -1,0 +1,137 @@
+// Internal declarations shared by the HIP translation units of libnosdd.
+// Complex values are float2 / double2 with (x, y) = (re, im).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nosdd {
+
+// ------------------------------------------------------------ complex helpers
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a + b*c
+__host__ __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
+    return make_float2(a.x + b.x * c.x - b.y * c.y, a.y + b.x * c.y + b.y * c.x);
+}
+// a - b*c
+__host__ __device__ __forceinline__ float2 cfms(float2 a, float2 b, float2 c) {
+    return make_float2(a.x - b.x * c.x + b.y * c.y, a.y - b.x * c.y - b.y * c.x);
+}
+// a + conj(b)*c
+__host__ __device__ __forceinline__ float2 cfma_conj(float2 a, float2 b, float2 c) {
+    return make_float2(a.x + b.x * c.x + b.y * c.y, a.y + b.x * c.y - b.y * c.x);
+}
+__host__ __device__ __forceinline__ float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+__host__ __device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ __forceinline__ double2 zfms(double2 a, double2 b, double2 c) {
+    return make_double2(a.x - b.x * c.x + b.y * c.y, a.y - b.x * c.y - b.y * c.x);
+}
+__host__ __device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
+    double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__host__ __device__ __forceinline__ double zabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// ------------------------------------------------------------ problem geometry
+// Interface-side bits of a tile.
+enum { SIDE_BOTTOM = 1, SIDE_RIGHT = 2, SIDE_TOP = 4, SIDE_LEFT = 8 };
+
+// One extended subdomain, as seen by the kernels.  The tile is factorised as
+// block-tridiagonal with nb blocks of size b: blocks are grid rows (tr = 0,
+// block k <-> y = y0 + k, position m <-> x = x0 + m) or grid columns (tr = 1,
+// block k <-> x = x0 + k, m <-> y = y0 + m), whichever makes b the smaller side.
+struct TileDesc {
+    int x0, x1, y0, y1;       // extended box [x0,x1) x [y0,y1)
+    int cx0, cx1, cy0, cy1;   // core
+    int tr, b, nb, iface;
+    long long loc_off;        // cell offset in a packed local vector (one RHS)
+    long long dinv_off;       // float2 offset of this tile's D_k^-1 blocks (one wavelength)
+    int tr_off, n_tr;         // trace entries
+    int box_off;              // float2 offset of this tile's coarse box (one column)
+    int bw, bh;               // coarse box (core grown by one cell, clipped)
+    int bx0, by0;
+};
+
+// Per-wavelength stencil coefficient layout inside a float2 array:
+// [cxm(nx) | cxp(nx) | cym(ny) | cyp(ny)], stride 2*(nx+ny) per wavelength.
+__host__ __device__ __forceinline__ long long coef_stride(int nx, int ny) { return 2LL * (nx + ny); }
+
+// ------------------------------------------------------------ launchers
+// All launches go on `s`; vectors are [rhs][ny][nx] float2 with rhs = wl*n_src + src.
+void launch_stencil(hipStream_t s, const float2 *x, const float2 *b, float2 *y, const float *eps,
+                    const float2 *coef, const float *k0sq, int nx, int ny, int n_rhs, int n_src,
+                    const int *active);
+
+void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_wl, const float *eps,
+                      const float2 *coef_f, const double *coef_d, const double *k0, double h, int nx,
+                      int ny, float2 *dinv, long long dinv_wl_stride, int bmax);
+
+// mode bit 0: input is a packed local vector (else gathered from a global vector)
+// mode bit 1: output is a packed local vector (else core cells scattered to a global vector)
+void launch_bt_solve(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_rhs, int n_src,
+                     const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
+                     const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
+                     float2 *hist, long long hist_stride, const int *active, int mode, int bmax);
+
+void launch_robin_trace(hipStream_t s, const int4 *entries, int n_entries, const float *eps,
+                        const float *k0, float h, int nx, int ny, const float2 *x, float2 *g,
+                        int n_vec, int vec_per_wl);
+
+// Krylov helpers.  V is the basis: vector i of rhs r at V + i*vstride + r*N.
+void launch_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, long long N,
+                 int n_rhs, const int *active, double2 *partial, int nblk);
+void launch_reduce_dots(hipStream_t s, const double2 *partial, int nblk, int nv, int n_rhs,
+                        const int *active, float2 *H, int ldh, int m, int col, int accumulate,
+                        double *norm2_out);
+void launch_update(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
+                   long long N, int n_rhs, const int *active, const float2 *H, int ldh, int m, int col,
+                   const int *gate, double2 *partial, int nblk);
+void launch_reduce_norm(hipStream_t s, const double2 *partial, int nblk, int n_rhs, const int *active,
+                        double *out);
+void launch_hadd(hipStream_t s, float2 *H, const float2 *H2, int m, int col, int nv, const int *gate, int n_rhs);
+void launch_scale(hipStream_t s, float2 *v, long long N, int n_rhs, const int *active, const float *sc);
+
+struct GivensArgs {
+    float2 *H; int ldh; int m;        // H[r][i][j] at H + (r*(m+1) + i)*m + j
+    float *cs; float2 *sn; float2 *gam;
+    const double *nw_pre;             // ||w||^2 before orthogonalisation
+    const double *nw_post;            // ||w'||^2 after
+    const double *nw_reorth;          // ||w''||^2 after the second pass (if gated)
+    int *reorth;                      // per-rhs gate set here (DGKS test)
+    const float *bnorm; float tol;
+    int *active; int *iters; int *kcyc; int max_iters;
+    float *hist; int hist_ld;
+    float *inv_h; int *flags;         // flags bit 0 converged, bit 1 breakdown, bit 2 budget
+};
+void launch_dgks(hipStream_t s, const double *nw_pre, const double *nw_post, int *reorth, const int *active,
+                 int n_rhs);
+void launch_givens(hipStream_t s, const GivensArgs &a, int j, int n_rhs);
+void launch_backsolve(hipStream_t s, const float2 *H, int ldh, int m, const float2 *gam, const int *kcyc,
+                      float2 *y, int n_rhs);
+void launch_xupdate(hipStream_t s, float2 *x, const float2 *Z, long long zstride, const float2 *y, int m,
+                    const int *kcyc, long long N, int n_rhs);
+void launch_start_cycle(hipStream_t s, float2 *V0, const float2 *r, const double *beta2, const float *bnorm,
+                        float2 *gam, int m, int *kcyc, int *active, const int *want, long long N, int n_rhs);
+
+// Coarse space
+void launch_coarse_dot(hipStream_t s, const TileDesc *tiles, const int *col_tile, int n_c, int kc,
+                       const float2 *Wbox, long long box_wl_stride, int box_col_stride_unused,
+                       const float2 *v, const float2 *w1, int nx, long long N, int n_rhs, int n_src,
+                       const int *active, double2 *d);
+void launch_coarse_solve(hipStream_t s, const double2 *GinvT, int n_c, const double2 *d, float2 *c,
+                         int n_rhs, int n_src, const int *active);
+void launch_coarse_update(hipStream_t s, const TileDesc *tiles, int ncx, int ncy, const int *tile_of_x,
+                          const int *tile_of_y, int kc, const float2 *Phibox, const float2 *Wbox,
+                          long long box_wl_stride, long long box_total, const float2 *c, int n_c, float2 *z,
+                          float2 *w, int nx, int ny, int n_rhs, int n_src, const int *active);
+
+}  // namespace nosdd

@@ -1,0 +1,231 @@
+"""Python binding of libnosdd (ctypes).  Argument marshalling only: every step
+of the solve runs in the library's HIP kernels; PyTorch supplies device memory
+and the stream.  The library must be built (``python -m
+paper_2509_03622_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libnosdd.so")
+
+OK, NOT_CONVERGED = 0, 1
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EPARTITION",
+          -5: "EBREAKDOWN", -6: "ENONFINITE", -7: "ENOWEIGHTS", -8: "ESTATE"}
+
+EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_problem_create",
+           "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device",
+           "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
+           "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing"]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("h", C.c_double), ("npml", C.c_int),
+                ("pml_m", C.c_int), ("pml_lnR", C.c_double)]
+
+
+class PartitionSpec(C.Structure):
+    _fields_ = [("core_x", C.POINTER(C.c_int)), ("ncx", C.c_int), ("core_y", C.POINTER(C.c_int)),
+                ("ncy", C.c_int), ("overlap", C.c_int)]
+
+
+class SetupOpts(C.Structure):
+    _fields_ = [("sub_solver", C.c_int), ("k_coarse", C.c_int), ("k_trial", C.c_int),
+                ("nn_weights", C.c_char_p), ("inner_max", C.c_int), ("inner_tol", C.c_float)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("x0", C.c_void_p)]
+
+
+class NosddError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path=LIBPATH):
+    """Load libnosdd.so and declare its C signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2509_03622_amd.build`")
+    L = C.CDLL(path)
+    vp, i, ll = C.c_void_p, C.c_int, C.c_longlong
+    sig = {
+        "nosdd_ctx_create": (i, [i, vp, C.POINTER(vp)]),
+        "nosdd_ctx_destroy": (None, [vp]),
+        "nosdd_last_error": (C.c_char_p, [vp]),
+        "nosdd_problem_create": (i, [vp, C.POINTER(Grid), vp, C.POINTER(PartitionSpec), vp, i, C.POINTER(vp)]),
+        "nosdd_problem_setup": (i, [vp, C.POINTER(SetupOpts)]),
+        "nosdd_problem_destroy": (None, [vp]),
+        "nosdd_solve": (i, [vp, vp, i, C.POINTER(SolveOpts), vp, vp, vp, vp]),
+        "nosdd_solve_device": (i, [vp, vp, i, C.POINTER(SolveOpts), vp, vp, vp, vp]),
+        "nosdd_apply_operator": (i, [vp, vp, vp, vp, i]),
+        "nosdd_schwarz_sweep": (i, [vp, vp, vp, i]),
+        "nosdd_precond_apply": (i, [vp, vp, vp, vp, i]),
+        "nosdd_local_solve": (i, [vp, vp, vp]),
+        "nosdd_robin_trace": (i, [vp, vp, vp]),
+        "nosdd_tile_info": (i, [vp, i, C.POINTER(ll)]),
+        "nosdd_sizes": (i, [vp, C.POINTER(i), C.POINTER(ll), C.POINTER(ll), C.POINTER(i)]),
+        "nosdd_last_timing": (i, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    """Data pointer of a torch tensor or a numpy array (C-contiguous)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr()
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return a.ctypes.data
+
+
+class Context:
+    def __init__(self, device=0, stream=None):
+        L = load()
+        self.L = L
+        h = C.c_void_p()
+        st = L.nosdd_ctx_create(device, stream, C.byref(h))
+        if st != OK:
+            raise NosddError(st, "nosdd_ctx_create failed")
+        self.h = h
+
+    def check(self, st):
+        if st < 0:
+            raise NosddError(st, self.L.nosdd_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if self.h:
+            self.L.nosdd_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """A grid, permittivity map, partition and wavelength set (one operator per wavelength)."""
+
+    def __init__(self, ctx: Context, eps, h, npml, core_x, core_y, overlap, wavelengths, pml_m=2, pml_lnR=-30.0):
+        self.ctx, self.L = ctx, ctx.L
+        eps = np.ascontiguousarray(eps, dtype=np.float32)
+        self.ny, self.nx = eps.shape
+        self.wavelengths = [float(w) for w in wavelengths]
+        g = Grid(self.nx, self.ny, float(h), int(npml), int(pml_m), float(pml_lnR))
+        cx = (C.c_int * len(core_x))(*core_x)
+        cy = (C.c_int * len(core_y))(*core_y)
+        part = PartitionSpec(cx, len(core_x), cy, len(core_y), int(overlap))
+        wl = np.ascontiguousarray(self.wavelengths, dtype=np.float64)
+        hp = C.c_void_p()
+        ctx.check(self.L.nosdd_problem_create(ctx.h, C.byref(g), eps.ctypes.data, C.byref(part), wl.ctypes.data,
+                                              len(wl), C.byref(hp)))
+        self.h = hp
+        self.n_wl = len(wl)
+
+    def setup(self, k_coarse=0, k_trial=8, sub_solver=0, nn_weights=None, inner_max=2, inner_tol=1e-1):
+        o = SetupOpts(sub_solver, k_coarse, k_trial, nn_weights.encode() if nn_weights else None, inner_max,
+                      inner_tol)
+        return self.ctx.check(self.L.nosdd_problem_setup(self.h, C.byref(o)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.nosdd_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ whole solves
+    def solve(self, J, tol=1e-6, restart=30, max_iters=1000, x0=None):
+        """Host arrays in and out.  J [n_src][ny][nx] complex64."""
+        J = np.ascontiguousarray(J, dtype=np.complex64)
+        if J.ndim == 2:
+            J = J[None]
+        ns = J.shape[0]
+        nr = self.n_wl * ns
+        E = np.zeros((self.n_wl, ns, self.ny, self.nx), np.complex64)
+        hist = np.zeros((self.n_wl, ns, max(1, max_iters)), np.float32)
+        iters = np.zeros((self.n_wl, ns), np.int32)
+        fin = np.zeros((self.n_wl, ns), np.float32)
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.complex64)
+        o = SolveOpts(tol, restart, max_iters, _ptr(x0a))
+        st = self.ctx.check(self.L.nosdd_solve(self.h, J.ctypes.data, ns, C.byref(o), E.ctypes.data,
+                                               hist.ctypes.data, iters.ctypes.data, fin.ctypes.data))
+        del nr
+        return E, hist, iters, fin, st
+
+    def solve_device(self, J, E, tol=1e-6, restart=30, max_iters=1000, x0=None):
+        """Device tensors: J [n_src][ny][nx] complex64, E [n_wl][n_src][ny][nx] complex64."""
+        ns = J.shape[0]
+        hist = np.zeros((self.n_wl, ns, max(1, max_iters)), np.float32)
+        iters = np.zeros((self.n_wl, ns), np.int32)
+        fin = np.zeros((self.n_wl, ns), np.float32)
+        o = SolveOpts(tol, restart, max_iters, _ptr(x0))
+        st = self.ctx.check(self.L.nosdd_solve_device(self.h, _ptr(J), ns, C.byref(o), _ptr(E), hist.ctypes.data,
+                                                      iters.ctypes.data, fin.ctypes.data))
+        return hist, iters, fin, st
+
+    # ------------------------------------------------------------ sweep steps (device tensors)
+    def apply_operator(self, x, y, b=None, n_src=1):
+        return self.ctx.check(self.L.nosdd_apply_operator(self.h, _ptr(x), _ptr(b), _ptr(y), n_src))
+
+    def schwarz_sweep(self, v, z, n_src=1):
+        return self.ctx.check(self.L.nosdd_schwarz_sweep(self.h, _ptr(v), _ptr(z), n_src))
+
+    def precond_apply(self, v, z, Az=None, n_src=1):
+        return self.ctx.check(self.L.nosdd_precond_apply(self.h, _ptr(v), _ptr(z), _ptr(Az), n_src))
+
+    def local_solve(self, rhs, u):
+        return self.ctx.check(self.L.nosdd_local_solve(self.h, _ptr(rhs), _ptr(u)))
+
+    def robin_trace(self, x, g):
+        return self.ctx.check(self.L.nosdd_robin_trace(self.h, _ptr(x), _ptr(g)))
+
+    # ------------------------------------------------------------ queries
+    def sizes(self):
+        nt, nc = C.c_int(), C.c_int()
+        lc, te = C.c_longlong(), C.c_longlong()
+        self.ctx.check(self.L.nosdd_sizes(self.h, C.byref(nt), C.byref(lc), C.byref(te), C.byref(nc)))
+        return nt.value, lc.value, te.value, nc.value
+
+    def tile_info(self, t):
+        a = (C.c_longlong * 10)()
+        self.ctx.check(self.L.nosdd_tile_info(self.h, t, a))
+        return list(a)
+
+    def last_timing(self):
+        s, v, i = C.c_double(), C.c_double(), C.c_int()
+        self.ctx.check(self.L.nosdd_last_timing(self.h, C.byref(s), C.byref(v), C.byref(i)))
+        return s.value, v.value, i.value
+
+
+def torch_stream_handle():
+    """The current PyTorch HIP stream as a raw handle for Context(stream=...)."""
+    import torch
+    return torch.cuda.current_stream().cuda_stream

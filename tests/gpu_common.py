@@ -1,0 +1,34 @@
+"""Shared set-up for the GPU parity tests: builds a HIP-side problem and the
+matching oracle objects from one seeded workload."""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2509_03622_amd.workloads import Workload
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make_gpu_problem(w: Workload, k_coarse=None, k_trial=None):
+    import torch
+    from paper_2509_03622_amd import nosdd
+    ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+    P.setup(k_coarse=w.k_coarse if k_coarse is None else k_coarse, k_trial=k_trial or w.k_trial)
+    torch.cuda.synchronize()
+    return ctx, P
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
