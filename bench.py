@@ -1,0 +1,214 @@
+"""Benchmark of the batched two-level Schwarz-FGMRES solve on one MI355X.
+
+A step is one complete global solve, through the C ABI (nosdd_solve_device,
+inputs resident in HBM), of every right-hand side of the workload to a 1e-6
+relative residual.  Default workload: 512 x 512 grid, 8 x 8 subdomain cores of
+64 with 8-cell overlap, 16-cell blocks of permittivity in [1, 12], four
+wavelengths {0.8, 1.0, 1.2, 1.5} in one launch, one coarse basis function per
+subdomain, exact subdomain LU, complex64 arithmetic.
+
+Printed (one JSON line): subdomain solves per second (one exact local solve of
+one subdomain for one RHS is one unit), the time per global solve, the
+roofline of the dominant kernel (the batched subdomain solve; HIP events on
+the library stream over the timed region), the FP64 oracle timed on a bounded
+sample on the host, and the field error of every RHS against the FP64 direct
+solution.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time to 1e-6 residual per global solve; subdomain solves/s; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+PROFILE_PMC = os.path.join(ROOT, "profiles", "bt_solve_blocks512_pmc.txt")
+
+
+def tile_geometry(w):
+    """(lx, ly, core cells) of every extended subdomain, in tile order."""
+    ext = w.overlap // 2
+    out = []
+    xs = np.concatenate([[0], np.cumsum(w.core_x)])
+    ys = np.concatenate([[0], np.cumsum(w.core_y)])
+    for ty in range(len(w.core_y)):
+        for tx in range(len(w.core_x)):
+            lx = w.core_x[tx] + (ext if tx > 0 else 0) + (ext if tx < len(w.core_x) - 1 else 0)
+            ly = w.core_y[ty] + (ext if ty > 0 else 0) + (ext if ty < len(w.core_y) - 1 else 0)
+            out.append((lx, ly, w.core_x[tx] * w.core_y[ty]))
+    del xs, ys
+    return out
+
+
+def local_solve_bytes(lx, ly, core):
+    """Algorithmic HBM bytes of one exact subdomain solve (one tile, one RHS):
+    the 2 nb - 1 dense blocks D_k^-1 (b x b complex64) streamed by the block
+    forward/backward sweeps, the gathered tile input and the core output."""
+    b, nb = min(lx, ly), max(lx, ly)
+    return 8 * ((2 * nb - 1) * b * b + lx * ly + core)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2509_03622_amd", "csrc", "btlu.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(units_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when it is missing or was taken on a different version of the kernel."""
+    if not os.path.exists(PROFILE_PMC):
+        return None
+    vals = {}
+    for line in open(PROFILE_PMC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, iters):
+    """The FP64 oracle's Schwarz-FGMRES on one wavelength of the same workload,
+    set-up excluded, capped at `iters` outer iterations."""
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:
+        lim = None
+    from oracle.fdfd import source_rhs
+    from oracle.fgmres import fgmres
+    from oracle.schwarz import SchwarzProblem
+    lam = w.wavelengths[1] if len(w.wavelengths) > 1 else w.wavelengths[0]
+    t0 = time.perf_counter()
+    P = SchwarzProblem(w.eps, lam, w.h, w.npml, w.core_x, w.core_y, w.overlap, k_coarse=w.k_coarse,
+                       k_trial=w.k_trial)
+    setup_s = time.perf_counter() - t0
+    b = source_rhs(w.J()[0], lam)
+    t0 = time.perf_counter()
+    x, it, hist, res = fgmres(lambda u: P.A @ u, b, P.precond, tol=1e-6, restart=30, max_iters=iters)
+    dt = time.perf_counter() - t0
+    n_tiles = len(w.core_x) * len(w.core_y)
+    if lim is not None:
+        lim.unregister()
+    return {"value": n_tiles * it / dt, "unit": "subdomain solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"wavelength {lam}, one source, {it} outer FGMRES iterations of the two-level "
+                      f"Schwarz preconditioner with exact sparse-LU subdomain solves (k_coarse={w.k_coarse}), "
+                      f"set-up ({setup_s:.1f} s) excluded; {dt:.1f} s",
+            "ms_per_iteration": 1e3 * dt / max(it, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="blocks512")
+    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the FP64 direct-solve field check")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
+              "(the path shards over RHS and subdomain slabs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2509_03622_amd import nosdd
+    from paper_2509_03622_amd.workloads import WORKLOADS
+
+    w = WORKLOADS[a.workload]()
+    n_wl, n_src = len(w.wavelengths), len(w.sources)
+    n_rhs = n_wl * n_src
+    tiles = tile_geometry(w)
+    bytes_per_unit = float(np.mean([local_solve_bytes(*t) for t in tiles]))
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+    t0 = time.perf_counter()
+    P.setup(k_coarse=w.k_coarse, k_trial=w.k_trial)
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    J = torch.from_numpy(w.J()).to(dev)
+    E = torch.zeros((n_wl, n_src, w.ny, w.nx), dtype=torch.complex64, device=dev)
+
+    for _ in range(a.warmup):
+        hist, iters, fin, st = P.solve_device(J, E)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done: iterations per RHS {iters.ravel().tolist()}", file=sys.stderr, flush=True)
+
+    P.profile(True)
+    tot_units = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        hist, iters, fin, st = P.solve_device(J, E)
+        tot_units += int(iters.sum()) * len(tiles)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    P.profile(False)
+    ms_k, launches, units = P.kernel_times()
+    print(f"[bench] timed {a.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    ms_per_step = 1e3 * elapsed / a.steps
+    value = tot_units / elapsed
+    lu_bytes = units[0] * bytes_per_unit
+    lu_ms = ms_k[0]
+    achieved = lu_bytes / (lu_ms * 1e-3) / 1e9 if lu_ms > 0 else 0.0
+    per_launch = lu_bytes / max(launches[0], 1)
+    traffic = read_traffic(units[0] / max(launches[0], 1))
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "bt_solve_kernel (gather + block-Thomas subdomain LU solve + core scatter)",
+                "avg_launch_us": round(1e3 * lu_ms / max(launches[0], 1), 2),
+                "algorithmic_bytes_per_launch": round(per_launch),
+                "launches": int(launches[0])}
+    share = {k: round(float(v) / a.steps, 3) for k, v in zip(("local_solve", "operator", "arnoldi", "coarse"), ms_k)}
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "subdomain solves/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+           "data": "synthetic",
+           "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "cores": f"{len(w.core_x)}x{len(w.core_y)} of 64",
+                      "overlap": w.overlap, "wavelengths": w.wavelengths, "sources": n_src,
+                      "k_coarse": w.k_coarse, "subdomain_solver": "exact LU (block-Thomas)",
+                      "restart": 30, "tol": 1e-6},
+           "time_to_tol_ms": round(ms_per_step, 3),
+           "outer_iterations_per_rhs": iters.ravel().tolist(),
+           "final_rel_residual": [float(f"{v:.3e}") for v in fin.ravel()],
+           "setup_ms": round(setup_ms, 1),
+           "kernel_ms_per_step": share,
+           "roofline": roofline}
+
+    if not a.no_check:
+        from oracle.fdfd import assemble_A, solve_direct, source_rhs
+        Eh = E.cpu().numpy()
+        errs = []
+        for wi, lam in enumerate(w.wavelengths):
+            A = assemble_A(w.eps, lam, w.h, w.npml, w.pml_m, w.pml_lnR)
+            for s in range(n_src):
+                xs = solve_direct(A, source_rhs(w.J()[s], lam))
+                errs.append(float(np.linalg.norm(Eh[wi, s].ravel() - xs) / np.linalg.norm(xs)))
+        out["field_rel_err_vs_fp64_direct"] = [float(f"{e:.3e}") for e in errs]
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -117,7 +117,7 @@ void nosdd_ctx_destroy(nosdd_ctx *ctx);                /* NULL is accepted */
  * valid until the next call on it.  Never NULL. */
 const char *nosdd_last_error(const nosdd_ctx *ctx);
 
-/* Create a problem: eps is a host [ny][nx] real permittivity map (copied);
+/* Create a problem (destroy it before its context): eps is a host [ny][nx] real permittivity map (copied);
  * wavelengths[n_wl] are solved together, one operator per wavelength. */
 nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *grid, const float *eps,
                                   const nosdd_partition *part, const double *wavelengths,
@@ -177,6 +177,22 @@ nosdd_status nosdd_robin_trace(nosdd_problem *p, const nosdd_c32 *x, nosdd_c32 *
 nosdd_status nosdd_tile_info(const nosdd_problem *p, int tile, long long info[10]);
 nosdd_status nosdd_sizes(const nosdd_problem *p, int *n_tiles, long long *local_cells,
                          long long *trace_entries, int *n_coarse);
+
+/* Coarse basis fields of wavelength wl (host copy), for inspection and tests:
+ * phi[n_coarse] boxes concatenated in tile order, column l of tile t being
+ * [bh][bw] cells of the tile's core grown by one cell (clipped to the grid);
+ * box[4 * n_tiles] = {bx0, by0, bw, bh} per tile.  Either pointer may be NULL. */
+nosdd_status nosdd_coarse_basis(const nosdd_problem *p, int wl, nosdd_c32 *phi, long long *box);
+
+/* Kernel timing of the solve path (HIP events recorded on the context stream
+ * around every launch group while enabled).  Classes: 0 = subdomain solves
+ * (gather, block-Thomas, core scatter), 1 = operator and residuals,
+ * 2 = Arnoldi (Gram-Schmidt passes, reductions, Givens, scaling),
+ * 3 = coarse correction.  nosdd_profile(p, 1) enables and resets the
+ * counters, nosdd_profile(p, 0) disables.  units[0] counts (subdomain, RHS)
+ * solves. */
+nosdd_status nosdd_profile(nosdd_problem *p, int enable);
+nosdd_status nosdd_kernel_times(const nosdd_problem *p, double ms[4], long long launches[4], long long units[4]);
 
 /* Timing of the last solve (ms, GPU events): setup, total solve, iterations. */
 nosdd_status nosdd_last_timing(const nosdd_problem *p, double *setup_ms, double *solve_ms,

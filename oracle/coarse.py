@@ -10,7 +10,9 @@ Algorithm 3, in this reading:
    wavenumber kappa = k0 sqrt(eps):  phi_{m+1} = phi_m + h (kappa_m +
    kappa_{m+1})/2 * d_l . (p_{m+1} - p_m),  x_l(p) = exp(-i phi(p)).
    Entries on the global boundary are dropped.
-2. Gram-Schmidt (modified) orthonormalisation of the K trial vectors.
+2. Gram-Schmidt (modified) orthonormalisation of the K trial vectors;
+   dependent trial vectors are dropped (this happens on corner subdomains,
+   whose interface ring is an L-shape).
 3. Homogeneous local solves F_l = B_i^-1 inj(x_l) (no source term).
 4. y_l = Robin traces of F_l on the interface rings of the neighbouring
    subdomains (diagonal neighbours included), where those rings lie inside
@@ -18,7 +20,9 @@ Algorithm 3, in this reading:
 5. Rayleigh-Ritz on (x, y) in its SVD form (the paper reports SVD works about
    as well as the eigen-decomposition): Y = U S V^H, the k_coarse right
    singular vectors with the largest singular values (slowest decaying
-   modes) give the subdomain's basis, u_l = X V[:, l].
+   modes) give the subdomain's basis, u_l = X V[:, l].  A subdomain with fewer
+   independent probes than k_coarse gets zero basis columns, whose coefficient
+   is fixed at 0 by a unit diagonal entry in G.
 6. Basis fields phi_{i,l} = Rt_i^T B_i^-1 inj(u_l), spread over the global
    grid by the core-only (RAS) prolongation.
 
@@ -56,13 +60,26 @@ def pseudo_plane_waves(part, t, loc, K, eps, k0, h):
     return X_node[rows]
 
 
-def mgs_columns(X):
-    Q = np.array(X, dtype=np.complex128)
-    for l in range(Q.shape[1]):
-        for m in range(l):
-            Q[:, l] -= np.vdot(Q[:, m], Q[:, l]) * Q[:, m]
-        Q[:, l] /= np.linalg.norm(Q[:, l])
-    return Q
+DROP_TOL = 1e-8      # a probe whose Gram-Schmidt residual is below this fraction of its norm is dependent
+
+
+def mgs_columns(X, drop_tol=DROP_TOL):
+    """Modified Gram-Schmidt; dependent columns are dropped (the result spans span X).
+
+    On subdomains with only two interface sides the pseudo-plane waves can be
+    linearly dependent; normalising a residual of rounding size would create
+    a spurious direction, so such a probe is removed.
+    """
+    cols = []
+    for l in range(X.shape[1]):
+        v = np.array(X[:, l], dtype=np.complex128)
+        n0 = np.linalg.norm(v)
+        for q in cols:
+            v = v - np.vdot(q, v) * q
+        n = np.linalg.norm(v)
+        if n > drop_tol * n0:
+            cols.append(v / n)
+    return np.stack(cols, axis=1)
 
 
 def neighbour_traces(part, locs, i, F_loc):
@@ -100,7 +117,8 @@ class CoarseSpace:
             if len(L.entries) == 0:
                 continue
             X = mgs_columns(pseudo_plane_waves(part, t, L, K, eps, k0, h))
-            F = np.stack([L.solve(L.inj(X[:, l])) for l in range(K)], axis=1)
+            Kt = X.shape[1]
+            F = np.stack([L.solve(L.inj(X[:, l])) for l in range(Kt)], axis=1)
             if rotation == "svd":
                 Y = neighbour_traces(part, locs, i, F)
                 _, _, Vh = np.linalg.svd(Y, full_matrices=True)
@@ -112,10 +130,11 @@ class CoarseSpace:
                 w, Vv = np.linalg.eigh(Y.conj().T @ Y)
                 V = Vv[:, np.argsort(-w)]
             else:   # "none": keep the orthonormal trial directions as they are
-                V = np.eye(K, dtype=np.complex128)
+                V = np.eye(Kt, dtype=np.complex128)
             for l in range(k_coarse):
                 phi = np.zeros(n, dtype=np.complex128)
-                L.prolong_core(F @ V[:, l], phi)
+                if l < Kt:          # fewer independent probes than k_coarse: zero column
+                    L.prolong_core(F @ V[:, l], phi)
                 cols.append(phi)
                 self.tile_of_col.append(i)
         # each basis field lives on one core: keep Phi and W = A Phi sparse
@@ -123,6 +142,9 @@ class CoarseSpace:
                     else sp.csc_matrix((n, 0), dtype=np.complex128))
         self.W = (A @ self.Phi).tocsc()
         self.G = (self.W.conj().T @ self.W).toarray()
+        # a zero basis column gets a unit diagonal entry, so its coefficient is 0
+        zero = np.asarray(abs(self.W).sum(axis=0)).ravel() == 0
+        self.G[zero, zero] = 1.0
         self.nc = self.Phi.shape[1]
         self.chol = sla.cho_factor(self.G, lower=True) if self.nc else None
 

@@ -84,6 +84,16 @@ struct nosdd_problem {
     Workspace ws;
     double setup_ms = 0.0, solve_ms = 0.0;
     int last_iters = 0;
+    // optional per-class kernel timing (events on the context stream)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<int, int>>> ev_pending;   // class, (start, stop) pool index
+    int ev_next = 0;
+    double prof_ms[4] = {0, 0, 0, 0};
+    long long prof_launch[4] = {0, 0, 0, 0}, prof_units[4] = {0, 0, 0, 0};
+    ~nosdd_problem() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -244,7 +254,59 @@ __global__ void fill_f32_kernel(float *p, long long n, float v) {
         p[i] = v;
 }
 
+// x (FP64) = x0 (FP32), or 0 when x0 is null
+__global__ void widen_kernel(const float2 *x0, double2 *x, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] = x0 ? make_double2(x0[i].x, x0[i].y) : make_double2(0.0, 0.0);
+}
+
+__global__ void narrow_kernel(const double2 *x, float2 *e, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        e[i] = make_float2((float)x[i].x, (float)x[i].y);
+}
+
 long long grid_blocks(long long N) { return std::min<long long>(1024, (N + 255) / 256); }
+
+// Profiling marks: begin/end a launch group of class c on the context stream.
+int prof_mark(nosdd_problem *p) {
+    if (p->ev_next == (int)p->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        p->ev_pool.push_back(e);
+    }
+    const int i = p->ev_next++;
+    (void)hipEventRecord(p->ev_pool[i], p->ctx->stream);
+    return i;
+}
+
+struct ProfScope {
+    nosdd_problem *p;
+    int cls, start;
+    ProfScope(nosdd_problem *p_, int c, long long units) : p(p_), cls(c), start(-1) {
+        if (p->prof) {
+            start = prof_mark(p);
+            p->prof_launch[c] += 1;
+            p->prof_units[c] += units;
+        }
+    }
+    ~ProfScope() {
+        if (p->prof && start >= 0) {
+            const int stop = prof_mark(p);
+            if (stop >= 0) p->ev_pending.push_back({cls, {start, stop}});
+        }
+    }
+};
+
+// Fold recorded event pairs into the per-class totals (the stream must be idle).
+void prof_flush(nosdd_problem *p) {
+    for (auto &pe : p->ev_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->ev_pool[pe.second.first], p->ev_pool[pe.second.second]) == hipSuccess)
+            p->prof_ms[pe.first] += ms;
+    }
+    p->ev_pending.clear();
+    p->ev_next = 0;
+}
 
 nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     Workspace &w = p->ws;
@@ -257,7 +319,7 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     w.N = N;
     w.nblk = nblk;
     const size_t vec = (size_t)n_rhs * N * sizeof(float2);
-    HIPCHK(ctx, w.x.ensure(vec));
+    HIPCHK(ctx, w.x.ensure(vec * 2));        // FP64 iterate
     HIPCHK(ctx, w.b.ensure(vec));
     HIPCHK(ctx, w.w.ensure(vec));
     HIPCHK(ctx, w.V.ensure(vec * (m + 1)));
@@ -285,16 +347,23 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
 
 // z = M^-1 v (two-level), wout = A z.  v, z, wout: [n_rhs][N].
 void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2 *wout, int n_src, int n_rhs,
-             const int *active) {
+             const int *active, int n_live) {
     Workspace &w = p->ws;
     const long long N = (long long)p->nx * p->ny;
+    {
+    ProfScope ps(p, 0, (long long)n_live * (long long)p->tiles.size());
     launch_bt_solve(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src, p->d_dinv.as<float2>(),
                     p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, w.scratch.as<float2>(),
                     p->loc_total, active, 0, p->bmax);
+    }
     if (wout == nullptr) return;
-    launch_stencil(s, z, nullptr, wout, p->d_eps.as<float>(), p->d_coef.as<float2>(), p->d_k0sq.as<float>(), p->nx,
-                   p->ny, n_rhs, n_src, active);
+    {
+        ProfScope ps(p, 1, n_live);
+        launch_stencil(s, z, nullptr, wout, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(),
+                       p->nx, p->ny, n_rhs, n_src, active);
+    }
     if (p->n_c > 0) {
+        ProfScope ps(p, 3, n_live);
         launch_coarse_dot(s, p->d_tiles.as<TileDesc>(), nullptr, p->n_c, p->kc, p->d_W.as<float2>(), p->box_wl_stride,
                           0, v, wout, p->nx, N, n_rhs, n_src, active, w.cd_.as<double2>());
         launch_coarse_solve(s, p->d_GinvT.as<double2>(), p->n_c, w.cd_.as<double2>(), w.cc_.as<float2>(), n_rhs,
@@ -306,6 +375,57 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
 }
 
 // ---------------------------------------------------------------- coarse set-up
+// Pseudo-plane-wave probe Robin data of one tile (ne x K, row-major), made
+// orthonormal by modified Gram-Schmidt; *n_kept independent columns come first,
+// the rest are zero.  The phase is accumulated along the
+// counter-clockwise boundary ring with the local wavenumber k0 sqrt(eps).
+std::vector<cd> build_probes(const TileDesc &t, const std::vector<int4> &ent, const float *eps, int nx, double k0,
+                             double h, int K, int *n_kept) {
+    const int ne = (int)ent.size();
+    std::vector<std::pair<int, int>> nodes;
+    ring_nodes(t, nodes);
+    std::vector<double> kap(nodes.size());
+    for (size_t r = 0; r < nodes.size(); ++r)
+        kap[r] = k0 * std::sqrt((double)eps[(size_t)nodes[r].second * nx + nodes[r].first]);
+    std::vector<cd> Xe((size_t)ne * K);
+    for (int l = 0; l < K; ++l) {
+        const double th = 2.0 * M_PI * l / K;
+        const double dx = std::cos(th), dy = std::sin(th);
+        std::vector<double> phi(nodes.size(), 0.0);
+        for (size_t r = 0; r + 1 < nodes.size(); ++r) {
+            const double sx = nodes[r + 1].first - nodes[r].first, sy = nodes[r + 1].second - nodes[r].second;
+            phi[r + 1] = phi[r] + h * 0.5 * (kap[r] + kap[r + 1]) * (dx * sx + dy * sy);
+        }
+        for (int e = 0; e < ne; ++e) Xe[(size_t)e * K + l] = std::exp(cd(0.0, -phi[ent[e].w]));
+    }
+    // modified Gram-Schmidt; a probe whose residual falls below 1e-8 of its
+    // norm is dependent and removed, the kept ones are packed first
+    std::vector<cd> Q((size_t)ne * K, cd(0, 0));
+    int kept = 0;
+    for (int l = 0; l < K; ++l) {
+        std::vector<cd> v(ne);
+        double n0 = 0;
+        for (int e = 0; e < ne; ++e) {
+            v[e] = Xe[(size_t)e * K + l];
+            n0 += std::norm(v[e]);
+        }
+        for (int q = 0; q < kept; ++q) {
+            cd dot = 0;
+            for (int e = 0; e < ne; ++e) dot += std::conj(Q[(size_t)e * K + q]) * v[e];
+            for (int e = 0; e < ne; ++e) v[e] -= dot * Q[(size_t)e * K + q];
+        }
+        double nr = 0;
+        for (int e = 0; e < ne; ++e) nr += std::norm(v[e]);
+        if (!(std::sqrt(nr) > 1e-8 * std::sqrt(n0))) continue;
+        nr = std::sqrt(nr);
+        for (int e = 0; e < ne; ++e) Q[(size_t)e * K + kept] = v[e] / nr;
+        ++kept;
+    }
+    *n_kept = kept;
+    Xe.swap(Q);
+    return Xe;
+}
+
 nosdd_status coarse_setup(nosdd_problem *p) {
     nosdd_ctx *ctx = p->ctx;
     hipStream_t s = ctx->stream;
@@ -332,6 +452,7 @@ nosdd_status coarse_setup(nosdd_problem *p) {
     // probe Robin data per (wl, probe), injected into packed local vectors
     const long long LT = p->loc_total;
     std::vector<std::vector<cd>> Xt((size_t)nwl * nt);
+    std::vector<int> Kt((size_t)nwl * nt, 0);
     std::vector<float2> rhs((size_t)nwl * K * LT, make_float2(0.f, 0.f));
     for (int wi = 0; wi < nwl; ++wi) {
         const double k0 = 2.0 * M_PI / p->wl[wi];
@@ -340,34 +461,9 @@ nosdd_status coarse_setup(nosdd_problem *p) {
             const TileDesc &t = p->tiles[ti];
             const auto &ent = p->tile_entries[ti];
             const int ne = (int)ent.size();
-            std::vector<std::pair<int, int>> nodes;
-            ring_nodes(t, nodes);
-            std::vector<double> kap(nodes.size());
-            for (size_t r = 0; r < nodes.size(); ++r)
-                kap[r] = k0 * std::sqrt((double)p->eps[(size_t)nodes[r].second * nx + nodes[r].first]);
-            std::vector<cd> Xe((size_t)ne * K);
-            for (int l = 0; l < K; ++l) {
-                const double th = 2.0 * M_PI * l / K;
-                const double dx = std::cos(th), dy = std::sin(th);
-                std::vector<double> phi(nodes.size(), 0.0);
-                for (size_t r = 0; r + 1 < nodes.size(); ++r) {
-                    const double sx = nodes[r + 1].first - nodes[r].first, sy = nodes[r + 1].second - nodes[r].second;
-                    phi[r + 1] = phi[r] + h * 0.5 * (kap[r] + kap[r + 1]) * (dx * sx + dy * sy);
-                }
-                for (int e = 0; e < ne; ++e) Xe[(size_t)e * K + l] = std::exp(cd(0.0, -phi[ent[e].w]));
-            }
-            // modified Gram-Schmidt over the columns
-            for (int l = 0; l < K; ++l) {
-                for (int q = 0; q < l; ++q) {
-                    cd dot = 0;
-                    for (int e = 0; e < ne; ++e) dot += std::conj(Xe[(size_t)e * K + q]) * Xe[(size_t)e * K + l];
-                    for (int e = 0; e < ne; ++e) Xe[(size_t)e * K + l] -= dot * Xe[(size_t)e * K + q];
-                }
-                double nr = 0;
-                for (int e = 0; e < ne; ++e) nr += std::norm(Xe[(size_t)e * K + l]);
-                nr = std::sqrt(nr);
-                for (int e = 0; e < ne; ++e) Xe[(size_t)e * K + l] /= nr;
-            }
+            int kept = 0;
+            std::vector<cd> Xe = build_probes(t, ent, p->eps.data(), nx, k0, h, K, &kept);
+            Kt[(size_t)wi * nt + ti] = kept;
             // inj(g)_p = -a_pq tau_p g_p
             for (int e = 0; e < ne; ++e) {
                 const int pc = ent[e].x, px = pc % nx, py = pc / nx;
@@ -422,6 +518,7 @@ nosdd_status coarse_setup(nosdd_problem *p) {
                 return cd(f.x, f.y);
             };
             // rows of Y: traces on neighbours' ring entries lying inside this tile
+            const int Kk = Kt[(size_t)wi * nt + ti];
             std::vector<cd> Y;
             int nrows = 0;
             for (int dy = -1; dy <= 1; ++dy)
@@ -435,7 +532,7 @@ nosdd_status coarse_setup(nosdd_problem *p) {
                         if (px < t.x0 || px >= t.x1 || py < t.y0 || py >= t.y1) continue;
                         if (qx < t.x0 || qx >= t.x1 || qy < t.y0 || qy >= t.y1) continue;
                         const double kp = k0 * std::sqrt((double)p->eps[e.x]);
-                        for (int l = 0; l < K; ++l) {
+                        for (int l = 0; l < Kk; ++l) {
                             const cd up = Fv(l, px, py), uq = Fv(l, qx, qy);
                             Y.push_back((uq - up) / h + cd(0.0, 0.5 * kp) * (uq + up));
                         }
@@ -443,26 +540,26 @@ nosdd_status coarse_setup(nosdd_problem *p) {
                     }
                 }
             // right singular vectors of Y = eigenvectors of Y^H Y, by decreasing eigenvalue
-            std::vector<cd> YhY((size_t)K * K, cd(0, 0));
+            std::vector<cd> YhY((size_t)Kk * Kk, cd(0, 0));
             for (int rr = 0; rr < nrows; ++rr)
-                for (int a = 0; a < K; ++a)
-                    for (int bb = 0; bb < K; ++bb)
-                        YhY[(size_t)a * K + bb] += std::conj(Y[(size_t)rr * K + a]) * Y[(size_t)rr * K + bb];
+                for (int a = 0; a < Kk; ++a)
+                    for (int bb = 0; bb < Kk; ++bb)
+                        YhY[(size_t)a * Kk + bb] += std::conj(Y[(size_t)rr * Kk + a]) * Y[(size_t)rr * Kk + bb];
             std::vector<double> ev;
             std::vector<cd> Vv;
-            herm_eig(K, YhY, ev, Vv);
-            std::vector<int> order(K);
-            for (int i = 0; i < K; ++i) order[i] = i;
+            herm_eig(Kk, YhY, ev, Vv);
+            std::vector<int> order(Kk);
+            for (int i = 0; i < Kk; ++i) order[i] = i;
             std::stable_sort(order.begin(), order.end(), [&](int a, int bb) { return ev[a] > ev[bb]; });
             // basis fields on the core, stored on the box (core grown by one cell)
             const int bw = t.bw, bh = t.bh;
             std::vector<cd> phib((size_t)kc * bw * bh, cd(0, 0)), wb((size_t)kc * bw * bh, cd(0, 0));
-            for (int l = 0; l < kc; ++l) {
+            for (int l = 0; l < std::min(kc, Kk); ++l) {     // columns beyond Kk stay zero
                 const int col = order[l];
                 for (int y = t.cy0; y < t.cy1; ++y)
                     for (int x = t.cx0; x < t.cx1; ++x) {
                         cd v = 0;
-                        for (int q = 0; q < K; ++q) v += Fv(q, x, y) * Vv[(size_t)q * K + col];
+                        for (int q = 0; q < Kk; ++q) v += Fv(q, x, y) * Vv[(size_t)q * Kk + col];
                         phib[(size_t)l * bw * bh + (size_t)(y - t.by0) * bw + (x - t.bx0)] = v;
                     }
                 auto ph = [&](int x, int y) -> cd {
@@ -508,6 +605,11 @@ nosdd_status coarse_setup(nosdd_problem *p) {
                     }
             }
         }
+        // zero basis columns (tiles with fewer independent probes) get a unit
+        // diagonal entry, which pins their coefficient to 0
+        for (int ti = 0; ti < nt; ++ti)
+            for (int l = Kt[(size_t)wi * nt + ti]; l < kc; ++l)
+                G[(size_t)(ti * kc + l) * nc + (ti * kc + l)] = 1.0;
         std::vector<cd> Gi;
         if (!hpd_inverse(nc, G, Gi)) return fail(ctx, NOSDD_EBREAKDOWN, "coarse matrix G = W^H W is not positive definite");
         for (int j = 0; j < nc; ++j)
@@ -557,15 +659,13 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     HIPCHK(ctx, hipEventCreate(&e1));
     HIPCHK(ctx, hipEventRecord(e0, s));
 
-    float2 *x = w.x.as<float2>(), *b = w.b.as<float2>(), *V = w.V.as<float2>(), *Z = w.Z.as<float2>(),
+    double2 *x = w.x.as<double2>();
+    float2 *b = w.b.as<float2>(), *V = w.V.as<float2>(), *Z = w.Z.as<float2>(),
            *wv = w.w.as<float2>();
     const long long vstride = (long long)n_rhs * N;
     hipLaunchKernelGGL(make_rhs_kernel, dim3((unsigned)grid_blocks(N), n_rhs), dim3(256), 0, s, J_dev, b,
                        p->d_k0f.as<float>(), N, n_src);
-    if (x0_dev)
-        HIPCHK(ctx, hipMemcpyAsync(x, x0_dev, vstride * sizeof(float2), hipMemcpyDeviceToDevice, s));
-    else
-        HIPCHK(ctx, hipMemsetAsync(x, 0, vstride * sizeof(float2), s));
+    hipLaunchKernelGGL(widen_kernel, dim3((unsigned)grid_blocks(vstride)), dim3(256), 0, s, x0_dev, x, vstride);
     HIPCHK(ctx, hipMemsetAsync(w.iters.p, 0, n_rhs * sizeof(int), s));
     {
         const long long nh = (long long)n_rhs * std::max(1, o->max_iters);
@@ -611,9 +711,12 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     nosdd_status result = NOSDD_OK;
     int total_outer = 0;
     for (;;) {
-        // explicit residual r = b - A x into w, beta^2
-        launch_stencil(s, x, b, wv, p->d_eps.as<float>(), p->d_coef.as<float2>(), p->d_k0sq.as<float>(), p->nx,
-                       p->ny, n_rhs, n_src, nullptr);
+        // explicit residual r = b - A x (FP64) into w, beta^2
+        {
+        ProfScope ps(p, 1, n_rhs);
+        launch_residual64(s, x, b, wv, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->nx,
+                          p->ny, n_rhs, n_src);
+        }
         launch_dots(s, V, vstride, 0, wv, N, n_rhs, nullptr, w.partial.as<double2>(), nblk);
         launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, nullptr, w.beta2.as<double>());
         HIPCHK(ctx, hipMemcpyAsync(beta2.data(), w.beta2.p, n_rhs * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -635,39 +738,45 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         launch_start_cycle(s, V, wv, w.beta2.as<double>(), w.bnorm.as<float>(), w.gam.as<float2>(), m,
                            w.kcyc.as<int>(), w.active.as<int>(), w.want.as<int>(), N, n_rhs);
         const int *active = w.active.as<int>();
+        int n_live = 0;
+        for (int r = 0; r < n_rhs; ++r) n_live += want[r];
         for (int j = 0; j < m; ++j) {
             float2 *Vj = V + j * vstride, *Vn = V + (j + 1) * vstride, *Zj = Z + j * vstride;
-            precond(p, s, Vj, Zj, wv, n_src, n_rhs, active);
+            precond(p, s, Vj, Zj, wv, n_src, n_rhs, active, n_live);
             // classical Gram-Schmidt against V_0..V_j, selective second pass
-            launch_dots(s, V, vstride, j + 1, wv, N, n_rhs, active, w.partial.as<double2>(), nblk);
-            launch_reduce_dots(s, w.partial.as<double2>(), nblk, j + 1, n_rhs, active, w.H.as<float2>(), m, m, j, 0,
-                               w.nw_pre.as<double>());
-            launch_update(s, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, m, j, nullptr,
-                          w.partial.as<double2>(), nblk);
-            launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, active, w.nw_post.as<double>());
-            launch_dgks(s, w.nw_pre.as<double>(), w.nw_post.as<double>(), w.reorth.as<int>(), active, n_rhs);
-            const int *ro = w.reorth.as<int>();
-            launch_dots(s, V, vstride, j + 1, Vn, N, n_rhs, ro, w.partial.as<double2>(), nblk);
-            launch_reduce_dots(s, w.partial.as<double2>(), nblk, j + 1, n_rhs, ro, w.H2.as<float2>(), m, m, j, 0,
-                               nullptr);
-            launch_update(s, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, m, j, nullptr,
-                          w.partial.as<double2>(), nblk);
-            launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, ro, w.nw_re.as<double>());
-            launch_hadd(s, w.H.as<float2>(), w.H2.as<float2>(), m, j, j + 1, ro, n_rhs);
-            launch_givens(s, ga, j, n_rhs);
-            launch_scale(s, Vn, N, n_rhs, active, w.inv_h.as<float>());
+            {
+                ProfScope arn(p, 2, n_live);
+                launch_dots(s, V, vstride, j + 1, wv, N, n_rhs, active, w.partial.as<double2>(), nblk);
+                launch_reduce_dots(s, w.partial.as<double2>(), nblk, j + 1, n_rhs, active, w.H.as<float2>(), m, m, j, 0,
+                                   w.nw_pre.as<double>());
+                launch_update(s, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, m, j, nullptr,
+                              w.partial.as<double2>(), nblk);
+                launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, active, w.nw_post.as<double>());
+                launch_dgks(s, w.nw_pre.as<double>(), w.nw_post.as<double>(), w.reorth.as<int>(), active, n_rhs);
+                const int *ro = w.reorth.as<int>();
+                launch_dots(s, V, vstride, j + 1, Vn, N, n_rhs, ro, w.partial.as<double2>(), nblk);
+                launch_reduce_dots(s, w.partial.as<double2>(), nblk, j + 1, n_rhs, ro, w.H2.as<float2>(), m, m, j, 0,
+                                   nullptr);
+                launch_update(s, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, m, j, nullptr,
+                              w.partial.as<double2>(), nblk);
+                launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, ro, w.nw_re.as<double>());
+                launch_hadd(s, w.H.as<float2>(), w.H2.as<float2>(), m, j, j + 1, ro, n_rhs);
+                launch_givens(s, ga, j, n_rhs);
+                launch_scale(s, Vn, N, n_rhs, active, w.inv_h.as<float>());
+            }
             ++total_outer;
             HIPCHK(ctx, hipMemcpyAsync(h_act, w.active.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(ctx, hipStreamSynchronize(s));
-            int live = 0;
-            for (int r = 0; r < n_rhs; ++r) live |= h_act[r];
-            if (!live) break;
+            n_live = 0;
+            for (int r = 0; r < n_rhs; ++r) n_live += h_act[r] ? 1 : 0;
+            if (!n_live) break;
         }
         launch_backsolve(s, w.H.as<float2>(), m, m, w.gam.as<float2>(), w.kcyc.as<int>(), w.y.as<float2>(), n_rhs);
         launch_xupdate(s, x, Z, vstride, w.y.as<float2>(), m, w.kcyc.as<int>(), N, n_rhs);
     }
     HIPCHK(ctx, hipGetLastError());
-    if (E_dev) HIPCHK(ctx, hipMemcpyAsync(E_dev, x, vstride * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    if (E_dev)
+        hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)grid_blocks(vstride)), dim3(256), 0, s, x, E_dev, vstride);
     HIPCHK(ctx, hipEventRecord(e1, s));
     HIPCHK(ctx, hipMemcpyAsync(iters.data(), w.iters.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
     if (resid_hist && o->max_iters > 0)
@@ -679,6 +788,7 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipHostFree(h_act);
+    if (p->prof) prof_flush(p);
     p->solve_ms = ms;
     p->last_iters = total_outer;
     for (int r = 0; r < n_rhs; ++r) {
@@ -693,6 +803,7 @@ nosdd_status check_problem(nosdd_problem *p, bool need_setup) {
     if (!p) return NOSDD_EINVAL;
     if (need_setup && !p->setup_done) return fail(p->ctx, NOSDD_ESTATE, "nosdd_problem_setup has not been called");
     if (hipSetDevice(p->ctx->device) != hipSuccess) return fail(p->ctx, NOSDD_EHIP, "hipSetDevice failed");
+    (void)hipGetLastError();    // errors left by unrelated earlier runtime calls are not ours
     return NOSDD_OK;
 }
 
@@ -983,7 +1094,7 @@ nosdd_status nosdd_apply_operator(nosdd_problem *p, const nosdd_c32 *x, const no
     if (st) return st;
     if (!x || !y || n_src <= 0) return fail(p->ctx, NOSDD_EINVAL, "null argument or n_src <= 0");
     launch_stencil(p->ctx->stream, (const float2 *)x, (const float2 *)b, (float2 *)y, p->d_eps.as<float>(),
-                   p->d_coef.as<float2>(), p->d_k0sq.as<float>(), p->nx, p->ny, (int)p->wl.size() * n_src, n_src,
+                   p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->nx, p->ny, (int)p->wl.size() * n_src, n_src,
                    nullptr);
     HIPCHK(p->ctx, hipGetLastError());
     return NOSDD_OK;
@@ -1019,7 +1130,7 @@ nosdd_status nosdd_precond_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
         HIPCHK(p->ctx, tmp.ensure((size_t)n_rhs * N * sizeof(float2)));
         w = tmp.as<float2>();
     }
-    precond(p, p->ctx->stream, (const float2 *)v, (float2 *)z, w, n_src, n_rhs, nullptr);
+    precond(p, p->ctx->stream, (const float2 *)v, (float2 *)z, w, n_src, n_rhs, nullptr, n_rhs);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
     return NOSDD_OK;
@@ -1065,6 +1176,48 @@ nosdd_status nosdd_sizes(const nosdd_problem *p, int *n_tiles, long long *local_
     if (local_cells) *local_cells = p->loc_total;
     if (trace_entries) *trace_entries = p->n_entries;
     if (n_coarse) *n_coarse = p->n_c;
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_coarse_basis(const nosdd_problem *p, int wl, nosdd_c32 *phi, long long *box) {
+    if (!p || wl < 0 || wl >= (int)p->wl.size()) return NOSDD_EINVAL;
+    if (box)
+        for (size_t t = 0; t < p->tiles.size(); ++t) {
+            box[4 * t] = p->tiles[t].bx0;
+            box[4 * t + 1] = p->tiles[t].by0;
+            box[4 * t + 2] = p->tiles[t].bw;
+            box[4 * t + 3] = p->tiles[t].bh;
+        }
+    if (phi && p->n_c > 0) {
+        if (hipSetDevice(p->ctx->device) != hipSuccess) return NOSDD_EHIP;
+        if (hipMemcpy(phi, p->d_phi.as<float2>() + wl * p->box_wl_stride, p->box_wl_stride * sizeof(float2),
+                      hipMemcpyDeviceToHost) != hipSuccess)
+            return NOSDD_EHIP;
+    }
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_profile(nosdd_problem *p, int enable) {
+    if (!p) return NOSDD_EINVAL;
+    if (enable) {
+        for (int i = 0; i < 4; ++i) {
+            p->prof_ms[i] = 0;
+            p->prof_launch[i] = p->prof_units[i] = 0;
+        }
+        p->ev_pending.clear();
+        p->ev_next = 0;
+    }
+    p->prof = enable != 0;
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_kernel_times(const nosdd_problem *p, double ms[4], long long launches[4], long long units[4]) {
+    if (!p) return NOSDD_EINVAL;
+    for (int i = 0; i < 4; ++i) {
+        if (ms) ms[i] = p->prof_ms[i];
+        if (launches) launches[i] = p->prof_launch[i];
+        if (units) units[i] = p->prof_units[i];
+    }
     return NOSDD_OK;
 }
 

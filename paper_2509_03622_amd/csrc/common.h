@@ -68,8 +68,11 @@ __host__ __device__ __forceinline__ long long coef_stride(int nx, int ny) { retu
 // ------------------------------------------------------------ launchers
 // All launches go on `s`; vectors are [rhs][ny][nx] float2 with rhs = wl*n_src + src.
 void launch_stencil(hipStream_t s, const float2 *x, const float2 *b, float2 *y, const float *eps,
-                    const float2 *coef, const float *k0sq, int nx, int ny, int n_rhs, int n_src,
+                    const double2 *coef, const double *k0, int nx, int ny, int n_rhs, int n_src,
                     const int *active);
+
+void launch_residual64(hipStream_t s, const double2 *x, const float2 *b, float2 *r, const float *eps,
+                       const double2 *coef, const double *k0, int nx, int ny, int n_rhs, int n_src);
 
 void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_wl, const float *eps,
                       const float2 *coef_f, const double *coef_d, const double *k0, double h, int nx,
@@ -117,7 +120,7 @@ void launch_dgks(hipStream_t s, const double *nw_pre, const double *nw_post, int
 void launch_givens(hipStream_t s, const GivensArgs &a, int j, int n_rhs);
 void launch_backsolve(hipStream_t s, const float2 *H, int ldh, int m, const float2 *gam, const int *kcyc,
                       float2 *y, int n_rhs);
-void launch_xupdate(hipStream_t s, float2 *x, const float2 *Z, long long zstride, const float2 *y, int m,
+void launch_xupdate(hipStream_t s, double2 *x, const float2 *Z, long long zstride, const float2 *y, int m,
                     const int *kcyc, long long N, int n_rhs);
 void launch_start_cycle(hipStream_t s, float2 *V0, const float2 *r, const double *beta2, const float *bnorm,
                         float2 *gam, int m, int *kcyc, int *active, const int *want, long long N, int n_rhs);

@@ -334,8 +334,8 @@ void launch_backsolve(hipStream_t s, const float2 *H, int ldh, int m, const floa
     hipLaunchKernelGGL(backsolve_kernel, dim3((n_rhs + 63) / 64), dim3(64), 0, s, H, m, gam, kcyc, y, n_rhs);
 }
 
-// x += sum_{i < kcyc[r]} y_i Z_i
-__global__ __launch_bounds__(256) void xupdate_kernel(float2 *x, const float2 *Z, long long zstride, const float2 *y,
+// x += sum_{i < kcyc[r]} y_i Z_i  (x in FP64; the FP32 products are accumulated in FP64)
+__global__ __launch_bounds__(256) void xupdate_kernel(double2 *x, const float2 *Z, long long zstride, const float2 *y,
                                                       int m, const int *kcyc, long long N) {
     __shared__ float2 ys[KR_MAXV];
     const int r = blockIdx.y;
@@ -343,16 +343,21 @@ __global__ __launch_bounds__(256) void xupdate_kernel(float2 *x, const float2 *Z
     if (k == 0) return;
     if (threadIdx.x < k) ys[threadIdx.x] = y[r * m + threadIdx.x];
     __syncthreads();
-    float2 *xr = x + r * N;
+    double2 *xr = x + r * N;
     const float2 *Zr = Z + r * N;
     for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
-        float2 v = xr[n];
-        for (int i = 0; i < k; ++i) v = cfma(v, ys[i], Zr[i * zstride + n]);
+        double2 v = xr[n];
+        for (int i = 0; i < k; ++i) {
+            const float2 zz = Zr[i * zstride + n];
+            const float2 yy = ys[i];
+            v.x += (double)yy.x * zz.x - (double)yy.y * zz.y;
+            v.y += (double)yy.x * zz.y + (double)yy.y * zz.x;
+        }
         xr[n] = v;
     }
 }
 
-void launch_xupdate(hipStream_t s, float2 *x, const float2 *Z, long long zstride, const float2 *y, int m,
+void launch_xupdate(hipStream_t s, double2 *x, const float2 *Z, long long zstride, const float2 *y, int m,
                     const int *kcyc, long long N, int n_rhs) {
     const int nb = (int)(((N + 255) / 256) < 1024 ? (N + 255) / 256 : 1024);
     hipLaunchKernelGGL(xupdate_kernel, dim3(nb, n_rhs), dim3(256), 0, s, x, Z, zstride, y, m, kcyc, N);

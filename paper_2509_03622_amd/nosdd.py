@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -20,7 +21,8 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -
 EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_problem_create",
            "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
-           "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing"]
+           "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
+           "nosdd_profile", "nosdd_kernel_times"]
 
 
 class Grid(C.Structure):
@@ -77,6 +79,9 @@ def load(path=LIBPATH):
         "nosdd_tile_info": (i, [vp, i, C.POINTER(ll)]),
         "nosdd_sizes": (i, [vp, C.POINTER(i), C.POINTER(ll), C.POINTER(ll), C.POINTER(i)]),
         "nosdd_last_timing": (i, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i)]),
+        "nosdd_coarse_basis": (i, [vp, i, vp, vp]),
+        "nosdd_profile": (i, [vp, i]),
+        "nosdd_kernel_times": (i, [vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -108,6 +113,7 @@ class Context:
         if st != OK:
             raise NosddError(st, "nosdd_ctx_create failed")
         self.h = h
+        self._problems = weakref.WeakSet()
 
     def check(self, st):
         if st < 0:
@@ -115,6 +121,10 @@ class Context:
         return st
 
     def close(self):
+        # problems live on this context: release them first, whatever order
+        # the garbage collector finalises the Python objects in
+        for prob in list(getattr(self, "_problems", ())):
+            prob.close()
         if self.h:
             self.L.nosdd_ctx_destroy(self.h)
             self.h = None
@@ -144,6 +154,7 @@ class Problem:
                                               len(wl), C.byref(hp)))
         self.h = hp
         self.n_wl = len(wl)
+        ctx._problems.add(self)
 
     def setup(self, k_coarse=0, k_trial=8, sub_solver=0, nn_weights=None, inner_max=2, inner_tol=1e-1):
         o = SetupOpts(sub_solver, k_coarse, k_trial, nn_weights.encode() if nn_weights else None, inner_max,
@@ -151,9 +162,9 @@ class Problem:
         return self.ctx.check(self.L.nosdd_problem_setup(self.h, C.byref(o)))
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and self.ctx.h:
             self.L.nosdd_problem_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -218,6 +229,35 @@ class Problem:
         a = (C.c_longlong * 10)()
         self.ctx.check(self.L.nosdd_tile_info(self.h, t, a))
         return list(a)
+
+    def coarse_basis(self, wl=0):
+        """Basis fields per tile: list (per tile) of arrays [k_coarse][bh][bw] and box origins."""
+        nt, lc, ne, nc = self.sizes()
+        box = np.zeros((nt, 4), np.int64)
+        self.ctx.check(self.L.nosdd_coarse_basis(self.h, wl, None, box.ctypes.data))
+        if nc == 0:
+            return [], box
+        kc = nc // nt
+        total = int(sum(kc * b[2] * b[3] for b in box))
+        phi = np.zeros(total, np.complex64)
+        self.ctx.check(self.L.nosdd_coarse_basis(self.h, wl, phi.ctypes.data, None))
+        out, off = [], 0
+        for b in box:
+            n = kc * int(b[2]) * int(b[3])
+            out.append(phi[off:off + n].reshape(kc, int(b[3]), int(b[2])))
+            off += n
+        return out, box
+
+    def profile(self, enable=True):
+        return self.ctx.check(self.L.nosdd_profile(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        """(ms[4], launches[4], units[4]) per class: local solve, operator, Arnoldi, coarse."""
+        ms = np.zeros(4, np.float64)
+        la = np.zeros(4, np.int64)
+        un = np.zeros(4, np.int64)
+        self.ctx.check(self.L.nosdd_kernel_times(self.h, ms.ctypes.data, la.ctypes.data, un.ctypes.data))
+        return ms, la, un
 
     def last_timing(self):
         s, v, i = C.c_double(), C.c_double(), C.c_int()

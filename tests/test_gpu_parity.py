@@ -175,3 +175,26 @@ def test_batched_wavelengths_and_sources_two_level():
                 assert rel(E[wi, s].ravel(), xo) < 1e-5 + err_o
             assert abs(int(iters[wi, s]) - it_o) <= 1, (lam, s, iters[wi, s], it_o)
             assert fin[wi, s] <= 1e-6
+
+
+@pytest.mark.parametrize("k_coarse,k_trial", [(1, 8), (2, 4)])
+def test_coarse_basis_fields_match_oracle(k_coarse, k_trial):
+    """Each basis field agrees with the oracle's up to a unit complex factor
+    (singular vectors are unique up to phase when the singular values are distinct)."""
+    w = random_small(22, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.1,), npml=12, block=16)
+    w.k_coarse, w.k_trial = k_coarse, k_trial
+    ctx, P = make_gpu_problem(w)
+    phis, box = P.coarse_basis(0)
+    A, part, locs = oracle_parts(w, 1.1)
+    cs = CoarseSpace(part, locs, A, w.eps.astype(np.float64), 1.1, w.h, k_coarse, k_trial)
+    Phi = cs.Phi.toarray()
+    worst = []
+    for col, ti in enumerate(cs.tile_of_col):
+        l = col % k_coarse
+        bx0, by0, bw, bh = box[ti]
+        ref = Phi[:, col].reshape(w.ny, w.nx)[by0:by0 + bh, bx0:bx0 + bw]
+        g = phis[ti][l].astype(np.complex128)
+        ph = np.vdot(g, ref) / abs(np.vdot(g, ref))
+        worst.append((rel(g * ph, ref), ti, l))
+    print(sorted(worst)[-5:])
+    assert max(worst)[0] < 1e-4, sorted(worst)[-5:]

@@ -218,3 +218,24 @@ def test_two_level_converges_to_direct_solution():
     x, it, hist, res = P.solve(w.J()[0], tol=1e-9, max_iters=800)
     assert res <= 1e-9
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-6
+
+
+def test_dependent_probes_are_dropped_and_span_is_kept():
+    """On a corner subdomain (L-shaped interface ring) the 8 pseudo-plane waves are
+    linearly dependent; Gram-Schmidt keeps an orthonormal basis of their span."""
+    from oracle.coarse import mgs_columns, pseudo_plane_waves
+    w = random_small(22, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.1,), npml=12, block=16)
+    A = assemble_A(w.eps, 1.1, w.h, 12)
+    part = Partition(192, 192, [64] * 3, [64] * 3, 8, 12)
+    locs = build_local_problems(part, A, w.eps.astype(float), 1.1, w.h)
+    raw = pseudo_plane_waves(part, part.tiles[0], locs[0], 8, w.eps, 2 * np.pi / 1.1, w.h)
+    sv = np.linalg.svd(raw, compute_uv=False)
+    assert sv[-1] < 1e-10 * sv[0]                      # rank 7 in exact arithmetic
+    Q = mgs_columns(raw)
+    assert Q.shape[1] == 7
+    np.testing.assert_allclose(Q.conj().T @ Q, np.eye(7), atol=1e-12)
+    resid = raw - Q @ (Q.conj().T @ raw)
+    assert np.linalg.norm(resid) < 1e-10 * np.linalg.norm(raw)
+    # an interior subdomain keeps all 8
+    Q4 = mgs_columns(pseudo_plane_waves(part, part.tiles[4], locs[4], 8, w.eps, 2 * np.pi / 1.1, w.h))
+    assert Q4.shape[1] == 8
