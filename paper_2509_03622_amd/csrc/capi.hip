@@ -54,8 +54,8 @@ struct DevBuf {
 struct Workspace {
     int n_rhs = 0, m = 0, max_iters = 0, nblk = 0;
     long long N = 0;
-    DevBuf x, b, V, Z, w, scratch, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, nw_re, bnorm2, bnorm, beta2, iters,
-        kcyc, active, want, reorth, inv_h, flags, hist, cd_, cc_;
+    DevBuf x, b, V, Z, w, scratch, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, bnorm2, bnorm, beta2,
+        iters, kcyc, active, want, ones, reorth, inv_h, flags, hist, cd_, cc_;
 };
 
 }  // namespace
@@ -312,7 +312,10 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     Workspace &w = p->ws;
     nosdd_ctx *ctx = p->ctx;
     const long long N = (long long)p->nx * p->ny;
-    const int nblk = (int)std::max<long long>(1, std::min<long long>(1024, (N + 2047) / 2048));
+    // about 8 cells per thread and at least ~512 workgroups in all, at most 1024 per RHS
+    long long nb = (N + 2047) / 2048;
+    nb = std::max<long long>(nb, std::min<long long>((N + 255) / 256, (512 + n_rhs - 1) / n_rhs));
+    const int nblk = (int)std::max<long long>(1, std::min<long long>(1024, nb));
     w.n_rhs = n_rhs;
     w.m = m;
     w.max_iters = max_iters;
@@ -333,11 +336,19 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     HIPCHK(ctx, w.sn.ensure((size_t)n_rhs * m * sizeof(float2)));
     HIPCHK(ctx, w.gam.ensure((size_t)n_rhs * (m + 1) * sizeof(float2)));
     HIPCHK(ctx, w.y.ensure((size_t)n_rhs * m * sizeof(float2)));
-    for (DevBuf *d : {&w.nw_pre, &w.nw_post, &w.nw_re, &w.bnorm2, &w.beta2})
+    for (DevBuf *d : {&w.nw_pre, &w.nw_post, &w.bnorm2, &w.beta2})
         HIPCHK(ctx, d->ensure((size_t)n_rhs * sizeof(double)));
     for (DevBuf *d : {&w.bnorm, &w.inv_h}) HIPCHK(ctx, d->ensure((size_t)n_rhs * sizeof(float)));
     for (DevBuf *d : {&w.iters, &w.kcyc, &w.active, &w.want, &w.reorth, &w.flags})
         HIPCHK(ctx, d->ensure((size_t)n_rhs * sizeof(int)));
+    {
+        const bool fresh = w.ones.bytes < (size_t)n_rhs * sizeof(int);
+        HIPCHK(ctx, w.ones.ensure((size_t)n_rhs * sizeof(int)));
+        if (fresh) {
+            std::vector<int> one(n_rhs, 1);
+            HIPCHK(ctx, hipMemcpy(w.ones.p, one.data(), n_rhs * sizeof(int), hipMemcpyHostToDevice));
+        }
+    }
     HIPCHK(ctx, w.hist.ensure((size_t)n_rhs * std::max(1, max_iters) * sizeof(float)));
     const int nc = std::max(1, p->n_c);
     HIPCHK(ctx, w.cd_.ensure((size_t)n_rhs * nc * sizeof(double2)));
@@ -364,10 +375,10 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
     }
     if (p->n_c > 0) {
         ProfScope ps(p, 3, n_live);
-        launch_coarse_dot(s, p->d_tiles.as<TileDesc>(), nullptr, p->n_c, p->kc, p->d_W.as<float2>(), p->box_wl_stride,
-                          0, v, wout, p->nx, N, n_rhs, n_src, active, w.cd_.as<double2>());
-        launch_coarse_solve(s, p->d_GinvT.as<double2>(), p->n_c, w.cd_.as<double2>(), w.cc_.as<float2>(), n_rhs,
-                            n_src, active);
+        launch_coarse_dot(s, p->d_tiles.as<TileDesc>(), p->n_c, p->kc, p->d_W.as<float2>(), p->box_wl_stride, v,
+                          wout, p->nx, N, n_rhs, n_src, active, w.cd_.as<double2>());
+        launch_coarse_solve(s, p->d_GinvT.as<double2>(), p->n_c, w.cd_.as<double2>(), w.cc_.as<float2>(), n_rhs, n_src,
+                            active);
         launch_coarse_update(s, p->d_tiles.as<TileDesc>(), p->ncx, p->ncy, p->d_tox.as<int>(), p->d_toy.as<int>(),
                              p->kc, p->d_phi.as<float2>(), p->d_W.as<float2>(), p->box_wl_stride, 0,
                              w.cc_.as<float2>(), p->n_c, z, wout, p->nx, p->ny, n_rhs, n_src, active);
@@ -654,6 +665,27 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     if (st != NOSDD_OK) return st;
     Workspace &w = p->ws;
     const int nblk = w.nblk;
+    GivensArgs ga;
+    ga.H = w.H.as<float2>();
+    ga.ldh = m;
+    ga.m = m;
+    ga.cs = w.cs.as<float>();
+    ga.sn = w.sn.as<float2>();
+    ga.gam = w.gam.as<float2>();
+    ga.nw_pre = w.nw_pre.as<double>();
+    ga.nw_pre_w = w.nw_pre.as<double>();
+    ga.H2 = w.H2.as<float2>();
+    ga.reorth = w.reorth.as<int>();
+    ga.bnorm = w.bnorm.as<float>();
+    ga.tol = (float)o->tol;
+    ga.active = w.active.as<int>();
+    ga.iters = w.iters.as<int>();
+    ga.kcyc = w.kcyc.as<int>();
+    ga.max_iters = o->max_iters;
+    ga.hist = w.hist.as<float>();
+    ga.hist_ld = std::max(1, o->max_iters);
+    ga.inv_h = w.inv_h.as<float>();
+    ga.flags = w.flags.as<int>();
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
@@ -673,8 +705,8 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
                            -1.0f);
     }
     // ||b||
-    launch_dots(s, V, vstride, 0, b, N, n_rhs, nullptr, w.partial.as<double2>(), nblk);
-    launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, nullptr, w.bnorm2.as<double>());
+    launch_cgs_dots(s, V, vstride, 0, b, N, n_rhs, w.ones.as<int>(), w.partial.as<double2>(), nblk);
+    launch_cgs_reduce(s, w.partial.as<double2>(), nblk, 0, n_rhs, nullptr, 0, 0, w.bnorm2.as<double>(), ga);
     std::vector<double> bn2(n_rhs), beta2(n_rhs);
     HIPCHK(ctx, hipMemcpyAsync(bn2.data(), w.bnorm2.p, n_rhs * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
@@ -682,27 +714,6 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     for (int r = 0; r < n_rhs; ++r) bnorm[r] = (float)std::sqrt(bn2[r]);
     HIPCHK(ctx, hipMemcpyAsync(w.bnorm.p, bnorm.data(), n_rhs * sizeof(float), hipMemcpyHostToDevice, s));
 
-    GivensArgs ga;
-    ga.H = w.H.as<float2>();
-    ga.ldh = m;
-    ga.m = m;
-    ga.cs = w.cs.as<float>();
-    ga.sn = w.sn.as<float2>();
-    ga.gam = w.gam.as<float2>();
-    ga.nw_pre = w.nw_pre.as<double>();
-    ga.nw_post = w.nw_post.as<double>();
-    ga.nw_reorth = w.nw_re.as<double>();
-    ga.reorth = w.reorth.as<int>();
-    ga.bnorm = w.bnorm.as<float>();
-    ga.tol = (float)o->tol;
-    ga.active = w.active.as<int>();
-    ga.iters = w.iters.as<int>();
-    ga.kcyc = w.kcyc.as<int>();
-    ga.max_iters = o->max_iters;
-    ga.hist = w.hist.as<float>();
-    ga.hist_ld = std::max(1, o->max_iters);
-    ga.inv_h = w.inv_h.as<float>();
-    ga.flags = w.flags.as<int>();
 
     std::vector<int> iters(n_rhs, 0), want(n_rhs), act(n_rhs);
     std::vector<double> final_res(n_rhs, 0.0);
@@ -717,8 +728,8 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         launch_residual64(s, x, b, wv, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->nx,
                           p->ny, n_rhs, n_src);
         }
-        launch_dots(s, V, vstride, 0, wv, N, n_rhs, nullptr, w.partial.as<double2>(), nblk);
-        launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, nullptr, w.beta2.as<double>());
+        launch_cgs_dots(s, V, vstride, 0, wv, N, n_rhs, w.ones.as<int>(), w.partial.as<double2>(), nblk);
+        launch_cgs_reduce(s, w.partial.as<double2>(), nblk, 0, n_rhs, nullptr, 0, 0, w.beta2.as<double>(), ga);
         HIPCHK(ctx, hipMemcpyAsync(beta2.data(), w.beta2.p, n_rhs * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipMemcpyAsync(iters.data(), w.iters.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipStreamSynchronize(s));
@@ -734,6 +745,7 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         HIPCHK(ctx, hipMemcpyAsync(w.want.p, want.data(), n_rhs * sizeof(int), hipMemcpyHostToDevice, s));
         HIPCHK(ctx, hipMemsetAsync(w.kcyc.p, 0, n_rhs * sizeof(int), s));
         HIPCHK(ctx, hipMemsetAsync(w.active.p, 0, n_rhs * sizeof(int), s));
+        HIPCHK(ctx, hipMemsetAsync(w.reorth.p, 0, n_rhs * sizeof(int), s));
         HIPCHK(ctx, hipMemsetAsync(w.H.p, 0, (size_t)n_rhs * (m + 1) * m * sizeof(float2), s));
         launch_start_cycle(s, V, wv, w.beta2.as<double>(), w.bnorm.as<float>(), w.gam.as<float2>(), m,
                            w.kcyc.as<int>(), w.active.as<int>(), w.want.as<int>(), N, n_rhs);
@@ -746,23 +758,19 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
             // classical Gram-Schmidt against V_0..V_j, selective second pass
             {
                 ProfScope arn(p, 2, n_live);
-                launch_dots(s, V, vstride, j + 1, wv, N, n_rhs, active, w.partial.as<double2>(), nblk);
-                launch_reduce_dots(s, w.partial.as<double2>(), nblk, j + 1, n_rhs, active, w.H.as<float2>(), m, m, j, 0,
-                                   w.nw_pre.as<double>());
-                launch_update(s, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, m, j, nullptr,
-                              w.partial.as<double2>(), nblk);
-                launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, active, w.nw_post.as<double>());
-                launch_dgks(s, w.nw_pre.as<double>(), w.nw_post.as<double>(), w.reorth.as<int>(), active, n_rhs);
+                double2 *part = w.partial.as<double2>();
                 const int *ro = w.reorth.as<int>();
-                launch_dots(s, V, vstride, j + 1, Vn, N, n_rhs, ro, w.partial.as<double2>(), nblk);
-                launch_reduce_dots(s, w.partial.as<double2>(), nblk, j + 1, n_rhs, ro, w.H2.as<float2>(), m, m, j, 0,
-                                   nullptr);
-                launch_update(s, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, m, j, nullptr,
-                              w.partial.as<double2>(), nblk);
-                launch_reduce_norm(s, w.partial.as<double2>(), nblk, n_rhs, ro, w.nw_re.as<double>());
-                launch_hadd(s, w.H.as<float2>(), w.H2.as<float2>(), m, j, j + 1, ro, n_rhs);
-                launch_givens(s, ga, j, n_rhs);
-                launch_scale(s, Vn, N, n_rhs, active, w.inv_h.as<float>());
+                const float *ih = w.inv_h.as<float>();
+                // classical Gram-Schmidt; a second pass only where the DGKS test asks for it
+                launch_cgs_dots(s, V, vstride, j + 1, wv, N, n_rhs, active, part, nblk);
+                launch_cgs_reduce(s, part, nblk, j + 1, n_rhs, active, j, 1, nullptr, ga);
+                launch_cgs_update(s, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, j, part, nblk);
+                launch_cgs_reduce(s, part, nblk, 0, n_rhs, nullptr, j, 2, nullptr, ga);
+                launch_cgs_dots(s, V, vstride, j + 1, Vn, N, n_rhs, ro, part, nblk);
+                launch_cgs_reduce(s, part, nblk, j + 1, n_rhs, ro, j, 3, nullptr, ga);
+                launch_cgs_update(s, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, j, part, nblk);
+                launch_cgs_reduce(s, part, nblk, 0, n_rhs, ro, j, 4, nullptr, ga);
+                launch_scale(s, Vn, N, n_rhs, active, ih);
             }
             ++total_outer;
             HIPCHK(ctx, hipMemcpyAsync(h_act, w.active.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -10,7 +10,7 @@
 
 namespace nosdd {
 
-// d[r][col] = sum_box conj(W[wl][col]) (v - w1)   -- one workgroup per (col, rhs)
+// d[r][col] = sum_box conj(W[wl][col]) (v - w1), one workgroup per (col, rhs), FP64 sums.
 __global__ __launch_bounds__(256) void coarse_dot_kernel(const TileDesc *__restrict__ tiles, int kc,
                                                          const float2 *__restrict__ Wbox, long long wl_stride,
                                                          const float2 *__restrict__ v, const float2 *__restrict__ w1,
@@ -47,34 +47,36 @@ __global__ __launch_bounds__(256) void coarse_dot_kernel(const TileDesc *__restr
     }
 }
 
-void launch_coarse_dot(hipStream_t s, const TileDesc *tiles, const int *col_tile, int n_c, int kc, const float2 *Wbox,
-                       long long box_wl_stride, int unused, const float2 *v, const float2 *w1, int nx, long long N,
-                       int n_rhs, int n_src, const int *active, double2 *d) {
-    (void)col_tile;
-    (void)unused;
-    hipLaunchKernelGGL(coarse_dot_kernel, dim3(n_c, n_rhs), dim3(256), 0, s, tiles, kc, Wbox, box_wl_stride, v, w1, nx,
-                       N, n_src, n_c, active, d);
+void launch_coarse_dot(hipStream_t s, const TileDesc *tiles, int n_c, int kc, const float2 *Wbox,
+                       long long box_wl_stride, const float2 *v, const float2 *w1, int nx, long long N, int n_rhs,
+                       int n_src, const int *active, double2 *d) {
+    hipLaunchKernelGGL(coarse_dot_kernel, dim3(n_c, n_rhs), dim3(256), 0, s, tiles, kc, Wbox, box_wl_stride, v, w1,
+                       nx, N, n_src, n_c, active, d);
 }
 
-// c[r] = Ginv[wl] d[r] in FP64 (GinvT[wl][j][i] = Ginv[i][j], coalesced over i)
+// c[r] = G^-1 d[r] in FP64; G^-1 stored transposed (GinvT[wl][j][i] = Ginv[i][j])
+// so that consecutive outputs read contiguous entries.
 __global__ __launch_bounds__(256) void coarse_solve_kernel(const double2 *__restrict__ GinvT, int n_c,
                                                            const double2 *__restrict__ d, float2 *__restrict__ c,
                                                            int n_src, const int *__restrict__ active) {
+    __shared__ double2 ds[1024];
     const int r = blockIdx.y;
     if (active && !active[r]) return;
     const int wl = r / n_src;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const double2 *dr = d + (long long)r * n_c;
+    for (int j = threadIdx.x; j < n_c && j < 1024; j += 256) ds[j] = dr[j];
+    __syncthreads();
+    const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n_c) return;
     const double2 *G = GinvT + (long long)wl * n_c * n_c;
-    const double2 *dr = d + (long long)r * n_c;
-    double sx = 0.0, sy = 0.0;
+    double ax = 0.0, ay = 0.0;
     for (int j = 0; j < n_c; ++j) {
         const double2 g = G[(long long)j * n_c + i];
-        const double2 dv = dr[j];
-        sx += g.x * dv.x - g.y * dv.y;
-        sy += g.x * dv.y + g.y * dv.x;
+        const double2 dv = j < 1024 ? ds[j] : dr[j];
+        ax += g.x * dv.x - g.y * dv.y;
+        ay += g.x * dv.y + g.y * dv.x;
     }
-    c[(long long)r * n_c + i] = make_float2((float)sx, (float)sy);
+    c[(long long)r * n_c + i] = make_float2((float)ax, (float)ay);
 }
 
 void launch_coarse_solve(hipStream_t s, const double2 *GinvT, int n_c, const double2 *d, float2 *c, int n_rhs,

@@ -90,34 +90,28 @@ void launch_robin_trace(hipStream_t s, const int4 *entries, int n_entries, const
                         int n_vec, int vec_per_wl);
 
 // Krylov helpers.  V is the basis: vector i of rhs r at V + i*vstride + r*N.
-void launch_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, long long N,
-                 int n_rhs, const int *active, double2 *partial, int nblk);
-void launch_reduce_dots(hipStream_t s, const double2 *partial, int nblk, int nv, int n_rhs,
-                        const int *active, float2 *H, int ldh, int m, int col, int accumulate,
-                        double *norm2_out);
-void launch_update(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
-                   long long N, int n_rhs, const int *active, const float2 *H, int ldh, int m, int col,
-                   const int *gate, double2 *partial, int nblk);
-void launch_reduce_norm(hipStream_t s, const double2 *partial, int nblk, int n_rhs, const int *active,
-                        double *out);
-void launch_hadd(hipStream_t s, float2 *H, const float2 *H2, int m, int col, int nv, const int *gate, int n_rhs);
-void launch_scale(hipStream_t s, float2 *v, long long N, int n_rhs, const int *active, const float *sc);
 
 struct GivensArgs {
     float2 *H; int ldh; int m;        // H[r][i][j] at H + (r*(m+1) + i)*m + j
+    float2 *H2;                       // second-pass coefficients, same layout
     float *cs; float2 *sn; float2 *gam;
-    const double *nw_pre;             // ||w||^2 before orthogonalisation
-    const double *nw_post;            // ||w'||^2 after
-    const double *nw_reorth;          // ||w''||^2 after the second pass (if gated)
+    const double *nw_pre;             // ||w||^2 before orthogonalisation (read by the Givens step)
+    double *nw_pre_w;                 // the same buffer, written by the first reduction
     int *reorth;                      // per-rhs gate set here (DGKS test)
     const float *bnorm; float tol;
     int *active; int *iters; int *kcyc; int max_iters;
     float *hist; int hist_ld;
     float *inv_h; int *flags;         // flags bit 0 converged, bit 1 breakdown, bit 2 budget
 };
-void launch_dgks(hipStream_t s, const double *nw_pre, const double *nw_post, int *reorth, const int *active,
-                 int n_rhs);
-void launch_givens(hipStream_t s, const GivensArgs &a, int j, int n_rhs);
+void launch_cgs_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, long long N,
+                     int n_rhs, const int *gate, double2 *partial, int nblk);
+void launch_cgs_update(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
+                       long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col, double2 *partial,
+                       int nblk);
+void launch_cgs_reduce(hipStream_t s, const double2 *partial, int nblk, int nv, int n_rhs, const int *gate, int col,
+                       int mode, double *norm_out, const GivensArgs &ga);
+void launch_scale(hipStream_t s, float2 *v, long long N, int n_rhs, const int *active, const float *sc);
+int nblk_for_update(long long N, int n_rhs);
 void launch_backsolve(hipStream_t s, const float2 *H, int ldh, int m, const float2 *gam, const int *kcyc,
                       float2 *y, int n_rhs);
 void launch_xupdate(hipStream_t s, double2 *x, const float2 *Z, long long zstride, const float2 *y, int m,
@@ -126,12 +120,11 @@ void launch_start_cycle(hipStream_t s, float2 *V0, const float2 *r, const double
                         float2 *gam, int m, int *kcyc, int *active, const int *want, long long N, int n_rhs);
 
 // Coarse space
-void launch_coarse_dot(hipStream_t s, const TileDesc *tiles, const int *col_tile, int n_c, int kc,
-                       const float2 *Wbox, long long box_wl_stride, int box_col_stride_unused,
-                       const float2 *v, const float2 *w1, int nx, long long N, int n_rhs, int n_src,
-                       const int *active, double2 *d);
-void launch_coarse_solve(hipStream_t s, const double2 *GinvT, int n_c, const double2 *d, float2 *c,
-                         int n_rhs, int n_src, const int *active);
+void launch_coarse_dot(hipStream_t s, const TileDesc *tiles, int n_c, int kc, const float2 *Wbox,
+                       long long box_wl_stride, const float2 *v, const float2 *w1, int nx, long long N, int n_rhs,
+                       int n_src, const int *active, double2 *d);
+void launch_coarse_solve(hipStream_t s, const double2 *GinvT, int n_c, const double2 *d, float2 *c, int n_rhs,
+                         int n_src, const int *active);
 void launch_coarse_update(hipStream_t s, const TileDesc *tiles, int ncx, int ncy, const int *tile_of_x,
                           const int *tile_of_y, int kc, const float2 *Phibox, const float2 *Wbox,
                           long long box_wl_stride, long long box_total, const float2 *c, int n_c, float2 *z,

@@ -11,6 +11,8 @@
 // Givens rotations (complex, FP32) follow
 //   rho = sqrt(|a|^2 + |b|^2), c = |a|/rho, s = (a/|a|) conj(b)/rho  (c=0, s=1 if a=0),
 //   gamma_{j+1} = -conj(s) gamma_j,  gamma_j <- c gamma_j.
+#include <algorithm>
+
 #include "common.h"
 
 namespace nosdd {
@@ -18,6 +20,15 @@ namespace nosdd {
 constexpr int KR_THREADS = 256;
 constexpr int KR_MAXV = 32;       // basis vectors handled per pass (restart <= 31)
 constexpr int KR_SLOTS = KR_MAXV + 1;
+
+// FP32 butterfly over the 64 lanes (result in every lane); the per-lane
+// inputs are sums of a few FP32 products, so FP32 is ample at this level and
+// the xor pattern maps onto cross-lane data movement without LDS round trips.
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -49,197 +60,10 @@ __device__ __forceinline__ void block_sum(double2 (&acc)[NV], int nv, double2 *r
     }
 }
 
-// partial[r][blk][i] = sum conj(V_i) w over this block's cells (i < nv);
-// partial[r][blk][KR_MAXV].x = sum |w|^2.  Each thread accumulates its few
-// cells in FP32, the workgroup sum is formed in FP64.
-__global__ __launch_bounds__(KR_THREADS) void dots_kernel(const float2 *__restrict__ V, long long vstride, int nv,
-                                                           const float2 *__restrict__ w, long long N,
-                                                           const int *__restrict__ active,
-                                                           double2 *__restrict__ partial, int nblk) {
-    __shared__ double2 red[(KR_THREADS / 64) * KR_SLOTS];
-    const int r = blockIdx.y;
-    if (active && !active[r]) return;
-    const float2 *wr = w + r * N;
-    const float2 *Vr = V + r * N;
-    float2 facc[KR_MAXV];
-    float fn = 0.f;
-#pragma unroll
-    for (int i = 0; i < KR_MAXV; ++i) facc[i] = make_float2(0.f, 0.f);
-    const long long stride = (long long)gridDim.x * KR_THREADS;
-    for (long long n = (long long)blockIdx.x * KR_THREADS + threadIdx.x; n < N; n += stride) {
-        const float2 wv = wr[n];
-        fn += cabs2(wv);
-#pragma unroll
-        for (int i = 0; i < KR_MAXV; ++i)
-            if (i < nv) facc[i] = cfma_conj(facc[i], Vr[i * vstride + n], wv);
-    }
-    // per-wave FP64 sums, then one thread per value sums the waves
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < KR_MAXV; ++i) {
-        if (i < nv) {
-            const double rx = wave_sum((double)facc[i].x), ry = wave_sum((double)facc[i].y);
-            if (lane == 0) red[wid * KR_SLOTS + i] = make_double2(rx, ry);
-        }
-    }
-    {
-        const double rn = wave_sum((double)fn);
-        if (lane == 0) red[wid * KR_SLOTS + KR_MAXV] = make_double2(rn, 0.0);
-    }
-    __syncthreads();
-    const int i = threadIdx.x;
-    if (i < nv || i == KR_MAXV) {
-        double2 s = red[i];
-        for (int wv = 1; wv < KR_THREADS / 64; ++wv) s = zadd(s, red[wv * KR_SLOTS + i]);
-        partial[((long long)r * nblk + blockIdx.x) * KR_SLOTS + i] = s;
-    }
-}
-
-void launch_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, long long N, int n_rhs,
-                 const int *active, double2 *partial, int nblk) {
-    hipLaunchKernelGGL(dots_kernel, dim3(nblk, n_rhs), dim3(KR_THREADS), 0, s, V, vstride, nv, w, N, active,
-                       partial, nblk);
-}
-
-// Sum partials (fixed order).  Writes H[r][i][col] (i < nv) as FP32 (added to
-// the existing entries when accumulate), and norm2_out[r] = ||w||^2.
-__global__ __launch_bounds__(KR_THREADS) void reduce_dots_kernel(const double2 *__restrict__ partial, int nblk,
-                                                                  int nv, const int *__restrict__ active,
-                                                                  float2 *__restrict__ H, int m, int col,
-                                                                  int accumulate, double *__restrict__ norm2_out) {
-    __shared__ double2 red[KR_THREADS];
-    const int r = blockIdx.x;
-    if (active && !active[r]) return;
-    const double2 *pr = partial + (long long)r * nblk * KR_SLOTS;
-    for (int i = 0; i <= nv; ++i) {
-        const int slot = i < nv ? i : KR_MAXV;
-        double2 s = make_double2(0.0, 0.0);
-        for (int bk = threadIdx.x; bk < nblk; bk += KR_THREADS) s = zadd(s, pr[(long long)bk * KR_SLOTS + slot]);
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int o = KR_THREADS / 2; o > 0; o >>= 1) {
-            if (threadIdx.x < o) red[threadIdx.x] = zadd(red[threadIdx.x], red[threadIdx.x + o]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            const double2 v = red[0];
-            if (i < nv) {
-                float2 *h = H + ((long long)r * (m + 1) + i) * m + col;
-                if (accumulate) *h = make_float2(h->x + (float)v.x, h->y + (float)v.y);
-                else *h = make_float2((float)v.x, (float)v.y);
-            } else if (norm2_out) {
-                norm2_out[r] = v.x;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-void launch_reduce_dots(hipStream_t s, const double2 *partial, int nblk, int nv, int n_rhs, const int *active,
-                        float2 *H, int ldh, int m, int col, int accumulate, double *norm2_out) {
-    (void)ldh;
-    hipLaunchKernelGGL(reduce_dots_kernel, dim3(n_rhs), dim3(KR_THREADS), 0, s, partial, nblk, nv, active, H, m, col,
-                       accumulate, norm2_out);
-}
-
-// dst = w - sum_{i<nv} coef_i V_i with coef_i = H[r][i][col] (or the second-pass
-// correction stored in the same layout when gate is given); partial norm of dst.
-// When gate is non-null and gate[r] == 0 the RHS is skipped.
-__global__ __launch_bounds__(KR_THREADS) void update_kernel(const float2 *__restrict__ V, long long vstride, int nv,
-                                                             const float2 *w, float2 *dst, long long N,
-                                                             const int *__restrict__ active,
-                                                             const float2 *__restrict__ Hc, int m, int col,
-                                                             const int *__restrict__ gate,
-                                                             double2 *__restrict__ partial, int nblk) {
-    __shared__ double2 red[(KR_THREADS / 64) * 1];
-    __shared__ float2 hs[KR_MAXV];
-    const int r = blockIdx.y;
-    if (active && !active[r]) return;
-    if (gate && !gate[r]) return;
-    if (threadIdx.x < nv) hs[threadIdx.x] = Hc[((long long)r * (m + 1) + threadIdx.x) * m + col];
-    __syncthreads();
-    float2 hreg[KR_MAXV];
-#pragma unroll
-    for (int i = 0; i < KR_MAXV; ++i) hreg[i] = i < nv ? hs[i] : make_float2(0.f, 0.f);
-    const float2 *wr = w + r * N;
-    float2 *dr = dst + r * N;
-    const float2 *Vr = V + r * N;
-    double nrm = 0.0;
-    float fn = 0.f;
-    int cnt = 0;
-    const long long stride = (long long)gridDim.x * KR_THREADS;
-    for (long long n = (long long)blockIdx.x * KR_THREADS + threadIdx.x; n < N; n += stride) {
-        float2 v = wr[n];
-#pragma unroll
-        for (int i = 0; i < KR_MAXV; ++i)
-            if (i < nv) v = cfms(v, hreg[i], Vr[i * vstride + n]);
-        dr[n] = v;
-        fn += cabs2(v);
-        if (++cnt == 16) { nrm += fn; fn = 0.f; cnt = 0; }
-    }
-    nrm += fn;
-    double2 acc[1] = {make_double2(nrm, 0.0)};
-    block_sum<1>(acc, 0, red);
-    if (threadIdx.x == 0) partial[((long long)r * nblk + blockIdx.x) * KR_SLOTS + KR_MAXV] = acc[0];
-}
-
-void launch_update(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst, long long N,
-                   int n_rhs, const int *active, const float2 *H, int ldh, int m, int col, const int *gate,
-                   double2 *partial, int nblk) {
-    (void)ldh;
-    hipLaunchKernelGGL(update_kernel, dim3(nblk, n_rhs), dim3(KR_THREADS), 0, s, V, vstride, nv, w, dst, N, active,
-                       H, m, col, gate, partial, nblk);
-}
-
-__global__ __launch_bounds__(KR_THREADS) void reduce_norm_kernel(const double2 *__restrict__ partial, int nblk,
-                                                                  const int *__restrict__ active,
-                                                                  const int *__restrict__ gate,
-                                                                  double *__restrict__ out) {
-    __shared__ double red[KR_THREADS];
-    const int r = blockIdx.x;
-    if (active && !active[r]) return;
-    if (gate && !gate[r]) return;
-    double s = 0.0;
-    for (int bk = threadIdx.x; bk < nblk; bk += KR_THREADS) s += partial[((long long)r * nblk + bk) * KR_SLOTS + KR_MAXV].x;
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = KR_THREADS / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[r] = red[0];
-}
-
-void launch_reduce_norm(hipStream_t s, const double2 *partial, int nblk, int n_rhs, const int *active, double *out) {
-    hipLaunchKernelGGL(reduce_norm_kernel, dim3(n_rhs), dim3(KR_THREADS), 0, s, partial, nblk, active,
-                       (const int *)nullptr, out);
-}
-
-void launch_reduce_norm_gated(hipStream_t s, const double2 *partial, int nblk, int n_rhs, const int *active,
-                              const int *gate, double *out) {
-    hipLaunchKernelGGL(reduce_norm_kernel, dim3(n_rhs), dim3(KR_THREADS), 0, s, partial, nblk, active, gate, out);
-}
-
-// DGKS: ask for a second Gram-Schmidt pass when ||w'|| < 0.7 ||w||.
-__global__ void dgks_kernel(const double *nw_pre, const double *nw_post, int *reorth, const int *active, int n_rhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rhs) return;
-    reorth[r] = (active[r] && nw_post[r] < 0.49 * nw_pre[r]) ? 1 : 0;
-}
-
-void launch_dgks(hipStream_t s, const double *nw_pre, const double *nw_post, int *reorth, const int *active,
-                 int n_rhs) {
-    hipLaunchKernelGGL(dgks_kernel, dim3((n_rhs + 63) / 64), dim3(64), 0, s, nw_pre, nw_post, reorth, active, n_rhs);
-}
-
-// One Givens step per active RHS (column j of H already holds h_{0..j,j};
-// h_{j+1,j} = ||w'|| comes from nw_post, or nw_reorth after a second pass).
-__global__ void givens_kernel(GivensArgs a, int j, int n_rhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rhs || !a.active[r]) return;
+// One Givens step for RHS r (column j of H holds h_{0..j,j}; ||w'||^2 = nw).
+__device__ void givens_step(const GivensArgs &a, int r, int j, double nw) {
     const int m = a.m;
     float2 *Hr = a.H + (long long)r * (m + 1) * m;
-    const double nw = (a.reorth && a.reorth[r]) ? a.nw_reorth[r] : a.nw_post[r];
     const float hn = (float)sqrt(nw);
     Hr[(j + 1) * m + j] = make_float2(hn, 0.f);
     float *cs = a.cs + r * m;
@@ -248,9 +72,9 @@ __global__ void givens_kernel(GivensArgs a, int j, int n_rhs) {
         const float2 hi = Hr[i * m + j], hi1 = Hr[(i + 1) * m + j];
         const float c = cs[i];
         const float2 s = sn[i];
-        // t = c*hi + s*hi1 ; hi1' = -conj(s)*hi + c*hi1
-        float2 t = make_float2(c * hi.x + s.x * hi1.x - s.y * hi1.y, c * hi.y + s.x * hi1.y + s.y * hi1.x);
-        float2 u = make_float2(-(s.x * hi.x + s.y * hi.y) + c * hi1.x, -(s.x * hi.y - s.y * hi.x) + c * hi1.y);
+        // t = c hi + s hi1 ; hi1' = -conj(s) hi + c hi1
+        const float2 t = make_float2(c * hi.x + s.x * hi1.x - s.y * hi1.y, c * hi.y + s.x * hi1.y + s.y * hi1.x);
+        const float2 u = make_float2(-(s.x * hi.x + s.y * hi.y) + c * hi1.x, -(s.x * hi.y - s.y * hi.x) + c * hi1.y);
         Hr[i * m + j] = t;
         Hr[(i + 1) * m + j] = u;
     }
@@ -265,8 +89,7 @@ __global__ void givens_kernel(GivensArgs a, int j, int n_rhs) {
         const float rho = sqrtf(cabs2(av) + cabs2(bv));
         c = aa / rho;
         const float2 ph = make_float2(av.x / aa, av.y / aa);
-        // s = ph * conj(bv) / rho
-        s = make_float2((ph.x * bv.x + ph.y * bv.y) / rho, (ph.y * bv.x - ph.x * bv.y) / rho);
+        s = make_float2((ph.x * bv.x + ph.y * bv.y) / rho, (ph.y * bv.x - ph.x * bv.y) / rho);   // ph conj(b) / rho
     }
     cs[j] = c;
     sn[j] = s;
@@ -281,8 +104,7 @@ __global__ void givens_kernel(GivensArgs a, int j, int n_rhs) {
     if (it < a.hist_ld) a.hist[(long long)r * a.hist_ld + it] = res;
     a.iters[r] = it + 1;
     a.kcyc[r] = j + 1;
-    const double nwpre = a.nw_pre[r];
-    const bool breakdown = nw <= 1e-12 * nwpre;        // ||w'|| <= 1e-6 ||w|| in FP32
+    const bool breakdown = nw <= 1e-12 * a.nw_pre[r];   // ||w'|| <= 1e-6 ||w||
     int fl = 0;
     if (res <= a.tol) fl |= 1;
     if (breakdown) fl |= 2;
@@ -292,11 +114,229 @@ __global__ void givens_kernel(GivensArgs a, int j, int n_rhs) {
     if (fl) a.active[r] = 0;
 }
 
-void launch_givens(hipStream_t s, const GivensArgs &a, int j, int n_rhs) {
-    hipLaunchKernelGGL(givens_kernel, dim3((n_rhs + 63) / 64), dim3(64), 0, s, a, j, n_rhs);
+// Gram-Schmidt dots pass: per-workgroup partials of h_i = V_i^H w (i < NV) and
+// ||w||^2 (slot KR_MAXV), summed by cgs_reduce_kernel.
+template <int NV, int U>
+__global__ __launch_bounds__(KR_THREADS) void cgs_dots_kernel(const float2 *__restrict__ V, long long vstride,
+                                                              const float2 *__restrict__ w, long long N,
+                                                              const int *__restrict__ gate,
+                                                              double2 *__restrict__ partial, int nblk) {
+    __shared__ double2 red[(KR_THREADS / 64) * KR_SLOTS];
+    const int r = blockIdx.y;
+    if (!gate[r]) return;
+    const float2 *wr = w + r * N;
+    const float2 *Vr = V + r * N;
+    float2 facc[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) facc[i] = make_float2(0.f, 0.f);
+    float fn = 0.f;
+    // U cells per thread per trip, all loads of a trip issued before any use
+    const long long stride = (long long)gridDim.x * KR_THREADS * U;
+    for (long long n0 = (long long)blockIdx.x * KR_THREADS * U + threadIdx.x; n0 < N; n0 += stride) {
+        float2 wv[U], vv[U][NV > 0 ? NV : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long n = n0 + (long long)u * KR_THREADS;
+            const bool in = n < N;
+            wv[u] = in ? wr[n] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) vv[u][i] = in ? Vr[i * vstride + n] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            fn += cabs2(wv[u]);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) facc[i] = cfma_conj(facc[i], vv[u][i], wv[u]);
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const float rx = wave_sum_f(facc[i].x), ry = wave_sum_f(facc[i].y);
+        if (lane == 0) red[wid * KR_SLOTS + i] = make_double2(rx, ry);
+    }
+    {
+        const float rn = wave_sum_f(fn);
+        if (lane == 0) red[wid * KR_SLOTS + KR_MAXV] = make_double2(rn, 0.0);
+    }
+    __syncthreads();
+    double2 *pr = partial + (long long)r * nblk * KR_SLOTS;
+    const int i = threadIdx.x;
+    if (i < NV || i == KR_MAXV) {
+        double2 s = red[i];
+        for (int wv = 1; wv < KR_THREADS / 64; ++wv) s = zadd(s, red[wv * KR_SLOTS + i]);
+        pr[(long long)blockIdx.x * KR_SLOTS + i] = s;
+    }
 }
 
-// v *= sc[r]
+// Gram-Schmidt update pass:  dst = w - sum_{i<NV} Hc[r][i][col] V_i, with the
+// per-workgroup partial of ||dst||^2 written to slot KR_MAXV of `partial`.
+template <int NV, int U>
+__global__ __launch_bounds__(KR_THREADS) void cgs_update_kernel(const float2 *__restrict__ V, long long vstride,
+                                                                const float2 *w, float2 *dst, long long N,
+                                                                const int *__restrict__ gate,
+                                                                const float2 *__restrict__ Hc, int m, int col,
+                                                                double2 *__restrict__ partial, int nblk) {
+    __shared__ float2 hs[NV > 0 ? NV : 1];
+    __shared__ float red[KR_THREADS / 64];
+    const int r = blockIdx.y;
+    if (!gate[r]) return;
+    if (threadIdx.x < NV) hs[threadIdx.x] = Hc[((long long)r * (m + 1) + threadIdx.x) * m + col];
+    __syncthreads();
+    float2 hreg[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hreg[i] = hs[i];
+    const float2 *wr = w + r * N;
+    float2 *dr = dst + r * N;
+    const float2 *Vr = V + r * N;
+    float fn = 0.f;
+    const long long stride = (long long)gridDim.x * KR_THREADS * U;
+    for (long long n0 = (long long)blockIdx.x * KR_THREADS * U + threadIdx.x; n0 < N; n0 += stride) {
+        float2 wv[U], vv[U][NV > 0 ? NV : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long n = n0 + (long long)u * KR_THREADS;
+            const bool in = n < N;
+            wv[u] = in ? wr[n] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) vv[u][i] = in ? Vr[i * vstride + n] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float2 v = wv[u];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v = cfms(v, hreg[i], vv[u][i]);
+            const long long n = n0 + (long long)u * KR_THREADS;
+            if (n < N) dr[n] = v;
+            fn += cabs2(v);
+        }
+    }
+    fn = wave_sum_f(fn);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = fn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < KR_THREADS / 64; ++q) t += (double)red[q];
+        partial[((long long)r * nblk + blockIdx.x) * KR_SLOTS + KR_MAXV] = make_double2(t, 0.0);
+    }
+}
+
+// Sum the partials of each RHS (fixed order; waves split the slots, lanes the
+// workgroups) and take the scalar step of the Arnoldi recurrence:
+//   mode 0  norm only: ||.||^2 -> norm_out (||b||, restart residuals);
+//   mode 1  first-pass dots: h -> H[:, col], ||w||^2 -> nw_pre;
+//   mode 2  first-pass norm: ||w'||^2; DGKS (||w'|| < 0.7 ||w|| asks for a
+//           second pass: reorth = 1), else the Givens step;
+//   mode 3  second-pass dots: h2 -> H2[:, col], H[:, col] += h2;
+//   mode 4  second-pass norm: ||w''||^2 and the Givens step.
+constexpr int RED_THREADS = 1024;
+__global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *__restrict__ partial, int nblk, int nv,
+                                                                 const int *__restrict__ gate, int col, int mode,
+                                                                 double *__restrict__ norm_out, GivensArgs ga) {
+    __shared__ double2 vals[KR_SLOTS];
+    const int r = blockIdx.x;
+    if (mode == 2 && !ga.active[r]) {       // keep the second-pass flag of idle RHS cleared
+        if (threadIdx.x == 0) ga.reorth[r] = 0;
+        return;
+    }
+    if (gate && !gate[r]) return;
+    const int ns = (mode == 1 || mode == 3) ? nv : 0;
+    const double2 *pr = partial + (long long)r * nblk * KR_SLOTS;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int v = wid; v <= ns; v += RED_THREADS / 64) {
+        const int slot = v < ns ? v : KR_MAXV;
+        double sx = 0.0, sy = 0.0;
+        for (int bk = lane; bk < nblk; bk += 64) {
+            const double2 q = pr[(long long)bk * KR_SLOTS + slot];
+            sx += q.x;
+            sy += q.y;
+        }
+        sx = wave_sum(sx);
+        sy = wave_sum(sy);
+        if (lane == 0) vals[slot] = make_double2(sx, sy);
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double n2 = vals[KR_MAXV].x;
+    const int m = ga.m;
+    float2 *Hr = ga.H + (long long)r * (m + 1) * m;
+    switch (mode) {
+        case 0:
+            norm_out[r] = n2;
+            break;
+        case 1:
+            for (int i = 0; i < nv; ++i) Hr[i * m + col] = make_float2((float)vals[i].x, (float)vals[i].y);
+            ga.nw_pre_w[r] = n2;
+            break;
+        case 2:
+            if (n2 < 0.49 * ga.nw_pre[r]) {
+                ga.reorth[r] = 1;
+            } else {
+                ga.reorth[r] = 0;
+                givens_step(ga, r, col, n2);
+            }
+            break;
+        case 3:
+            for (int i = 0; i < nv; ++i) {
+                const float2 h = make_float2((float)vals[i].x, (float)vals[i].y);
+                ga.H2[((long long)r * (m + 1) + i) * m + col] = h;
+                Hr[i * m + col] = cadd(Hr[i * m + col], h);
+            }
+            break;
+        default:
+            givens_step(ga, r, col, n2);
+            break;
+    }
+}
+
+int nblk_for_update(long long N, int n_rhs) {
+    long long nb = (N + 2047) / 2048;
+    nb = std::max<long long>(nb, std::min<long long>((N + 255) / 256, (512 + n_rhs - 1) / n_rhs));
+    return (int)std::max<long long>(1, std::min<long long>(1024, nb));
+}
+
+#define NOSDD_NV_CASES(X) \
+    X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
+    X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+void launch_cgs_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, long long N,
+                     int n_rhs, const int *gate, double2 *partial, int nblk) {
+    dim3 grid(nblk, n_rhs);
+    switch (nv) {
+#define CASE(K)                                                                                                  \
+    case K:                                                                                                      \
+        hipLaunchKernelGGL((cgs_dots_kernel<K, (K > 16 ? 2 : 1)>), grid, dim3(KR_THREADS), 0, s, V, vstride, w, N, \
+                           gate, partial, nblk);                                                                 \
+        break;
+        NOSDD_NV_CASES(CASE)
+#undef CASE
+        default: break;
+    }
+}
+
+void launch_cgs_update(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
+                       long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col, double2 *partial,
+                       int nblk) {
+    dim3 grid(nblk, n_rhs);
+    switch (nv) {
+#define CASE(K)                                                                                                     \
+    case K:                                                                                                         \
+        hipLaunchKernelGGL((cgs_update_kernel<K, (K > 16 ? 2 : 1)>), grid, dim3(KR_THREADS), 0, s, V, vstride, w,  \
+                           dst, N, gate, Hc, m, col, partial, nblk);                                                \
+        break;
+        NOSDD_NV_CASES(CASE)
+#undef CASE
+        default: break;
+    }
+}
+
+void launch_cgs_reduce(hipStream_t s, const double2 *partial, int nblk, int nv, int n_rhs, const int *gate, int col,
+                       int mode, double *norm_out, const GivensArgs &ga) {
+    hipLaunchKernelGGL(cgs_reduce_kernel, dim3(n_rhs), dim3(RED_THREADS), 0, s, partial, nblk, nv, gate, col, mode,
+                       norm_out, ga);
+}
+
+// v *= sc[r]  (normalise the new basis vector)
 __global__ void scale_kernel(float2 *v, long long N, const int *active, const float *sc) {
     const int r = blockIdx.y;
     if (active && !active[r]) return;
@@ -388,19 +428,6 @@ void launch_start_cycle(hipStream_t s, float2 *V0, const float2 *r, const double
     const int nb = (int)(((N + 255) / 256) < 1024 ? (N + 255) / 256 : 1024);
     hipLaunchKernelGGL(start_cycle_kernel, dim3(nb, n_rhs), dim3(256), 0, s, V0, r, beta2, gam, m, kcyc, active, want,
                        N);
-}
-
-// H[r][i][col] += H2[r][i][col] for i < nv (second Gram-Schmidt pass), gated.
-__global__ void hadd_kernel(float2 *H, const float2 *H2, int m, int col, int nv, const int *gate, int n_rhs) {
-    const int r = blockIdx.x;
-    const int i = threadIdx.x;
-    if (r >= n_rhs || !gate[r] || i >= nv) return;
-    const long long o = ((long long)r * (m + 1) + i) * m + col;
-    H[o] = cadd(H[o], H2[o]);
-}
-
-void launch_hadd(hipStream_t s, float2 *H, const float2 *H2, int m, int col, int nv, const int *gate, int n_rhs) {
-    hipLaunchKernelGGL(hadd_kernel, dim3(n_rhs), dim3(64), 0, s, H, H2, m, col, nv, gate, n_rhs);
 }
 
 }  // namespace nosdd
