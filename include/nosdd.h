@@ -164,6 +164,11 @@ nosdd_status nosdd_precond_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
  * [n_wl][n_tiles][ly_t][lx_t] packed in tile order (tile sizes differ; use
  * nosdd_tile_info for offsets), one vector per (wl, tile). */
 nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32 *u);
+/* Apply the subdomain neural operator once to every subdomain-local vector
+ * (Fig. 2 network as loaded at setup, BF16 MFMA channel mixes, FP32 DFTs):
+ * e = NN(v) for v, e laid out [n_wl][n_tiles][ly_t][lx_t] like
+ * nosdd_local_solve.  Needs a problem set up with sub_solver = 1. */
+nosdd_status nosdd_nn_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *e);
 /* Robin traces g_p(x) = (x_q - x_p)/h + i kappa_p (x_q + x_p)/2 on every
  * interface-ring entry of every tile, for one global field per wavelength.
  * g is [n_wl][n_entries]; entry order per tile: counter-clockwise ring walk

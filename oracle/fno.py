@@ -106,3 +106,39 @@ def fno_forward(weights, v, eps, k0h, inv_sx, inv_sy, ring_mask):
     p = leaky(np.einsum("oi,iyx->oyx", wt["proj1_w"], u) + wt["proj1_b"][:, None, None])
     o = np.einsum("oi,iyx->oyx", wt["proj2_w"], p) + wt["proj2_b"][:, None, None]
     return (o[0] + 1j * o[1]) * s
+
+
+def load_weights(path):
+    """Read a weights file ("NOSDDFNO" header, bfloat16 tensors) into the dict
+    fno_forward takes (float32 values, complex R)."""
+    import struct
+    with open(path, "rb") as f:
+        raw = f.read()
+    if raw[:8] != b"NOSDDFNO":
+        raise ValueError("not a weights file")
+    version, C, m, L, in_ch, hidden, dtype = struct.unpack("<7i", raw[8:36])
+    if version != 1 or dtype != 1:
+        raise ValueError("unsupported weights file version/dtype")
+    bits = np.frombuffer(raw[36:], dtype=np.uint16)
+    vals = (bits.astype(np.uint32) << 16).view(np.float32)
+    pos = [0]
+
+    def take(*shape):
+        n = int(np.prod(shape))
+        out = vals[pos[0]:pos[0] + n].reshape(shape)
+        pos[0] += n
+        return out
+    w = {"modes": m, "layers": L, "lift_w": take(C, in_ch), "lift_b": take(C)}
+    for l in range(L):
+        rr = take(2 * m, m, C, C)
+        ri = take(2 * m, m, C, C)
+        w[f"R{l}"] = rr.astype(np.float64) + 1j * ri.astype(np.float64)
+        w[f"W{l}"] = take(C, C)
+        w[f"b{l}"] = take(C)
+    w["proj1_w"] = take(hidden, C)
+    w["proj1_b"] = take(hidden)
+    w["proj2_w"] = take(2, hidden)
+    w["proj2_b"] = take(2)
+    if pos[0] != vals.size:
+        raise ValueError("weights file size does not match its header")
+    return w

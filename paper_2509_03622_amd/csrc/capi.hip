@@ -82,6 +82,15 @@ struct nosdd_problem {
     bool setup_done = false;
     int sub_solver = 0;
     Workspace ws;
+    // neural subdomain solver
+    FnoDevice net;
+    DevBuf d_net, d_aux, d_smp;
+    int nn_steps = 2, max_cells = 0;
+    float nn_tol = 0.1f;
+    int smp_rhs = 0;                              // samples built for this many RHS
+    DevBuf nn_Vin, nn_Zin, nn_w, nn_beta, nn_vs, nn_os, nn_cs, nn_sact, nn_kstep, nn_gam, nn_H, nn_sn, nn_act0, nn_act1,
+        nn_spec, nn_X, nn_Y;
+    NnWork nw;
     double setup_ms = 0.0, solve_ms = 0.0;
     int last_iters = 0;
     // optional per-class kernel timing (events on the context stream)
@@ -356,6 +365,206 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     return NOSDD_OK;
 }
 
+// ---------------------------------------------------------------- neural subdomain solver
+uint16_t bf16_of(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float f32_of_bf16(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Read the weights file ("NOSDDFNO", int32 header, bfloat16 tensors) into device
+// buffers; R is expanded to the real 128 x 128 block form used by the MFMA mix.
+nosdd_status load_network(nosdd_problem *p, const char *path) {
+    nosdd_ctx *ctx = p->ctx;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(ctx, NOSDD_ENOWEIGHTS, std::string("cannot open weights file ") + path);
+    char magic[8];
+    int32_t hdr[7];
+    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "NOSDDFNO", 8) != 0 || std::fread(hdr, 4, 7, f) != 7) {
+        std::fclose(f);
+        return fail(ctx, NOSDD_ENOWEIGHTS, "not a network weights file");
+    }
+    const int C = hdr[1], m = hdr[2], L = hdr[3], in_ch = hdr[4], hid = hdr[5];
+    if (hdr[0] != 1 || hdr[6] != 1 || C != 64 || m != 16 || in_ch != 9 || hid != 128 || L < 1 || L > 16) {
+        std::fclose(f);
+        return fail(ctx, NOSDD_ENOWEIGHTS, "weights file must hold a bf16 network of width 64, 16 modes, 9 inputs, "
+                                           "projection 128");
+    }
+    const size_t per_layer = 2ull * (2 * m) * m * C * C + (size_t)C * C + C;
+    const size_t total = (size_t)C * in_ch + C + L * per_layer + (size_t)hid * C + hid + 2ull * hid + 2;
+    std::vector<uint16_t> w(total);
+    const size_t got = std::fread(w.data(), 2, total, f);
+    const bool extra = std::fgetc(f) != EOF;
+    std::fclose(f);
+    if (got != total || extra) return fail(ctx, NOSDD_ENOWEIGHTS, "weights file size does not match its header");
+    size_t pos = 0;
+    auto f32s = [&](size_t n) {
+        std::vector<float> v(n);
+        for (size_t i = 0; i < n; ++i) v[i] = f32_of_bf16(w[pos + i]);
+        pos += n;
+        return v;
+    };
+    std::vector<float> lift_w = f32s((size_t)C * in_ch), lift_b = f32s(C);
+    const int nmodes = 2 * m * m;
+    std::vector<uint16_t> R((size_t)L * nmodes * 128 * 128), Wb((size_t)L * C * C);
+    std::vector<float> bias((size_t)L * C);
+    for (int l = 0; l < L; ++l) {
+        const uint16_t *rr = &w[pos];
+        const uint16_t *ri = rr + (size_t)nmodes * C * C;
+        for (int md = 0; md < nmodes; ++md) {
+            uint16_t *dst = &R[((size_t)l * nmodes + md) * 128 * 128];
+            for (int i = 0; i < C; ++i)
+                for (int o = 0; o < C; ++o) {
+                    const uint16_t a = rr[((size_t)md * C + i) * C + o], b = ri[((size_t)md * C + i) * C + o];
+                    dst[i * 128 + o] = a;
+                    dst[i * 128 + 64 + o] = b;
+                    dst[(64 + i) * 128 + o] = (uint16_t)(b ^ 0x8000u);     // -Im R
+                    dst[(64 + i) * 128 + 64 + o] = a;
+                }
+        }
+        pos += 2ull * nmodes * C * C;
+        std::memcpy(&Wb[(size_t)l * C * C], &w[pos], (size_t)C * C * 2);
+        pos += (size_t)C * C;
+        for (int o = 0; o < C; ++o) bias[(size_t)l * C + o] = f32_of_bf16(w[pos + o]);
+        pos += C;
+    }
+    std::vector<uint16_t> p1w(w.begin() + pos, w.begin() + pos + (size_t)hid * C);
+    pos += (size_t)hid * C;
+    std::vector<float> p1b = f32s(hid), p2w = f32s(2ull * hid), p2b = f32s(2);
+    // one device buffer, carved
+    const size_t bytes = (lift_w.size() + lift_b.size() + bias.size() + p1b.size() + p2w.size() + p2b.size()) * 4 +
+                         (R.size() + Wb.size() + p1w.size()) * 2 + 8 * 256;
+    HIPCHK(ctx, p->d_net.ensure(bytes));
+    char *base = p->d_net.as<char>();
+    size_t off = 0;
+    hipStream_t st = ctx->stream;
+    auto put = [&](const void *src, size_t nb) -> void * {
+        void *dst = base + off;
+        off += (nb + 255) / 256 * 256;
+        (void)hipMemcpyAsync(dst, src, nb, hipMemcpyHostToDevice, st);
+        return dst;
+    };
+    FnoDevice &n = p->net;
+    n.layers = L;
+    n.lift_w = (float *)put(lift_w.data(), lift_w.size() * 4);
+    n.lift_b = (float *)put(lift_b.data(), lift_b.size() * 4);
+    n.R = (unsigned short *)put(R.data(), R.size() * 2);
+    n.W = (unsigned short *)put(Wb.data(), Wb.size() * 2);
+    n.b = (float *)put(bias.data(), bias.size() * 4);
+    n.p1w = (unsigned short *)put(p1w.data(), p1w.size() * 2);
+    n.p1b = (float *)put(p1b.data(), p1b.size() * 4);
+    n.p2w = (float *)put(p2w.data(), p2w.size() * 4);
+    n.p2b = (float *)put(p2b.data(), p2b.size() * 4);
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return NOSDD_OK;
+}
+
+// Constant network inputs per (wavelength, subdomain): (eps-1)/11, k0 h sqrt(eps),
+// Re/Im 1/s_x, Re/Im 1/s_y (cell-centre stretches of the global PML), ring mask.
+nosdd_status build_aux(nosdd_problem *p) {
+    nosdd_ctx *ctx = p->ctx;
+    const int nwl = (int)p->wl.size(), nx = p->nx, ny = p->ny;
+    const long long LT = p->loc_total;
+    std::vector<float> aux((size_t)nwl * 7 * LT, 0.f);
+    for (int wi = 0; wi < nwl; ++wi) {
+        const double k0 = 2.0 * M_PI / p->wl[wi];
+        const double sh = p->npml ? (p->pml_m + 1) * (-p->lnR) / (2.0 * k0 * p->npml * p->h) : 0.0;
+        for (auto &t : p->tiles) {
+            const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
+            for (int yy = 0; yy < ly; ++yy)
+                for (int xx = 0; xx < lx; ++xx) {
+                    const int x = t.x0 + xx, y = t.y0 + yy;
+                    const double e = p->eps[(size_t)y * nx + x];
+                    const cd isx = 1.0 / stretch(x, nx, p->npml, p->pml_m, sh);
+                    const cd isy = 1.0 / stretch(y, ny, p->npml, p->pml_m, sh);
+                    const bool ring = ((t.iface & SIDE_LEFT) && xx == 0) || ((t.iface & SIDE_RIGHT) && xx == lx - 1) ||
+                                      ((t.iface & SIDE_BOTTOM) && yy == 0) || ((t.iface & SIDE_TOP) && yy == ly - 1);
+                    const float v[7] = {(float)((e - 1.0) / 11.0), (float)(k0 * p->h * std::sqrt(e)),
+                                        (float)isx.real(), (float)isx.imag(), (float)isy.real(), (float)isy.imag(),
+                                        ring ? 1.f : 0.f};
+                    const long long c = t.loc_off + (long long)yy * lx + xx;
+                    for (int k = 0; k < 7; ++k) aux[((size_t)wi * 7 + k) * LT + c] = v[k];
+                }
+        }
+    }
+    HIPCHK(ctx, p->d_aux.ensure(aux.size() * 4));
+    HIPCHK(ctx, hipMemcpyAsync(p->d_aux.p, aux.data(), aux.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return NOSDD_OK;
+}
+
+// Sample descriptors and inner-solver workspace for n_rhs right-hand sides.
+nosdd_status ensure_nn(nosdd_problem *p, int n_rhs, int n_src) {
+    nosdd_ctx *ctx = p->ctx;
+    const int nt = (int)p->tiles.size();
+    const int S = n_rhs * nt;
+    const long long LT = p->loc_total;
+    if (p->smp_rhs != n_rhs) {
+        std::vector<FnoSample> smp(S);
+        for (int r = 0; r < n_rhs; ++r)
+            for (int t = 0; t < nt; ++t) {
+                const TileDesc &T = p->tiles[t];
+                FnoSample &q = smp[(size_t)r * nt + t];
+                q.lx = T.x1 - T.x0;
+                q.ly = T.y1 - T.y0;
+                q.cell_off = (long long)r * LT + T.loc_off;
+                q.aux_off = (long long)(r / n_src) * 7 * LT + T.loc_off;
+            }
+        HIPCHK(ctx, p->d_smp.ensure(smp.size() * sizeof(FnoSample)));
+        HIPCHK(ctx, hipMemcpy(p->d_smp.p, smp.data(), smp.size() * sizeof(FnoSample), hipMemcpyHostToDevice));
+        p->smp_rhs = n_rhs;
+    }
+    const int K = p->nn_steps;
+    const size_t vec = (size_t)n_rhs * LT * sizeof(float2);
+    HIPCHK(ctx, p->nn_Vin.ensure(vec * (K + 1)));
+    HIPCHK(ctx, p->nn_Zin.ensure(vec * K));
+    HIPCHK(ctx, p->nn_w.ensure(vec));
+    for (DevBuf *d : {&p->nn_beta, &p->nn_vs, &p->nn_os}) HIPCHK(ctx, d->ensure((size_t)S * 4));
+    for (DevBuf *d : {&p->nn_sact, &p->nn_kstep}) HIPCHK(ctx, d->ensure((size_t)S * 4));
+    HIPCHK(ctx, p->nn_cs.ensure((size_t)S * K * 4));
+    HIPCHK(ctx, p->nn_sn.ensure((size_t)S * K * 8));
+    HIPCHK(ctx, p->nn_gam.ensure((size_t)S * (K + 1) * 8));
+    HIPCHK(ctx, p->nn_H.ensure((size_t)S * (K + 1) * K * 8));
+    const size_t actb = (size_t)n_rhs * LT * 64 * 4;
+    HIPCHK(ctx, p->nn_act0.ensure(actb));
+    HIPCHK(ctx, p->nn_act1.ensure(actb));
+    HIPCHK(ctx, p->nn_spec.ensure(actb));
+    HIPCHK(ctx, p->nn_X.ensure((size_t)512 * S * 128 * 4));
+    HIPCHK(ctx, p->nn_Y.ensure((size_t)512 * S * 128 * 4));
+    NnWork &nw = p->nw;
+    nw.net = &p->net;
+    nw.smp = p->d_smp.as<FnoSample>();
+    nw.steps = K;
+    nw.maxk = K;
+    nw.tol = p->nn_tol;
+    nw.Vin = p->nn_Vin.as<float2>();
+    nw.Zin = p->nn_Zin.as<float2>();
+    nw.w = p->nn_w.as<float2>();
+    nw.beta = p->nn_beta.as<float>();
+    nw.vscale = p->nn_vs.as<float>();
+    nw.oscale = p->nn_os.as<float>();
+    nw.cs = p->nn_cs.as<float>();
+    nw.sact = p->nn_sact.as<int>();
+    nw.kstep = p->nn_kstep.as<int>();
+    nw.gam = p->nn_gam.as<float2>();
+    nw.H = p->nn_H.as<float2>();
+    nw.sn = p->nn_sn.as<float2>();
+    nw.aux = p->d_aux.as<float>();
+    nw.act0 = p->nn_act0.as<float>();
+    nw.act1 = p->nn_act1.as<float>();
+    nw.spec = p->nn_spec.as<float>();
+    nw.X = p->nn_X.as<float>();
+    nw.Y = p->nn_Y.as<float>();
+    return NOSDD_OK;
+}
+
 // z = M^-1 v (two-level), wout = A z.  v, z, wout: [n_rhs][N].
 void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2 *wout, int n_src, int n_rhs,
              const int *active, int n_live) {
@@ -363,6 +572,11 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
     const long long N = (long long)p->nx * p->ny;
     {
     ProfScope ps(p, 0, (long long)n_live * (long long)p->tiles.size());
+    if (p->sub_solver == 1) {
+        nn_precond(s, p->nw, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src, p->loc_total,
+                   p->max_cells, v, z, active, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(),
+                   p->h, p->nx, p->ny);
+    } else
     launch_bt_solve(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src, p->d_dinv.as<float2>(),
                     p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, w.scratch.as<float2>(),
                     p->loc_total, active, 0, p->bmax);
@@ -663,6 +877,10 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     const long long N = (long long)p->nx * p->ny;
     nosdd_status st = ensure_ws(p, n_rhs, m, o->max_iters);
     if (st != NOSDD_OK) return st;
+    if (p->sub_solver == 1) {
+        st = ensure_nn(p, n_rhs, n_src);
+        if (st != NOSDD_OK) return st;
+    }
     Workspace &w = p->ws;
     const int nblk = w.nblk;
     GivensArgs ga;
@@ -1013,7 +1231,8 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
     if (o->k_coarse < 0 || o->k_trial < 0) return fail(ctx, NOSDD_EINVAL, "negative coarse size");
     if (o->sub_solver == 1 && (!o->nn_weights || !o->nn_weights[0]))
         return fail(ctx, NOSDD_ENOWEIGHTS, "neural subdomain solver requested without a weights file");
-    if (o->sub_solver == 1) return fail(ctx, NOSDD_EINVAL, "neural subdomain solver is not available in this build");
+    if (o->sub_solver == 1 && (o->inner_max < 1 || o->inner_max > 8 || !(o->inner_tol >= 0.f)))
+        return fail(ctx, NOSDD_EINVAL, "inner_max must be in [1, 8] and inner_tol >= 0");
     hipStream_t s = ctx->stream;
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
@@ -1026,6 +1245,21 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
                      p->dinv_wl_stride, p->bmax);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
+    p->max_cells = 0;
+    for (auto &t : p->tiles) p->max_cells = std::max(p->max_cells, (t.x1 - t.x0) * (t.y1 - t.y0));
+    if (o->sub_solver == 1) {
+        for (auto &t : p->tiles)
+            if (t.x1 - t.x0 > 72 || t.y1 - t.y0 > 72)
+                return fail(ctx, NOSDD_EPARTITION, "the neural subdomain solver takes subdomains of at most 72 x 72");
+        st = load_network(p, o->nn_weights);
+        if (st) return st;
+        st = build_aux(p);
+        if (st) return st;
+        p->nn_steps = o->inner_max;
+        p->nn_tol = o->inner_tol;
+        p->smp_rhs = 0;
+    }
+    p->sub_solver = 0;          // the coarse probes below use the exact subdomain solves
     p->kc = (p->tiles.size() > 1) ? o->k_coarse : 0;
     p->ktrial = o->k_trial > 0 ? o->k_trial : 8;
     p->n_c = 0;
@@ -1131,6 +1365,10 @@ nosdd_status nosdd_precond_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
     const int n_rhs = (int)p->wl.size() * n_src;
     st = ensure_ws(p, n_rhs, std::max(1, p->ws.m), std::max(1, p->ws.max_iters));
     if (st) return st;
+    if (p->sub_solver == 1) {
+        st = ensure_nn(p, n_rhs, n_src);
+        if (st) return st;
+    }
     const long long N = (long long)p->nx * p->ny;
     DevBuf tmp;
     float2 *w = (float2 *)Az;
@@ -1156,6 +1394,24 @@ nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32
                     (float2 *)u, p->loc_total, scr.as<float2>(), p->loc_total, nullptr, 3, p->bmax);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_nn_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *e) {
+    nosdd_status st = check_problem(p, true);
+    if (st) return st;
+    if (!v || !e) return fail(p->ctx, NOSDD_EINVAL, "null argument");
+    if (p->sub_solver != 1) return fail(p->ctx, NOSDD_ESTATE, "the problem was not set up with the neural solver");
+    const int nwl = (int)p->wl.size();
+    st = ensure_nn(p, nwl, 1);
+    if (st) return st;
+    hipStream_t s = p->ctx->stream;
+    const int S = nwl * (int)p->tiles.size();
+    nn_rms_scales(s, p->nw.smp, S, (const float2 *)v, p->nw.vscale, p->nw.oscale);
+    fno_forward(s, p->net, p->nw.smp, nullptr, S, p->max_cells, (const float2 *)v, p->nw.vscale, p->nw.oscale,
+                p->nw.aux, p->loc_total, p->nw.act0, p->nw.act1, p->nw.spec, p->nw.X, p->nw.Y, (float2 *)e);
+    HIPCHK(p->ctx, hipGetLastError());
+    HIPCHK(p->ctx, hipStreamSynchronize(s));
     return NOSDD_OK;
 }
 

@@ -130,4 +130,48 @@ void launch_coarse_update(hipStream_t s, const TileDesc *tiles, int ncx, int ncy
                           long long box_wl_stride, long long box_total, const float2 *c, int n_c, float2 *z,
                           float2 *w, int nx, int ny, int n_rhs, int n_src, const int *active);
 
+// ------------------------------------------------------------ neural subdomain solver
+// One sample = one (subdomain, RHS) pair: tile geometry and where its vectors live.
+struct FnoSample {
+    int lx, ly;
+    long long cell_off;     // offset of the sample's cells in a sample-packed cell array
+    long long aux_off;      // offset (cells) of its aux channels in [wl][7][loc_total]
+};
+
+// Network parameters on the device (C = 64, 16 modes, projection width 128).
+struct FnoDevice {
+    int layers = 0;
+    float *lift_w = nullptr, *lift_b = nullptr;   // [64][9], [64]
+    unsigned short *R = nullptr;                  // [layer][512][128][128] bf16, [[Re, Im], [-Im, Re]]
+    unsigned short *W = nullptr;                  // [layer][64][64] bf16
+    float *b = nullptr;                           // [layer][64]
+    unsigned short *p1w = nullptr;                // [128][64] bf16
+    float *p1b = nullptr, *p2w = nullptr, *p2b = nullptr;   // [128], [2][128], [2]
+};
+
+// Workspace of the batched inner NN-FGMRES (device pointers).
+struct NnWork {
+    const FnoDevice *net = nullptr;
+    const FnoSample *smp = nullptr;
+    int steps = 0, maxk = 0;
+    float tol = 0.f;
+    float2 *Vin = nullptr, *Zin = nullptr, *w = nullptr;     // [k][rhs][loc_total]
+    float *beta = nullptr, *vscale = nullptr, *oscale = nullptr, *cs = nullptr;
+    int *sact = nullptr, *kstep = nullptr;
+    float2 *gam = nullptr, *H = nullptr, *sn = nullptr;
+    const float *aux = nullptr;                               // [wl][7][loc_total]
+    float *act0 = nullptr, *act1 = nullptr, *spec = nullptr, *X = nullptr, *Y = nullptr;
+};
+
+void nn_precond(hipStream_t st, const NnWork &nw, const TileDesc *tiles, int n_tiles, int n_rhs, int n_src,
+                long long loc_total, int max_cells, const float2 *v, float2 *z, const int *active, const float *eps,
+                const double2 *coef, const double *k0, double h, int nx, int ny);
+// per-sample rms scalings for a plain network application on arbitrary vectors
+void nn_rms_scales(hipStream_t st, const FnoSample *smp, int S, const float2 *v, float *vscale, float *oscale);
+
+// e = NN(v) for every active sample; v, e: sample-packed complex cells.
+void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, const int *sact, int S_tot, int max_cells,
+                 const float2 *v, const float *vscale, const float *oscale, const float *aux, long long aux_ch_stride,
+                 float *act0, float *act1, float *spec, float *X, float *Y, float2 *e);
+
 }  // namespace nosdd

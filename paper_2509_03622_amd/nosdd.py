@@ -22,7 +22,7 @@ EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_p
            "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
-           "nosdd_profile", "nosdd_kernel_times"]
+           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply"]
 
 
 class Grid(C.Structure):
@@ -82,6 +82,7 @@ def load(path=LIBPATH):
         "nosdd_coarse_basis": (i, [vp, i, vp, vp]),
         "nosdd_profile": (i, [vp, i]),
         "nosdd_kernel_times": (i, [vp, vp, vp, vp]),
+        "nosdd_nn_apply": (i, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -214,6 +215,9 @@ class Problem:
 
     def local_solve(self, rhs, u):
         return self.ctx.check(self.L.nosdd_local_solve(self.h, _ptr(rhs), _ptr(u)))
+
+    def nn_apply(self, v, e):
+        return self.ctx.check(self.L.nosdd_nn_apply(self.h, _ptr(v), _ptr(e)))
 
     def robin_trace(self, x, g):
         return self.ctx.check(self.L.nosdd_robin_trace(self.h, _ptr(x), _ptr(g)))
