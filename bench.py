@@ -81,6 +81,37 @@ def read_traffic(units_per_launch):
         return None
 
 
+def stencil_roofline(torch, nosdd, n_rhs=16, reps=20):
+    """Operator y = A x and residual r = b - A x on HBM-sized arrays (2048 x 1536
+    grid, n_rhs vectors of 25 MB each), timed with events on the library stream."""
+    from paper_2509_03622_amd.workloads import uneven_2048x1536
+    w = uneven_2048x1536()
+    N = w.nx * w.ny
+    ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, [64] * (w.nx // 64), [64] * (w.ny // 64), w.overlap, [1.0])
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn((n_rhs, w.ny, w.nx), dtype=torch.complex64, device="cuda", generator=g)
+    b = torch.randn((n_rhs, w.ny, w.nx), dtype=torch.complex64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    out = {}
+    for name, bb, bytes_per_cell in (("operator", None, 16.0 + 4.0 / n_rhs), ("residual", b, 24.0 + 4.0 / n_rhs)):
+        P.apply_operator(x, y, bb, n_rhs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            P.apply_operator(x, y, bb, n_rhs)
+        e1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        gbs = bytes_per_cell * N * n_rhs / (us * 1e-6) / 1e9
+        out[name] = {"avg_launch_us": round(us, 1), "achieved_GBs": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_cell_per_rhs": round(bytes_per_cell, 3)}
+    out["shape"] = f"{w.nx}x{w.ny} x {n_rhs} RHS (complex64), algorithmic bytes: x, b read, y written, eps shared"
+    P.close()
+    ctx.close()
+    return out
+
+
 def cpu_baseline(w, iters):
     """The FP64 oracle's Schwarz-FGMRES on one wavelength of the same workload,
     set-up excluded, capped at `iters` outer iterations."""
@@ -120,10 +151,11 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 direct-solve field check")
+    ap.add_argument("--no-stencil", action="store_true", help="skip the operator/residual roofline measurement")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
-              "(the path shards over RHS and subdomain slabs, see DESIGN.md)", file=sys.stderr)
+              "(the path would shard over right-hand sides and subdomain slabs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -195,6 +227,10 @@ def main():
            "kernel_ms_per_step": share,
            "roofline": roofline}
 
+    if not a.no_stencil:
+        P.close()
+        out["stencil_roofline"] = stencil_roofline(torch, nosdd)
+        print(f"[bench] stencil roofline {out['stencil_roofline']}", file=sys.stderr, flush=True)
     if not a.no_check:
         from oracle.fdfd import assemble_A, solve_direct, source_rhs
         Eh = E.cpu().numpy()

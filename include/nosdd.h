@@ -159,10 +159,13 @@ nosdd_status nosdd_schwarz_sweep(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
  * c = G^-1 W^H (v - A z1) (coarse correction, FP64 solve). Az nullable. */
 nosdd_status nosdd_precond_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *z, nosdd_c32 *Az,
                                  int n_src);
-/* Exact local solves on subdomain-local vectors: for tile t (index ty*ncx+tx)
- * and wavelength wl, u = B_{t,wl}^-1 rhs.  rhs and u are
- * [n_wl][n_tiles][ly_t][lx_t] packed in tile order (tile sizes differ; use
- * nosdd_tile_info for offsets), one vector per (wl, tile). */
+/* Subdomain solves on subdomain-local vectors with the configured sub-solver:
+ * for tile t (index ty*ncx+tx) and wavelength wl, u = B_{t,wl}^-1 rhs.
+ * sub_solver 0: exact block-Thomas LU.  sub_solver 1: the inner NN-FGMRES of
+ * Algorithm 1 (inference branch; x0 = 0, no restart, at most inner_max steps,
+ * stop once |gamma_{k+1}| / ||rhs|| <= inner_tol), u over the whole tile.
+ * rhs and u are [n_wl][n_tiles][ly_t][lx_t] packed in tile order (tile sizes
+ * differ; use nosdd_tile_info for offsets), one vector per (wl, tile). */
 nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32 *u);
 /* Apply the subdomain neural operator once to every subdomain-local vector
  * (Fig. 2 network as loaded at setup, BF16 MFMA channel mixes, FP32 DFTs):

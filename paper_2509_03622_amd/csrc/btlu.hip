@@ -13,12 +13,11 @@
 // in FP64 and inverts it by Gauss-Jordan elimination with partial pivoting;
 // D_k^-1 is stored as complex64, column-major per block ([c][r]).
 //
-// bt_solve_kernel (hot path): one 512-thread workgroup per (tile, RHS) streams
-// the 2 nb - 1 blocks D_k^-1 from HBM, each once, and keeps the sequential
+// bt_solve_kernel (hot path): one workgroup per (tile, RHS) streams the
+// 2 nb - 1 blocks D_k^-1 from HBM, each once, and keeps the sequential
 // recurrence in LDS.  The D blocks do not depend on the data, so each thread
 // holds the blocks of the next two steps in registers while it multiplies the
-// current one; this keeps ~80 KB per CU in flight, enough to hide HBM latency
-// with one workgroup per CU.  The gather of R_i v (input restricted to the
+// current one (~80 KB per CU in flight with one workgroup per CU).  The gather of R_i v (input restricted to the
 // extended tile, which carries the neighbours' Robin traces by the Robin
 // identity) and the core-only scatter (restricted additive Schwarz
 // prolongation) are fused into the same kernel.
@@ -176,65 +175,44 @@ void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_w
 }
 
 // ------------------------------------------------------------------ solve
-constexpr int BT_THREADS = 512;
+// Thread layout per (subdomain, RHS) workgroup: lane group rp (8 lanes) owns
+// rows 2rp, 2rp+1 of every block; lane cg of the group covers the columns
+// c = cg + 8 j.  Each lane loads one float4 (the two rows' entries of one
+// column) per column, the 8 lanes' partial sums are combined with three xor
+// shuffles inside the wave, and lane 0 of the group runs the recurrence for
+// its two rows.  One barrier per block step.
 constexpr int BT_BMAX = 128;
+constexpr int BT_GROUP = 8;
 
-template <int MAXC>
-struct BtSolver {
-    const float2 *__restrict__ D;      // this tile's blocks (one wavelength)
-    int b, half, NG, cg, rp;
-    bool mv;
-
-    __device__ __forceinline__ void load(float4 (&slot)[MAXC], int k) const {
-        const float4 *Dk = reinterpret_cast<const float4 *>(D + (long long)k * b * b);
+template <int MAXJ>
+__device__ __forceinline__ void bt_load(float4 (&slot)[MAXJ], const float2 *__restrict__ Dk, int b, int half, int rp,
+                                        int cg, bool on) {
+    const float4 *D4 = reinterpret_cast<const float4 *>(Dk);
 #pragma unroll
-        for (int i = 0; i < MAXC; ++i) {
-            const int c = cg + i * NG;
-            slot[i] = (mv && c < b) ? Dk[c * half + rp] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+    for (int j = 0; j < MAXJ; ++j) {
+        const int c = cg + BT_GROUP * j;
+        slot[j] = (on && c < b) ? D4[c * half + rp] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    // partial products of rows 2rp, 2rp+1 over this thread's column group
-    __device__ __forceinline__ void matvec(const float4 (&slot)[MAXC], const float2 *ysh, float2 *part) const {
-        float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int i = 0; i < MAXC; ++i) {
-            const int c = cg + i * NG;
-            if (c < b) {
-                const float2 yc = ysh[c];
-                a0 = cfma(a0, make_float2(slot[i].x, slot[i].y), yc);
-                a1 = cfma(a1, make_float2(slot[i].z, slot[i].w), yc);
-            }
-        }
-        if (mv) {
-            part[cg * b + 2 * rp] = a0;
-            part[cg * b + 2 * rp + 1] = a1;
-        }
-    }
-};
+}
 
-template <int MAXC>
-__global__ __launch_bounds__(BT_THREADS) void bt_solve_kernel(
-    const TileDesc *__restrict__ tiles, int n_src, const float2 *__restrict__ dinv, long long dinv_wl_stride,
-    const float2 *__restrict__ coef, int nx, int ny, const float2 *__restrict__ vin, long long vin_stride,
-    float2 *__restrict__ out, long long out_stride, float2 *__restrict__ hist, long long hist_stride,
-    const int *__restrict__ active, int mode) {
+template <int MAXJ>
+__global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restrict__ tiles, int n_src, const float2 *__restrict__ dinv,
+                                long long dinv_wl_stride, const float2 *__restrict__ coef, int nx, int ny,
+                                const float2 *__restrict__ vin, long long vin_stride, float2 *__restrict__ out,
+                                long long out_stride, float2 *__restrict__ hist, long long hist_stride,
+                                const int *__restrict__ active, int mode) {
     __shared__ float2 ysh[BT_BMAX];
-    __shared__ float2 part[2 * BT_THREADS];
     const int tile = blockIdx.x, rhs = blockIdx.y;
     if (active && !active[rhs]) return;
     const int wl = rhs / n_src;
     const TileDesc t = tiles[tile];
-    const int b = t.b, nb = t.nb, tid = threadIdx.x;
-    const int half = b >> 1;
-    const int NG = BT_THREADS / half;
-    BtSolver<MAXC> S;
-    S.D = dinv + wl * dinv_wl_stride + t.dinv_off;
-    S.b = b;
-    S.half = half;
-    S.NG = NG;
-    S.cg = tid / half;
-    S.rp = tid - S.cg * half;
-    S.mv = S.cg < NG;
+    const int b = t.b, nb = t.nb, half = b >> 1;
+    const int tid = threadIdx.x;
+    const int rp = tid / BT_GROUP, cg = tid - rp * BT_GROUP;
+    const bool on = rp < half;
+    const bool lead = on && cg == 0;
+    const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
+    const long long bb = (long long)b * b;
     const BlockMap bm{t.x0, t.y0, t.x1 - t.x0, t.tr};
     const float2 *cf = coef + wl * coef_stride(nx, ny);
     const float2 *clo_a = t.tr ? cf : cf + 2 * nx;               // cxm or cym
@@ -243,14 +221,14 @@ __global__ __launch_bounds__(BT_THREADS) void bt_solve_kernel(
     const bool local_in = mode & 1, local_out = mode & 2;
     const float2 *vr = vin + rhs * vin_stride + (local_in ? t.loc_off : 0);
     float2 *orr = out + rhs * out_stride + (local_out ? t.loc_off : 0);
-    float2 *hr = hist + rhs * hist_stride + t.loc_off;
-    const int r = tid;                       // row owned in the recurrence (r < b)
+    float4 *hr = reinterpret_cast<float4 *>(hist + rhs * hist_stride + t.loc_off);
+    const int r0 = 2 * rp;
 
-    auto vload = [&](int k) -> float2 {
+    auto vload = [&](int k, int r) -> float2 {
         const int idx = local_in ? bm.lidx(k, r) : bm.cy(k, r) * nx + bm.cx(k, r);
         return vr[idx];
     };
-    auto emit = [&](int k, float2 u) {
+    auto emit = [&](int k, int r, float2 u) {
         const int x = bm.cx(k, r), y = bm.cy(k, r);
         if (local_out) {
             orr[bm.lidx(k, r)] = u;
@@ -258,60 +236,86 @@ __global__ __launch_bounds__(BT_THREADS) void bt_solve_kernel(
             orr[(long long)y * nx + x] = u;
         }
     };
-
     const int nsteps = 2 * nb - 1;
     auto blk = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
 
-    // y_0 = v_0
-    if (r < b) ysh[r] = vload(0);
+    if (lead) {
+        ysh[r0] = vload(0, r0);
+        ysh[r0 + 1] = vload(0, r0 + 1);
+    }
     __syncthreads();
 
-    float4 pa[MAXC], pb[MAXC], pc[MAXC];
-    S.load(pa, blk(0));
-    if (nsteps > 1) S.load(pb, blk(1));
+    float4 pa[MAXJ], pb[MAXJ], pc[MAXJ];
+    bt_load<MAXJ>(pa, D + blk(0) * bb, b, half, rp, cg, on);
+    if (nsteps > 1) bt_load<MAXJ>(pb, D + blk(1) * bb, b, half, rp, cg, on);
 
-    auto step = [&](int s, const float4(&slot)[MAXC]) {
+    auto step = [&](int s, const float4(&slot)[MAXJ]) {
         const int k = blk(s);
         const bool fwd = s < nb;
-        float2 pre = make_float2(0.f, 0.f);
-        if (r < b) {
+        float4 pre = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lead) {
             if (fwd) {
-                if (k + 1 < nb) pre = vload(k + 1);
-            } else {
-                pre = hr[k * b + r];
-            }
-        }
-        S.matvec(slot, ysh, part);
-        __syncthreads();
-        if (r < b) {
-            float2 acc = part[r];
-            for (int g = 1; g < NG; ++g) acc = cadd(acc, part[g * b + r]);
-            if (fwd) {
-                hr[k * b + r] = acc;                               // w_k
                 if (k + 1 < nb) {
-                    ysh[r] = cfms(pre, clo_a[base + k + 1], acc);  // y_{k+1}
-                } else {
-                    emit(k, acc);                                  // u_{nb-1} = w_{nb-1}
-                    ysh[r] = acc;
+                    const float2 a = vload(k + 1, r0), c = vload(k + 1, r0 + 1);
+                    pre = make_float4(a.x, a.y, c.x, c.y);
                 }
             } else {
-                const float2 u = cfms(pre, chi_a[base + k], acc);   // u_k
-                emit(k, u);
-                ysh[r] = u;
+                pre = hr[(k * b + r0) >> 1];
+            }
+        }
+        float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < MAXJ; ++j) {
+            const int c = cg + BT_GROUP * j;
+            if (c < b) {
+                const float2 yc = ysh[c];
+                a0 = cfma(a0, make_float2(slot[j].x, slot[j].y), yc);
+                a1 = cfma(a1, make_float2(slot[j].z, slot[j].w), yc);
+            }
+        }
+#pragma unroll
+        for (int o = 1; o < BT_GROUP; o <<= 1) {
+            a0.x += __shfl_xor(a0.x, o, 64);
+            a0.y += __shfl_xor(a0.y, o, 64);
+            a1.x += __shfl_xor(a1.x, o, 64);
+            a1.y += __shfl_xor(a1.y, o, 64);
+        }
+        __syncthreads();     // every lane has read ysh for this step
+        if (lead) {
+            if (fwd) {
+                hr[(k * b + r0) >> 1] = make_float4(a0.x, a0.y, a1.x, a1.y);     // w_k
+                if (k + 1 < nb) {
+                    const float2 cl = clo_a[base + k + 1];
+                    ysh[r0] = cfms(make_float2(pre.x, pre.y), cl, a0);          // y_{k+1}
+                    ysh[r0 + 1] = cfms(make_float2(pre.z, pre.w), cl, a1);
+                } else {
+                    emit(k, r0, a0);                                            // u_{nb-1} = w_{nb-1}
+                    emit(k, r0 + 1, a1);
+                    ysh[r0] = a0;
+                    ysh[r0 + 1] = a1;
+                }
+            } else {
+                const float2 ch = chi_a[base + k];
+                const float2 u0 = cfms(make_float2(pre.x, pre.y), ch, a0);     // u_k
+                const float2 u1 = cfms(make_float2(pre.z, pre.w), ch, a1);
+                emit(k, r0, u0);
+                emit(k, r0 + 1, u1);
+                ysh[r0] = u0;
+                ysh[r0 + 1] = u1;
             }
         }
         __syncthreads();
     };
 
     for (int s = 0; s < nsteps; s += 3) {
-        if (s + 2 < nsteps) S.load(pc, blk(s + 2));
+        if (s + 2 < nsteps) bt_load<MAXJ>(pc, D + blk(s + 2) * bb, b, half, rp, cg, on);
         step(s, pa);
         if (s + 1 < nsteps) {
-            if (s + 3 < nsteps) S.load(pa, blk(s + 3));
+            if (s + 3 < nsteps) bt_load<MAXJ>(pa, D + blk(s + 3) * bb, b, half, rp, cg, on);
             step(s + 1, pb);
         }
         if (s + 2 < nsteps) {
-            if (s + 4 < nsteps) S.load(pb, blk(s + 4));
+            if (s + 4 < nsteps) bt_load<MAXJ>(pb, D + blk(s + 4) * bb, b, half, rp, cg, on);
             step(s + 2, pc);
         }
     }
@@ -322,18 +326,17 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_rh
                      long long vin_stride, float2 *out, long long out_stride, float2 *hist, long long hist_stride,
                      const int *active, int mode, int bmax) {
     dim3 grid(n_tiles, n_rhs);
-    const int half = bmax / 2;
-    const int ng = BT_THREADS / half;
-    const int need = (bmax + ng - 1) / ng;
-    if (need <= 6) {
-        hipLaunchKernelGGL(bt_solve_kernel<6>, grid, dim3(BT_THREADS), 0, s, tiles, n_src, dinv, dinv_wl_stride,
-                           coef, nx, ny, vin, vin_stride, out, out_stride, hist, hist_stride, active, mode);
-    } else if (need <= 10) {
-        hipLaunchKernelGGL(bt_solve_kernel<10>, grid, dim3(BT_THREADS), 0, s, tiles, n_src, dinv, dinv_wl_stride,
-                           coef, nx, ny, vin, vin_stride, out, out_stride, hist, hist_stride, active, mode);
+    const int threads = ((bmax / 2) * BT_GROUP + 63) / 64 * 64;
+    const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
+    if (maxj <= 9) {
+        hipLaunchKernelGGL(bt_solve_kernel<9>, grid, dim3(threads), 0, s, tiles, n_src, dinv, dinv_wl_stride, coef, nx,
+                           ny, vin, vin_stride, out, out_stride, hist, hist_stride, active, mode);
+    } else if (maxj <= 13) {
+        hipLaunchKernelGGL(bt_solve_kernel<13>, grid, dim3(threads), 0, s, tiles, n_src, dinv, dinv_wl_stride, coef,
+                           nx, ny, vin, vin_stride, out, out_stride, hist, hist_stride, active, mode);
     } else {
-        hipLaunchKernelGGL(bt_solve_kernel<16>, grid, dim3(BT_THREADS), 0, s, tiles, n_src, dinv, dinv_wl_stride,
-                           coef, nx, ny, vin, vin_stride, out, out_stride, hist, hist_stride, active, mode);
+        hipLaunchKernelGGL(bt_solve_kernel<16>, grid, dim3(threads), 0, s, tiles, n_src, dinv, dinv_wl_stride, coef,
+                           nx, ny, vin, vin_stride, out, out_stride, hist, hist_stride, active, mode);
     }
 }
 

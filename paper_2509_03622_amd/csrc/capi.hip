@@ -575,7 +575,7 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
     if (p->sub_solver == 1) {
         nn_precond(s, p->nw, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src, p->loc_total,
                    p->max_cells, v, z, active, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(),
-                   p->h, p->nx, p->ny);
+                   p->h, p->nx, p->ny, 0);
     } else
     launch_bt_solve(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src, p->d_dinv.as<float2>(),
                     p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, w.scratch.as<float2>(),
@@ -1387,6 +1387,16 @@ nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32
     if (st) return st;
     if (!rhs || !u) return fail(p->ctx, NOSDD_EINVAL, "null argument");
     const int nwl = (int)p->wl.size();
+    if (p->sub_solver == 1) {
+        st = ensure_nn(p, nwl, 1);
+        if (st) return st;
+        nn_precond(p->ctx->stream, p->nw, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, 1, p->loc_total,
+                   p->max_cells, (const float2 *)rhs, (float2 *)u, nullptr, p->d_eps.as<float>(),
+                   p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->h, p->nx, p->ny, 1);
+        HIPCHK(p->ctx, hipGetLastError());
+        HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
+        return NOSDD_OK;
+    }
     DevBuf scr;
     HIPCHK(p->ctx, scr.ensure((size_t)nwl * p->loc_total * sizeof(float2)));
     launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, 1, p->d_dinv.as<float2>(),

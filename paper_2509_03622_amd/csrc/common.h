@@ -163,9 +163,12 @@ struct NnWork {
     float *act0 = nullptr, *act1 = nullptr, *spec = nullptr, *X = nullptr, *Y = nullptr;
 };
 
+// Inner NN-FGMRES on every (tile, RHS) sample.  local == 0: v and z are
+// global [n_rhs][N] vectors (gather over the extended subdomain, core-only
+// scatter); local != 0: v and z are subdomain-local [n_rhs][loc_total].
 void nn_precond(hipStream_t st, const NnWork &nw, const TileDesc *tiles, int n_tiles, int n_rhs, int n_src,
                 long long loc_total, int max_cells, const float2 *v, float2 *z, const int *active, const float *eps,
-                const double2 *coef, const double *k0, double h, int nx, int ny);
+                const double2 *coef, const double *k0, double h, int nx, int ny, int local);
 // per-sample rms scalings for a plain network application on arbitrary vectors
 void nn_rms_scales(hipStream_t st, const FnoSample *smp, int S, const float2 *v, float *vscale, float *oscale);
 

@@ -27,10 +27,11 @@ __device__ __forceinline__ double bsum(double v, double *red) {
     return s;
 }
 
-// vloc[s][c] = v[rhs][global cell of c]   (s = rhs * n_tiles + tile)
+// vloc[s][c] = v[rhs][global cell of c]   (s = rhs * n_tiles + tile), or a
+// plain copy when v is already subdomain-local (local != 0).
 __global__ void loc_gather_kernel(const TileDesc *__restrict__ tiles, int n_tiles, const float2 *__restrict__ v,
                                   long long N, int nx, long long loc_total, float2 *__restrict__ vloc,
-                                  const int *__restrict__ active) {
+                                  const int *__restrict__ active, int local) {
     const int s = blockIdx.y;
     const int rhs = s / n_tiles, t = s - rhs * n_tiles;
     if (active && !active[rhs]) return;
@@ -38,8 +39,13 @@ __global__ void loc_gather_kernel(const TileDesc *__restrict__ tiles, int n_tile
     const int lx = T.x1 - T.x0, n = lx * (T.y1 - T.y0);
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
+    const long long dst = rhs * loc_total + T.loc_off + c;
+    if (local) {
+        vloc[dst] = v[dst];
+        return;
+    }
     const int y = c / lx, x = c - y * lx;
-    vloc[rhs * loc_total + T.loc_off + c] = v[rhs * N + (long long)(T.y0 + y) * nx + (T.x0 + x)];
+    vloc[dst] = v[rhs * N + (long long)(T.y0 + y) * nx + (T.x0 + x)];
 }
 
 // beta = ||b_i||; v_1 = b_i / beta; network scalings; sample flags.
@@ -205,13 +211,14 @@ __global__ __launch_bounds__(256) void loc_arnoldi_kernel(const TileDesc *__rest
     if (res <= tol || hn == 0.0) sact[s] = 0;
 }
 
-// u_i = Z y (y = R^-1 gamma over kstep columns); core cells -> global z.
+// u_i = Z y (y = R^-1 gamma over kstep columns); core cells -> global z, or
+// every cell -> the subdomain-local z (local != 0).
 __global__ __launch_bounds__(256) void loc_finish_kernel(const TileDesc *__restrict__ tiles, int n_tiles,
                                                          long long loc_total, long long vstride,
                                                          const float2 *__restrict__ Zin, int maxk,
                                                          const float2 *__restrict__ H, const float2 *__restrict__ gam,
                                                          const int *__restrict__ kstep, const int *__restrict__ active,
-                                                         float2 *__restrict__ zout, long long N, int nx) {
+                                                         float2 *__restrict__ zout, long long N, int nx, int local) {
     __shared__ float2 y[NN_MAXK];
     const int s = blockIdx.x;
     const int rhs = s / n_tiles, t = s - rhs * n_tiles;
@@ -236,22 +243,25 @@ __global__ __launch_bounds__(256) void loc_finish_kernel(const TileDesc *__restr
     for (int c = threadIdx.x; c < n; c += 256) {
         const int yy = c / lx, xx = c - yy * lx;
         const int gx = T.x0 + xx, gy = T.y0 + yy;
-        if (gx < T.cx0 || gx >= T.cx1 || gy < T.cy0 || gy >= T.cy1) continue;
+        if (!local && (gx < T.cx0 || gx >= T.cx1 || gy < T.cy0 || gy >= T.cy1)) continue;
         float2 u = make_float2(0.f, 0.f);
         for (int i = 0; i < k; ++i) u = cfma(u, y[i], Zin[i * vstride + off + c]);
-        zout[rhs * N + (long long)gy * nx + gx] = u;
+        if (local)
+            zout[off + c] = u;
+        else
+            zout[rhs * N + (long long)gy * nx + gx] = u;
     }
 }
 
 void nn_precond(hipStream_t st, const NnWork &nw, const TileDesc *tiles, int n_tiles, int n_rhs, int n_src,
                 long long loc_total, int max_cells, const float2 *v, float2 *z, const int *active, const float *eps,
-                const double2 *coef, const double *k0, double h, int nx, int ny) {
+                const double2 *coef, const double *k0, double h, int nx, int ny, int local) {
     const long long N = (long long)nx * ny;
     const int S = n_rhs * n_tiles;
     const long long vstride = (long long)n_rhs * loc_total;
     const int cblk = (max_cells + 255) / 256;
     hipLaunchKernelGGL(loc_gather_kernel, dim3(cblk, S), dim3(256), 0, st, tiles, n_tiles, v, N, nx, loc_total, nw.Vin,
-                       active);
+                       active, local);
     hipLaunchKernelGGL(loc_start_kernel, dim3(S), dim3(256), 0, st, tiles, n_tiles, loc_total, nw.Vin, active, nw.beta,
                        nw.vscale, nw.oscale, nw.sact, nw.kstep, nw.gam, nw.maxk);
     for (int k = 0; k < nw.steps; ++k) {
@@ -263,7 +273,7 @@ void nn_precond(hipStream_t st, const NnWork &nw, const TileDesc *tiles, int n_t
                            nw.w, k, nw.maxk, nw.tol, nw.H, nw.cs, nw.sn, nw.gam, nw.beta, nw.sact, nw.kstep);
     }
     hipLaunchKernelGGL(loc_finish_kernel, dim3(S), dim3(256), 0, st, tiles, n_tiles, loc_total, vstride, nw.Zin,
-                       nw.maxk, nw.H, nw.gam, nw.kstep, active, z, N, nx);
+                       nw.maxk, nw.H, nw.gam, nw.kstep, active, z, N, nx, local);
 }
 
 // vscale = 1/rms(v_s), oscale = rms(v_s) per sample (rms over the subdomain's cells)

@@ -1,0 +1,75 @@
+"""Failure handling through the C ABI (GPU context needed; no kernel is made to fail)."""
+import numpy as np
+import pytest
+
+from paper_2509_03622_amd.workloads import random_small
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx():
+    from paper_2509_03622_amd import nosdd
+    return nosdd, nosdd.Context(0, nosdd.torch_stream_handle())
+
+
+def test_invalid_partitions_are_rejected():
+    nosdd, ctx = _ctx()
+    eps = np.ones((128, 128), np.float32)
+    with pytest.raises(nosdd.NosddError) as e:
+        nosdd.Problem(ctx, eps, 0.05, 12, [64, 63], [64, 64], 8, [1.0])
+    assert e.value.status == -4
+    with pytest.raises(nosdd.NosddError) as e:
+        nosdd.Problem(ctx, eps, 0.05, 12, [8, 120], [64, 64], 8, [1.0])     # interface inside the PML
+    assert e.value.status == -4
+    with pytest.raises(nosdd.NosddError) as e:
+        nosdd.Problem(ctx, eps, 0.05, 12, [64, 64], [64, 64], 7, [1.0])     # odd overlap
+    assert e.value.status == -4
+    bad = eps.copy()
+    bad[3, 3] = np.nan
+    with pytest.raises(nosdd.NosddError) as e:
+        nosdd.Problem(ctx, bad, 0.05, 12, [64, 64], [64, 64], 8, [1.0])
+    assert e.value.status == -1
+
+
+def test_solve_before_setup_and_missing_weights():
+    nosdd, ctx = _ctx()
+    w = random_small(40, 128, 128, [64, 64], [64, 64])
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths)
+    with pytest.raises(nosdd.NosddError) as e:
+        P.solve(w.J())
+    assert e.value.status == -8
+    with pytest.raises(nosdd.NosddError) as e:
+        P.setup(sub_solver=1, nn_weights=None)
+    assert e.value.status == -7
+    with pytest.raises(nosdd.NosddError) as e:
+        P.setup(sub_solver=1, nn_weights="/nonexistent/weights.bin")
+    assert e.value.status == -7
+
+
+def test_unreachable_tolerance_reports_not_converged():
+    nosdd, ctx = _ctx()
+    w = random_small(41, 128, 128, [64, 64], [64, 64])
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths)
+    P.setup()
+    E, hist, iters, fin, st = P.solve(w.J(), tol=1e-6, max_iters=3)
+    assert st == 1 and int(iters[0, 0]) == 3 and fin[0, 0] > 1e-6
+    assert np.all(hist[0, 0, :3] > 0)
+
+
+def test_zero_source_gives_zero_field_without_iterations():
+    nosdd, ctx = _ctx()
+    w = random_small(42, 128, 128, [64, 64], [64, 64])
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths)
+    P.setup()
+    E, hist, iters, fin, st = P.solve(np.zeros((1, 128, 128), np.complex64))
+    assert st == 0 and int(iters[0, 0]) == 0 and np.all(E == 0)
+
+
+def test_repeated_solves_are_bit_identical():
+    nosdd, ctx = _ctx()
+    w = random_small(43, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.0, 1.3), k_coarse=1, block=16)
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths)
+    P.setup(k_coarse=1)
+    E1, h1, i1, f1, _ = P.solve(w.J())
+    E2, h2, i2, f2, _ = P.solve(w.J())
+    assert np.array_equal(E1, E2) and np.array_equal(h1, h2) and np.array_equal(i1, i2)

@@ -4,9 +4,15 @@
   FP32 truncated DFTs) against the oracle's NumPy forward pass in FP64 on the
   same BF16 weights: relative L2 error per subdomain below 3e-2 (BF16 rounding
   of activations at every layer).
-* The flexible outer GMRES with the NN-FGMRES subdomain solver converges to
-  the tolerance and the field matches the direct solution to 1e-5 whatever
-  the quality of the network (the network only changes the iteration count).
+* The inner NN-FGMRES (Algorithm 1, inference branch) on every subdomain
+  against the oracle's FP64 flexible GMRES preconditioned by the oracle's
+  forward pass: same iterate to 5e-2 (BF16 network), same residual reached,
+  and the relative-threshold exit taken at the same step.
+* With the trained network, the outer FGMRES with NN-FGMRES subdomain solves
+  converges to 1e-6 and the field matches the direct solution to 1e-5.
+* With a random (useless) network the outer solve still keeps its books: the
+  reported final residual is the explicit one and the history never rises
+  within a restart cycle.
 """
 import os
 
@@ -36,6 +42,18 @@ def random_weights(tmp_path_factory):
     path = str(tmp_path_factory.mktemp("w") / "random.bin")
     ft.write_weights(model, path)
     return path
+
+
+def _weights(random_weights):
+    return TRAINED if os.path.exists(TRAINED) else random_weights
+
+
+def _smooth_field(rng, ly, lx, passes=4):
+    u = rng.standard_normal((ly, lx)) + 1j * rng.standard_normal((ly, lx))
+    for _ in range(passes):
+        p = np.pad(u, 1, mode="edge")
+        u = (p[:-2, 1:-1] + p[2:, 1:-1] + p[1:-1, :-2] + p[1:-1, 2:] + 4 * u) / 8
+    return u
 
 
 def _problem(w, weights, steps=2, tol=0.1):
@@ -80,16 +98,81 @@ def test_network_application_matches_oracle(random_weights):
     assert worst < 3e-2, worst
 
 
-@pytest.mark.parametrize("weights", ["random", "trained"])
-def test_nn_fgmres_solve_reaches_direct_solution(weights, random_weights):
-    path = random_weights if weights == "random" else TRAINED
-    if not os.path.exists(path):
+@pytest.mark.parametrize("steps,tol", [(4, 0.0), (8, 0.9)])
+def test_inner_nn_fgmres_matches_oracle(steps, tol, random_weights):
+    from oracle.fgmres import fgmres_fixed
+    from oracle.partition import LocalProblem
+    path = _weights(random_weights)
+    lam = 1.05
+    w = random_small(33, 192, 192, [64] * 3, [64] * 3, wavelengths=(lam,), npml=12, block=16)
+    ctx, P = _problem(w, path, steps=steps, tol=tol)
+    nt, lc, ne, nc = P.sizes()
+    k0 = 2 * np.pi / lam
+    part = Partition(w.nx, w.ny, w.core_x, w.core_y, w.overlap, w.npml)
+    A = assemble_A(w.eps.astype(np.float64), lam, w.h, w.npml)
+    sc, _ = pml_stretch(w.nx, w.npml, w.pml_m, w.pml_lnR, k0, w.h)
+    wt = load_weights(path)
+    rng = np.random.default_rng(7)
+    rhs = np.zeros((1, lc), np.complex128)
+    locs = []
+    for t, tile in enumerate(part.tiles):
+        loc = LocalProblem(part, tile, A, w.eps.astype(np.float64), k0, w.h)
+        off = P.tile_info(t)[8]
+        b = loc.B @ _smooth_field(rng, tile.ly, tile.lx).ravel()
+        rhs[0, off:off + b.size] = b
+        locs.append((loc, off))
+    u = dev(np.zeros_like(rhs))
+    P.local_solve(dev(rhs), u)
+    u = host(u)[0]
+    for t, tile in enumerate(part.tiles):
+        loc, off = locs[t]
+        n = tile.lx * tile.ly
+        b = rhs[0, off:off + n]
+        mask = np.zeros((tile.ly, tile.lx))
+        mask[:, 0] += tile.iface["left"]
+        mask[:, -1] += tile.iface["right"]
+        mask[0, :] += tile.iface["bottom"]
+        mask[-1, :] += tile.iface["top"]
+        mask = np.minimum(mask, 1)
+        eps_t = w.eps[tile.y0:tile.y1, tile.x0:tile.x1].astype(np.float64)
+        isx, isy = 1 / sc[tile.x0:tile.x1], 1 / sc[tile.y0:tile.y1]
+
+        def M(r, tile=tile):
+            return fno_forward(wt, r.reshape(tile.ly, tile.lx), eps_t, k0 * w.h, isx, isy, mask).ravel()
+
+        ref, k, hist = fgmres_fixed(lambda x: loc.B @ x, b, M, tol, steps)
+        if tol > 0:
+            assert k < steps, (t, k, hist)          # the threshold exit is taken
+        ug = u[off:off + n]
+        res_g = np.linalg.norm(b - loc.B @ ug) / np.linalg.norm(b)
+        res_o = np.linalg.norm(b - loc.B @ ref) / np.linalg.norm(b)
+        assert rel(ug, ref) < 5e-2, (t, rel(ug, ref), res_g, res_o)
+        assert abs(res_g - res_o) <= 0.1 * res_o + 5e-3, (t, res_g, res_o)
+
+
+def test_nn_fgmres_solve_reaches_direct_solution():
+    if not os.path.exists(TRAINED):
         pytest.skip("trained weights not present")
     w = random_small(32, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.0,), npml=12, k_coarse=1, block=16)
-    ctx, P = _problem(w, path, steps=2, tol=0.1)
+    ctx, P = _problem(w, TRAINED, steps=8, tol=1e-2)
     E, hist, iters, fin, st = P.solve(w.J(), tol=1e-6, restart=30, max_iters=1500)
     assert st == 0, (iters, fin)
     A = assemble_A(w.eps, 1.0, w.h, w.npml)
     xs = solve_direct(A, source_rhs(w.J()[0], 1.0))
     assert rel(E[0, 0].ravel(), xs) < 1e-5
     print("NN-FGMRES outer iterations", int(iters[0, 0]))
+
+
+def test_outer_bookkeeping_with_random_network(random_weights):
+    w = random_small(34, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.0,), npml=12, k_coarse=1, block=16)
+    ctx, P = _problem(w, random_weights, steps=2, tol=0.1)
+    E, hist, iters, fin, st = P.solve(w.J(), tol=1e-6, restart=30, max_iters=90)
+    assert st in (0, 1)
+    A = assemble_A(w.eps, 1.0, w.h, w.npml)
+    b = source_rhs(w.J()[0], 1.0)
+    explicit = np.linalg.norm(b - A @ E[0, 0].ravel().astype(np.complex128)) / np.linalg.norm(b)
+    assert abs(fin[0, 0] - explicit) <= 1e-3 * explicit + 1e-7, (fin[0, 0], explicit)
+    h = hist[0, 0][: int(iters[0, 0])]
+    for c0 in range(0, h.size, 30):
+        cyc = h[c0:c0 + 30]
+        assert np.all(np.diff(cyc) <= 1e-6 * cyc[:-1] + 1e-12), cyc
