@@ -16,8 +16,8 @@
 // bt_solve_kernel (hot path): one workgroup per (tile, RHS) streams the
 // 2 nb - 1 blocks D_k^-1 from HBM, each once, and keeps the sequential
 // recurrence in LDS.  The D blocks do not depend on the data, so each thread
-// holds the blocks of the next two steps in registers while it multiplies the
-// current one (~80 KB per CU in flight with one workgroup per CU).  The gather of R_i v (input restricted to the
+// holds the blocks of the next steps in registers while it multiplies the
+// current one (~125 KB per CU in flight with one workgroup per CU).  The gather of R_i v (input restricted to the
 // extended tile, which carries the neighbours' Robin traces by the Robin
 // identity) and the core-only scatter (restricted additive Schwarz
 // prolongation) are fused into the same kernel.
@@ -180,28 +180,38 @@ void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_w
 // c = cg + 8 j.  Each lane loads one float4 (the two rows' entries of one
 // column) per column, the 8 lanes' partial sums are combined with three xor
 // shuffles inside the wave, and lane 0 of the group runs the recurrence for
-// its two rows.  One barrier per block step.
+// its two rows.
+//
+// Only the D_k^-1 stream touches HBM inside the recurrence: the subdomain RHS
+// is gathered into LDS up front (block-major, [k][r]), w_k overwrites v_k in
+// place during the forward sweep and is read back by the backward sweep, and
+// the inter-block couplings sit in LDS too.  The matrix-vector operand is
+// double-buffered, so each block step ends with a single barrier; D blocks
+// are prefetched NS - 1 steps ahead into a register ring.
 constexpr int BT_BMAX = 128;
 constexpr int BT_GROUP = 8;
 
+// Unconditional loads: lanes without a column (c >= b, or no row pair) read a
+// valid element of the same block instead, and their products are zeroed by
+// the zero padding of the operand vector.  Keeping every load unpredicated
+// lets the compiler wait only for the oldest slot of the ring.
 template <int MAXJ>
-__device__ __forceinline__ void bt_load(float4 (&slot)[MAXJ], const float2 *__restrict__ Dk, int b, int half, int rp,
-                                        int cg, bool on) {
+__device__ __forceinline__ void bt_load(float4 (&slot)[MAXJ], const float2 *__restrict__ Dk, const int (&off)[MAXJ]) {
     const float4 *D4 = reinterpret_cast<const float4 *>(Dk);
 #pragma unroll
-    for (int j = 0; j < MAXJ; ++j) {
-        const int c = cg + BT_GROUP * j;
-        slot[j] = (on && c < b) ? D4[c * half + rp] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int j = 0; j < MAXJ; ++j) slot[j] = D4[off[j]];
 }
 
-template <int MAXJ>
-__global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restrict__ tiles, int n_src, const float2 *__restrict__ dinv,
-                                long long dinv_wl_stride, const float2 *__restrict__ coef, int nx, int ny,
-                                const float2 *__restrict__ vin, long long vin_stride, float2 *__restrict__ out,
-                                long long out_stride, float2 *__restrict__ hist, long long hist_stride,
-                                const int *__restrict__ active, int mode) {
-    __shared__ float2 ysh[BT_BMAX];
+template <int MAXJ, int NS>
+__global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restrict__ tiles, int n_src,
+                                                       const float2 *__restrict__ dinv, long long dinv_wl_stride,
+                                                       const float2 *__restrict__ coef, int nx, int ny,
+                                                       const float2 *__restrict__ vin, long long vin_stride,
+                                                       float2 *__restrict__ out, long long out_stride,
+                                                       const int *__restrict__ active, int mode) {
+    extern __shared__ float2 vl[];                    // [nb][b]: v_k, then w_k
+    __shared__ float2 ysh[2][BT_BMAX];
+    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX];
     const int tile = blockIdx.x, rhs = blockIdx.y;
     if (active && !active[rhs]) return;
     const int wl = rhs / n_src;
@@ -213,7 +223,8 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     const bool lead = on && cg == 0;
     const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
     const long long bb = (long long)b * b;
-    const BlockMap bm{t.x0, t.y0, t.x1 - t.x0, t.tr};
+    const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
+    const BlockMap bm{t.x0, t.y0, lx, t.tr};
     const float2 *cf = coef + wl * coef_stride(nx, ny);
     const float2 *clo_a = t.tr ? cf : cf + 2 * nx;               // cxm or cym
     const float2 *chi_a = t.tr ? cf + nx : cf + 2 * nx + ny;      // cxp or cyp
@@ -221,13 +232,37 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     const bool local_in = mode & 1, local_out = mode & 2;
     const float2 *vr = vin + rhs * vin_stride + (local_in ? t.loc_off : 0);
     float2 *orr = out + rhs * out_stride + (local_out ? t.loc_off : 0);
-    float4 *hr = reinterpret_cast<float4 *>(hist + rhs * hist_stride + t.loc_off);
     const int r0 = 2 * rp;
 
-    auto vload = [&](int k, int r) -> float2 {
-        const int idx = local_in ? bm.lidx(k, r) : bm.cy(k, r) * nx + bm.cx(k, r);
-        return vr[idx];
-    };
+    // gather R_i v (row-major over the tile, coalesced) into block-major LDS
+    for (int e = tid; e < lx * ly; e += blockDim.x) {
+        const int yy = e / lx, xx = e - yy * lx;
+        const float2 val = local_in ? vr[e] : vr[(long long)(t.y0 + yy) * nx + (t.x0 + xx)];
+        vl[t.tr ? xx * b + yy : e] = val;
+    }
+    for (int k = tid; k < nb; k += blockDim.x) {
+        cl_s[k] = clo_a[base + k];
+        ch_s[k] = chi_a[base + k];
+    }
+    const int nsteps = 2 * nb - 1;
+    auto blk = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
+    int off[MAXJ];
+#pragma unroll
+    for (int j = 0; j < MAXJ; ++j) {
+        const int c = cg + BT_GROUP * j;
+        off[j] = (on && c < b) ? c * half + rp : 0;
+    }
+    for (int i = tid; i < 2 * BT_BMAX; i += blockDim.x) (&ysh[0][0])[i] = make_float2(0.f, 0.f);
+    float4 ring[NS][MAXJ];
+#pragma unroll
+    for (int i = 0; i < NS - 1; ++i) bt_load<MAXJ>(ring[i], D + blk(min(i, nsteps - 1)) * bb, off);
+    __syncthreads();
+    if (lead) {
+        ysh[0][r0] = vl[r0];
+        ysh[0][r0 + 1] = vl[r0 + 1];
+    }
+    __syncthreads();
+
     auto emit = [&](int k, int r, float2 u) {
         const int x = bm.cx(k, r), y = bm.cy(k, r);
         if (local_out) {
@@ -236,42 +271,15 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
             orr[(long long)y * nx + x] = u;
         }
     };
-    const int nsteps = 2 * nb - 1;
-    auto blk = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
-
-    if (lead) {
-        ysh[r0] = vload(0, r0);
-        ysh[r0 + 1] = vload(0, r0 + 1);
-    }
-    __syncthreads();
-
-    float4 pa[MAXJ], pb[MAXJ], pc[MAXJ];
-    bt_load<MAXJ>(pa, D + blk(0) * bb, b, half, rp, cg, on);
-    if (nsteps > 1) bt_load<MAXJ>(pb, D + blk(1) * bb, b, half, rp, cg, on);
-
     auto step = [&](int s, const float4(&slot)[MAXJ]) {
         const int k = blk(s);
-        const bool fwd = s < nb;
-        float4 pre = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lead) {
-            if (fwd) {
-                if (k + 1 < nb) {
-                    const float2 a = vload(k + 1, r0), c = vload(k + 1, r0 + 1);
-                    pre = make_float4(a.x, a.y, c.x, c.y);
-                }
-            } else {
-                pre = hr[(k * b + r0) >> 1];
-            }
-        }
+        const int p = s & 1;
         float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
 #pragma unroll
         for (int j = 0; j < MAXJ; ++j) {
-            const int c = cg + BT_GROUP * j;
-            if (c < b) {
-                const float2 yc = ysh[c];
-                a0 = cfma(a0, make_float2(slot[j].x, slot[j].y), yc);
-                a1 = cfma(a1, make_float2(slot[j].z, slot[j].w), yc);
-            }
+            const float2 yc = ysh[p][cg + BT_GROUP * j];           // zero beyond b
+            a0 = cfma(a0, make_float2(slot[j].x, slot[j].y), yc);
+            a1 = cfma(a1, make_float2(slot[j].z, slot[j].w), yc);
         }
 #pragma unroll
         for (int o = 1; o < BT_GROUP; o <<= 1) {
@@ -280,64 +288,79 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
             a1.x += __shfl_xor(a1.x, o, 64);
             a1.y += __shfl_xor(a1.y, o, 64);
         }
-        __syncthreads();     // every lane has read ysh for this step
         if (lead) {
-            if (fwd) {
-                hr[(k * b + r0) >> 1] = make_float4(a0.x, a0.y, a1.x, a1.y);     // w_k
+            float2 *slotk = vl + k * b + r0;
+            if (s < nb) {
+                slotk[0] = a0;                                              // w_k
+                slotk[1] = a1;
                 if (k + 1 < nb) {
-                    const float2 cl = clo_a[base + k + 1];
-                    ysh[r0] = cfms(make_float2(pre.x, pre.y), cl, a0);          // y_{k+1}
-                    ysh[r0 + 1] = cfms(make_float2(pre.z, pre.w), cl, a1);
+                    const float2 cl = cl_s[k + 1];
+                    ysh[p ^ 1][r0] = cfms(slotk[b], cl, a0);                // y_{k+1}
+                    ysh[p ^ 1][r0 + 1] = cfms(slotk[b + 1], cl, a1);
                 } else {
-                    emit(k, r0, a0);                                            // u_{nb-1} = w_{nb-1}
+                    emit(k, r0, a0);                                        // u_{nb-1} = w_{nb-1}
                     emit(k, r0 + 1, a1);
-                    ysh[r0] = a0;
-                    ysh[r0 + 1] = a1;
+                    ysh[p ^ 1][r0] = a0;
+                    ysh[p ^ 1][r0 + 1] = a1;
                 }
             } else {
-                const float2 ch = chi_a[base + k];
-                const float2 u0 = cfms(make_float2(pre.x, pre.y), ch, a0);     // u_k
-                const float2 u1 = cfms(make_float2(pre.z, pre.w), ch, a1);
+                const float2 ch = ch_s[k];
+                const float2 u0 = cfms(slotk[0], ch, a0);                   // u_k
+                const float2 u1 = cfms(slotk[1], ch, a1);
                 emit(k, r0, u0);
                 emit(k, r0 + 1, u1);
-                ysh[r0] = u0;
-                ysh[r0 + 1] = u1;
+                ysh[p ^ 1][r0] = u0;
+                ysh[p ^ 1][r0 + 1] = u1;
             }
         }
         __syncthreads();
     };
 
-    for (int s = 0; s < nsteps; s += 3) {
-        if (s + 2 < nsteps) bt_load<MAXJ>(pc, D + blk(s + 2) * bb, b, half, rp, cg, on);
-        step(s, pa);
-        if (s + 1 < nsteps) {
-            if (s + 3 < nsteps) bt_load<MAXJ>(pa, D + blk(s + 3) * bb, b, half, rp, cg, on);
-            step(s + 1, pb);
-        }
-        if (s + 2 < nsteps) {
-            if (s + 4 < nsteps) bt_load<MAXJ>(pb, D + blk(s + 4) * bb, b, half, rp, cg, on);
-            step(s + 2, pc);
+    // steady state: step s uses ring[s % NS] and refills the slot of step s - 1
+    // with the block of step s + NS - 1 (clamped at the end: a re-read)
+    int s0 = 0;
+    for (; s0 + NS <= nsteps; s0 += NS) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            bt_load<MAXJ>(ring[(i + NS - 1) % NS], D + blk(min(s0 + i + NS - 1, nsteps - 1)) * bb, off);
+            step(s0 + i, ring[i]);
         }
     }
+    // tail: fewer than NS steps left, their blocks are already in the ring
+#pragma unroll
+    for (int i = 0; i < NS - 1; ++i)
+        if (s0 + i < nsteps) step(s0 + i, ring[i]);
+}
+
+template <int MAXJ, int NS>
+static void bt_solve_launch(hipStream_t s, dim3 grid, int threads, size_t lds, const TileDesc *tiles, int n_src,
+                            const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
+                            const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
+                            const int *active, int mode) {
+    if (lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_kernel<MAXJ, NS>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((bt_solve_kernel<MAXJ, NS>), grid, dim3(threads), lds, s, tiles, n_src, dinv, dinv_wl_stride,
+                       coef, nx, ny, vin, vin_stride, out, out_stride, active, mode);
 }
 
 void launch_bt_solve(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_rhs, int n_src, const float2 *dinv,
                      long long dinv_wl_stride, const float2 *coef, int nx, int ny, const float2 *vin,
-                     long long vin_stride, float2 *out, long long out_stride, float2 *hist, long long hist_stride,
-                     const int *active, int mode, int bmax) {
+                     long long vin_stride, float2 *out, long long out_stride, const int *active, int mode, int bmax,
+                     int max_cells) {
     dim3 grid(n_tiles, n_rhs);
     const int threads = ((bmax / 2) * BT_GROUP + 63) / 64 * 64;
     const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
-    if (maxj <= 9) {
-        hipLaunchKernelGGL(bt_solve_kernel<9>, grid, dim3(threads), 0, s, tiles, n_src, dinv, dinv_wl_stride, coef, nx,
-                           ny, vin, vin_stride, out, out_stride, hist, hist_stride, active, mode);
-    } else if (maxj <= 13) {
-        hipLaunchKernelGGL(bt_solve_kernel<13>, grid, dim3(threads), 0, s, tiles, n_src, dinv, dinv_wl_stride, coef,
-                           nx, ny, vin, vin_stride, out, out_stride, hist, hist_stride, active, mode);
-    } else {
-        hipLaunchKernelGGL(bt_solve_kernel<16>, grid, dim3(threads), 0, s, tiles, n_src, dinv, dinv_wl_stride, coef,
-                           nx, ny, vin, vin_stride, out, out_stride, hist, hist_stride, active, mode);
-    }
+    const size_t lds = (size_t)max_cells * sizeof(float2);
+    if (maxj <= 9)
+        bt_solve_launch<9, 4>(s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin, vin_stride,
+                              out, out_stride, active, mode);
+    else if (maxj <= 13)
+        bt_solve_launch<13, 3>(s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin,
+                               vin_stride, out, out_stride, active, mode);
+    else
+        bt_solve_launch<16, 3>(s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin,
+                               vin_stride, out, out_stride, active, mode);
 }
 
 }  // namespace nosdd

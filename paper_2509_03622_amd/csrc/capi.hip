@@ -54,7 +54,7 @@ struct DevBuf {
 struct Workspace {
     int n_rhs = 0, m = 0, max_iters = 0, nblk = 0;
     long long N = 0;
-    DevBuf x, b, V, Z, w, scratch, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, bnorm2, bnorm, beta2,
+    DevBuf x, b, V, Z, w, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, bnorm2, bnorm, beta2,
         iters, kcyc, active, want, ones, reorth, inv_h, flags, hist, cd_, cc_;
 };
 
@@ -336,7 +336,6 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     HIPCHK(ctx, w.w.ensure(vec));
     HIPCHK(ctx, w.V.ensure(vec * (m + 1)));
     HIPCHK(ctx, w.Z.ensure(vec * m));
-    HIPCHK(ctx, w.scratch.ensure((size_t)n_rhs * p->loc_total * sizeof(float2)));
     HIPCHK(ctx, w.partial.ensure((size_t)n_rhs * nblk * 33 * sizeof(double2)));
     const size_t hsz = (size_t)n_rhs * (m + 1) * m * sizeof(float2);
     HIPCHK(ctx, w.H.ensure(hsz));
@@ -578,8 +577,8 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
                    p->h, p->nx, p->ny, 0);
     } else
     launch_bt_solve(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src, p->d_dinv.as<float2>(),
-                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, w.scratch.as<float2>(),
-                    p->loc_total, active, 0, p->bmax);
+                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, active, 0, p->bmax,
+                    p->max_cells);
     }
     if (wout == nullptr) return;
     {
@@ -713,15 +712,14 @@ nosdd_status coarse_setup(nosdd_problem *p) {
         }
     }
     // batched homogeneous probe solves on the GPU: F = B^-1 inj(X)
-    DevBuf d_rhs, d_F, d_scr;
+    DevBuf d_rhs, d_F;
     const size_t bytes = rhs.size() * sizeof(float2);
     HIPCHK(ctx, d_rhs.ensure(bytes));
     HIPCHK(ctx, d_F.ensure(bytes));
-    HIPCHK(ctx, d_scr.ensure(bytes));
     HIPCHK(ctx, hipMemcpyAsync(d_rhs.p, rhs.data(), bytes, hipMemcpyHostToDevice, s));
     launch_bt_solve(s, p->d_tiles.as<TileDesc>(), nt, nwl * K, K, p->d_dinv.as<float2>(), p->dinv_wl_stride,
-                    p->d_coef.as<float2>(), nx, ny, d_rhs.as<float2>(), LT, d_F.as<float2>(), LT,
-                    d_scr.as<float2>(), LT, nullptr, 3, p->bmax);
+                    p->d_coef.as<float2>(), nx, ny, d_rhs.as<float2>(), LT, d_F.as<float2>(), LT, nullptr, 3,
+                    p->bmax, p->max_cells);
     std::vector<float2> F(rhs.size());
     HIPCHK(ctx, hipMemcpyAsync(F.data(), d_F.p, bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
@@ -1153,6 +1151,11 @@ nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const flo
                 delete p;
                 return fail(ctx, NOSDD_EPARTITION, "extended subdomains need an even short side of at most 72 cells");
             }
+            if (t.nb > BT_NBMAX || lx * ly > BT_LDS_MAX_CELLS) {
+                delete p;
+                return fail(ctx, NOSDD_EPARTITION, "an extended subdomain is too large for an LDS-resident solve");
+            }
+            p->max_cells = std::max(p->max_cells, lx * ly);
             t.loc_off = loc;
             loc += (long long)lx * ly;
             t.dinv_off = dinv;
@@ -1245,8 +1248,6 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
                      p->dinv_wl_stride, p->bmax);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
-    p->max_cells = 0;
-    for (auto &t : p->tiles) p->max_cells = std::max(p->max_cells, (t.x1 - t.x0) * (t.y1 - t.y0));
     if (o->sub_solver == 1) {
         for (auto &t : p->tiles)
             if (t.x1 - t.x0 > 72 || t.y1 - t.y0 > 72)
@@ -1347,12 +1348,10 @@ nosdd_status nosdd_schwarz_sweep(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
     if (st) return st;
     if (!v || !z || n_src <= 0) return fail(p->ctx, NOSDD_EINVAL, "null argument or n_src <= 0");
     const int n_rhs = (int)p->wl.size() * n_src;
-    DevBuf scr;
-    HIPCHK(p->ctx, scr.ensure((size_t)n_rhs * p->loc_total * sizeof(float2)));
     const long long N = (long long)p->nx * p->ny;
     launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src,
                     p->d_dinv.as<float2>(), p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny,
-                    (const float2 *)v, N, (float2 *)z, N, scr.as<float2>(), p->loc_total, nullptr, 0, p->bmax);
+                    (const float2 *)v, N, (float2 *)z, N, nullptr, 0, p->bmax, p->max_cells);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
     return NOSDD_OK;
@@ -1397,11 +1396,9 @@ nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32
         HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
         return NOSDD_OK;
     }
-    DevBuf scr;
-    HIPCHK(p->ctx, scr.ensure((size_t)nwl * p->loc_total * sizeof(float2)));
     launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, 1, p->d_dinv.as<float2>(),
                     p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, (const float2 *)rhs, p->loc_total,
-                    (float2 *)u, p->loc_total, scr.as<float2>(), p->loc_total, nullptr, 3, p->bmax);
+                    (float2 *)u, p->loc_total, nullptr, 3, p->bmax, p->max_cells);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
     return NOSDD_OK;

@@ -80,10 +80,13 @@ void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_w
 
 // mode bit 0: input is a packed local vector (else gathered from a global vector)
 // mode bit 1: output is a packed local vector (else core cells scattered to a global vector)
+// Subdomain LU solves; the tile's RHS lives in max_cells * 8 bytes of LDS.
+constexpr int BT_NBMAX = 256;                                // longest tile side
+constexpr int BT_LDS_MAX_CELLS = 15360;                      // 120 KB of LDS
 void launch_bt_solve(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_rhs, int n_src,
                      const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
                      const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
-                     float2 *hist, long long hist_stride, const int *active, int mode, int bmax);
+                     const int *active, int mode, int bmax, int max_cells);
 
 void launch_robin_trace(hipStream_t s, const int4 *entries, int n_entries, const float *eps,
                         const float *k0, float h, int nx, int ny, const float2 *x, float2 *g,
