@@ -194,12 +194,29 @@ constexpr int BT_GROUP = 8;
 // Unconditional loads: lanes without a column (c >= b, or no row pair) read a
 // valid element of the same block instead, and their products are zeroed by
 // the zero padding of the operand vector.  Keeping every load unpredicated
-// lets the compiler wait only for the oldest slot of the ring.
+// lets the compiler wait only for the oldest slot of the ring; the block base
+// is wave-uniform and the per-lane part a 32-bit byte offset, so the loads
+// take the scalar-base addressing form.
 template <int MAXJ>
-__device__ __forceinline__ void bt_load(float4 (&slot)[MAXJ], const float2 *__restrict__ Dk, const int (&off)[MAXJ]) {
-    const float4 *D4 = reinterpret_cast<const float4 *>(Dk);
+__device__ __forceinline__ void bt_load(float4 (&slot)[MAXJ], const char *__restrict__ blkbase,
+                                        const unsigned (&off)[MAXJ]) {
 #pragma unroll
-    for (int j = 0; j < MAXJ; ++j) slot[j] = D4[off[j]];
+    for (int j = 0; j < MAXJ; ++j) slot[j] = *reinterpret_cast<const float4 *>(blkbase + off[j]);
+}
+
+// Cross-lane moves inside groups of 8 lanes (DPP): swap neighbours, swap
+// pairs, mirror the half-row of 8 lanes.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;    // row_half_mirror
+__device__ __forceinline__ float group8_sum(float v) {
+    v += dpp<DPP_QUAD_XOR1>(v);
+    v += dpp<DPP_QUAD_XOR2>(v);
+    return v + dpp<DPP_HALF_MIRROR>(v);
 }
 
 template <int MAXJ, int NS>
@@ -220,11 +237,9 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     const int tid = threadIdx.x;
     const int rp = tid / BT_GROUP, cg = tid - rp * BT_GROUP;
     const bool on = rp < half;
-    const bool lead = on && cg == 0;
     const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
-    const long long bb = (long long)b * b;
+    const long long bbytes = (long long)b * b * sizeof(float2);
     const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
-    const BlockMap bm{t.x0, t.y0, lx, t.tr};
     const float2 *cf = coef + wl * coef_stride(nx, ny);
     const float2 *clo_a = t.tr ? cf : cf + 2 * nx;               // cxm or cym
     const float2 *chi_a = t.tr ? cf + nx : cf + 2 * nx + ny;      // cxp or cyp
@@ -232,7 +247,6 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     const bool local_in = mode & 1, local_out = mode & 2;
     const float2 *vr = vin + rhs * vin_stride + (local_in ? t.loc_off : 0);
     float2 *orr = out + rhs * out_stride + (local_out ? t.loc_off : 0);
-    const int r0 = 2 * rp;
 
     // gather R_i v (row-major over the tile, coalesced) into block-major LDS
     for (int e = tid; e < lx * ly; e += blockDim.x) {
@@ -246,72 +260,85 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     }
     const int nsteps = 2 * nb - 1;
     auto blk = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
-    int off[MAXJ];
+    unsigned off[MAXJ];
 #pragma unroll
     for (int j = 0; j < MAXJ; ++j) {
         const int c = cg + BT_GROUP * j;
-        off[j] = (on && c < b) ? c * half + rp : 0;
+        off[j] = (on && c < b) ? (unsigned)(c * half + rp) * 16u : 0u;
     }
     for (int i = tid; i < 2 * BT_BMAX; i += blockDim.x) (&ysh[0][0])[i] = make_float2(0.f, 0.f);
+    const char *Dc = reinterpret_cast<const char *>(D);
     float4 ring[NS][MAXJ];
 #pragma unroll
-    for (int i = 0; i < NS - 1; ++i) bt_load<MAXJ>(ring[i], D + blk(min(i, nsteps - 1)) * bb, off);
-    __syncthreads();
-    if (lead) {
-        ysh[0][r0] = vl[r0];
-        ysh[0][r0 + 1] = vl[r0 + 1];
+    for (int i = 0; i < NS - 1; ++i) bt_load<MAXJ>(ring[i], Dc + blk(min(i, nsteps - 1)) * bbytes, off);
+
+    // lanes 0 and 1 of each group carry the recurrence for rows r0 and r0 + 1
+    const int myr = 2 * rp + (cg & 1);
+    const bool wr = on && cg < 2;
+    // output index of row myr in block k: obase + k * kstride; the block index
+    // range [kc0, kc1) and okr select the core rows (all rows for local output)
+    long long obase;
+    int kstride, kc0, kc1;
+    bool okr;
+    if (local_out) {
+        obase = t.tr ? (long long)myr * lx : myr;
+        kstride = t.tr ? 1 : lx;
+        kc0 = 0;
+        kc1 = nb;
+        okr = true;
+    } else if (t.tr) {
+        obase = (long long)(t.y0 + myr) * nx + t.x0;
+        kstride = 1;
+        kc0 = t.cx0 - t.x0;
+        kc1 = t.cx1 - t.x0;
+        okr = t.y0 + myr >= t.cy0 && t.y0 + myr < t.cy1;
+    } else {
+        obase = (long long)t.y0 * nx + t.x0 + myr;
+        kstride = nx;
+        kc0 = t.cy0 - t.y0;
+        kc1 = t.cy1 - t.y0;
+        okr = t.x0 + myr >= t.cx0 && t.x0 + myr < t.cx1;
     }
+    const bool emit_lane = wr && okr;
+    __syncthreads();
+    if (wr) ysh[0][myr] = vl[myr];
     __syncthreads();
 
-    auto emit = [&](int k, int r, float2 u) {
-        const int x = bm.cx(k, r), y = bm.cy(k, r);
-        if (local_out) {
-            orr[bm.lidx(k, r)] = u;
-        } else if (x >= t.cx0 && x < t.cx1 && y >= t.cy0 && y < t.cy1) {
-            orr[(long long)y * nx + x] = u;
-        }
-    };
     auto step = [&](int s, const float4(&slot)[MAXJ]) {
         const int k = blk(s);
         const int p = s & 1;
-        float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+        const bool fwd = s < nb;
+        // the recurrence's other operand does not depend on this step's product
+        float2 pre = make_float2(0.f, 0.f);
+        if (wr) pre = vl[min(fwd ? k + 1 : k, nb - 1) * b + myr];
+        float2 a0, a1;
+        {
+            const float2 yc = ysh[p][cg];
+            a0 = cmul(make_float2(slot[0].x, slot[0].y), yc);
+            a1 = cmul(make_float2(slot[0].z, slot[0].w), yc);
+        }
 #pragma unroll
-        for (int j = 0; j < MAXJ; ++j) {
+        for (int j = 1; j < MAXJ; ++j) {
             const float2 yc = ysh[p][cg + BT_GROUP * j];           // zero beyond b
             a0 = cfma(a0, make_float2(slot[j].x, slot[j].y), yc);
             a1 = cfma(a1, make_float2(slot[j].z, slot[j].w), yc);
         }
-#pragma unroll
-        for (int o = 1; o < BT_GROUP; o <<= 1) {
-            a0.x += __shfl_xor(a0.x, o, 64);
-            a0.y += __shfl_xor(a0.y, o, 64);
-            a1.x += __shfl_xor(a1.x, o, 64);
-            a1.y += __shfl_xor(a1.y, o, 64);
-        }
-        if (lead) {
-            float2 *slotk = vl + k * b + r0;
-            if (s < nb) {
-                slotk[0] = a0;                                              // w_k
-                slotk[1] = a1;
-                if (k + 1 < nb) {
-                    const float2 cl = cl_s[k + 1];
-                    ysh[p ^ 1][r0] = cfms(slotk[b], cl, a0);                // y_{k+1}
-                    ysh[p ^ 1][r0 + 1] = cfms(slotk[b + 1], cl, a1);
-                } else {
-                    emit(k, r0, a0);                                        // u_{nb-1} = w_{nb-1}
-                    emit(k, r0 + 1, a1);
-                    ysh[p ^ 1][r0] = a0;
-                    ysh[p ^ 1][r0 + 1] = a1;
-                }
+        a0.x = group8_sum(a0.x);
+        a0.y = group8_sum(a0.y);
+        a1.x = group8_sum(a1.x);
+        a1.y = group8_sum(a1.y);
+        const float2 a = (cg & 1) ? a1 : a0;
+        if (wr) {
+            float2 y;
+            if (fwd) {
+                vl[k * b + myr] = a;                                        // w_k
+                y = (k + 1 < nb) ? cfms(pre, cl_s[k + 1], a) : a;           // y_{k+1}, or u_{nb-1} = w_{nb-1}
+                if (k + 1 == nb && emit_lane && k >= kc0 && k < kc1) orr[obase + (long long)k * kstride] = a;
             } else {
-                const float2 ch = ch_s[k];
-                const float2 u0 = cfms(slotk[0], ch, a0);                   // u_k
-                const float2 u1 = cfms(slotk[1], ch, a1);
-                emit(k, r0, u0);
-                emit(k, r0 + 1, u1);
-                ysh[p ^ 1][r0] = u0;
-                ysh[p ^ 1][r0 + 1] = u1;
+                y = cfms(pre, ch_s[k], a);                                  // u_k
+                if (emit_lane && k >= kc0 && k < kc1) orr[obase + (long long)k * kstride] = y;
             }
+            ysh[p ^ 1][myr] = y;
         }
         __syncthreads();
     };
@@ -322,7 +349,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     for (; s0 + NS <= nsteps; s0 += NS) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-            bt_load<MAXJ>(ring[(i + NS - 1) % NS], D + blk(min(s0 + i + NS - 1, nsteps - 1)) * bb, off);
+            bt_load<MAXJ>(ring[(i + NS - 1) % NS], Dc + blk(min(s0 + i + NS - 1, nsteps - 1)) * bbytes, off);
             step(s0 + i, ring[i]);
         }
     }
