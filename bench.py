@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "time to 1e-6 residual per global solve; subdomain solves/s; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 PROFILE_PMC = os.path.join(ROOT, "profiles", "bt_solve_blocks512_pmc.txt")
+NN_WEIGHTS = os.path.join(ROOT, "paper_2509_03622_amd", "weights", "fno_c64_m16_l4.bin")
 
 
 def tile_geometry(w):
@@ -142,6 +143,63 @@ def cpu_baseline(w, iters):
             "ms_per_iteration": 1e3 * dt / max(it, 1)}
 
 
+def timed_solve(torch, P, J, E, max_iters, reps=1):
+    """One untimed solve, then `reps` timed ones; returns seconds per solve,
+    iterations, final residuals, status and per-class kernel ms per solve."""
+    P.solve_device(J, E, max_iters=max_iters)
+    torch.cuda.synchronize()
+    P.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hist, iters, fin, st = P.solve_device(J, E, max_iters=max_iters)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    P.profile(False)
+    ms_k, launches, units = P.kernel_times()
+    return dt, iters, fin, st, [round(float(v) / reps, 2) for v in ms_k]
+
+
+def nn_compare(torch, nosdd, workload, configs, max_iters, check):
+    """Time to a 1e-6 residual of the exact-LU form and of the NN-FGMRES form
+    (BF16 network inside FP32 inner FGMRES) on the same problem and GPU."""
+    from paper_2509_03622_amd.workloads import WORKLOADS
+    w = WORKLOADS[workload]()
+    dev = torch.device("cuda:0")
+    J = torch.from_numpy(w.J()).to(dev)
+    E = torch.zeros((len(w.wavelengths), len(w.sources), w.ny, w.nx), dtype=torch.complex64, device=dev)
+    ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+    xs = None
+    if check:
+        from oracle.fdfd import assemble_A, solve_direct, source_rhs
+        lam = w.wavelengths[0]
+        xs = solve_direct(assemble_A(w.eps, lam, w.h, w.npml, w.pml_m, w.pml_lnR), source_rhs(w.J()[0], lam))
+    rows = []
+    for kc, solver, steps, tol in configs:
+        P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+        t0 = time.perf_counter()
+        if solver == "lu":
+            P.setup(k_coarse=kc, k_trial=w.k_trial)
+        else:
+            P.setup(k_coarse=kc, k_trial=w.k_trial, sub_solver=1, nn_weights=NN_WEIGHTS, inner_max=steps,
+                    inner_tol=tol)
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        dt, iters, fin, st, ms_k = timed_solve(torch, P, J, E, max_iters)
+        row = {"solver": solver, "k_coarse": kc, "inner_max": steps, "inner_tol": tol,
+               "time_to_tol_ms": round(1e3 * dt, 2), "outer_iterations": int(iters.ravel()[0]),
+               "final_rel_residual": float(f"{float(fin.ravel()[0]):.3e}"), "status": int(st),
+               "setup_ms": round(setup_ms, 1),
+               "kernel_ms": dict(zip(("local_solve", "operator", "arnoldi", "coarse"), ms_k))}
+        if xs is not None:
+            e = E[0, 0].cpu().numpy().ravel()
+            row["field_rel_err_vs_fp64_direct"] = float(f"{np.linalg.norm(e - xs) / np.linalg.norm(xs):.3e}")
+        rows.append(row)
+        print(f"[bench] {row}", file=sys.stderr, flush=True)
+        P.close()
+    ctx.close()
+    return w, rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +210,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 direct-solve field check")
     ap.add_argument("--no-stencil", action="store_true", help="skip the operator/residual roofline measurement")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (calibration of the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--nn-compare", action="store_true",
+                    help="instead of the default line: exact-LU against NN-FGMRES subdomain solves, time to 1e-6 "
+                         "on the 1024 x 1024 workload (16 x 16 subdomains)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
@@ -162,6 +226,34 @@ def main():
 
     from paper_2509_03622_amd import nosdd
     from paper_2509_03622_amd.workloads import WORKLOADS
+
+    if a.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy_probe", "bytes_read_per_copy": src.numel() * 4,
+                          "bytes_written_per_copy": dst.numel() * 4, "copies": 3}), flush=True)
+        return
+    if a.nn_compare:
+        torch.cuda.init()
+        configs = [(kc, "lu", 0, 0.0) for kc in (0, 1)]
+        configs += [(kc, "nn", n, t) for kc in (1, 0) for n, t in ((1, 0.1), (2, 0.1), (4, 0.1), (4, 0.01),
+                                                                 (8, 0.01))]
+        w, rows = nn_compare(torch, nosdd, "blocks1024", configs, max_iters=3000, check=not a.no_check)
+        lu = min((r for r in rows if r["solver"] == "lu" and r["status"] == 0), key=lambda r: r["time_to_tol_ms"])
+        nn = [r for r in rows if r["solver"] == "nn" and r["status"] == 0]
+        best = min(nn, key=lambda r: r["time_to_tol_ms"]) if nn else None
+        print(json.dumps({"metric": METRIC, "mode": "nn_vs_lu", "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "cores": "16x16 of 64",
+                                     "overlap": w.overlap, "wavelengths": w.wavelengths, "tol": 1e-6,
+                                     "network": "FNO C=64, 16 modes, 4 layers, BF16 MFMA, FP32 accumulation"},
+                          "best_lu_ms": lu["time_to_tol_ms"],
+                          "best_nn_ms": best["time_to_tol_ms"] if best else None,
+                          "nn_over_lu_time": round(best["time_to_tol_ms"] / lu["time_to_tol_ms"], 3) if best else None,
+                          "rows": rows}), flush=True)
+        return
 
     w = WORKLOADS[a.workload]()
     n_wl, n_src = len(w.wavelengths), len(w.sources)
@@ -183,7 +275,8 @@ def main():
     for _ in range(a.warmup):
         hist, iters, fin, st = P.solve_device(J, E)
     torch.cuda.synchronize()
-    print(f"[bench] warmup done: iterations per RHS {iters.ravel().tolist()}", file=sys.stderr, flush=True)
+    if a.warmup > 0:
+        print(f"[bench] warmup done: iterations per RHS {iters.ravel().tolist()}", file=sys.stderr, flush=True)
 
     P.profile(True)
     tot_units = 0
