@@ -278,7 +278,7 @@ def main():
     if a.warmup > 0:
         print(f"[bench] warmup done: iterations per RHS {iters.ravel().tolist()}", file=sys.stderr, flush=True)
 
-    P.profile(True)
+    # timed region: per-step graphs replayed, no profiling events
     tot_units = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -287,9 +287,14 @@ def main():
         tot_units += int(iters.sum()) * len(tiles)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    print(f"[bench] timed {a.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # kernel classes: one more solve, launched kernel by kernel with HIP events
+    # on the library stream around every launch group
+    P.profile(True)
+    P.solve_device(J, E)
+    torch.cuda.synchronize()
     P.profile(False)
     ms_k, launches, units = P.kernel_times()
-    print(f"[bench] timed {a.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
     ms_per_step = 1e3 * elapsed / a.steps
     value = tot_units / elapsed
@@ -304,7 +309,7 @@ def main():
                 "avg_launch_us": round(1e3 * lu_ms / max(launches[0], 1), 2),
                 "algorithmic_bytes_per_launch": round(per_launch),
                 "launches": int(launches[0])}
-    share = {k: round(float(v) / a.steps, 3) for k, v in zip(("local_solve", "operator", "arnoldi", "coarse"), ms_k)}
+    share = {k: round(float(v), 3) for k, v in zip(("local_solve", "operator", "arnoldi", "coarse"), ms_k)}
     out = {"metric": METRIC, "value": round(value, 1), "unit": "subdomain solves/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",

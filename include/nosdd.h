@@ -202,6 +202,16 @@ nosdd_status nosdd_coarse_basis(const nosdd_problem *p, int wl, nosdd_c32 *phi, 
 nosdd_status nosdd_profile(nosdd_problem *p, int enable);
 nosdd_status nosdd_kernel_times(const nosdd_problem *p, double ms[4], long long launches[4], long long units[4]);
 
+/* Launch mode of the solve loop.  Enabled (the default): every Arnoldi step
+ * of a restart cycle (subdomain solves, operator, coarse correction,
+ * Gram-Schmidt passes, Givens) is captured once into a HIP graph on a private
+ * stream and replayed on the context stream; convergence is read from pinned
+ * host memory two steps behind, so the host never blocks the device inside a
+ * cycle.  Graphs are rebuilt when buffers, sizes or solve options change.
+ * Disabled, or while nosdd_profile is on: the same kernels are launched one
+ * by one.  Results are bit-identical in both modes. */
+nosdd_status nosdd_graphs(nosdd_problem *p, int enable);
+
 /* Timing of the last solve (ms, GPU events): setup, total solve, iterations. */
 nosdd_status nosdd_last_timing(const nosdd_problem *p, double *setup_ms, double *solve_ms,
                                int *outer_iters);

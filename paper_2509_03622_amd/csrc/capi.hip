@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -26,10 +27,15 @@ struct nosdd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t cap_stream = nullptr;     // private stream for graph capture (created on first use)
     std::string err;
 };
 
 namespace {
+
+// Bumped on every device (re)allocation: captured graphs bake buffer addresses
+// into their kernel arguments and are rebuilt when this changes.
+std::atomic<long long> g_alloc_gen{0};
 
 struct DevBuf {
     void *p = nullptr;
@@ -43,6 +49,7 @@ struct DevBuf {
     hipError_t ensure(size_t n) {
         if (n <= bytes && p) return hipSuccess;
         release();
+        ++g_alloc_gen;
         hipError_t e = hipMalloc(&p, n ? n : 16);
         if (e == hipSuccess) bytes = n;
         return e;
@@ -100,8 +107,24 @@ struct nosdd_problem {
     int ev_next = 0;
     double prof_ms[4] = {0, 0, 0, 0};
     long long prof_launch[4] = {0, 0, 0, 0}, prof_units[4] = {0, 0, 0, 0};
+    // one captured graph per Arnoldi step j of a restart cycle (replayed every cycle)
+    bool use_graphs = true;
+    std::vector<hipGraphExec_t> gexec;
+    std::vector<long long> gkey;
+    int *h_flags = nullptr;                       // pinned: active flags of steps of either parity
+    int h_flags_n = 0;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    void drop_graphs() {
+        for (hipGraphExec_t g : gexec) (void)hipGraphExecDestroy(g);
+        gexec.clear();
+        gkey.clear();
+    }
     ~nosdd_problem() {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        drop_graphs();
+        for (hipEvent_t e : gev)
+            if (e) (void)hipEventDestroy(e);
+        if (h_flags) (void)hipHostFree(h_flags);
     }
 };
 
@@ -865,6 +888,55 @@ nosdd_status coarse_setup(nosdd_problem *p) {
     return NOSDD_OK;
 }
 
+// Capture (or reuse) one graph per Arnoldi step j of a restart cycle.  The
+// graphs bake in buffer addresses, sizes and the solve options, so they are
+// keyed on those and on the allocation generation.  Each graph ends with a
+// copy of the active flags into pinned host memory (one buffer per parity of
+// j), which the host reads two steps later.  Only kernels and that copy are
+// captured: no memsets.
+template <class Step>
+nosdd_status ensure_graphs(nosdd_problem *p, int n_rhs, int n_src, int m, const nosdd_solve_opts *o, Step &step) {
+    nosdd_ctx *ctx = p->ctx;
+    Workspace &w = p->ws;
+    if (p->h_flags_n < n_rhs) {
+        if (p->h_flags) (void)hipHostFree(p->h_flags);
+        p->h_flags = nullptr;
+        p->h_flags_n = 0;
+        HIPCHK(ctx, hipHostMalloc((void **)&p->h_flags, 2 * (size_t)n_rhs * sizeof(int), hipHostMallocDefault));
+        p->h_flags_n = n_rhs;
+        ++g_alloc_gen;
+    }
+    for (hipEvent_t &e : p->gev)
+        if (!e) HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    long long tolbits = 0;
+    std::memcpy(&tolbits, &o->tol, sizeof(double));
+    const std::vector<long long> key = {g_alloc_gen.load(), n_rhs, n_src, m, o->max_iters, tolbits,
+                                        (long long)(intptr_t)p->h_flags};
+    if (key == p->gkey && (int)p->gexec.size() == m) return NOSDD_OK;
+    p->drop_graphs();
+    if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = ctx->cap_stream;
+    for (int j = 0; j < m; ++j) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        step(cs, j, n_rhs);
+        hipError_t e = hipMemcpyAsync(p->h_flags + (j & 1) * n_rhs, w.active.p, n_rhs * sizeof(int),
+                                      hipMemcpyDeviceToHost, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            p->drop_graphs();
+            return fail(ctx, NOSDD_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+        }
+        p->gexec.push_back(ge);
+    }
+    p->gkey = key;
+    return NOSDD_OK;
+}
+
 nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const nosdd_solve_opts *o, const float2 *x0_dev,
                         float2 *E_dev, float *resid_hist, int *iters_out, float *final_out) {
     nosdd_ctx *ctx = p->ctx;
@@ -937,6 +1009,36 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     HIPCHK(ctx, hipHostMalloc((void **)&h_act, n_rhs * sizeof(int) * 2, hipHostMallocDefault));
     nosdd_status result = NOSDD_OK;
     int total_outer = 0;
+    const int *active = w.active.as<int>();
+    // One Arnoldi step j: z_j = M^-1 v_j, w = A z_j, classical Gram-Schmidt
+    // against v_0..v_j with a second pass where the DGKS test asks for it,
+    // Givens rotation and residual estimate, v_{j+1} = w / h_{j+1,j}.  Every
+    // argument is fixed for the solve, so the step can be captured in a graph.
+    auto step = [&](hipStream_t st, int j, int n_live_) {
+        float2 *Vj = V + j * vstride, *Vn = V + (j + 1) * vstride, *Zj = Z + j * vstride;
+        precond(p, st, Vj, Zj, wv, n_src, n_rhs, active, n_live_);
+        ProfScope arn(p, 2, n_live_);
+        double2 *part = w.partial.as<double2>();
+        const int *ro = w.reorth.as<int>();
+        const float *ih = w.inv_h.as<float>();
+        launch_cgs_dots(st, V, vstride, j + 1, wv, N, n_rhs, active, part, nblk);
+        launch_cgs_reduce(st, part, nblk, j + 1, n_rhs, active, j, 1, nullptr, ga);
+        launch_cgs_update(st, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, j, part, nblk);
+        launch_cgs_reduce(st, part, nblk, 0, n_rhs, nullptr, j, 2, nullptr, ga);
+        launch_cgs_dots(st, V, vstride, j + 1, Vn, N, n_rhs, ro, part, nblk);
+        launch_cgs_reduce(st, part, nblk, j + 1, n_rhs, ro, j, 3, nullptr, ga);
+        launch_cgs_update(st, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, j, part, nblk);
+        launch_cgs_reduce(st, part, nblk, 0, n_rhs, ro, j, 4, nullptr, ga);
+        launch_scale(st, Vn, N, n_rhs, active, ih);
+    };
+    const bool graphs = p->use_graphs && !p->prof;
+    if (graphs) {
+        nosdd_status gs = ensure_graphs(p, n_rhs, n_src, m, o, step);
+        if (gs != NOSDD_OK) {
+            (void)hipHostFree(h_act);
+            return gs;
+        }
+    }
     for (;;) {
         // explicit residual r = b - A x (FP64) into w, beta^2
         {
@@ -965,35 +1067,34 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         HIPCHK(ctx, hipMemsetAsync(w.H.p, 0, (size_t)n_rhs * (m + 1) * m * sizeof(float2), s));
         launch_start_cycle(s, V, wv, w.beta2.as<double>(), w.bnorm.as<float>(), w.gam.as<float2>(), m,
                            w.kcyc.as<int>(), w.active.as<int>(), w.want.as<int>(), N, n_rhs);
-        const int *active = w.active.as<int>();
         int n_live = 0;
         for (int r = 0; r < n_rhs; ++r) n_live += want[r];
-        for (int j = 0; j < m; ++j) {
-            float2 *Vj = V + j * vstride, *Vn = V + (j + 1) * vstride, *Zj = Z + j * vstride;
-            precond(p, s, Vj, Zj, wv, n_src, n_rhs, active, n_live);
-            // classical Gram-Schmidt against V_0..V_j, selective second pass
-            {
-                ProfScope arn(p, 2, n_live);
-                double2 *part = w.partial.as<double2>();
-                const int *ro = w.reorth.as<int>();
-                const float *ih = w.inv_h.as<float>();
-                // classical Gram-Schmidt; a second pass only where the DGKS test asks for it
-                launch_cgs_dots(s, V, vstride, j + 1, wv, N, n_rhs, active, part, nblk);
-                launch_cgs_reduce(s, part, nblk, j + 1, n_rhs, active, j, 1, nullptr, ga);
-                launch_cgs_update(s, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, j, part, nblk);
-                launch_cgs_reduce(s, part, nblk, 0, n_rhs, nullptr, j, 2, nullptr, ga);
-                launch_cgs_dots(s, V, vstride, j + 1, Vn, N, n_rhs, ro, part, nblk);
-                launch_cgs_reduce(s, part, nblk, j + 1, n_rhs, ro, j, 3, nullptr, ga);
-                launch_cgs_update(s, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, j, part, nblk);
-                launch_cgs_reduce(s, part, nblk, 0, n_rhs, ro, j, 4, nullptr, ga);
-                launch_scale(s, Vn, N, n_rhs, active, ih);
+        if (graphs) {
+            // Replay the captured steps; the host stays at most two steps ahead
+            // and stops once a completed step reports no active right-hand side
+            // (steps launched after that are masked out on the device).
+            for (int j = 0; j < m; ++j) {
+                if (j >= 2) {
+                    HIPCHK(ctx, hipEventSynchronize(p->gev[j & 1]));
+                    const int *f = p->h_flags + (j & 1) * n_rhs;
+                    n_live = 0;
+                    for (int r = 0; r < n_rhs; ++r) n_live += f[r] ? 1 : 0;
+                    if (!n_live) break;
+                }
+                HIPCHK(ctx, hipGraphLaunch(p->gexec[j], s));
+                HIPCHK(ctx, hipEventRecord(p->gev[j & 1], s));
+                ++total_outer;
             }
-            ++total_outer;
-            HIPCHK(ctx, hipMemcpyAsync(h_act, w.active.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(ctx, hipStreamSynchronize(s));
-            n_live = 0;
-            for (int r = 0; r < n_rhs; ++r) n_live += h_act[r] ? 1 : 0;
-            if (!n_live) break;
+        } else {
+            for (int j = 0; j < m; ++j) {
+                step(s, j, n_live);
+                ++total_outer;
+                HIPCHK(ctx, hipMemcpyAsync(h_act, w.active.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(ctx, hipStreamSynchronize(s));
+                n_live = 0;
+                for (int r = 0; r < n_rhs; ++r) n_live += h_act[r] ? 1 : 0;
+                if (!n_live) break;
+            }
         }
         launch_backsolve(s, w.H.as<float2>(), m, m, w.gam.as<float2>(), w.kcyc.as<int>(), w.y.as<float2>(), n_rhs);
         launch_xupdate(s, x, Z, vstride, w.y.as<float2>(), m, w.kcyc.as<int>(), N, n_rhs);
@@ -1059,10 +1160,9 @@ nosdd_status nosdd_ctx_create(int hip_device, void *hip_stream, nosdd_ctx **out)
 
 void nosdd_ctx_destroy(nosdd_ctx *ctx) {
     if (!ctx) return;
-    if (ctx->own_stream && ctx->stream) {
-        (void)hipSetDevice(ctx->device);
-        (void)hipStreamDestroy(ctx->stream);
-    }
+    (void)hipSetDevice(ctx->device);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
@@ -1279,6 +1379,7 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
     p->setup_ms = ms;
     p->sub_solver = o->sub_solver;
     p->setup_done = true;
+    p->drop_graphs();
     return NOSDD_OK;
 }
 
@@ -1479,6 +1580,13 @@ nosdd_status nosdd_profile(nosdd_problem *p, int enable) {
         p->ev_next = 0;
     }
     p->prof = enable != 0;
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_graphs(nosdd_problem *p, int enable) {
+    if (!p) return NOSDD_EINVAL;
+    p->use_graphs = enable != 0;
+    if (!p->use_graphs) p->drop_graphs();
     return NOSDD_OK;
 }
 

@@ -22,7 +22,7 @@ EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_p
            "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
-           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply"]
+           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs"]
 
 
 class Grid(C.Structure):
@@ -83,6 +83,7 @@ def load(path=LIBPATH):
         "nosdd_profile": (i, [vp, i]),
         "nosdd_kernel_times": (i, [vp, vp, vp, vp]),
         "nosdd_nn_apply": (i, [vp, vp, vp]),
+        "nosdd_graphs": (i, [vp, i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -251,6 +252,10 @@ class Problem:
             out.append(phi[off:off + n].reshape(kc, int(b[3]), int(b[2])))
             off += n
         return out, box
+
+    def graphs(self, enable=True):
+        """Replay captured per-step HIP graphs (default) or launch kernels one by one."""
+        return self.ctx.check(self.L.nosdd_graphs(self.h, 1 if enable else 0))
 
     def profile(self, enable=True):
         return self.ctx.check(self.L.nosdd_profile(self.h, 1 if enable else 0))

@@ -73,3 +73,30 @@ def test_repeated_solves_are_bit_identical():
     E1, h1, i1, f1, _ = P.solve(w.J())
     E2, h2, i2, f2, _ = P.solve(w.J())
     assert np.array_equal(E1, E2) and np.array_equal(h1, h2) and np.array_equal(i1, i2)
+
+
+def test_graph_replay_is_bit_identical_to_eager_launch():
+    """The captured per-step graphs replay the eager kernel sequence exactly:
+    fields, residual histories and iteration counts agree bit for bit, over
+    several solves in a row with eager work and synchronisations in between."""
+    import torch
+    from paper_2509_03622_amd import nosdd
+    w = random_small(41, 192, 160, [64, 64, 64], [80, 80], wavelengths=(0.9, 1.3), n_src=2, k_coarse=1)
+    ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+    P.setup(k_coarse=1, k_trial=8)
+    P.graphs(False)
+    E0, h0, it0, f0, s0 = P.solve(w.J(), tol=1e-6, restart=30, max_iters=600)
+    assert s0 == 0
+    P.graphs(True)
+    for rep in range(3):
+        E1, h1, it1, f1, s1 = P.solve(w.J(), tol=1e-6, restart=30, max_iters=600)
+        assert s1 == 0
+        assert np.array_equal(it0, it1), (rep, it0, it1)
+        assert np.array_equal(h0, h1), rep
+        assert np.array_equal(E0, E1), rep
+        x = torch.ones(4, device="cuda")           # unrelated eager work between replays
+        torch.cuda.synchronize()
+        del x
+    P.close()
+    ctx.close()
