@@ -1023,10 +1023,9 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         const float *ih = w.inv_h.as<float>();
         launch_cgs_dots(st, V, vstride, j + 1, wv, N, n_rhs, active, part, nblk);
         launch_cgs_reduce(st, part, nblk, j + 1, n_rhs, active, j, 1, nullptr, ga);
-        launch_cgs_update(st, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, j, part, nblk);
-        launch_cgs_reduce(st, part, nblk, 0, n_rhs, nullptr, j, 2, nullptr, ga);
-        launch_cgs_dots(st, V, vstride, j + 1, Vn, N, n_rhs, ro, part, nblk);
-        launch_cgs_reduce(st, part, nblk, j + 1, n_rhs, ro, j, 3, nullptr, ga);
+        // first-pass update with the second pass's dots taken from the same loads
+        launch_cgs_update_dots(st, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, j, part, nblk);
+        launch_cgs_reduce(st, part, nblk, j + 1, n_rhs, nullptr, j, 5, nullptr, ga);
         launch_cgs_update(st, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, j, part, nblk);
         launch_cgs_reduce(st, part, nblk, 0, n_rhs, ro, j, 4, nullptr, ga);
         launch_scale(st, Vn, N, n_rhs, active, ih);

@@ -111,6 +111,9 @@ void launch_cgs_dots(hipStream_t s, const float2 *V, long long vstride, int nv, 
 void launch_cgs_update(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
                        long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col, double2 *partial,
                        int nblk);
+void launch_cgs_update_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
+                            long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col,
+                            double2 *partial, int nblk);
 void launch_cgs_reduce(hipStream_t s, const double2 *partial, int nblk, int nv, int n_rhs, const int *gate, int col,
                        int mode, double *norm_out, const GivensArgs &ga);
 void launch_scale(hipStream_t s, float2 *v, long long N, int n_rhs, const int *active, const float *sc);

@@ -221,6 +221,62 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_kernel(const float2 *__
     }
 }
 
+// First-pass update fused with the second pass's dots: dst = w - sum_i Hc_i V_i,
+// and, from the same loads of V, per-workgroup partials of V_i^H dst (slots
+// i < NV) and of ||dst||^2 (slot KR_MAXV).  The second pass then needs one
+// more read of V (its update) instead of two.
+template <int NV>
+__global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float2 *__restrict__ V, long long vstride,
+                                                                     const float2 *w, float2 *dst, long long N,
+                                                                     const int *__restrict__ gate,
+                                                                     const float2 *__restrict__ Hc, int m, int col,
+                                                                     double2 *__restrict__ partial, int nblk) {
+    __shared__ float2 hs[NV > 0 ? NV : 1];
+    __shared__ double2 red[(KR_THREADS / 64) * KR_SLOTS];
+    const int r = blockIdx.y;
+    if (!gate[r]) return;
+    if (threadIdx.x < NV) hs[threadIdx.x] = Hc[((long long)r * (m + 1) + threadIdx.x) * m + col];
+    __syncthreads();
+    const float2 *wr = w + r * N;
+    float2 *dr = dst + r * N;
+    const float2 *Vr = V + r * N;
+    float2 facc[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) facc[i] = make_float2(0.f, 0.f);
+    float fn = 0.f;
+    const long long stride = (long long)gridDim.x * KR_THREADS;
+    for (long long n = (long long)blockIdx.x * KR_THREADS + threadIdx.x; n < N; n += stride) {
+        float2 vv[NV > 0 ? NV : 1];
+        float2 v = wr[n];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) vv[i] = Vr[i * vstride + n];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v = cfms(v, hs[i], vv[i]);
+        dr[n] = v;
+        fn += cabs2(v);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) facc[i] = cfma_conj(facc[i], vv[i], v);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const float rx = wave_sum_f(facc[i].x), ry = wave_sum_f(facc[i].y);
+        if (lane == 0) red[wid * KR_SLOTS + i] = make_double2(rx, ry);
+    }
+    {
+        const float rn = wave_sum_f(fn);
+        if (lane == 0) red[wid * KR_SLOTS + KR_MAXV] = make_double2(rn, 0.0);
+    }
+    __syncthreads();
+    double2 *pr = partial + (long long)r * nblk * KR_SLOTS;
+    const int i = threadIdx.x;
+    if (i < NV || i == KR_MAXV) {
+        double2 s = red[i];
+        for (int q = 1; q < KR_THREADS / 64; ++q) s = zadd(s, red[q * KR_SLOTS + i]);
+        pr[(long long)blockIdx.x * KR_SLOTS + i] = s;
+    }
+}
+
 // Sum the partials of each RHS (fixed order; waves split the slots, lanes the
 // workgroups) and take the scalar step of the Arnoldi recurrence:
 //   mode 0  norm only: ||.||^2 -> norm_out (||b||, restart residuals);
@@ -228,19 +284,21 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_kernel(const float2 *__
 //   mode 2  first-pass norm: ||w'||^2; DGKS (||w'|| < 0.7 ||w|| asks for a
 //           second pass: reorth = 1), else the Givens step;
 //   mode 3  second-pass dots: h2 -> H2[:, col], H[:, col] += h2;
-//   mode 4  second-pass norm: ||w''||^2 and the Givens step.
+//   mode 4  second-pass norm: ||w''||^2 and the Givens step;
+//   mode 5  fused first-pass norm and second-pass dots: the DGKS test of mode 2,
+//           and where a second pass is due, the h2 bookkeeping of mode 3.
 constexpr int RED_THREADS = 1024;
 __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *__restrict__ partial, int nblk, int nv,
                                                                  const int *__restrict__ gate, int col, int mode,
                                                                  double *__restrict__ norm_out, GivensArgs ga) {
     __shared__ double2 vals[KR_SLOTS];
     const int r = blockIdx.x;
-    if (mode == 2 && !ga.active[r]) {       // keep the second-pass flag of idle RHS cleared
+    if ((mode == 2 || mode == 5) && !ga.active[r]) {       // keep the second-pass flag of idle RHS cleared
         if (threadIdx.x == 0) ga.reorth[r] = 0;
         return;
     }
     if (gate && !gate[r]) return;
-    const int ns = (mode == 1 || mode == 3) ? nv : 0;
+    const int ns = (mode == 1 || mode == 3 || mode == 5) ? nv : 0;
     const double2 *pr = partial + (long long)r * nblk * KR_SLOTS;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int v = wid; v <= ns; v += RED_THREADS / 64) {
@@ -276,6 +334,14 @@ __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *
                 givens_step(ga, r, col, n2);
             }
             break;
+        case 5:
+            if (n2 >= 0.49 * ga.nw_pre[r]) {
+                ga.reorth[r] = 0;
+                givens_step(ga, r, col, n2);
+                break;
+            }
+            ga.reorth[r] = 1;
+            [[fallthrough]];
         case 3:
             for (int i = 0; i < nv; ++i) {
                 const float2 h = make_float2((float)vals[i].x, (float)vals[i].y);
@@ -323,6 +389,22 @@ void launch_cgs_update(hipStream_t s, const float2 *V, long long vstride, int nv
     case K:                                                                                                         \
         hipLaunchKernelGGL((cgs_update_kernel<K, (K > 16 ? 2 : 1)>), grid, dim3(KR_THREADS), 0, s, V, vstride, w,  \
                            dst, N, gate, Hc, m, col, partial, nblk);                                                \
+        break;
+        NOSDD_NV_CASES(CASE)
+#undef CASE
+        default: break;
+    }
+}
+
+void launch_cgs_update_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
+                            long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col,
+                            double2 *partial, int nblk) {
+    dim3 grid(nblk, n_rhs);
+    switch (nv) {
+#define CASE(K)                                                                                                     \
+    case K:                                                                                                         \
+        hipLaunchKernelGGL((cgs_update_dots_kernel<K>), grid, dim3(KR_THREADS), 0, s, V, vstride, w, dst, N, gate,  \
+                           Hc, m, col, partial, nblk);                                                              \
         break;
         NOSDD_NV_CASES(CASE)
 #undef CASE
