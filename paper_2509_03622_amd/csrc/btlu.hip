@@ -37,20 +37,18 @@ struct BlockMap {
 
 // ------------------------------------------------------------------ factor
 constexpr int BT_FACT_THREADS = 256;
+constexpr int BT_FACT_LDS_B = 72;        // FP64 block of 72 x 72 = 81 KB of LDS
+constexpr int BT_FACT_MAX_B = 128;       // larger blocks work in a global FP64 scratch
 
+// Block-Thomas factorisation of one (tile, wavelength): D_k^-1 for every block
+// k, with the b x b FP64 working matrix M (row-major) in LDS or in global
+// scratch private to the workgroup.
 template <int BMAX>
-__global__ __launch_bounds__(BT_FACT_THREADS) void bt_factor_kernel(const TileDesc *__restrict__ tiles,
-                                                                    const float *__restrict__ eps,
-                                                                    const double2 *__restrict__ coef,
-                                                                    const double *__restrict__ k0v, double h,
-                                                                    int nx, int ny, float2 *__restrict__ dinv,
-                                                                    long long wl_stride) {
-    __shared__ double2 M[BMAX * BMAX];
-    __shared__ double2 fcol[BMAX], prow[BMAX];
-    __shared__ int piv[BMAX];
-    __shared__ int pivrow;
-    const TileDesc t = tiles[blockIdx.x];
-    const int wl = blockIdx.y;
+__device__ __forceinline__ void bt_factor_body(double2 *M, double2 *fcol, double2 *prow, int *piv, int *pivrow,
+                                               const TileDesc &t, int wl, const float *__restrict__ eps,
+                                               const double2 *__restrict__ coef, const double *__restrict__ k0v,
+                                               double h, int nx, int ny, float2 *__restrict__ dinv,
+                                               long long wl_stride) {
     const int b = t.b, nb = t.nb, tid = threadIdx.x;
     const double2 *cd = coef + wl * coef_stride(nx, ny);
     const double2 *cxm = cd, *cxp = cd + nx, *cym = cd + 2 * nx, *cyp = cd + 2 * nx + ny;
@@ -108,10 +106,10 @@ __global__ __launch_bounds__(BT_FACT_THREADS) void bt_factor_kernel(const TileDe
                     int oi = __shfl_down(bi, off, 64);
                     if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
                 }
-                if (tid == 0) { pivrow = bi; piv[col] = bi; }
+                if (tid == 0) { *pivrow = bi; piv[col] = bi; }
             }
             __syncthreads();
-            const int p = pivrow;
+            const int p = *pivrow;
             if (p != col) {
                 for (int j = tid; j < b; j += BT_FACT_THREADS) {
                     double2 a = M[p * b + j];
@@ -163,15 +161,50 @@ __global__ __launch_bounds__(BT_FACT_THREADS) void bt_factor_kernel(const TileDe
     }
 }
 
+// Tiles whose short side fits the LDS matrix (others return at once).
+__global__ __launch_bounds__(BT_FACT_THREADS) void bt_factor_lds_kernel(const TileDesc *__restrict__ tiles,
+                                                                        const float *__restrict__ eps,
+                                                                        const double2 *__restrict__ coef,
+                                                                        const double *__restrict__ k0v, double h,
+                                                                        int nx, int ny, float2 *__restrict__ dinv,
+                                                                        long long wl_stride) {
+    __shared__ double2 M[BT_FACT_LDS_B * BT_FACT_LDS_B];
+    __shared__ double2 fcol[BT_FACT_LDS_B], prow[BT_FACT_LDS_B];
+    __shared__ int piv[BT_FACT_LDS_B];
+    __shared__ int pivrow;
+    const TileDesc t = tiles[blockIdx.x];
+    if (t.b > BT_FACT_LDS_B) return;
+    bt_factor_body<BT_FACT_LDS_B>(M, fcol, prow, piv, &pivrow, t, blockIdx.y, eps, coef, k0v, h, nx, ny, dinv,
+                                  wl_stride);
+}
+
+// Tiles listed in `big` (short side above the LDS limit): the working matrix
+// lives in scratch[(blockIdx.y * n_big + blockIdx.x) * BT_FACT_MAX_B^2].
+__global__ __launch_bounds__(BT_FACT_THREADS) void bt_factor_global_kernel(const TileDesc *__restrict__ tiles,
+                                                                           const int *__restrict__ big, int n_big,
+                                                                           const float *__restrict__ eps,
+                                                                           const double2 *__restrict__ coef,
+                                                                           const double *__restrict__ k0v, double h,
+                                                                           int nx, int ny, float2 *__restrict__ dinv,
+                                                                           long long wl_stride,
+                                                                           double2 *__restrict__ scratch) {
+    __shared__ double2 fcol[BT_FACT_MAX_B], prow[BT_FACT_MAX_B];
+    __shared__ int piv[BT_FACT_MAX_B];
+    __shared__ int pivrow;
+    const TileDesc t = tiles[big[blockIdx.x]];
+    double2 *M = scratch + ((long long)blockIdx.y * n_big + blockIdx.x) * BT_FACT_MAX_B * BT_FACT_MAX_B;
+    bt_factor_body<BT_FACT_MAX_B>(M, fcol, prow, piv, &pivrow, t, blockIdx.y, eps, coef, k0v, h, nx, ny, dinv,
+                                  wl_stride);
+}
+
 void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_wl, const float *eps,
-                      const float2 *coef_f, const double *coef_d, const double *k0, double h, int nx, int ny,
-                      float2 *dinv, long long dinv_wl_stride, int bmax) {
-    (void)coef_f;
-    dim3 grid(n_tiles, n_wl);
-    // the caller guarantees bmax <= 72 (FP64 block of 72 x 72 = 81 KB of LDS)
-    (void)bmax;
-    hipLaunchKernelGGL(bt_factor_kernel<72>, grid, dim3(BT_FACT_THREADS), 0, s, tiles, eps,
+                      const double *coef_d, const double *k0, double h, int nx, int ny, float2 *dinv,
+                      long long dinv_wl_stride, const int *big, int n_big, double2 *scratch) {
+    hipLaunchKernelGGL(bt_factor_lds_kernel, dim3(n_tiles, n_wl), dim3(BT_FACT_THREADS), 0, s, tiles, eps,
                        (const double2 *)coef_d, k0, h, nx, ny, dinv, dinv_wl_stride);
+    if (n_big > 0)
+        hipLaunchKernelGGL(bt_factor_global_kernel, dim3(n_big, n_wl), dim3(BT_FACT_THREADS), 0, s, tiles, big,
+                           n_big, eps, (const double2 *)coef_d, k0, h, nx, ny, dinv, dinv_wl_stride, scratch);
 }
 
 // ------------------------------------------------------------------ solve
@@ -225,12 +258,14 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
                                                        const float2 *__restrict__ coef, int nx, int ny,
                                                        const float2 *__restrict__ vin, long long vin_stride,
                                                        float2 *__restrict__ out, long long out_stride,
-                                                       const int *__restrict__ active, int mode) {
+                                                       const int *__restrict__ active, int mode,
+                                                       const int2 *__restrict__ order) {
     extern __shared__ float2 vl[];                    // [nb][b]: v_k, then w_k
     __shared__ float2 ysh[2][BT_BMAX];
     __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX];
-    const int tile = blockIdx.x, rhs = blockIdx.y;
-    if (active && !active[rhs]) return;
+    const int2 job = order[blockIdx.x];               // (tile, rhs); tile < 0 pads the queue
+    const int tile = job.x, rhs = job.y;
+    if (tile < 0 || (active && !active[rhs])) return;
     const int wl = rhs / n_src;
     const TileDesc t = tiles[tile];
     const int b = t.b, nb = t.nb, half = b >> 1;
@@ -363,31 +398,40 @@ template <int MAXJ, int NS>
 static void bt_solve_launch(hipStream_t s, dim3 grid, int threads, size_t lds, const TileDesc *tiles, int n_src,
                             const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
                             const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
-                            const int *active, int mode) {
-    if (lds > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_kernel<MAXJ, NS>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                            const int *active, int mode, const int2 *order) {
     hipLaunchKernelGGL((bt_solve_kernel<MAXJ, NS>), grid, dim3(threads), lds, s, tiles, n_src, dinv, dinv_wl_stride,
-                       coef, nx, ny, vin, vin_stride, out, out_stride, active, mode);
+                       coef, nx, ny, vin, vin_stride, out, out_stride, active, mode, order);
 }
 
-void launch_bt_solve(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_rhs, int n_src, const float2 *dinv,
-                     long long dinv_wl_stride, const float2 *coef, int nx, int ny, const float2 *vin,
-                     long long vin_stride, float2 *out, long long out_stride, const int *active, int mode, int bmax,
-                     int max_cells) {
-    dim3 grid(n_tiles, n_rhs);
+// Kernels that need more than 64 KB of dynamic LDS must say so once per
+// process, before any launch (and outside graph capture).
+void bt_solve_prepare(int bmax, int max_cells) {
+    const size_t lds = (size_t)max_cells * sizeof(float2);
+    if (lds <= 65536) return;
+    const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
+    const void *f = maxj <= 9    ? reinterpret_cast<const void *>(&bt_solve_kernel<9, 4>)
+                    : maxj <= 13 ? reinterpret_cast<const void *>(&bt_solve_kernel<13, 3>)
+                                 : reinterpret_cast<const void *>(&bt_solve_kernel<16, 3>);
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, int n_jobs, int n_src,
+                     const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
+                     const float2 *vin, long long vin_stride, float2 *out, long long out_stride, const int *active,
+                     int mode, int bmax, int max_cells) {
+    dim3 grid(n_jobs);
     const int threads = ((bmax / 2) * BT_GROUP + 63) / 64 * 64;
     const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
     const size_t lds = (size_t)max_cells * sizeof(float2);
     if (maxj <= 9)
         bt_solve_launch<9, 4>(s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin, vin_stride,
-                              out, out_stride, active, mode);
+                              out, out_stride, active, mode, order);
     else if (maxj <= 13)
         bt_solve_launch<13, 3>(s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin,
-                               vin_stride, out, out_stride, active, mode);
+                               vin_stride, out, out_stride, active, mode, order);
     else
         bt_solve_launch<16, 3>(s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin,
-                               vin_stride, out, out_stride, active, mode);
+                               vin_stride, out, out_stride, active, mode, order);
 }
 
 }  // namespace nosdd

@@ -12,6 +12,7 @@
 #include <atomic>
 #include <cmath>
 #include <complex>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -107,6 +108,12 @@ struct nosdd_problem {
     int ev_next = 0;
     double prof_ms[4] = {0, 0, 0, 0};
     long long prof_launch[4] = {0, 0, 0, 0}, prof_units[4] = {0, 0, 0, 0};
+    // launch queues of the subdomain solve, per (n_rhs, n_src)
+    struct OrderBuf {
+        DevBuf buf;
+        int n_jobs = 0;
+    };
+    std::map<std::pair<int, int>, OrderBuf> orders;
     // one captured graph per Arnoldi step j of a restart cycle (replayed every cycle)
     bool use_graphs = true;
     std::vector<hipGraphExec_t> gexec;
@@ -587,6 +594,46 @@ nosdd_status ensure_nn(nosdd_problem *p, int n_rhs, int n_src) {
     return NOSDD_OK;
 }
 
+// Launch queue of the batched subdomain solve.  Jobs (tile, rhs) are grouped by
+// the factorisation they stream (tile, wavelength), groups ordered largest
+// tile first and dealt round-robin to eight queues, one per XCD: workgroup i
+// of a launch is placed on XCD i mod 8, so the right-hand sides that share a
+// factorisation run on one XCD and share its L2.  Queues are padded with
+// (-1, -1) to equal length.  Built once per (n_rhs, n_src), outside any
+// graph capture.
+nosdd_status solve_order(nosdd_problem *p, int n_rhs, int n_src, const int2 **order, int *n_jobs) {
+    auto key = std::make_pair(n_rhs, n_src);
+    auto it = p->orders.find(key);
+    if (it == p->orders.end()) {
+        const int nt = (int)p->tiles.size(), nwl = n_rhs / n_src;
+        std::vector<std::pair<int, int>> groups;              // (tile, wavelength)
+        for (int w = 0; w < nwl; ++w)
+            for (int t = 0; t < nt; ++t) groups.push_back({t, w});
+        auto cells = [&](int t) { return (p->tiles[t].x1 - p->tiles[t].x0) * (p->tiles[t].y1 - p->tiles[t].y0); };
+        std::stable_sort(groups.begin(), groups.end(),
+                         [&](const std::pair<int, int> &a, const std::pair<int, int> &b) { return cells(a.first) > cells(b.first); });
+        constexpr int NXCD = 8;
+        std::vector<std::vector<int2>> q(NXCD);
+        for (size_t g = 0; g < groups.size(); ++g)
+            for (int sidx = 0; sidx < n_src; ++sidx)
+                q[g % NXCD].push_back(make_int2(groups[g].first, groups[g].second * n_src + sidx));
+        size_t len = 0;
+        for (auto &v : q) len = std::max(len, v.size());
+        std::vector<int2> ord(len * NXCD, make_int2(-1, -1));
+        for (size_t slot = 0; slot < len; ++slot)
+            for (int x = 0; x < NXCD; ++x)
+                if (slot < q[x].size()) ord[slot * NXCD + x] = q[x][slot];
+        auto &ob = p->orders[key];
+        HIPCHK(p->ctx, ob.buf.ensure(ord.size() * sizeof(int2)));
+        HIPCHK(p->ctx, hipMemcpy(ob.buf.p, ord.data(), ord.size() * sizeof(int2), hipMemcpyHostToDevice));
+        ob.n_jobs = (int)ord.size();
+        it = p->orders.find(key);
+    }
+    *order = it->second.buf.as<int2>();
+    *n_jobs = it->second.n_jobs;
+    return NOSDD_OK;
+}
+
 // z = M^-1 v (two-level), wout = A z.  v, z, wout: [n_rhs][N].
 void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2 *wout, int n_src, int n_rhs,
              const int *active, int n_live) {
@@ -599,9 +646,12 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
                    p->max_cells, v, z, active, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(),
                    p->h, p->nx, p->ny, 0);
     } else
-    launch_bt_solve(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src, p->d_dinv.as<float2>(),
-                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, active, 0, p->bmax,
-                    p->max_cells);
+    {
+        const auto &ob = p->orders.at(std::make_pair(n_rhs, n_src));
+        launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ob.buf.as<int2>(), ob.n_jobs, n_src, p->d_dinv.as<float2>(),
+                        p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, active, 0, p->bmax,
+                        p->max_cells);
+    }
     }
     if (wout == nullptr) return;
     {
@@ -740,9 +790,15 @@ nosdd_status coarse_setup(nosdd_problem *p) {
     HIPCHK(ctx, d_rhs.ensure(bytes));
     HIPCHK(ctx, d_F.ensure(bytes));
     HIPCHK(ctx, hipMemcpyAsync(d_rhs.p, rhs.data(), bytes, hipMemcpyHostToDevice, s));
-    launch_bt_solve(s, p->d_tiles.as<TileDesc>(), nt, nwl * K, K, p->d_dinv.as<float2>(), p->dinv_wl_stride,
-                    p->d_coef.as<float2>(), nx, ny, d_rhs.as<float2>(), LT, d_F.as<float2>(), LT, nullptr, 3,
-                    p->bmax, p->max_cells);
+    {
+        const int2 *ord = nullptr;
+        int nj = 0;
+        nosdd_status so = solve_order(p, nwl * K, K, &ord, &nj);
+        if (so != NOSDD_OK) return so;
+        launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ord, nj, K, p->d_dinv.as<float2>(), p->dinv_wl_stride,
+                        p->d_coef.as<float2>(), nx, ny, d_rhs.as<float2>(), LT, d_F.as<float2>(), LT, nullptr, 3,
+                        p->bmax, p->max_cells);
+    }
     std::vector<float2> F(rhs.size());
     HIPCHK(ctx, hipMemcpyAsync(F.data(), d_F.p, bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
@@ -1030,6 +1086,15 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         launch_cgs_reduce(st, part, nblk, 0, n_rhs, ro, j, 4, nullptr, ga);
         launch_scale(st, Vn, N, n_rhs, active, ih);
     };
+    {
+        const int2 *ord = nullptr;
+        int nj = 0;
+        nosdd_status so = solve_order(p, n_rhs, n_src, &ord, &nj);
+        if (so != NOSDD_OK) {
+            (void)hipHostFree(h_act);
+            return so;
+        }
+    }
     const bool graphs = p->use_graphs && !p->prof;
     if (graphs) {
         nosdd_status gs = ensure_graphs(p, n_rhs, n_src, m, o, step);
@@ -1246,9 +1311,9 @@ nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const flo
             t.tr = lx > ly ? 1 : 0;
             t.b = std::min(lx, ly);
             t.nb = std::max(lx, ly);
-            if (t.b % 2 || t.b > 72) {
+            if (t.b % 2 || t.b > BT_FACT_SCRATCH_B) {
                 delete p;
-                return fail(ctx, NOSDD_EPARTITION, "extended subdomains need an even short side of at most 72 cells");
+                return fail(ctx, NOSDD_EPARTITION, "extended subdomains need an even short side of at most 128 cells");
             }
             if (t.nb > BT_NBMAX || lx * ly > BT_LDS_MAX_CELLS) {
                 delete p;
@@ -1342,9 +1407,25 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
     HIPCHK(ctx, hipEventRecord(e0, s));
     const int nwl = (int)p->wl.size();
     HIPCHK(ctx, p->d_dinv.ensure((size_t)nwl * p->dinv_wl_stride * sizeof(float2)));
-    launch_bt_factor(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, p->d_eps.as<float>(), nullptr,
-                     p->d_coefd.as<double>(), p->d_k0.as<double>(), p->h, p->nx, p->ny, p->d_dinv.as<float2>(),
-                     p->dinv_wl_stride, p->bmax);
+    {
+        // tiles whose short side exceeds the LDS factorisation limit work in global scratch
+        std::vector<int> big;
+        for (int t = 0; t < (int)p->tiles.size(); ++t)
+            if (p->tiles[t].b > 72) big.push_back(t);
+        DevBuf d_big, d_scr;
+        if (!big.empty()) {
+            HIPCHK(ctx, d_big.ensure(big.size() * sizeof(int)));
+            HIPCHK(ctx, hipMemcpy(d_big.p, big.data(), big.size() * sizeof(int), hipMemcpyHostToDevice));
+            HIPCHK(ctx, d_scr.ensure((size_t)nwl * big.size() * BT_FACT_SCRATCH_B * BT_FACT_SCRATCH_B *
+                                     sizeof(double2)));
+        }
+        launch_bt_factor(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, p->d_eps.as<float>(),
+                         p->d_coefd.as<double>(), p->d_k0.as<double>(), p->h, p->nx, p->ny, p->d_dinv.as<float2>(),
+                         p->dinv_wl_stride, d_big.as<int>(), (int)big.size(), d_scr.as<double2>());
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, hipStreamSynchronize(s));
+    }
+    bt_solve_prepare(p->bmax, p->max_cells);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (o->sub_solver == 1) {
@@ -1449,9 +1530,13 @@ nosdd_status nosdd_schwarz_sweep(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
     if (!v || !z || n_src <= 0) return fail(p->ctx, NOSDD_EINVAL, "null argument or n_src <= 0");
     const int n_rhs = (int)p->wl.size() * n_src;
     const long long N = (long long)p->nx * p->ny;
-    launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src,
-                    p->d_dinv.as<float2>(), p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny,
-                    (const float2 *)v, N, (float2 *)z, N, nullptr, 0, p->bmax, p->max_cells);
+    const int2 *ord = nullptr;
+    int nj = 0;
+    st = solve_order(p, n_rhs, n_src, &ord, &nj);
+    if (st) return st;
+    launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), ord, nj, n_src, p->d_dinv.as<float2>(),
+                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, (const float2 *)v, N, (float2 *)z, N,
+                    nullptr, 0, p->bmax, p->max_cells);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
     return NOSDD_OK;
@@ -1466,6 +1551,12 @@ nosdd_status nosdd_precond_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
     if (st) return st;
     if (p->sub_solver == 1) {
         st = ensure_nn(p, n_rhs, n_src);
+        if (st) return st;
+    }
+    {
+        const int2 *ord = nullptr;
+        int nj = 0;
+        st = solve_order(p, n_rhs, n_src, &ord, &nj);
         if (st) return st;
     }
     const long long N = (long long)p->nx * p->ny;
@@ -1496,9 +1587,13 @@ nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32
         HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
         return NOSDD_OK;
     }
-    launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, 1, p->d_dinv.as<float2>(),
-                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, (const float2 *)rhs, p->loc_total,
-                    (float2 *)u, p->loc_total, nullptr, 3, p->bmax, p->max_cells);
+    const int2 *ord = nullptr;
+    int nj = 0;
+    st = solve_order(p, nwl, 1, &ord, &nj);
+    if (st) return st;
+    launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), ord, nj, 1, p->d_dinv.as<float2>(), p->dinv_wl_stride,
+                    p->d_coef.as<float2>(), p->nx, p->ny, (const float2 *)rhs, p->loc_total, (float2 *)u,
+                    p->loc_total, nullptr, 3, p->bmax, p->max_cells);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
     return NOSDD_OK;

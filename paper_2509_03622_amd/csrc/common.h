@@ -74,19 +74,24 @@ void launch_stencil(hipStream_t s, const float2 *x, const float2 *b, float2 *y, 
 void launch_residual64(hipStream_t s, const double2 *x, const float2 *b, float2 *r, const float *eps,
                        const double2 *coef, const double *k0, int nx, int ny, int n_rhs, int n_src);
 
+// Factorisation of every (tile, wavelength); tiles whose short side exceeds
+// 72 (listed in big[n_big]) use scratch[n_wl * n_big * 128 * 128] (FP64 complex).
 void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_wl, const float *eps,
-                      const float2 *coef_f, const double *coef_d, const double *k0, double h, int nx,
-                      int ny, float2 *dinv, long long dinv_wl_stride, int bmax);
+                      const double *coef_d, const double *k0, double h, int nx, int ny, float2 *dinv,
+                      long long dinv_wl_stride, const int *big, int n_big, double2 *scratch);
+constexpr int BT_FACT_SCRATCH_B = 128;
 
 // mode bit 0: input is a packed local vector (else gathered from a global vector)
 // mode bit 1: output is a packed local vector (else core cells scattered to a global vector)
 // Subdomain LU solves; the tile's RHS lives in max_cells * 8 bytes of LDS.
 constexpr int BT_NBMAX = 256;                                // longest tile side
 constexpr int BT_LDS_MAX_CELLS = 15360;                      // 120 KB of LDS
-void launch_bt_solve(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_rhs, int n_src,
+// One workgroup per job: order[n_jobs] = (tile, rhs), tile < 0 for padding.
+void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, int n_jobs, int n_src,
                      const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
                      const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
                      const int *active, int mode, int bmax, int max_cells);
+void bt_solve_prepare(int bmax, int max_cells);
 
 void launch_robin_trace(hipStream_t s, const int4 *entries, int n_entries, const float *eps,
                         const float *k0, float h, int nx, int ny, const float2 *x, float2 *g,

@@ -198,3 +198,47 @@ def test_coarse_basis_fields_match_oracle(k_coarse, k_trial):
         worst.append((rel(g * ph, ref), ti, l))
     print(sorted(worst)[-5:])
     assert max(worst)[0] < 1e-4, sorted(worst)[-5:]
+
+
+def uneven():
+    """Mixed 96/64 cores: 100 x 100 corner subdomains (short side above the LDS
+    factorisation limit), 100 x 72 edge subdomains, 72 x 72 interior ones."""
+    return random_small(51, 320, 256, [96, 64, 64, 96], [96, 64, 96], wavelengths=(1.0, 1.2), n_src=3,
+                        npml=12, k_coarse=1, block=16)
+
+
+def test_uneven_subdomains_local_solves_match_sparse_lu():
+    w = uneven()
+    ctx, P = make_gpu_problem(w, k_coarse=0)
+    nt, lc, ne, nc = P.sizes()
+    rng = np.random.default_rng(4)
+    rhs = (rng.standard_normal((len(w.wavelengths), lc)) + 1j * rng.standard_normal((len(w.wavelengths), lc)))
+    u = dev(np.zeros_like(rhs))
+    P.local_solve(dev(rhs), u)
+    u = host(u)
+    worst, shapes = 0.0, set()
+    for wi, lam in enumerate(w.wavelengths):
+        A, part, locs = oracle_parts(w, lam)
+        for t, L in enumerate(locs):
+            off = P.tile_info(t)[8]
+            n = L.B.shape[0]
+            shapes.add((L.t.x1 - L.t.x0, L.t.y1 - L.t.y0))
+            worst = max(worst, rel(u[wi, off:off + n], L.solve(rhs[wi, off:off + n])))
+    assert (100, 100) in shapes and (100, 72) in shapes and (72, 100) in shapes, shapes
+    assert worst < 2e-5, worst
+
+
+def test_uneven_subdomains_many_sources_solve():
+    w = uneven()
+    ctx, P = make_gpu_problem(w)
+    E, hist, iters, fin, st = P.solve(w.J(), tol=1e-6, restart=30, max_iters=800)
+    assert st == 0, (iters, fin)
+    for wi, lam in enumerate(w.wavelengths):
+        A = assemble_A(w.eps, lam, w.h, w.npml)
+        for s in range(len(w.sources)):
+            xs = solve_direct(A, source_rhs(w.J()[s], lam))
+            assert rel(E[wi, s].ravel(), xs) < 1e-5, (wi, s)
+    lam = w.wavelengths[0]
+    op = SchwarzProblem(w.eps, lam, w.h, w.npml, w.core_x, w.core_y, w.overlap, k_coarse=1)
+    xo, it_o, hist_o, res_o = op.solve(w.J()[0], tol=1e-6)
+    assert abs(int(iters[0, 0]) - it_o) <= 1, (int(iters[0, 0]), it_o)
