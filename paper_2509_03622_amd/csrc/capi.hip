@@ -452,10 +452,12 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
             for (int i = 0; i < C; ++i)
                 for (int o = 0; o < C; ++o) {
                     const uint16_t a = rr[((size_t)md * C + i) * C + o], b = ri[((size_t)md * C + i) * C + o];
-                    dst[i * 128 + o] = a;
-                    dst[i * 128 + 64 + o] = b;
-                    dst[(64 + i) * 128 + o] = (uint16_t)(b ^ 0x8000u);     // -Im R
-                    dst[(64 + i) * 128 + 64 + o] = a;
+                    // real form of the complex mix, rows (Re X_i, Im X_i) interleaved as
+                    // 2i, 2i+1 and columns (Re Y_o, Im Y_o) as 2o, 2o+1
+                    dst[(2 * i) * 128 + 2 * o] = a;
+                    dst[(2 * i) * 128 + 2 * o + 1] = b;
+                    dst[(2 * i + 1) * 128 + 2 * o] = (uint16_t)(b ^ 0x8000u);     // -Im R
+                    dst[(2 * i + 1) * 128 + 2 * o + 1] = a;
                 }
         }
         pos += 2ull * nmodes * C * C;
@@ -467,9 +469,29 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
     std::vector<uint16_t> p1w(w.begin() + pos, w.begin() + pos + (size_t)hid * C);
     pos += (size_t)hid * C;
     std::vector<float> p1b = f32s(hid), p2w = f32s(2ull * hid), p2b = f32s(2);
+    // truncated-DFT twiddle tables for every subdomain side L <= 72 (FP64 on the host)
+    std::vector<float2> tw((size_t)FNO_TW_UNIT * FNO_MAXL * (FNO_MAXL + 1) / 2);
+    for (int L = 1; L <= FNO_MAXL; ++L) {
+        float2 *base = &tw[(size_t)FNO_TW_UNIT * L * (L - 1) / 2];
+        auto kx = [&](int q) { return q < m ? q : L - 2 * m + q; };
+        auto ph = [&](long long k, int i, double sign) {
+            const double a = sign * 2.0 * M_PI * (double)((k * i) % L) / (double)L;
+            return make_float2((float)std::cos(a), (float)std::sin(a));
+        };
+        for (int i = 0; i < L; ++i)
+            for (int q = 0; q < 2 * m; ++q) {
+                base[i * 2 * m + q] = ph(kx(q), i, -1.0);                   // forward, [x][q]
+                base[FNO_TW_INV_X * L + q * L + i] = ph(kx(q), i, 1.0);     // inverse, [q][x]
+            }
+        for (int i = 0; i < L; ++i)
+            for (int q = 0; q < m; ++q) {
+                base[FNO_TW_FWD_Y * L + i * m + q] = ph(q, i, -1.0);       // forward, [y][ky]
+                base[FNO_TW_INV_Y * L + i * m + q] = ph(q, i, 1.0);        // inverse, [y][ky]
+            }
+    }
     // one device buffer, carved
     const size_t bytes = (lift_w.size() + lift_b.size() + bias.size() + p1b.size() + p2w.size() + p2b.size()) * 4 +
-                         (R.size() + Wb.size() + p1w.size()) * 2 + 8 * 256;
+                         (R.size() + Wb.size() + p1w.size()) * 2 + tw.size() * sizeof(float2) + 9 * 256;
     HIPCHK(ctx, p->d_net.ensure(bytes));
     char *base = p->d_net.as<char>();
     size_t off = 0;
@@ -491,6 +513,7 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
     n.p1b = (float *)put(p1b.data(), p1b.size() * 4);
     n.p2w = (float *)put(p2w.data(), p2w.size() * 4);
     n.p2b = (float *)put(p2b.data(), p2b.size() * 4);
+    n.tw = (float2 *)put(tw.data(), tw.size() * sizeof(float2));
     HIPCHK(ctx, hipStreamSynchronize(st));
     return NOSDD_OK;
 }

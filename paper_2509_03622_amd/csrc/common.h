@@ -153,12 +153,19 @@ struct FnoSample {
 struct FnoDevice {
     int layers = 0;
     float *lift_w = nullptr, *lift_b = nullptr;   // [64][9], [64]
-    unsigned short *R = nullptr;                  // [layer][512][128][128] bf16, [[Re, Im], [-Im, Re]]
+    unsigned short *R = nullptr;                  // [layer][512][128][128] bf16: real form of the complex mix,
+                                                  // rows (Re, Im) of input channel i at 2i, 2i+1, columns likewise
     unsigned short *W = nullptr;                  // [layer][64][64] bf16
     float *b = nullptr;                           // [layer][64]
     unsigned short *p1w = nullptr;                // [128][64] bf16
     float *p1b = nullptr, *p2w = nullptr, *p2b = nullptr;   // [128], [2][128], [2]
+    float2 *tw = nullptr;                         // twiddle tables, FNO_TW_UNIT * L float2 per side L
 };
+// Twiddle tables of the truncated DFTs for side L, at tw + FNO_TW_UNIT L (L-1)/2:
+// forward kx [x][q] (L x 32), inverse kx [q][x] at FNO_TW_INV_X L, forward ky
+// [y][ky] (L x 16) at FNO_TW_FWD_Y L, inverse ky at FNO_TW_INV_Y L.
+constexpr int FNO_MAXL = 72;
+constexpr int FNO_TW_INV_X = 32, FNO_TW_FWD_Y = 64, FNO_TW_INV_Y = 80, FNO_TW_UNIT = 96;
 
 // Workspace of the batched inner NN-FGMRES (device pointers).
 struct NnWork {

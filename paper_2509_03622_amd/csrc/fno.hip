@@ -12,9 +12,10 @@
 // launch per stage.  Activations are FP32 [sample][C][cells] with the
 // subdomain's own (lx, ly).  The dense channel contractions -- the 1x1 mix W
 // and the per-mode complex mix R -- run on MFMA in BF16 with FP32
-// accumulation (v_mfma_f32_32x32x8_bf16): R is applied as a real 128 x 128
-// block [[Re R, Im R], [-Im R, Re R]] to [Re X | Im X].  The truncated DFTs
-// are separable FP32 sums in LDS.
+// accumulation (v_mfma_f32_32x32x8_bf16): R is applied as the real 128 x 128
+// form of the complex 64 x 64 mix to (Re X_c, Im X_c) interleaved per
+// channel.  The truncated DFTs are separable FP32 sums in LDS with twiddle
+// tables precomputed per subdomain side.
 #include "common.h"
 
 namespace nosdd {
@@ -70,24 +71,12 @@ __global__ __launch_bounds__(256) void fno_lift_kernel(const FnoSample *__restri
     }
 }
 
-// ------------------------------------------------------------------ twiddles
-// E[i][q] = exp(sign 2 pi i k(q) i / L) for q < nq, with k(q) = q for the ky axis
-// (half = 0) or the kept kx of q (half = 1: q < FM -> q, else L - 2 FM + q).
-__device__ __forceinline__ void twiddles(float2 *E, int L, int nq, int half, float sign) {
-    for (int e = threadIdx.x; e < L * nq; e += blockDim.x) {
-        const int i = e / nq, q = e - i * nq;
-        const int k = (half && q >= FM) ? L - 2 * FM + q : q;
-        float sn, cs;
-        sincospif(sign * 2.0f * (float)((k * i) % L) / (float)L, &sn, &cs);
-        E[e] = make_float2(cs, sn);
-    }
-}
-
 // ------------------------------------------------------------------ forward DFT
-// X[mode][s][0..63] = Re, [64..127] = Im of the kept modes of channel c,
+// X[mode][s][2c], X[mode][s][2c+1] = Re, Im of the kept mode of channel c,
 // mode = q * FM + ky.
 __global__ __launch_bounds__(256) void fno_dft_fwd_kernel(const FnoSample *__restrict__ smp, const int *__restrict__ sact,
-                                                          const float *__restrict__ act, float *__restrict__ X, int S_tot) {
+                                                          const float *__restrict__ act, float *__restrict__ X, int S_tot,
+                                                          const float2 *__restrict__ tw) {
     __shared__ float u[72 * 72];
     __shared__ float2 T[72 * 2 * FM];
     __shared__ float2 Ex[72 * 2 * FM];
@@ -98,20 +87,34 @@ __global__ __launch_bounds__(256) void fno_dft_fwd_kernel(const FnoSample *__res
     const int lx = S.lx, ly = S.ly, n = lx * ly;
     const float *src = act + S.cell_off * FC + (long long)ch * n;
     for (int i = threadIdx.x; i < n; i += 256) u[i] = src[i];
-    twiddles(Ex, lx, 2 * FM, 1, -1.f);
-    twiddles(Ey, ly, FM, 0, -1.f);
+    {
+        const float2 *twx = tw + (long long)FNO_TW_UNIT * lx * (lx - 1) / 2;
+        const float2 *twy = tw + (long long)FNO_TW_UNIT * ly * (ly - 1) / 2 + FNO_TW_FWD_Y * ly;
+        for (int i = threadIdx.x; i < lx * 2 * FM; i += 256) Ex[i] = twx[i];
+        for (int i = threadIdx.x; i < ly * FM; i += 256) Ey[i] = twy[i];
+    }
     __syncthreads();
-    // along x: T[y][q] = sum_x u[y][x] Ex[x][q]
-    for (int e = threadIdx.x; e < ly * 2 * FM; e += 256) {
-        const int y = e / (2 * FM), q = e - y * (2 * FM);
-        float re = 0.f, im = 0.f;
+    // along x: T[y][q] = sum_x u[y][x] Ex[x][q]; a thread owns one q and FWD_RY
+    // rows, so each twiddle load (consecutive q across lanes) feeds FWD_RY
+    // products and the u loads are broadcasts
+    constexpr int FWD_RY = 4;
+    for (int e = threadIdx.x; e < ((ly + FWD_RY - 1) / FWD_RY) * 2 * FM; e += 256) {
+        const int yb = (e / (2 * FM)) * FWD_RY, q = e - (e / (2 * FM)) * (2 * FM);
+        float re[FWD_RY], im[FWD_RY];
+#pragma unroll
+        for (int i = 0; i < FWD_RY; ++i) re[i] = im[i] = 0.f;
         for (int x = 0; x < lx; ++x) {
-            const float a = u[y * lx + x];
             const float2 t = Ex[x * 2 * FM + q];
-            re += a * t.x;
-            im += a * t.y;
+#pragma unroll
+            for (int i = 0; i < FWD_RY; ++i) {
+                const float a = u[min(yb + i, ly - 1) * lx + x];
+                re[i] += a * t.x;
+                im[i] += a * t.y;
+            }
         }
-        T[y * 2 * FM + q] = make_float2(re, im);
+#pragma unroll
+        for (int i = 0; i < FWD_RY; ++i)
+            if (yb + i < ly) T[(yb + i) * 2 * FM + q] = make_float2(re[i], im[i]);
     }
     __syncthreads();
     // along y: X[q][ky] = sum_y T[y][q] Ey[y][ky]
@@ -123,9 +126,7 @@ __global__ __launch_bounds__(256) void fno_dft_fwd_kernel(const FnoSample *__res
             re += t.x * w.x - t.y * w.y;
             im += t.x * w.y + t.y * w.x;
         }
-        float *dst = X + ((long long)e * S_tot + s) * (2 * FC);
-        dst[ch] = re;
-        dst[FC + ch] = im;
+        reinterpret_cast<float2 *>(X)[((long long)e * S_tot + s) * FC + ch] = make_float2(re, im);
     }
 }
 
@@ -152,7 +153,8 @@ __device__ __forceinline__ void mfma_tile(const unsigned short *A, int lda, cons
 __device__ __forceinline__ int mfma_row(int i) { return 8 * (i >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (i & 3); }
 
 // ------------------------------------------------------------------ spectral mix (MFMA)
-// Y[mode][s][:] = [Re X | Im X] (1 x 128) . Rb[mode] (128 x 128), 64 samples per workgroup.
+// Y[mode][s][:] = X[mode][s][:] (1 x 128, Re/Im interleaved per channel) . Rb[mode] (128 x 128),
+// 64 samples per workgroup.
 __global__ __launch_bounds__(256) void fno_spectral_kernel(const float *__restrict__ X,
                                                            const unsigned short *__restrict__ Rb,
                                                            float *__restrict__ Y, int S_tot) {
@@ -189,22 +191,26 @@ __global__ __launch_bounds__(256) void fno_spectral_kernel(const float *__restri
 // with c_0 = 1, c_ky = 2 (Hermitian completion of the real signal along y).
 __global__ __launch_bounds__(256) void fno_dft_inv_kernel(const FnoSample *__restrict__ smp, const int *__restrict__ sact,
                                                           const float *__restrict__ Y, float *__restrict__ spec,
-                                                          int S_tot) {
+                                                          int S_tot, const float2 *__restrict__ tw) {
     __shared__ float2 Ys[FMODES];
     __shared__ float2 P[72 * 2 * FM];
-    __shared__ float2 Ex[72 * 2 * FM];
+    __shared__ float2 ExT[2 * FM * 72];     // [q][x]: consecutive x in consecutive banks
     __shared__ float2 Ey[72 * FM];
     const int ch = blockIdx.x, s = blockIdx.y;
     if (sact && !sact[s]) return;
     const FnoSample S = smp[s];
     const int lx = S.lx, ly = S.ly, n = lx * ly;
     for (int e = threadIdx.x; e < FMODES; e += 256) {
-        const float *src = Y + ((long long)e * S_tot + s) * (2 * FC);
+        const float2 v = reinterpret_cast<const float2 *>(Y)[((long long)e * S_tot + s) * FC + ch];
         const float c = (e % FM) == 0 ? 1.f : 2.f;
-        Ys[e] = make_float2(c * src[ch], c * src[FC + ch]);
+        Ys[e] = make_float2(c * v.x, c * v.y);
     }
-    twiddles(Ex, lx, 2 * FM, 1, 1.f);
-    twiddles(Ey, ly, FM, 0, 1.f);
+    {
+        const float2 *twx = tw + (long long)FNO_TW_UNIT * lx * (lx - 1) / 2 + FNO_TW_INV_X * lx;
+        const float2 *twy = tw + (long long)FNO_TW_UNIT * ly * (ly - 1) / 2 + FNO_TW_INV_Y * ly;
+        for (int i = threadIdx.x; i < lx * 2 * FM; i += 256) ExT[i] = twx[i];
+        for (int i = threadIdx.x; i < ly * FM; i += 256) Ey[i] = twy[i];
+    }
     __syncthreads();
     // along y: P[y][q] = sum_ky Ys[q][ky] Ey[y][ky]
     for (int e = threadIdx.x; e < ly * 2 * FM; e += 256) {
@@ -218,17 +224,28 @@ __global__ __launch_bounds__(256) void fno_dft_inv_kernel(const FnoSample *__res
         P[y * 2 * FM + q] = make_float2(re, im);
     }
     __syncthreads();
-    // along x: out[y][x] = Re sum_q P[y][q] Ex[x][q]
+    // along x: out[y][x] = Re sum_q P[y][q] Ex[x][q]; a thread owns one x and
+    // INV_RY rows: one conflict-free twiddle load per q feeds INV_RY products,
+    // the P loads are broadcasts
+    constexpr int INV_RY = 8;
     const float norm = 1.f / (float)(lx * ly);
     float *dst = spec + S.cell_off * FC + (long long)ch * n;
-    for (int e = threadIdx.x; e < n; e += 256) {
-        const int y = e / lx, x = e - y * lx;
-        float re = 0.f;
+    for (int e = threadIdx.x; e < ((ly + INV_RY - 1) / INV_RY) * lx; e += 256) {
+        const int yb = (e / lx) * INV_RY, x = e - (e / lx) * lx;
+        float re[INV_RY];
+#pragma unroll
+        for (int i = 0; i < INV_RY; ++i) re[i] = 0.f;
         for (int q = 0; q < 2 * FM; ++q) {
-            const float2 t = P[y * 2 * FM + q], w = Ex[x * 2 * FM + q];
-            re += t.x * w.x - t.y * w.y;
+            const float2 w = ExT[q * lx + x];
+#pragma unroll
+            for (int i = 0; i < INV_RY; ++i) {
+                const float2 t = P[min(yb + i, ly - 1) * 2 * FM + q];
+                re[i] += t.x * w.x - t.y * w.y;
+            }
         }
-        dst[e] = re * norm;
+#pragma unroll
+        for (int i = 0; i < INV_RY; ++i)
+            if (yb + i < ly) dst[(yb + i) * lx + x] = re[i] * norm;
     }
 }
 
@@ -331,10 +348,10 @@ void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, con
                        net.lift_w, net.lift_b, act0);
     float *cur = act0, *nxt = act1;
     for (int l = 0; l < net.layers; ++l) {
-        hipLaunchKernelGGL(fno_dft_fwd_kernel, dim3(FC, S_tot), dim3(256), 0, st, smp, sact, cur, X, S_tot);
+        hipLaunchKernelGGL(fno_dft_fwd_kernel, dim3(FC, S_tot), dim3(256), 0, st, smp, sact, cur, X, S_tot, net.tw);
         hipLaunchKernelGGL(fno_spectral_kernel, dim3(FMODES, (S_tot + 63) / 64), dim3(256), 0, st, X,
                            net.R + (long long)l * FMODES * 128 * 128, Y, S_tot);
-        hipLaunchKernelGGL(fno_dft_inv_kernel, dim3(FC, S_tot), dim3(256), 0, st, smp, sact, Y, spec, S_tot);
+        hipLaunchKernelGGL(fno_dft_inv_kernel, dim3(FC, S_tot), dim3(256), 0, st, smp, sact, Y, spec, S_tot, net.tw);
         hipLaunchKernelGGL(fno_pointwise_kernel, dim3(tblk, S_tot), dim3(256), 0, st, smp, sact, cur, spec,
                            net.W + (long long)l * FC * FC, net.b + (long long)l * FC, nxt,
                            l < net.layers - 1 ? 1 : 0);
