@@ -323,6 +323,7 @@ def main():
            "final_rel_residual": [float(f"{v:.3e}") for v in fin.ravel()],
            "setup_ms": round(setup_ms, 1),
            "kernel_ms_per_step": share,
+           "launch_parameters": P.tuning(),
            "roofline": roofline}
 
     if not a.no_stencil:

@@ -202,6 +202,19 @@ nosdd_status nosdd_coarse_basis(const nosdd_problem *p, int wl, nosdd_c32 *phi, 
 nosdd_status nosdd_profile(nosdd_problem *p, int enable);
 nosdd_status nosdd_kernel_times(const nosdd_problem *p, double ms[4], long long launches[4], long long units[4]);
 
+/* Launch-parameter autotuning (enabled by default).  At the first solve of a
+ * given batch shape, before any graph capture, the library times candidate
+ * launch parameters on the problem's own buffers and keeps the fastest: the
+ * number of workgroups per right-hand side of the Gram-Schmidt passes (per
+ * basis-size bucket j + 1 <= 8, 16, 24, 32) and the prefetch depth of the
+ * batched subdomain solve (the depths the subdomain block size allows).  The
+ * arithmetic is the same for every candidate.  Disabling restores the
+ * defaults.  nosdd_tuning reports out[6] = {solve prefetch depth (0 =
+ * default), workgroups per RHS for the four buckets, flags: 1 Gram-Schmidt
+ * tuned, 2 subdomain solve tuned}. */
+nosdd_status nosdd_autotune(nosdd_problem *p, int enable);
+nosdd_status nosdd_tuning(const nosdd_problem *p, int out[6]);
+
 /* Launch mode of the solve loop.  Enabled (the default): every Arnoldi step
  * of a restart cycle (subdomain solves, operator, coarse correction,
  * Gram-Schmidt passes, Givens) is captured once into a HIP graph on a private

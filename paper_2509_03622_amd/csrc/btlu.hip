@@ -409,29 +409,57 @@ void bt_solve_prepare(int bmax, int max_cells) {
     const size_t lds = (size_t)max_cells * sizeof(float2);
     if (lds <= 65536) return;
     const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
-    const void *f = maxj <= 9    ? reinterpret_cast<const void *>(&bt_solve_kernel<9, 4>)
-                    : maxj <= 13 ? reinterpret_cast<const void *>(&bt_solve_kernel<13, 3>)
-                                 : reinterpret_cast<const void *>(&bt_solve_kernel<16, 3>);
-    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *fs[3];
+    int nf = 0;
+    if (maxj <= 9) {
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<9, 3>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<9, 4>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<9, 5>);
+    } else if (maxj <= 13) {
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<13, 3>);
+    } else {
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<16, 3>);
+    }
+    for (int i = 0; i < nf; ++i) (void)hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// Prefetch depths available for a block size (the register ring holds NS - 1
+// blocks ahead); the first is the default.
+int bt_solve_depths(int bmax, int *depths) {
+    const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
+    if (maxj <= 9) {
+        depths[0] = 4;
+        depths[1] = 3;
+        depths[2] = 5;
+        return 3;
+    }
+    depths[0] = 3;
+    return 1;
 }
 
 void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, int n_jobs, int n_src,
                      const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
                      const float2 *vin, long long vin_stride, float2 *out, long long out_stride, const int *active,
-                     int mode, int bmax, int max_cells) {
+                     int mode, int bmax, int max_cells, int depth) {
     dim3 grid(n_jobs);
     const int threads = ((bmax / 2) * BT_GROUP + 63) / 64 * 64;
     const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
     const size_t lds = (size_t)max_cells * sizeof(float2);
-    if (maxj <= 9)
-        bt_solve_launch<9, 4>(s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin, vin_stride,
-                              out, out_stride, active, mode, order);
-    else if (maxj <= 13)
-        bt_solve_launch<13, 3>(s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin,
-                               vin_stride, out, out_stride, active, mode, order);
-    else
-        bt_solve_launch<16, 3>(s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin,
-                               vin_stride, out, out_stride, active, mode, order);
+#define BT_ARGS s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin, vin_stride, out, \
+                out_stride, active, mode, order
+    if (maxj <= 9) {
+        if (depth == 3)
+            bt_solve_launch<9, 3>(BT_ARGS);
+        else if (depth == 5)
+            bt_solve_launch<9, 5>(BT_ARGS);
+        else
+            bt_solve_launch<9, 4>(BT_ARGS);
+    } else if (maxj <= 13) {
+        bt_solve_launch<13, 3>(BT_ARGS);
+    } else {
+        bt_solve_launch<16, 3>(BT_ARGS);
+    }
+#undef BT_ARGS
 }
 
 }  // namespace nosdd

@@ -61,6 +61,10 @@ struct DevBuf {
 
 struct Workspace {
     int n_rhs = 0, m = 0, max_iters = 0, nblk = 0;
+    // Gram-Schmidt workgroups per RHS by basis size (bucket of j + 1: <= 8, 16, 24, 32),
+    // chosen by the autotuner; nblk_max bounds the partials buffer
+    int nblk_b[4] = {0, 0, 0, 0}, nblk_max = 0;
+    bool tuned = false;
     long long N = 0;
     DevBuf x, b, V, Z, w, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, bnorm2, bnorm, beta2,
         iters, kcyc, active, want, ones, reorth, inv_h, flags, hist, cd_, cc_;
@@ -114,6 +118,11 @@ struct nosdd_problem {
         int n_jobs = 0;
     };
     std::map<std::pair<int, int>, OrderBuf> orders;
+    // autotuned launch parameters (subdomain-solve prefetch depth; the Gram-Schmidt
+    // grid lives in the workspace)
+    bool use_autotune = true;
+    int bt_depth = 0;
+    bool bt_tuned = false;
     // one captured graph per Arnoldi step j of a restart cycle (replayed every cycle)
     bool use_graphs = true;
     std::vector<hipGraphExec_t> gexec;
@@ -355,18 +364,22 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     long long nb = (N + 2047) / 2048;
     nb = std::max<long long>(nb, std::min<long long>((N + 255) / 256, (512 + n_rhs - 1) / n_rhs));
     const int nblk = (int)std::max<long long>(1, std::min<long long>(1024, nb));
+    if (w.n_rhs != n_rhs || w.N != N || w.m != m) w.tuned = false;
     w.n_rhs = n_rhs;
     w.m = m;
     w.max_iters = max_iters;
     w.N = N;
     w.nblk = nblk;
+    w.nblk_max = std::min(1024, 2 * nblk);
+    if (!w.tuned)
+        for (int &v : w.nblk_b) v = nblk;
     const size_t vec = (size_t)n_rhs * N * sizeof(float2);
     HIPCHK(ctx, w.x.ensure(vec * 2));        // FP64 iterate
     HIPCHK(ctx, w.b.ensure(vec));
     HIPCHK(ctx, w.w.ensure(vec));
     HIPCHK(ctx, w.V.ensure(vec * (m + 1)));
     HIPCHK(ctx, w.Z.ensure(vec * m));
-    HIPCHK(ctx, w.partial.ensure((size_t)n_rhs * nblk * 33 * sizeof(double2)));
+    HIPCHK(ctx, w.partial.ensure((size_t)n_rhs * w.nblk_max * 33 * sizeof(double2)));
     const size_t hsz = (size_t)n_rhs * (m + 1) * m * sizeof(float2);
     HIPCHK(ctx, w.H.ensure(hsz));
     HIPCHK(ctx, w.H2.ensure(hsz));
@@ -673,7 +686,7 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
         const auto &ob = p->orders.at(std::make_pair(n_rhs, n_src));
         launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ob.buf.as<int2>(), ob.n_jobs, n_src, p->d_dinv.as<float2>(),
                         p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, active, 0, p->bmax,
-                        p->max_cells);
+                        p->max_cells, p->bt_depth);
     }
     }
     if (wout == nullptr) return;
@@ -967,6 +980,100 @@ nosdd_status coarse_setup(nosdd_problem *p) {
     return NOSDD_OK;
 }
 
+int cgs_bucket(int nv) { return nv <= 8 ? 0 : nv <= 16 ? 1 : nv <= 24 ? 2 : 3; }
+
+// Launch-parameter autotuning on the problem's own buffers, once per
+// workspace shape (and, for the subdomain solve, once per set-up), before any
+// graph capture.  Every candidate computes the same result (the Gram-Schmidt
+// reductions are fixed-order for a given grid, and the prefetch depth does
+// not change the arithmetic), so only time decides:
+//   * Gram-Schmidt workgroups per RHS: {nblk/2, nblk, 2 nblk} around the
+//     bandwidth heuristic, per basis-size bucket, timing one dots, fused
+//     update-dots and update pass at the bucket's middle size;
+//   * subdomain-solve prefetch depth among those the block size allows.
+// Each candidate is timed as the median of three runs with HIP events.
+nosdd_status autotune(nosdd_problem *p, int n_rhs, int n_src, int m, const GivensArgs &ga) {
+    (void)ga;
+    nosdd_ctx *ctx = p->ctx;
+    Workspace &w = p->ws;
+    hipStream_t s = ctx->stream;
+    const long long N = w.N;
+    const long long vstride = (long long)n_rhs * N;
+    float2 *V = w.V.as<float2>(), *wv = w.w.as<float2>(), *Z = w.Z.as<float2>();
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    auto time_ms = [&](auto &&launch) -> float {
+        float t[3];
+        launch();                                      // warm
+        for (int r = 0; r < 3; ++r) {
+            (void)hipEventRecord(e0, s);
+            launch();
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&t[r], e0, e1);
+        }
+        std::sort(t, t + 3);
+        return t[1];
+    };
+    if (!w.tuned) {
+        std::vector<int> cand;
+        for (int c : {w.nblk, std::max(1, w.nblk / 2), std::min(w.nblk_max, 2 * w.nblk)})
+            if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+        const int probe_nv[4] = {6, 14, 22, 30};
+        double2 *part = w.partial.as<double2>();
+        const int *ones = w.ones.as<int>();
+        for (int bk = 0; bk < 4; ++bk) {
+            const int nv = std::min(probe_nv[bk], m);        // the update writes basis slot nv <= m
+            if (nv < 1) continue;
+            float best = 1e30f;
+            int pick = w.nblk;
+            for (int c : cand) {
+                const float ms = time_ms([&] {
+                    launch_cgs_dots(s, V, vstride, nv, wv, N, n_rhs, ones, part, c);
+                    launch_cgs_update_dots(s, V, vstride, nv, wv, V + nv * vstride, N, n_rhs, ones,
+                                           w.H.as<float2>(), m, nv - 1, part, c);
+                    launch_cgs_update(s, V, vstride, nv, V + nv * vstride, V + nv * vstride, N, n_rhs, ones,
+                                      w.H2.as<float2>(), m, nv - 1, part, c);
+                });
+                if (ms < best) {
+                    best = ms;
+                    pick = c;
+                }
+            }
+            w.nblk_b[bk] = pick;
+        }
+        w.tuned = true;
+    }
+    if (!p->bt_tuned && p->sub_solver == 0) {
+        int depths[4];
+        const int nd = bt_solve_depths(p->bmax, depths);
+        const int2 *ord = nullptr;
+        int nj = 0;
+        nosdd_status so = solve_order(p, n_rhs, n_src, &ord, &nj);
+        if (so != NOSDD_OK) return so;
+        float best = 1e30f;
+        int pick = 0;
+        for (int i = 0; i < nd; ++i) {
+            const float ms = time_ms([&] {
+                launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ord, nj, n_src, p->d_dinv.as<float2>(),
+                                p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, V, N, Z, N,
+                                w.ones.as<int>(), 0, p->bmax, p->max_cells, depths[i]);
+            });
+            if (ms < best) {
+                best = ms;
+                pick = depths[i];
+            }
+        }
+        p->bt_depth = pick;
+        p->bt_tuned = true;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(ctx, hipGetLastError());
+    return NOSDD_OK;
+}
+
 // Capture (or reuse) one graph per Arnoldi step j of a restart cycle.  The
 // graphs bake in buffer addresses, sizes and the solve options, so they are
 // keyed on those and on the allocation generation.  Each graph ends with a
@@ -990,7 +1097,8 @@ nosdd_status ensure_graphs(nosdd_problem *p, int n_rhs, int n_src, int m, const 
     long long tolbits = 0;
     std::memcpy(&tolbits, &o->tol, sizeof(double));
     const std::vector<long long> key = {g_alloc_gen.load(), n_rhs, n_src, m, o->max_iters, tolbits,
-                                        (long long)(intptr_t)p->h_flags};
+                                        (long long)(intptr_t)p->h_flags, p->bt_depth, w.nblk_b[0], w.nblk_b[1],
+                                        w.nblk_b[2], w.nblk_b[3]};
     if (key == p->gkey && (int)p->gexec.size() == m) return NOSDD_OK;
     p->drop_graphs();
     if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -1031,7 +1139,6 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         if (st != NOSDD_OK) return st;
     }
     Workspace &w = p->ws;
-    const int nblk = w.nblk;
     GivensArgs ga;
     ga.H = w.H.as<float2>();
     ga.ldh = m;
@@ -1072,8 +1179,8 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
                            -1.0f);
     }
     // ||b||
-    launch_cgs_dots(s, V, vstride, 0, b, N, n_rhs, w.ones.as<int>(), w.partial.as<double2>(), nblk);
-    launch_cgs_reduce(s, w.partial.as<double2>(), nblk, 0, n_rhs, nullptr, 0, 0, w.bnorm2.as<double>(), ga);
+    launch_cgs_dots(s, V, vstride, 0, b, N, n_rhs, w.ones.as<int>(), w.partial.as<double2>(), w.nblk_b[0]);
+    launch_cgs_reduce(s, w.partial.as<double2>(), w.nblk_b[0], 0, n_rhs, nullptr, 0, 0, w.bnorm2.as<double>(), ga);
     std::vector<double> bn2(n_rhs), beta2(n_rhs);
     HIPCHK(ctx, hipMemcpyAsync(bn2.data(), w.bnorm2.p, n_rhs * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
@@ -1100,13 +1207,14 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         double2 *part = w.partial.as<double2>();
         const int *ro = w.reorth.as<int>();
         const float *ih = w.inv_h.as<float>();
-        launch_cgs_dots(st, V, vstride, j + 1, wv, N, n_rhs, active, part, nblk);
-        launch_cgs_reduce(st, part, nblk, j + 1, n_rhs, active, j, 1, nullptr, ga);
+        const int nb = w.nblk_b[cgs_bucket(j + 1)];
+        launch_cgs_dots(st, V, vstride, j + 1, wv, N, n_rhs, active, part, nb);
+        launch_cgs_reduce(st, part, nb, j + 1, n_rhs, active, j, 1, nullptr, ga);
         // first-pass update with the second pass's dots taken from the same loads
-        launch_cgs_update_dots(st, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, j, part, nblk);
-        launch_cgs_reduce(st, part, nblk, j + 1, n_rhs, nullptr, j, 5, nullptr, ga);
-        launch_cgs_update(st, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, j, part, nblk);
-        launch_cgs_reduce(st, part, nblk, 0, n_rhs, ro, j, 4, nullptr, ga);
+        launch_cgs_update_dots(st, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, j, part, nb);
+        launch_cgs_reduce(st, part, nb, j + 1, n_rhs, nullptr, j, 5, nullptr, ga);
+        launch_cgs_update(st, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, j, part, nb);
+        launch_cgs_reduce(st, part, nb, 0, n_rhs, ro, j, 4, nullptr, ga);
         launch_scale(st, Vn, N, n_rhs, active, ih);
     };
     {
@@ -1116,6 +1224,13 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         if (so != NOSDD_OK) {
             (void)hipHostFree(h_act);
             return so;
+        }
+    }
+    if (p->use_autotune) {
+        nosdd_status ts = autotune(p, n_rhs, n_src, m, ga);
+        if (ts != NOSDD_OK) {
+            (void)hipHostFree(h_act);
+            return ts;
         }
     }
     const bool graphs = p->use_graphs && !p->prof;
@@ -1133,8 +1248,8 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         launch_residual64(s, x, b, wv, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->nx,
                           p->ny, n_rhs, n_src);
         }
-        launch_cgs_dots(s, V, vstride, 0, wv, N, n_rhs, w.ones.as<int>(), w.partial.as<double2>(), nblk);
-        launch_cgs_reduce(s, w.partial.as<double2>(), nblk, 0, n_rhs, nullptr, 0, 0, w.beta2.as<double>(), ga);
+        launch_cgs_dots(s, V, vstride, 0, wv, N, n_rhs, w.ones.as<int>(), w.partial.as<double2>(), w.nblk_b[0]);
+        launch_cgs_reduce(s, w.partial.as<double2>(), w.nblk_b[0], 0, n_rhs, nullptr, 0, 0, w.beta2.as<double>(), ga);
         HIPCHK(ctx, hipMemcpyAsync(beta2.data(), w.beta2.p, n_rhs * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipMemcpyAsync(iters.data(), w.iters.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(ctx, hipStreamSynchronize(s));
@@ -1483,6 +1598,8 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
     p->sub_solver = o->sub_solver;
     p->setup_done = true;
     p->drop_graphs();
+    p->bt_tuned = false;
+    p->bt_depth = 0;
     return NOSDD_OK;
 }
 
@@ -1697,6 +1814,27 @@ nosdd_status nosdd_profile(nosdd_problem *p, int enable) {
         p->ev_next = 0;
     }
     p->prof = enable != 0;
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_autotune(nosdd_problem *p, int enable) {
+    if (!p) return NOSDD_EINVAL;
+    p->use_autotune = enable != 0;
+    if (!p->use_autotune) {
+        p->ws.tuned = false;
+        for (int &v : p->ws.nblk_b) v = p->ws.nblk;
+        p->bt_tuned = false;
+        p->bt_depth = 0;
+        p->drop_graphs();
+    }
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_tuning(const nosdd_problem *p, int out[6]) {
+    if (!p || !out) return NOSDD_EINVAL;
+    out[0] = p->bt_depth;
+    for (int i = 0; i < 4; ++i) out[1 + i] = p->ws.nblk_b[i];
+    out[5] = (p->ws.tuned ? 1 : 0) | (p->bt_tuned ? 2 : 0);
     return NOSDD_OK;
 }
 

@@ -87,11 +87,13 @@ constexpr int BT_FACT_SCRATCH_B = 128;
 constexpr int BT_NBMAX = 256;                                // longest tile side
 constexpr int BT_LDS_MAX_CELLS = 15360;                      // 120 KB of LDS
 // One workgroup per job: order[n_jobs] = (tile, rhs), tile < 0 for padding.
+// depth: prefetch depth of the D-block ring (one of bt_solve_depths, 0 = default).
 void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, int n_jobs, int n_src,
                      const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
                      const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
-                     const int *active, int mode, int bmax, int max_cells);
+                     const int *active, int mode, int bmax, int max_cells, int depth = 0);
 void bt_solve_prepare(int bmax, int max_cells);
+int bt_solve_depths(int bmax, int *depths);
 
 void launch_robin_trace(hipStream_t s, const int4 *entries, int n_entries, const float *eps,
                         const float *k0, float h, int nx, int ny, const float2 *x, float2 *g,

@@ -22,7 +22,7 @@ EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_p
            "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
-           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs"]
+           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_autotune", "nosdd_tuning"]
 
 
 class Grid(C.Structure):
@@ -84,6 +84,8 @@ def load(path=LIBPATH):
         "nosdd_kernel_times": (i, [vp, vp, vp, vp]),
         "nosdd_nn_apply": (i, [vp, vp, vp]),
         "nosdd_graphs": (i, [vp, i]),
+        "nosdd_autotune": (i, [vp, i]),
+        "nosdd_tuning": (i, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -252,6 +254,17 @@ class Problem:
             out.append(phi[off:off + n].reshape(kc, int(b[3]), int(b[2])))
             off += n
         return out, box
+
+    def autotune(self, enable=True):
+        """Time candidate launch parameters at the first solve of a batch shape (default on)."""
+        return self.ctx.check(self.L.nosdd_autotune(self.h, 1 if enable else 0))
+
+    def tuning(self):
+        """{depth, nblk per basis bucket, flags} chosen by the autotuner."""
+        out = np.zeros(6, np.int32)
+        self.ctx.check(self.L.nosdd_tuning(self.h, out.ctypes.data))
+        return {"solve_prefetch_depth": int(out[0]), "gs_workgroups_per_rhs": out[1:5].tolist(),
+                "tuned_gram_schmidt": bool(out[5] & 1), "tuned_subdomain_solve": bool(out[5] & 2)}
 
     def graphs(self, enable=True):
         """Replay captured per-step HIP graphs (default) or launch kernels one by one."""

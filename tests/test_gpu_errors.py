@@ -100,3 +100,28 @@ def test_graph_replay_is_bit_identical_to_eager_launch():
         del x
     P.close()
     ctx.close()
+
+
+def test_autotuned_launch_parameters_keep_the_result():
+    """The autotuner only picks among launch parameters with the same
+    arithmetic: the tuned solve reaches the same field as the defaults."""
+    from paper_2509_03622_amd import nosdd
+    w = random_small(42, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.1,), n_src=2, k_coarse=1)
+    ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+    P.setup(k_coarse=1, k_trial=8)
+    P.autotune(False)
+    E0, h0, it0, f0, s0 = P.solve(w.J(), tol=1e-6, restart=30, max_iters=600)
+    t0 = P.tuning()
+    assert not t0["tuned_gram_schmidt"] and not t0["tuned_subdomain_solve"]
+    P.autotune(True)
+    E1, h1, it1, f1, s1 = P.solve(w.J(), tol=1e-6, restart=30, max_iters=600)
+    t1 = P.tuning()
+    assert t1["tuned_gram_schmidt"] and t1["tuned_subdomain_solve"], t1
+    assert t1["solve_prefetch_depth"] in (3, 4, 5)
+    assert all(v > 0 for v in t1["gs_workgroups_per_rhs"])
+    assert s0 == 0 and s1 == 0
+    assert np.all(np.abs(it0 - it1) <= 1), (it0, it1)
+    assert np.linalg.norm(E1 - E0) <= 2e-6 * np.linalg.norm(E0)
+    P.close()
+    ctx.close()
