@@ -1568,8 +1568,9 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (o->sub_solver == 1) {
         for (auto &t : p->tiles)
-            if (t.x1 - t.x0 > 72 || t.y1 - t.y0 > 72)
-                return fail(ctx, NOSDD_EPARTITION, "the neural subdomain solver takes subdomains of at most 72 x 72");
+            if (t.x1 - t.x0 > 72 || t.y1 - t.y0 > 72 || t.x1 - t.x0 < 32 || t.y1 - t.y0 < 32)
+                return fail(ctx, NOSDD_EPARTITION,
+                            "the neural subdomain solver takes subdomains of 32 x 32 to 72 x 72 cells");
         st = load_network(p, o->nn_weights);
         if (st) return st;
         st = build_aux(p);

@@ -71,62 +71,185 @@ __global__ __launch_bounds__(256) void fno_lift_kernel(const FnoSample *__restri
     }
 }
 
-// ------------------------------------------------------------------ forward DFT
-// X[mode][s][2c], X[mode][s][2c+1] = Re, Im of the kept mode of channel c,
-// mode = q * FM + ky.
-__global__ __launch_bounds__(256) void fno_dft_fwd_kernel(const FnoSample *__restrict__ smp, const int *__restrict__ sact,
-                                                          const float *__restrict__ act, float *__restrict__ X, int S_tot,
-                                                          const float2 *__restrict__ tw) {
-    __shared__ float u[72 * 72];
-    __shared__ float2 T[72 * 2 * FM];
-    __shared__ float2 Ex[72 * 2 * FM];
-    __shared__ float2 Ey[72 * FM];
-    const int ch = blockIdx.x, s = blockIdx.y;
+// ------------------------------------------------------------------ truncated DFTs on MFMA
+// The truncated transforms of one subdomain are small dense contractions over
+// all 64 channels at once, computed as FP32 MFMA GEMMs (v_mfma_f32_32x32x2f32):
+//   forward  A: T1[c][x][ky]   = sum_y u[c][y][x] e^{-2pi i ky y/Ly}        (M = 64 Lx, K = Ly, N = 32)
+//            B: X[kx][ky][c]   = sum_x T1[c][x][ky] e^{-2pi i kx x/Lx}      (M = 64 x 16, K = 2 Lx, N = 64)
+//   inverse  C: P[c][ky][x]    = sum_kx Y[kx][ky][c] e^{+2pi i kx x/Lx}     (M = 64 x 16, K = 64, N = 2 Lx)
+//            D: s[c][y][x]     = Re sum_ky w_ky P[c][ky][x] e^{+2pi i ky y/Ly} / (Lx Ly)   (M = 64 Lx, K = 32, N = Ly)
+// with w_0 = 1, w_ky = 2 (Hermitian completion along y).  Complex products
+// use the real 2 x 2 form of each complex entry (Re/Im interleaved in K and
+// N).  T1 lives in the spec buffer and P in the next-activation buffer of
+// the same sample, both free at that point of the layer.
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+constexpr int DG_KC = 16;     // K chunk staged in LDS
+
+// Block tile (32 WM) x (32 WN), one 32 x 32 MFMA tile per wave (4 waves).
+// Staging: thread t owns tile row t % (32 WM) and a stride of K; arow(m)
+// precomputes whatever the A address needs for row m once per chunk, and
+// la(ctx, k) returns the operand; lb(k, n) returns B (zero outside M, N, K is
+// handled here).  sink(row, col, v) receives the tile (block-local row and
+// column): either a direct store or a write into an LDS tile that the caller
+// stores with its own coalesced mapping after a barrier.
+template <int WM, int WN, class AR, class LA, class LB, class SC>
+__device__ __forceinline__ void dft_gemm(int M, int N, int K, int m0, int n0, AR arow, LA la, LB lb, SC sink) {
+    __shared__ float As[32 * WM][DG_KC + 1];
+    __shared__ float Bs[DG_KC][32 * WN + 1];
+    constexpr int BM = 32 * WM, KSTEP = 256 / BM;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = wv % WM, wn = wv / WM;
+    const int r = threadIdx.x % BM, kq = threadIdx.x / BM;
+    const bool rin = m0 + r < M;
+    const auto actx = arow(rin ? m0 + r : m0);
+    f32x16v acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    for (int kc = 0; kc < K; kc += DG_KC) {
+#pragma unroll
+        for (int k = kq; k < DG_KC; k += KSTEP) {
+            const int kk = kc + k;
+            As[r][k] = (rin && kk < K) ? la(actx, kk) : 0.f;
+        }
+        for (int i = threadIdx.x; i < DG_KC * 32 * WN; i += 256) {
+            const int c = i % (32 * WN), k = i / (32 * WN);
+            const int n = n0 + c, kk = kc + k;
+            Bs[k][c] = (n < N && kk < K) ? lb(kk, n) : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < DG_KC; k += 2) {
+            const float av = As[wm * 32 + (lane & 31)][k + (lane >> 5)];
+            const float bv = Bs[k + (lane >> 5)][wn * 32 + (lane & 31)];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sink(wm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3), wn * 32 + (lane & 31), acc[i]);
+}
+
+// real 2 x 2 form of the complex twiddle e (input Re/Im = rin, output = rout)
+__device__ __forceinline__ float cplx_entry(float2 e, int rin, int rout) {
+    return rin == 0 ? (rout == 0 ? e.x : e.y) : (rout == 0 ? -e.y : e.x);
+}
+__device__ __forceinline__ const float2 *tw_side(const float2 *tw, int L) {
+    return tw + (long long)FNO_TW_UNIT * L * (L - 1) / 2;
+}
+
+// A: forward along y (real input): rows (c, x), K = y, N = (ky, ri).
+// Grid (ceil(64 Lmax / 128), 1, S).  T1[c][x][2 ky + ri].
+__global__ __launch_bounds__(256) void fno_dft_y_fwd_kernel(const FnoSample *__restrict__ smp,
+                                                            const int *__restrict__ sact,
+                                                            const float *__restrict__ act, float *__restrict__ T1,
+                                                            const float2 *__restrict__ tw) {
+    const int s = blockIdx.z;
     if (sact && !sact[s]) return;
     const FnoSample S = smp[s];
     const int lx = S.lx, ly = S.ly, n = lx * ly;
-    const float *src = act + S.cell_off * FC + (long long)ch * n;
-    for (int i = threadIdx.x; i < n; i += 256) u[i] = src[i];
-    {
-        const float2 *twx = tw + (long long)FNO_TW_UNIT * lx * (lx - 1) / 2;
-        const float2 *twy = tw + (long long)FNO_TW_UNIT * ly * (ly - 1) / 2 + FNO_TW_FWD_Y * ly;
-        for (int i = threadIdx.x; i < lx * 2 * FM; i += 256) Ex[i] = twx[i];
-        for (int i = threadIdx.x; i < ly * FM; i += 256) Ey[i] = twy[i];
-    }
+    const int M = FC * lx, m0 = blockIdx.x * 128;
+    if (m0 >= M) return;
+    const float *u = act + S.cell_off * FC;
+    const float *ey = reinterpret_cast<const float *>(tw_side(tw, ly) + FNO_TW_FWD_Y * ly);   // [y][2 ky + ri]
+    float *t1 = T1 + S.cell_off * FC;
+    // output rows are 32 contiguous floats and the MFMA lanes run along them
+    dft_gemm<4, 1>(
+        M, 2 * FM, ly, m0, 0, [&](int m) { return u + (m / lx) * n + (m % lx); },
+        [&](const float *row, int k) { return row[k * lx]; }, [&](int k, int nn) { return ey[k * 2 * FM + nn]; },
+        [&](int rr, int c, float v) {
+            if (m0 + rr < M) t1[(long long)(m0 + rr) * 2 * FM + c] = v;
+        });
+}
+
+// B: forward along x (complex): rows (ky, c) (all 64 channels of one ky per
+// block), K = (x, ri), N = (kx, ri).  Grid (16, 1, S).
+// X[mode = kx * 16 + ky][s][2 c + ri].
+__global__ __launch_bounds__(256) void fno_dft_x_fwd_kernel(const FnoSample *__restrict__ smp,
+                                                            const int *__restrict__ sact,
+                                                            const float *__restrict__ T1, float *__restrict__ X,
+                                                            int S_tot, const float2 *__restrict__ tw) {
+    __shared__ float Cs[64][65];
+    const int s = blockIdx.z;
+    if (sact && !sact[s]) return;
+    const FnoSample S = smp[s];
+    const int lx = S.lx, ky = blockIdx.x;
+    const float *t1 = T1 + S.cell_off * FC;
+    const float2 *ex = tw_side(tw, lx);                  // [x][kx]
+    dft_gemm<2, 2>(
+        FC, 4 * FM, 2 * lx, 0, 0, [&](int c) { return t1 + (long long)c * lx * 2 * FM + 2 * ky; },
+        [&](const float *row, int k) { return row[(k >> 1) * 2 * FM + (k & 1)]; },
+        [&](int k, int nn) { return cplx_entry(ex[(k >> 1) * 2 * FM + (nn >> 1)], k & 1, nn & 1); },
+        [&](int rr, int c, float v) { Cs[rr][c] = v; });
     __syncthreads();
-    // along x: T[y][q] = sum_x u[y][x] Ex[x][q]; a thread owns one q and FWD_RY
-    // rows, so each twiddle load (consecutive q across lanes) feeds FWD_RY
-    // products and the u loads are broadcasts
-    constexpr int FWD_RY = 4;
-    for (int e = threadIdx.x; e < ((ly + FWD_RY - 1) / FWD_RY) * 2 * FM; e += 256) {
-        const int yb = (e / (2 * FM)) * FWD_RY, q = e - (e / (2 * FM)) * (2 * FM);
-        float re[FWD_RY], im[FWD_RY];
-#pragma unroll
-        for (int i = 0; i < FWD_RY; ++i) re[i] = im[i] = 0.f;
-        for (int x = 0; x < lx; ++x) {
-            const float2 t = Ex[x * 2 * FM + q];
-#pragma unroll
-            for (int i = 0; i < FWD_RY; ++i) {
-                const float a = u[min(yb + i, ly - 1) * lx + x];
-                re[i] += a * t.x;
-                im[i] += a * t.y;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < FWD_RY; ++i)
-            if (yb + i < ly) T[(yb + i) * 2 * FM + q] = make_float2(re[i], im[i]);
+    // for each kx: 64 channels x (Re, Im) = 128 contiguous floats
+    for (int i = threadIdx.x; i < 2 * FM * 2 * FC; i += 256) {
+        const int kx = i / (2 * FC), j = i % (2 * FC), c = j >> 1, ri = j & 1;
+        X[((long long)(kx * FM + ky) * S_tot + s) * (2 * FC) + j] = Cs[c][2 * kx + ri];
     }
+}
+
+// C: inverse along x (complex): rows (c, ky), K = (kx, ri), N = (x, ri).
+// Grid (16, ceil(2 Lmax / 64), S).  P[c][ky][2 x + ri].
+__global__ __launch_bounds__(256) void fno_dft_x_inv_kernel(const FnoSample *__restrict__ smp,
+                                                            const int *__restrict__ sact,
+                                                            const float *__restrict__ Y, float *__restrict__ P,
+                                                            int S_tot, const float2 *__restrict__ tw) {
+    __shared__ float Cs[64][65];
+    const int s = blockIdx.z;
+    if (sact && !sact[s]) return;
+    const FnoSample S = smp[s];
+    const int lx = S.lx;
+    const int N = 2 * lx, m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    if (n0 >= N) return;
+    float *pp = P + S.cell_off * FC;
+    const float2 *ext = tw_side(tw, lx) + FNO_TW_INV_X * lx;     // [kx][x]
+    const float *Ys = Y + (long long)s * (2 * FC);
+    const long long mode_stride = (long long)S_tot * (2 * FC);
+    dft_gemm<2, 2>(
+        FC * FM, N, 4 * FM, m0, n0,
+        [&](int m) { return Ys + (long long)(m % FM) * mode_stride + 2 * (m / FM); },
+        [&](const float *row, int k) { return row[(long long)(k >> 1) * FM * mode_stride + (k & 1)]; },
+        [&](int k, int nn) { return cplx_entry(ext[(k >> 1) * lx + (nn >> 1)], k & 1, nn & 1); },
+        [&](int rr, int c, float v) { Cs[rr][c] = v; });
     __syncthreads();
-    // along y: X[q][ky] = sum_y T[y][q] Ey[y][ky]
-    for (int e = threadIdx.x; e < FMODES; e += 256) {
-        const int q = e / FM, ky = e - q * FM;
-        float re = 0.f, im = 0.f;
-        for (int y = 0; y < ly; ++y) {
-            const float2 t = T[y * 2 * FM + q], w = Ey[y * FM + ky];
-            re += t.x * w.x - t.y * w.y;
-            im += t.x * w.y + t.y * w.x;
-        }
-        reinterpret_cast<float2 *>(X)[((long long)e * S_tot + s) * FC + ch] = make_float2(re, im);
+    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+        const int rr = i / 64, c = i % 64;
+        if (n0 + c < N) pp[(long long)(m0 + rr) * N + n0 + c] = Cs[rr][c];
+    }
+}
+
+// D: inverse along y, real part: rows (c, x), K = (ky, ri), N = y.
+// Grid (ceil(64 Lmax / 128), ceil(Lmax / 32), S).  spec[c][y][x].
+__global__ __launch_bounds__(256) void fno_dft_y_inv_kernel(const FnoSample *__restrict__ smp,
+                                                            const int *__restrict__ sact,
+                                                            const float *__restrict__ P, float *__restrict__ spec,
+                                                            const float2 *__restrict__ tw) {
+    __shared__ float Cs[128][33];
+    const int s = blockIdx.z;
+    if (sact && !sact[s]) return;
+    const FnoSample S = smp[s];
+    const int lx = S.lx, ly = S.ly, n = lx * ly;
+    const int M = FC * lx, m0 = blockIdx.x * 128, n0 = blockIdx.y * 32;
+    if (m0 >= M || n0 >= ly) return;
+    const float *pp = P + S.cell_off * FC;
+    const float2 *ey = tw_side(tw, ly) + FNO_TW_INV_Y * ly;       // [y][ky]
+    const float norm = 1.f / (float)n;
+    float *sp = spec + S.cell_off * FC;
+    dft_gemm<4, 1>(
+        M, ly, 2 * FM, m0, n0, [&](int m) { return pp + (m / lx) * FM * 2 * lx + 2 * (m % lx); },
+        [&](const float *row, int k) { return row[(k >> 1) * 2 * lx + (k & 1)]; },
+        [&](int k, int nn) {
+            const float2 e = ey[nn * FM + (k >> 1)];
+            const float w = ((k >> 1) == 0 ? 1.f : 2.f) * norm;
+            return (k & 1) ? -w * e.y : w * e.x;
+        },
+        [&](int rr, int c, float v) { Cs[rr][c] = v; });
+    __syncthreads();
+    // rows m = (c, x) with x fastest: lanes along m give contiguous x runs
+    for (int i = threadIdx.x; i < 128 * 32; i += 256) {
+        const int rr = i % 128, c = i / 128;
+        const int m = m0 + rr, y = n0 + c;
+        if (m < M && y < ly) sp[(m / lx) * n + y * lx + (m % lx)] = Cs[rr][c];
     }
 }
 
@@ -183,69 +306,6 @@ __global__ __launch_bounds__(256) void fno_spectral_kernel(const float *__restri
             const int r = s0 + rb + mfma_row(i);
             if (r < S_tot) Ym[(long long)r * 128 + col] = acc[i];
         }
-    }
-}
-
-// ------------------------------------------------------------------ inverse DFT
-// spec[s][c][y][x] = 1/(lx ly) sum_q sum_ky c_ky Re(Y[q][ky] exp(+2 pi i (kx x/lx + ky y/ly)))
-// with c_0 = 1, c_ky = 2 (Hermitian completion of the real signal along y).
-__global__ __launch_bounds__(256) void fno_dft_inv_kernel(const FnoSample *__restrict__ smp, const int *__restrict__ sact,
-                                                          const float *__restrict__ Y, float *__restrict__ spec,
-                                                          int S_tot, const float2 *__restrict__ tw) {
-    __shared__ float2 Ys[FMODES];
-    __shared__ float2 P[72 * 2 * FM];
-    __shared__ float2 ExT[2 * FM * 72];     // [q][x]: consecutive x in consecutive banks
-    __shared__ float2 Ey[72 * FM];
-    const int ch = blockIdx.x, s = blockIdx.y;
-    if (sact && !sact[s]) return;
-    const FnoSample S = smp[s];
-    const int lx = S.lx, ly = S.ly, n = lx * ly;
-    for (int e = threadIdx.x; e < FMODES; e += 256) {
-        const float2 v = reinterpret_cast<const float2 *>(Y)[((long long)e * S_tot + s) * FC + ch];
-        const float c = (e % FM) == 0 ? 1.f : 2.f;
-        Ys[e] = make_float2(c * v.x, c * v.y);
-    }
-    {
-        const float2 *twx = tw + (long long)FNO_TW_UNIT * lx * (lx - 1) / 2 + FNO_TW_INV_X * lx;
-        const float2 *twy = tw + (long long)FNO_TW_UNIT * ly * (ly - 1) / 2 + FNO_TW_INV_Y * ly;
-        for (int i = threadIdx.x; i < lx * 2 * FM; i += 256) ExT[i] = twx[i];
-        for (int i = threadIdx.x; i < ly * FM; i += 256) Ey[i] = twy[i];
-    }
-    __syncthreads();
-    // along y: P[y][q] = sum_ky Ys[q][ky] Ey[y][ky]
-    for (int e = threadIdx.x; e < ly * 2 * FM; e += 256) {
-        const int y = e / (2 * FM), q = e - y * (2 * FM);
-        float re = 0.f, im = 0.f;
-        for (int ky = 0; ky < FM; ++ky) {
-            const float2 t = Ys[q * FM + ky], w = Ey[y * FM + ky];
-            re += t.x * w.x - t.y * w.y;
-            im += t.x * w.y + t.y * w.x;
-        }
-        P[y * 2 * FM + q] = make_float2(re, im);
-    }
-    __syncthreads();
-    // along x: out[y][x] = Re sum_q P[y][q] Ex[x][q]; a thread owns one x and
-    // INV_RY rows: one conflict-free twiddle load per q feeds INV_RY products,
-    // the P loads are broadcasts
-    constexpr int INV_RY = 8;
-    const float norm = 1.f / (float)(lx * ly);
-    float *dst = spec + S.cell_off * FC + (long long)ch * n;
-    for (int e = threadIdx.x; e < ((ly + INV_RY - 1) / INV_RY) * lx; e += 256) {
-        const int yb = (e / lx) * INV_RY, x = e - (e / lx) * lx;
-        float re[INV_RY];
-#pragma unroll
-        for (int i = 0; i < INV_RY; ++i) re[i] = 0.f;
-        for (int q = 0; q < 2 * FM; ++q) {
-            const float2 w = ExT[q * lx + x];
-#pragma unroll
-            for (int i = 0; i < INV_RY; ++i) {
-                const float2 t = P[min(yb + i, ly - 1) * 2 * FM + q];
-                re[i] += t.x * w.x - t.y * w.y;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < INV_RY; ++i)
-            if (yb + i < ly) dst[(yb + i) * lx + x] = re[i] * norm;
     }
 }
 
@@ -344,14 +404,22 @@ void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, con
                  float *act0, float *act1, float *spec, float *X, float *Y, float2 *e) {
     const int cblk = (max_cells + 255) / 256;
     const int tblk = (max_cells + 63) / 64;
+    const int lmax = FNO_MAXL;                 // longest subdomain side (blocks beyond a sample's size exit)
     hipLaunchKernelGGL(fno_lift_kernel, dim3(cblk, S_tot), dim3(256), 0, st, smp, sact, v, vscale, aux, aux_ch_stride,
                        net.lift_w, net.lift_b, act0);
     float *cur = act0, *nxt = act1;
     for (int l = 0; l < net.layers; ++l) {
-        hipLaunchKernelGGL(fno_dft_fwd_kernel, dim3(FC, S_tot), dim3(256), 0, st, smp, sact, cur, X, S_tot, net.tw);
+        // T1 in spec, P in nxt: both are free until the pointwise step of this layer
+        hipLaunchKernelGGL(fno_dft_y_fwd_kernel, dim3((FC * lmax + 127) / 128, 1, S_tot), dim3(256), 0, st, smp, sact,
+                           cur, spec, net.tw);
+        hipLaunchKernelGGL(fno_dft_x_fwd_kernel, dim3(FC * FM / 64, 1, S_tot), dim3(256), 0, st, smp, sact, spec, X,
+                           S_tot, net.tw);
         hipLaunchKernelGGL(fno_spectral_kernel, dim3(FMODES, (S_tot + 63) / 64), dim3(256), 0, st, X,
                            net.R + (long long)l * FMODES * 128 * 128, Y, S_tot);
-        hipLaunchKernelGGL(fno_dft_inv_kernel, dim3(FC, S_tot), dim3(256), 0, st, smp, sact, Y, spec, S_tot, net.tw);
+        hipLaunchKernelGGL(fno_dft_x_inv_kernel, dim3(FC * FM / 64, (2 * lmax + 63) / 64, S_tot), dim3(256), 0, st,
+                           smp, sact, Y, nxt, S_tot, net.tw);
+        hipLaunchKernelGGL(fno_dft_y_inv_kernel, dim3((FC * lmax + 127) / 128, (lmax + 31) / 32, S_tot), dim3(256), 0,
+                           st, smp, sact, nxt, spec, net.tw);
         hipLaunchKernelGGL(fno_pointwise_kernel, dim3(tblk, S_tot), dim3(256), 0, st, smp, sact, cur, spec,
                            net.W + (long long)l * FC * FC, net.b + (long long)l * FC, nxt,
                            l < net.layers - 1 ? 1 : 0);
