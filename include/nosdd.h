@@ -202,6 +202,24 @@ nosdd_status nosdd_coarse_basis(const nosdd_problem *p, int wl, nosdd_c32 *phi, 
 nosdd_status nosdd_profile(nosdd_problem *p, int enable);
 nosdd_status nosdd_kernel_times(const nosdd_problem *p, double ms[4], long long launches[4], long long units[4]);
 
+/* Gradient of the inverse-design figure of merit (adjoint-variables method of
+ * the paper's inverse-design section, with implicit differentiation of the
+ * converged fields):
+ *   FoM = sum over wavelengths, sources and focal cells f of |E(r_f)|^2,
+ *   grad[iy][ix] = dFoM/d eps(ix, iy) = sum 2 k0^2 Re(E lam),  A^T lam = P conj(E).
+ * The adjoint field is obtained from the same two-level Schwarz-FGMRES: with
+ * S = diag(s_x s_y) (centre PML stretches) S A is complex symmetric, so
+ * lam = S mu with A mu = S^-1 P conj(E).  Two solves per call (forward, then
+ * adjoint) with the options o (x0 ignored).  J: device [n_src][ny][nx];
+ * focal: host int [n_focal][2] = (ix, iy), repeats allowed; grad: device
+ * float [ny][nx] (every cell; mask the design region yourself); fom: host
+ * double, nullable; iters: host int [2][n_wl * n_src] (forward, adjoint
+ * outer iterations), nullable.  Returns NOSDD_NOT_CONVERGED (outputs valid)
+ * if either solve stopped at max_iters. */
+nosdd_status nosdd_fom_gradient_device(nosdd_problem *p, const nosdd_c32 *J, int n_src, const int *focal,
+                                       int n_focal, const nosdd_solve_opts *o, double *fom, float *grad,
+                                       int *iters);
+
 /* Launch-parameter autotuning (enabled by default).  At the first solve of a
  * given batch shape, before any graph capture, the library times candidate
  * launch parameters on the problem's own buffers and keeps the fastest: the

@@ -86,6 +86,8 @@ struct nosdd_problem {
     int bmax = 0;
     std::vector<std::vector<cd>> coefd;             // per wl: cxm|cxp|cym|cyp
     DevBuf d_eps, d_coef, d_coefd, d_k0sq, d_k0f, d_k0, d_tiles, d_dinv, d_entries, d_tox, d_toy;
+    DevBuf d_sc;                                   // per wl: centre stretches s_x(nx) | s_y(ny)
+    DevBuf adj_E, adj_mu, adj_J, adj_focal, adj_fom; // inverse-design gradient buffers
     int n_entries = 0;
     // coarse space
     int kc = 0, ktrial = 8, n_c = 0;
@@ -287,12 +289,15 @@ void trace_entries(const TileDesc &t, int nx, std::vector<int4> &out) {
     }
 }
 
-__global__ void make_rhs_kernel(const float2 *J, float2 *b, const float *k0, long long N, int n_src) {
+// b = -i omega J for every RHS; J is [n_src][N] (shared by the wavelengths),
+// or [n_rhs][N] when per_rhs is set.
+__global__ void make_rhs_kernel(const float2 *J, float2 *b, const float *k0, long long N, int n_src, int per_rhs) {
     const int r = blockIdx.y;
     const int wl = r / n_src, s = r - wl * n_src;
     const float om = k0[wl];
+    const float2 *Jr = J + (per_rhs ? r : s) * N;
     for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
-        const float2 j = J[s * N + n];
+        const float2 j = Jr[n];
         b[r * N + n] = make_float2(om * j.y, -om * j.x);    // -i omega J
     }
 }
@@ -1125,7 +1130,7 @@ nosdd_status ensure_graphs(nosdd_problem *p, int n_rhs, int n_src, int m, const 
 }
 
 nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const nosdd_solve_opts *o, const float2 *x0_dev,
-                        float2 *E_dev, float *resid_hist, int *iters_out, float *final_out) {
+                        float2 *E_dev, float *resid_hist, int *iters_out, float *final_out, bool j_per_rhs = false) {
     nosdd_ctx *ctx = p->ctx;
     hipStream_t s = ctx->stream;
     const int nwl = (int)p->wl.size();
@@ -1170,7 +1175,7 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
            *wv = w.w.as<float2>();
     const long long vstride = (long long)n_rhs * N;
     hipLaunchKernelGGL(make_rhs_kernel, dim3((unsigned)grid_blocks(N), n_rhs), dim3(256), 0, s, J_dev, b,
-                       p->d_k0f.as<float>(), N, n_src);
+                       p->d_k0f.as<float>(), N, n_src, j_per_rhs ? 1 : 0);
     hipLaunchKernelGGL(widen_kernel, dim3((unsigned)grid_blocks(vstride)), dim3(256), 0, s, x0_dev, x, vstride);
     HIPCHK(ctx, hipMemsetAsync(w.iters.p, 0, n_rhs * sizeof(int), s));
     {
@@ -1481,6 +1486,7 @@ nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const flo
     // coefficients
     const int nx = p->nx, ny = p->ny;
     std::vector<float2> cf((size_t)n_wl * 2 * (nx + ny));
+    std::vector<float2> scv;
     std::vector<double2> cdv((size_t)n_wl * 2 * (nx + ny));
     std::vector<float> k0sq(n_wl), k0f(n_wl);
     std::vector<double> k0d(n_wl);
@@ -1499,6 +1505,16 @@ nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const flo
             cdv[(size_t)w * all.size() + i] = make_double2(all[i].real(), all[i].imag());
         }
         p->coefd.push_back(all);
+        // centre stretches s_x(ix), s_y(iy) (inverse-design gradient)
+        const double sh = p->npml ? (p->pml_m + 1) * (-p->lnR) / (2.0 * k0 * p->npml * p->h) : 0.0;
+        for (int i = 0; i < nx; ++i) {
+            const cd v = stretch((double)i, nx, p->npml, p->pml_m, sh);
+            scv.push_back(make_float2((float)v.real(), (float)v.imag()));
+        }
+        for (int i = 0; i < ny; ++i) {
+            const cd v = stretch((double)i, ny, p->npml, p->pml_m, sh);
+            scv.push_back(make_float2((float)v.real(), (float)v.imag()));
+        }
     }
     std::vector<int4> ents;
     for (auto &e : p->tile_entries) ents.insert(ents.end(), e.begin(), e.end());
@@ -1517,6 +1533,7 @@ nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const flo
     if (e == hipSuccess) e = up(p->d_k0, k0d.data(), k0d.size() * sizeof(double));
     if (e == hipSuccess) e = up(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(TileDesc));
     if (e == hipSuccess) e = up(p->d_entries, ents.data(), ents.size() * sizeof(int4));
+    if (e == hipSuccess) e = up(p->d_sc, scv.data(), scv.size() * sizeof(float2));
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         ctx->err = std::string("HIP error during problem_create: ") + hipGetErrorString(e);
@@ -1626,6 +1643,63 @@ nosdd_status nosdd_solve_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_
     if (st) return st;
     return solve_impl(p, (const float2 *)J_dev, n_src, o, (const float2 *)o->x0, (float2 *)E_dev, resid_hist, iters,
                       final_resid);
+}
+
+nosdd_status nosdd_fom_gradient_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src, const int *focal,
+                                       int n_focal, const nosdd_solve_opts *o, double *fom, float *grad_dev,
+                                       int *iters) {
+    nosdd_status st = validate_solve(p, J_dev, n_src, o, grad_dev);
+    if (st) return st;
+    nosdd_ctx *ctx = p->ctx;
+    if (!focal || n_focal <= 0) return fail(ctx, NOSDD_EINVAL, "no focal cells");
+    for (int f = 0; f < n_focal; ++f)
+        if (focal[2 * f] < 0 || focal[2 * f] >= p->nx || focal[2 * f + 1] < 0 || focal[2 * f + 1] >= p->ny)
+            return fail(ctx, NOSDD_EINVAL, "focal cell outside the grid");
+    hipStream_t s = ctx->stream;
+    const int n_rhs = (int)p->wl.size() * n_src;
+    const long long N = (long long)p->nx * p->ny;
+    const size_t vec = (size_t)n_rhs * N * sizeof(float2);
+    HIPCHK(ctx, p->adj_E.ensure(vec));
+    HIPCHK(ctx, p->adj_mu.ensure(vec));
+    HIPCHK(ctx, p->adj_J.ensure(vec));
+    HIPCHK(ctx, p->adj_focal.ensure((size_t)n_focal * sizeof(int2)));
+    HIPCHK(ctx, p->adj_fom.ensure((size_t)n_rhs * n_focal * sizeof(double)));
+    HIPCHK(ctx, hipMemcpyAsync(p->adj_focal.p, focal, (size_t)n_focal * sizeof(int2), hipMemcpyHostToDevice, s));
+    nosdd_solve_opts fo = *o;
+    fo.x0 = nullptr;
+    std::vector<int> it_f(n_rhs, 0), it_a(n_rhs, 0);
+    // forward fields
+    nosdd_status sf = solve_impl(p, (const float2 *)J_dev, n_src, &fo, nullptr, p->adj_E.as<float2>(), nullptr,
+                                 it_f.data(), nullptr);
+    if (sf < 0) return sf;
+    // |E(r_f)|^2 and the adjoint current at the focal cells
+    hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)grid_blocks(2LL * n_rhs * N)), dim3(256), 0, s,
+                       p->adj_J.as<float>(), 2LL * n_rhs * N, 0.0f);
+    launch_adjoint_rhs(s, p->adj_E.as<float2>(), N, p->nx, p->ny, p->adj_focal.as<int2>(), n_focal,
+                       p->d_sc.as<float2>(), p->d_k0f.as<float>(), n_rhs, n_src, p->adj_J.as<float2>(),
+                       p->adj_fom.as<double>());
+    HIPCHK(ctx, hipGetLastError());
+    // adjoint fields mu (A mu = S^-1 P conj(E)), then the gradient
+    nosdd_status sa = solve_impl(p, p->adj_J.as<float2>(), n_src, &fo, nullptr, p->adj_mu.as<float2>(), nullptr,
+                                 it_a.data(), nullptr, true);
+    if (sa < 0) return sa;
+    launch_adjoint_grad(s, p->adj_E.as<float2>(), p->adj_mu.as<float2>(), N, p->nx, p->ny, n_rhs, n_src,
+                        p->d_sc.as<float2>(), p->d_k0f.as<float>(), (float *)grad_dev);
+    HIPCHK(ctx, hipGetLastError());
+    std::vector<double> fv((size_t)n_rhs * n_focal);
+    HIPCHK(ctx, hipMemcpyAsync(fv.data(), p->adj_fom.p, fv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (fom) {
+        double t = 0.0;
+        for (double v : fv) t += v;
+        *fom = t;
+    }
+    if (iters)
+        for (int r = 0; r < n_rhs; ++r) {
+            iters[r] = it_f[r];
+            iters[n_rhs + r] = it_a[r];
+        }
+    return (sf == NOSDD_NOT_CONVERGED || sa == NOSDD_NOT_CONVERGED) ? NOSDD_NOT_CONVERGED : NOSDD_OK;
 }
 
 nosdd_status nosdd_solve(nosdd_problem *p, const nosdd_c32 *J, int n_src, const nosdd_solve_opts *o, nosdd_c32 *E_out,

@@ -183,6 +183,13 @@ struct NnWork {
     float *act0 = nullptr, *act1 = nullptr, *spec = nullptr, *X = nullptr, *Y = nullptr;
 };
 
+// Inverse-design gradient (adjoint.hip).  sc: per wavelength [s_x(nx) | s_y(ny)]
+// centre stretches; focal: (ix, iy) cells.
+void launch_adjoint_rhs(hipStream_t s, const float2 *E, long long N, int nx, int ny, const int2 *focal, int n_focal,
+                        const float2 *sc, const float *k0f, int n_rhs, int n_src, float2 *Jadj, double *fomv);
+void launch_adjoint_grad(hipStream_t s, const float2 *E, const float2 *mu, long long N, int nx, int ny, int n_rhs,
+                         int n_src, const float2 *sc, const float *k0f, float *grad);
+
 // Inner NN-FGMRES on every (tile, RHS) sample.  local == 0: v and z are
 // global [n_rhs][N] vectors (gather over the extended subdomain, core-only
 // scatter); local != 0: v and z are subdomain-local [n_rhs][loc_total].

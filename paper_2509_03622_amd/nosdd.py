@@ -22,7 +22,8 @@ EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_p
            "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
-           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_autotune", "nosdd_tuning"]
+           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_autotune", "nosdd_tuning",
+           "nosdd_fom_gradient_device"]
 
 
 class Grid(C.Structure):
@@ -86,6 +87,7 @@ def load(path=LIBPATH):
         "nosdd_graphs": (i, [vp, i]),
         "nosdd_autotune": (i, [vp, i]),
         "nosdd_tuning": (i, [vp, vp]),
+        "nosdd_fom_gradient_device": (i, [vp, vp, i, vp, i, C.POINTER(SolveOpts), C.POINTER(C.c_double), vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -255,6 +257,23 @@ class Problem:
             off += n
         return out, box
 
+    def fom_gradient(self, J, focal, tol=1e-6, restart=30, max_iters=1000):
+        """FoM = sum |E(r_f)|^2 over wavelengths, sources, focal cells and its gradient
+        d FoM / d eps [ny][nx] (device float32 tensor), by a forward and an adjoint solve.
+        J: device complex64 [n_src][ny][nx]; focal: sequence of (ix, iy).
+        Returns (fom, grad, iters [2][n_wl][n_src], status)."""
+        import torch
+        ns = J.shape[0]
+        foc = np.ascontiguousarray(np.asarray(focal, dtype=np.int32).reshape(-1, 2))
+        grad = torch.empty((self.ny, self.nx), dtype=torch.float32, device=J.device)
+        iters = np.zeros((2, self.n_wl, ns), np.int32)
+        fom = C.c_double(0.0)
+        o = SolveOpts(tol, restart, max_iters, None)
+        st = self.ctx.check(self.L.nosdd_fom_gradient_device(self.h, _ptr(J), ns, foc.ctypes.data, foc.shape[0],
+                                                             C.byref(o), C.byref(fom), _ptr(grad),
+                                                             iters.ctypes.data))
+        return fom.value, grad, iters, st
+
     def autotune(self, enable=True):
         """Time candidate launch parameters at the first solve of a batch shape (default on)."""
         return self.ctx.check(self.L.nosdd_autotune(self.h, 1 if enable else 0))
@@ -291,3 +310,41 @@ def torch_stream_handle():
     """The current PyTorch HIP stream as a raw handle for Context(stream=...)."""
     import torch
     return torch.cuda.current_stream().cuda_stream
+
+
+def _fom_function():
+    import torch
+
+    class FomGradient(torch.autograd.Function):
+        """FoM(eps) = sum over wavelengths, sources and focal cells of |E(r_f)|^2 with
+        E = A(eps)^-1 (-i omega J), differentiable in eps through the library's
+        adjoint solve (the backward pass reuses the gradient computed with the FoM).
+        Every call builds and factorises the problem for the given eps."""
+
+        @staticmethod
+        def forward(ctx_, eps, J, focal, spec):
+            ctx = Context(0, torch_stream_handle())
+            P = Problem(ctx, eps.detach().cpu().numpy().astype(np.float32), spec["h"], spec["npml"],
+                        spec["core_x"], spec["core_y"], spec["overlap"], spec["wavelengths"],
+                        spec.get("pml_m", 2), spec.get("pml_lnR", -30.0))
+            P.setup(k_coarse=spec.get("k_coarse", 0), k_trial=spec.get("k_trial", 8))
+            fom, grad, iters, st = P.fom_gradient(J, focal, tol=spec.get("tol", 1e-6),
+                                                  max_iters=spec.get("max_iters", 1000))
+            torch.cuda.synchronize()
+            P.close()
+            ctx.close()
+            ctx_.save_for_backward(grad.to(eps.device))
+            return torch.tensor(fom, dtype=torch.float64, device=eps.device)
+
+        @staticmethod
+        def backward(ctx_, g):
+            (grad,) = ctx_.saved_tensors
+            return (g.to(grad.dtype) * grad, None, None, None)
+
+    return FomGradient
+
+
+def figure_of_merit(eps, J, focal, spec):
+    """Differentiable FoM(eps) (see FomGradient); spec holds the grid and partition:
+    h, npml, core_x, core_y, overlap, wavelengths (and optionally k_coarse, tol, max_iters)."""
+    return _fom_function().apply(eps, J, focal, spec)

@@ -1,0 +1,77 @@
+"""GPU inverse-design gradient (forward + adjoint two-level Schwarz-FGMRES through
+the C ABI) against the FP64 oracle: the figure of merit, the gradient over the
+whole grid (oracle: direct LU of A and A^T, no use of the S A symmetry), central
+finite differences of the oracle's FoM on 16 random design pixels, and the
+torch.autograd wrapper."""
+import numpy as np
+import pytest
+
+from oracle.adjoint import figure_of_merit, fom_and_gradient
+
+from gpu_common import rel
+
+pytestmark = pytest.mark.gpu
+
+
+def design_case(seed=61):
+    rng = np.random.default_rng(seed)
+    n, npml, h = 192, 12, 0.05
+    eps = np.ones((n, n), np.float32)
+    eps[64:128, 64:128] = rng.uniform(1, 12, (64, 64)).astype(np.float32)
+    J = np.zeros((1, n, n), np.complex64)
+    J[0, 48, 64:128] = 1.0                                   # line source below the design region
+    focal = [(int(rng.integers(64, 128)), int(rng.integers(140, 170))) for _ in range(3)]
+    spec = dict(h=h, npml=npml, core_x=[64] * 3, core_y=[64] * 3, overlap=8, wavelengths=[0.9, 1.2],
+                k_coarse=1, tol=1e-6, max_iters=800)
+    return eps, J, focal, spec, rng
+
+
+def gpu_gradient(eps, J, focal, spec):
+    import torch
+    from paper_2509_03622_amd import nosdd
+    ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+    P = nosdd.Problem(ctx, eps, spec["h"], spec["npml"], spec["core_x"], spec["core_y"], spec["overlap"],
+                      spec["wavelengths"])
+    P.setup(k_coarse=spec["k_coarse"], k_trial=8)
+    fom, grad, iters, st = P.fom_gradient(torch.from_numpy(J).cuda(), focal, tol=spec["tol"],
+                                          max_iters=spec["max_iters"])
+    g = grad.cpu().numpy()
+    P.close()
+    ctx.close()
+    return fom, g, iters, st
+
+
+def test_gradient_matches_oracle_and_finite_differences():
+    eps, J, focal, spec, rng = design_case()
+    fom, g, iters, st = gpu_gradient(eps, J, focal, spec)
+    assert st == 0, iters
+    wls = spec["wavelengths"]
+    e64 = eps.astype(np.float64)
+    fom_o, g_o, _ = fom_and_gradient(e64, wls, [J[0].astype(np.complex128)], focal, spec["h"], spec["npml"])
+    assert abs(fom - fom_o) <= 1e-4 * fom_o, (fom, fom_o)
+    assert rel(g, g_o) < 1e-3, rel(g, g_o)
+    design = (slice(64, 128), slice(64, 128))
+    assert rel(g[design], g_o[design]) < 1e-3
+    # central differences of the FP64 FoM on 16 random design pixels
+    gmax = np.abs(g_o[design]).max()
+    d = 1e-3
+    for _ in range(16):
+        ix, iy = int(rng.integers(64, 128)), int(rng.integers(64, 128))
+        ep, em = e64.copy(), e64.copy()
+        ep[iy, ix] += d
+        em[iy, ix] -= d
+        fd = (figure_of_merit(ep, wls, [J[0]], focal, spec["h"], spec["npml"])
+              - figure_of_merit(em, wls, [J[0]], focal, spec["h"], spec["npml"])) / (2 * d)
+        assert abs(g[iy, ix] - fd) <= 2e-3 * gmax, (ix, iy, g[iy, ix], fd)
+
+
+def test_autograd_wrapper_returns_the_library_gradient():
+    import torch
+    from paper_2509_03622_amd import nosdd
+    eps, J, focal, spec, rng = design_case(62)
+    fom, g, iters, st = gpu_gradient(eps, J, focal, spec)
+    e = torch.from_numpy(eps).cuda().requires_grad_(True)
+    f = nosdd.figure_of_merit(e, torch.from_numpy(J).cuda(), focal, spec)
+    f.backward()
+    assert abs(float(f.detach()) - fom) <= 1e-6 * fom
+    assert rel(e.grad.cpu().numpy(), g) < 1e-6
