@@ -210,6 +210,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 direct-solve field check")
     ap.add_argument("--no-stencil", action="store_true", help="skip the operator/residual roofline measurement")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead of the default line: one inverse-design gradient (forward + adjoint solves) on "
+                         "the 1024 x 1024, three-wavelength design workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (calibration of the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -227,6 +230,39 @@ def main():
     from paper_2509_03622_amd import nosdd
     from paper_2509_03622_amd.workloads import WORKLOADS
 
+    if a.adjoint:
+        from paper_2509_03622_amd.workloads import inverse_design_1024
+        torch.cuda.init()
+        w = inverse_design_1024()
+        ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+        P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths)
+        t0 = time.perf_counter()
+        P.setup(k_coarse=w.k_coarse, k_trial=8)
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        J = torch.from_numpy(w.J()).cuda()
+        fom, grad, iters, st = P.fom_gradient(J, w.focal, max_iters=2000)      # warm-up (graphs, tuning)
+        torch.cuda.synchronize()
+        reps = max(1, a.steps)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fom, grad, iters, st = P.fom_gradient(J, w.focal, max_iters=2000)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        x0, x1, y0, y1 = w.design
+        gd = grad[y0:y1, x0:x1]
+        print(json.dumps({"metric": "time per inverse-design gradient (forward + adjoint solves to 1e-6)",
+                          "mode": "adjoint", "n_gpus": 1, "data": "synthetic", "dtype": "c64",
+                          "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "cores": "16x16 of 64",
+                                     "wavelengths": w.wavelengths, "design_region": list(w.design),
+                                     "focal": w.focal, "k_coarse": w.k_coarse},
+                          "ms_per_gradient": round(ms, 1), "setup_ms": round(setup_ms, 1), "status": int(st),
+                          "fom": fom, "iterations_forward": iters[0].ravel().tolist(),
+                          "iterations_adjoint": iters[1].ravel().tolist(),
+                          "design_grad_abs_max": float(gd.abs().max())}), flush=True)
+        P.close()
+        ctx.close()
+        return
     if a.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -102,6 +102,44 @@ def uneven_2048x1536(seed=4, n_src=32):
                     [96] + [64] * 29 + [96], [96] + [64] * 21 + [96])
 
 
+@dataclass
+class DesignWorkload:
+    """Inverse-design problem: FoM = sum of |E|^2 at focal cells over wavelengths."""
+    name: str
+    nx: int
+    ny: int
+    eps: np.ndarray                  # [ny][nx] float32 (design region drawn, background 1)
+    wavelengths: list
+    line: tuple                      # (row, x0, x1): unit line current J = 1 on [x0, x1) of that row
+    focal: list                      # list of (ix, iy)
+    design: tuple                    # (x0, x1, y0, y1)
+    core_x: list
+    core_y: list
+    overlap: int = 8
+    k_coarse: int = 1
+    h: float = H
+    npml: int = NPML
+
+    def J(self):
+        J = np.zeros((1, self.ny, self.nx), dtype=np.complex64)
+        row, x0, x1 = self.line
+        J[0, row, x0:x1] = 1.0
+        return J
+
+
+def inverse_design_1024(seed=5):
+    """1024 x 1024, 256 x 256 design region at [384, 640)^2 with eps uniform in [1, 12],
+    wavelengths {0.9, 1.1, 1.3}, unit line source on row 320 across the design
+    columns, three focal cells in rows [704, 896) above it; 16 x 16 cores of 64."""
+    rng = np.random.default_rng(seed)
+    n = 1024
+    eps = np.ones((n, n), dtype=np.float32)
+    eps[384:640, 384:640] = rng.uniform(1, 12, (256, 256)).astype(np.float32)
+    focal = [(int(rng.integers(384, 640)), int(rng.integers(704, 896))) for _ in range(3)]
+    return DesignWorkload("design1024_16x16_3wl", n, n, eps, [0.9, 1.1, 1.3], (320, 384, 640), focal,
+                          (384, 640, 384, 640), [64] * 16, [64] * 16)
+
+
 def random_small(seed, nx, ny, core_x, core_y, wavelengths=(1.0,), n_src=1, k_coarse=0,
                  overlap=8, npml=NPML, block=8):
     """Small random test problem: blocks of eps in [1, 12], random source cells."""
