@@ -10,9 +10,10 @@ subdomain, exact subdomain LU, complex64 arithmetic.
 Printed (one JSON line): subdomain solves per second (one exact local solve of
 one subdomain for one RHS is one unit), the time per global solve, the
 roofline of the dominant kernel (the batched subdomain solve; HIP events on
-the library stream over the timed region), the FP64 oracle timed on a bounded
-sample on the host, and the field error of every RHS against the FP64 direct
-solution.
+the library stream over the timed region), the explicit final residual of
+every RHS (formed by the library in FP64), and the FP64 oracle timed on a
+bounded sample on the host.  The fields of this workload are checked against
+the FP64 direct solution by the full-size GPU parity tests, not here.
 """
 from __future__ import annotations
 
@@ -51,10 +52,11 @@ def tile_geometry(w):
 
 def local_solve_bytes(lx, ly, core):
     """Algorithmic HBM bytes of one exact subdomain solve (one tile, one RHS):
-    the 2 nb - 1 dense blocks D_k^-1 (b x b complex64) streamed by the block
+    the 2 nb - 1 symmetric factor blocks M_k (upper triangle in 2 x 2
+    sub-blocks, b (b + 2) / 2 complex64 each) streamed by the block
     forward/backward sweeps, the gathered tile input and the core output."""
     b, nb = min(lx, ly), max(lx, ly)
-    return 8 * ((2 * nb - 1) * b * b + lx * ly + core)
+    return 8 * ((2 * nb - 1) * b * (b + 2) // 2 + lx * ly + core)
 
 
 def kernel_hash():
@@ -159,7 +161,7 @@ def timed_solve(torch, P, J, E, max_iters, reps=1):
     return dt, iters, fin, st, [round(float(v) / reps, 2) for v in ms_k]
 
 
-def nn_compare(torch, nosdd, workload, configs, max_iters, check):
+def nn_compare(torch, nosdd, workload, configs, max_iters):
     """Time to a 1e-6 residual of the exact-LU form and of the NN-FGMRES form
     (BF16 network inside FP32 inner FGMRES) on the same problem and GPU."""
     from paper_2509_03622_amd.workloads import WORKLOADS
@@ -168,11 +170,6 @@ def nn_compare(torch, nosdd, workload, configs, max_iters, check):
     J = torch.from_numpy(w.J()).to(dev)
     E = torch.zeros((len(w.wavelengths), len(w.sources), w.ny, w.nx), dtype=torch.complex64, device=dev)
     ctx = nosdd.Context(0, nosdd.torch_stream_handle())
-    xs = None
-    if check:
-        from oracle.fdfd import assemble_A, solve_direct, source_rhs
-        lam = w.wavelengths[0]
-        xs = solve_direct(assemble_A(w.eps, lam, w.h, w.npml, w.pml_m, w.pml_lnR), source_rhs(w.J()[0], lam))
     rows = []
     for kc, solver, steps, tol in configs:
         P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
@@ -190,9 +187,6 @@ def nn_compare(torch, nosdd, workload, configs, max_iters, check):
                "final_rel_residual": float(f"{float(fin.ravel()[0]):.3e}"), "status": int(st),
                "setup_ms": round(setup_ms, 1),
                "kernel_ms": dict(zip(("local_solve", "operator", "arnoldi", "coarse"), ms_k))}
-        if xs is not None:
-            e = E[0, 0].cpu().numpy().ravel()
-            row["field_rel_err_vs_fp64_direct"] = float(f"{np.linalg.norm(e - xs) / np.linalg.norm(xs):.3e}")
         rows.append(row)
         print(f"[bench] {row}", file=sys.stderr, flush=True)
         P.close()
@@ -208,7 +202,7 @@ def main():
     ap.add_argument("--workload", default="blocks512")
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true", help="skip the FP64 direct-solve field check")
+    ap.add_argument("--no-check", action="store_true", help="accepted for compatibility; fields are checked by the tests")
     ap.add_argument("--no-stencil", action="store_true", help="skip the operator/residual roofline measurement")
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the default line: one inverse-design gradient (forward + adjoint solves) on "
@@ -277,7 +271,7 @@ def main():
         configs = [(kc, "lu", 0, 0.0) for kc in (0, 1)]
         configs += [(kc, "nn", n, t) for kc in (1, 0) for n, t in ((1, 0.1), (2, 0.1), (4, 0.1), (4, 0.01),
                                                                  (8, 0.01))]
-        w, rows = nn_compare(torch, nosdd, "blocks1024", configs, max_iters=3000, check=not a.no_check)
+        w, rows = nn_compare(torch, nosdd, "blocks1024", configs, max_iters=3000)
         lu = min((r for r in rows if r["solver"] == "lu" and r["status"] == 0), key=lambda r: r["time_to_tol_ms"])
         nn = [r for r in rows if r["solver"] == "nn" and r["status"] == 0]
         best = min(nn, key=lambda r: r["time_to_tol_ms"]) if nn else None
@@ -366,16 +360,6 @@ def main():
         P.close()
         out["stencil_roofline"] = stencil_roofline(torch, nosdd)
         print(f"[bench] stencil roofline {out['stencil_roofline']}", file=sys.stderr, flush=True)
-    if not a.no_check:
-        from oracle.fdfd import assemble_A, solve_direct, source_rhs
-        Eh = E.cpu().numpy()
-        errs = []
-        for wi, lam in enumerate(w.wavelengths):
-            A = assemble_A(w.eps, lam, w.h, w.npml, w.pml_m, w.pml_lnR)
-            for s in range(n_src):
-                xs = solve_direct(A, source_rhs(w.J()[s], lam))
-                errs.append(float(np.linalg.norm(Eh[wi, s].ravel() - xs) / np.linalg.norm(xs)))
-        out["field_rel_err_vs_fp64_direct"] = [float(f"{e:.3e}") for e in errs]
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -8,19 +8,24 @@
 //   D_0 = A_00,  D_k = A_kk - c_lo(k) c_hi(k-1) D_{k-1}^-1,
 //   forward   w_k = D_k^-1 (v_k - c_lo(k) w_{k-1}),
 //   backward  u_{nb-1} = w_{nb-1},  u_k = w_k - c_hi(k) D_k^-1 u_{k+1}.
+// The UPML operator is S^-1 times a complex-symmetric matrix (S = s_x s_y at
+// cell centres) and the Robin closure only changes the diagonal, so with
+// S_k the stretches of block k, S_k D_k is the Schur complement of the
+// symmetric matrix S B_i and M_k = D_k^-1 S_k^-1 is complex symmetric:
+// D_k^-1 y = M_k (S_k y), and half of M_k suffices (layout in common.h).
 //
-// bt_factor_kernel (set-up, once per tile and wavelength): builds D_k in LDS
-// in FP64 and inverts it by Gauss-Jordan elimination with partial pivoting;
-// D_k^-1 is stored as complex64, column-major per block ([c][r]).
+// bt_factor_*_kernel (set-up, once per tile and wavelength): builds D_k in
+// FP64 and inverts it by Gauss-Jordan elimination with partial pivoting, then
+// stores the upper triangle of M_k as complex64 sub-blocks.
 //
 // bt_solve_kernel (hot path): one workgroup per (tile, RHS) streams the
-// 2 nb - 1 blocks D_k^-1 from HBM, each once, and keeps the sequential
-// recurrence in LDS.  The D blocks do not depend on the data, so each thread
+// 2 nb - 1 blocks M_k from HBM, each once, and keeps the sequential
+// recurrence in LDS.  The M blocks do not depend on the data, so each thread
 // holds the blocks of the next steps in registers while it multiplies the
-// current one (~125 KB per CU in flight with one workgroup per CU).  The gather of R_i v (input restricted to the
-// extended tile, which carries the neighbours' Robin traces by the Robin
-// identity) and the core-only scatter (restricted additive Schwarz
-// prolongation) are fused into the same kernel.
+// current one.  The gather of R_i v (input restricted to the extended tile,
+// which carries the neighbours' Robin traces by the Robin identity) and the
+// core-only scatter (restricted additive Schwarz prolongation) are fused into
+// the same kernel.
 #include "common.h"
 
 namespace nosdd {
@@ -47,9 +52,15 @@ template <int BMAX>
 __device__ __forceinline__ void bt_factor_body(double2 *M, double2 *fcol, double2 *prow, int *piv, int *pivrow,
                                                const TileDesc &t, int wl, const float *__restrict__ eps,
                                                const double2 *__restrict__ coef, const double *__restrict__ k0v,
-                                               double h, int nx, int ny, float2 *__restrict__ dinv,
-                                               long long wl_stride) {
+                                               double h, int nx, int ny, const float2 *__restrict__ sc,
+                                               float2 *__restrict__ dinv, long long wl_stride) {
     const int b = t.b, nb = t.nb, tid = threadIdx.x;
+    const int P = b / 2;
+    const long long blk = bt_sym_block(b);
+    // centre stretches along the block (s_in, per row r) and across blocks (s_out, per block k)
+    const float2 *scw = sc + (long long)wl * (nx + ny);
+    const float2 *s_in = t.tr ? scw + nx + t.y0 : scw + t.x0;
+    const float2 *s_out = t.tr ? scw + t.x0 : scw + nx + t.y0;
     const double2 *cd = coef + wl * coef_stride(nx, ny);
     const double2 *cxm = cd, *cxp = cd + nx, *cym = cd + 2 * nx, *cyp = cd + 2 * nx + ny;
     const double k0 = k0v[wl];
@@ -150,11 +161,18 @@ __device__ __forceinline__ void bt_factor_body(double2 *M, double2 *fcol, double
                 __syncthreads();
             }
         }
-        // store D_k^-1 column-major: element (r, c) at c*b + r
-        float2 *dk = outw + (long long)k * b * b;
-        for (int e = tid; e < b * b; e += BT_FACT_THREADS) {
-            const int c = e / b, r = e - c * b;
-            const double2 v = M[r * b + c];
+        // store the upper triangle of M_k = D_k^-1 S_k^-1 (symmetric), 2 x 2 sub-blocks
+        float2 *dk = outw + (long long)k * blk;
+        const float2 so = s_out[k];
+        for (int e = tid; e < (int)blk; e += BT_FACT_THREADS) {
+            const int sub = e >> 2, comp = e & 3;
+            int bp, bq;
+            bt_sym_pq(P, sub, bp, bq);
+            const int r = 2 * bp + (comp & 1), c = 2 * bq + (comp >> 1);
+            const float2 si = s_in[c];
+            const double2 sk = make_double2((double)si.x * so.x - (double)si.y * so.y,
+                                            (double)si.x * so.y + (double)si.y * so.x);
+            const double2 v = zdiv(M[r * b + c], sk);
             dk[e] = make_float2((float)v.x, (float)v.y);
         }
         __syncthreads();
@@ -166,7 +184,8 @@ __global__ __launch_bounds__(BT_FACT_THREADS) void bt_factor_lds_kernel(const Ti
                                                                         const float *__restrict__ eps,
                                                                         const double2 *__restrict__ coef,
                                                                         const double *__restrict__ k0v, double h,
-                                                                        int nx, int ny, float2 *__restrict__ dinv,
+                                                                        int nx, int ny, const float2 *__restrict__ sc,
+                                                                        float2 *__restrict__ dinv,
                                                                         long long wl_stride) {
     __shared__ double2 M[BT_FACT_LDS_B * BT_FACT_LDS_B];
     __shared__ double2 fcol[BT_FACT_LDS_B], prow[BT_FACT_LDS_B];
@@ -174,7 +193,7 @@ __global__ __launch_bounds__(BT_FACT_THREADS) void bt_factor_lds_kernel(const Ti
     __shared__ int pivrow;
     const TileDesc t = tiles[blockIdx.x];
     if (t.b > BT_FACT_LDS_B) return;
-    bt_factor_body<BT_FACT_LDS_B>(M, fcol, prow, piv, &pivrow, t, blockIdx.y, eps, coef, k0v, h, nx, ny, dinv,
+    bt_factor_body<BT_FACT_LDS_B>(M, fcol, prow, piv, &pivrow, t, blockIdx.y, eps, coef, k0v, h, nx, ny, sc, dinv,
                                   wl_stride);
 }
 
@@ -185,7 +204,9 @@ __global__ __launch_bounds__(BT_FACT_THREADS) void bt_factor_global_kernel(const
                                                                            const float *__restrict__ eps,
                                                                            const double2 *__restrict__ coef,
                                                                            const double *__restrict__ k0v, double h,
-                                                                           int nx, int ny, float2 *__restrict__ dinv,
+                                                                           int nx, int ny,
+                                                                           const float2 *__restrict__ sc,
+                                                                           float2 *__restrict__ dinv,
                                                                            long long wl_stride,
                                                                            double2 *__restrict__ scratch) {
     __shared__ double2 fcol[BT_FACT_MAX_B], prow[BT_FACT_MAX_B];
@@ -193,48 +214,55 @@ __global__ __launch_bounds__(BT_FACT_THREADS) void bt_factor_global_kernel(const
     __shared__ int pivrow;
     const TileDesc t = tiles[big[blockIdx.x]];
     double2 *M = scratch + ((long long)blockIdx.y * n_big + blockIdx.x) * BT_FACT_MAX_B * BT_FACT_MAX_B;
-    bt_factor_body<BT_FACT_MAX_B>(M, fcol, prow, piv, &pivrow, t, blockIdx.y, eps, coef, k0v, h, nx, ny, dinv,
+    bt_factor_body<BT_FACT_MAX_B>(M, fcol, prow, piv, &pivrow, t, blockIdx.y, eps, coef, k0v, h, nx, ny, sc, dinv,
                                   wl_stride);
 }
 
 void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_wl, const float *eps,
-                      const double *coef_d, const double *k0, double h, int nx, int ny, float2 *dinv,
-                      long long dinv_wl_stride, const int *big, int n_big, double2 *scratch) {
+                      const double *coef_d, const double *k0, double h, int nx, int ny, const float2 *sc,
+                      float2 *dinv, long long dinv_wl_stride, const int *big, int n_big, double2 *scratch) {
     hipLaunchKernelGGL(bt_factor_lds_kernel, dim3(n_tiles, n_wl), dim3(BT_FACT_THREADS), 0, s, tiles, eps,
-                       (const double2 *)coef_d, k0, h, nx, ny, dinv, dinv_wl_stride);
+                       (const double2 *)coef_d, k0, h, nx, ny, sc, dinv, dinv_wl_stride);
     if (n_big > 0)
         hipLaunchKernelGGL(bt_factor_global_kernel, dim3(n_big, n_wl), dim3(BT_FACT_THREADS), 0, s, tiles, big,
-                           n_big, eps, (const double2 *)coef_d, k0, h, nx, ny, dinv, dinv_wl_stride, scratch);
+                           n_big, eps, (const double2 *)coef_d, k0, h, nx, ny, sc, dinv, dinv_wl_stride, scratch);
 }
 
 // ------------------------------------------------------------------ solve
 // Thread layout per (subdomain, RHS) workgroup: lane group rp (8 lanes) owns
-// rows 2rp, 2rp+1 of every block; lane cg of the group covers the columns
-// c = cg + 8 j.  Each lane loads one float4 (the two rows' entries of one
-// column) per column, the 8 lanes' partial sums are combined with three xor
-// shuffles inside the wave, and lane 0 of the group runs the recurrence for
-// its two rows.
+// rows 2rp, 2rp+1 of every block; lane cg of the group takes the column pairs
+// q = (rp + d) mod P for the offsets d = cg + 8 j.  For each it loads one 2 x 2
+// sub-block of M_k (two float4), directly (q >= rp) or as the transpose of the
+// stored sub-block (q, rp); every off-diagonal sub-block is therefore read by
+// two groups in the same step, once from HBM and once from cache.  For a fixed
+// d the groups of a wave read consecutive entries of one storage row, so the
+// loads coalesce.  The 8 lanes' partial sums are combined with three DPP
+// steps and lanes 0 and 1 of the group run the recurrence for rows 2rp and
+// 2rp + 1.
 //
-// Only the D_k^-1 stream touches HBM inside the recurrence: the subdomain RHS
-// is gathered into LDS up front (block-major, [k][r]), w_k overwrites v_k in
+// Only the M stream touches HBM inside the recurrence: the subdomain RHS is
+// gathered into LDS up front (block-major, [k][r]), w_k overwrites v_k in
 // place during the forward sweep and is read back by the backward sweep, and
-// the inter-block couplings sit in LDS too.  The matrix-vector operand is
-// double-buffered, so each block step ends with a single barrier; D blocks
-// are prefetched NS - 1 steps ahead into a register ring.
+// the inter-block couplings and the stretches sit in LDS too.  The operand
+// vector (already multiplied by S_k) is double-buffered, so each block step
+// ends with a single barrier; M blocks are prefetched NS - 1 steps ahead into
+// a register ring.
 constexpr int BT_BMAX = 128;
 constexpr int BT_GROUP = 8;
 
-// Unconditional loads: lanes without a column (c >= b, or no row pair) read a
-// valid element of the same block instead, and their products are zeroed by
-// the zero padding of the operand vector.  Keeping every load unpredicated
-// lets the compiler wait only for the oldest slot of the ring; the block base
-// is wave-uniform and the per-lane part a 32-bit byte offset, so the loads
-// take the scalar-base addressing form.
-template <int MAXJ>
-__device__ __forceinline__ void bt_load(float4 (&slot)[MAXJ], const char *__restrict__ blkbase,
-                                        const unsigned (&off)[MAXJ]) {
+// Unconditional loads: lanes without a sub-block (offset d >= P, or no row
+// pair) read a valid entry instead and their products are zeroed at use.
+// Keeping every load unpredicated lets the compiler wait only for the oldest
+// slot of the ring.
+template <int NJ>
+__device__ __forceinline__ void bt_load(float4 (&slot)[2 * NJ], const char *__restrict__ blkbase,
+                                        const unsigned (&off)[NJ]) {
 #pragma unroll
-    for (int j = 0; j < MAXJ; ++j) slot[j] = *reinterpret_cast<const float4 *>(blkbase + off[j]);
+    for (int j = 0; j < NJ; ++j) {
+        const float4 *q = reinterpret_cast<const float4 *>(blkbase + off[j]);
+        slot[2 * j] = q[0];
+        slot[2 * j + 1] = q[1];
+    }
 }
 
 // Cross-lane moves inside groups of 8 lanes (DPP): swap neighbours, swap
@@ -252,32 +280,36 @@ __device__ __forceinline__ float group8_sum(float v) {
     return v + dpp<DPP_HALF_MIRROR>(v);
 }
 
-template <int MAXJ, int NS>
+template <int NJ, int NS>
 __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restrict__ tiles, int n_src,
                                                        const float2 *__restrict__ dinv, long long dinv_wl_stride,
-                                                       const float2 *__restrict__ coef, int nx, int ny,
+                                                       const float2 *__restrict__ coef,
+                                                       const float2 *__restrict__ sc, int nx, int ny,
                                                        const float2 *__restrict__ vin, long long vin_stride,
                                                        float2 *__restrict__ out, long long out_stride,
                                                        const int *__restrict__ active, int mode,
                                                        const int2 *__restrict__ order) {
     extern __shared__ float2 vl[];                    // [nb][b]: v_k, then w_k
     __shared__ float2 ysh[2][BT_BMAX];
-    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX];
+    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX];
     const int2 job = order[blockIdx.x];               // (tile, rhs); tile < 0 pads the queue
     const int tile = job.x, rhs = job.y;
     if (tile < 0 || (active && !active[rhs])) return;
     const int wl = rhs / n_src;
     const TileDesc t = tiles[tile];
-    const int b = t.b, nb = t.nb, half = b >> 1;
+    const int b = t.b, nb = t.nb, P = b >> 1;
     const int tid = threadIdx.x;
     const int rp = tid / BT_GROUP, cg = tid - rp * BT_GROUP;
-    const bool on = rp < half;
+    const bool on = rp < P;
     const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
-    const long long bbytes = (long long)b * b * sizeof(float2);
+    const long long bbytes = bt_sym_block(b) * (long long)sizeof(float2);
     const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
     const float2 *cf = coef + wl * coef_stride(nx, ny);
     const float2 *clo_a = t.tr ? cf : cf + 2 * nx;               // cxm or cym
     const float2 *chi_a = t.tr ? cf + nx : cf + 2 * nx + ny;      // cxp or cyp
+    const float2 *scw = sc + (long long)wl * (nx + ny);
+    const float2 *s_in = t.tr ? scw + nx + t.y0 : scw + t.x0;     // along the block
+    const float2 *s_out = t.tr ? scw + t.x0 : scw + nx + t.y0;    // across blocks
     const int base = t.tr ? t.x0 : t.y0;
     const bool local_in = mode & 1, local_out = mode & 2;
     const float2 *vr = vin + rhs * vin_stride + (local_in ? t.loc_off : 0);
@@ -292,24 +324,34 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     for (int k = tid; k < nb; k += blockDim.x) {
         cl_s[k] = clo_a[base + k];
         ch_s[k] = chi_a[base + k];
+        so_s[k] = s_out[k];
     }
     const int nsteps = 2 * nb - 1;
     auto blk = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
-    unsigned off[MAXJ];
+    // per offset: storage entry (byte offset within a block), transposed flag, operand pair
+    unsigned off[NJ];
+    int qj[NJ];
+    unsigned direct_mask = 0, valid_mask = 0;
 #pragma unroll
-    for (int j = 0; j < MAXJ; ++j) {
-        const int c = cg + BT_GROUP * j;
-        off[j] = (on && c < b) ? (unsigned)(c * half + rp) * 16u : 0u;
+    for (int j = 0; j < NJ; ++j) {
+        const int d = cg + BT_GROUP * j;
+        const bool valid = on && d < P;          // blocks narrower than the widest tile leave slots unused
+        bool direct = true;
+        const int sub = valid ? bt_sym_index(P, rp, d, direct) : 0;
+        off[j] = (unsigned)sub * 32u;
+        qj[j] = valid ? (rp + d) % P : 0;
+        if (direct) direct_mask |= 1u << j;
+        if (valid) valid_mask |= 1u << j;
     }
-    for (int i = tid; i < 2 * BT_BMAX; i += blockDim.x) (&ysh[0][0])[i] = make_float2(0.f, 0.f);
     const char *Dc = reinterpret_cast<const char *>(D);
-    float4 ring[NS][MAXJ];
+    float4 ring[NS][2 * NJ];
 #pragma unroll
-    for (int i = 0; i < NS - 1; ++i) bt_load<MAXJ>(ring[i], Dc + blk(min(i, nsteps - 1)) * bbytes, off);
+    for (int i = 0; i < NS - 1; ++i) bt_load<NJ>(ring[i], Dc + blk(min(i, nsteps - 1)) * bbytes, off);
 
-    // lanes 0 and 1 of each group carry the recurrence for rows r0 and r0 + 1
+    // lanes 0 and 1 of each group carry the recurrence for rows 2rp and 2rp + 1
     const int myr = 2 * rp + (cg & 1);
     const bool wr = on && cg < 2;
+    const float2 si = wr ? s_in[myr] : make_float2(0.f, 0.f);
     // output index of row myr in block k: obase + k * kstride; the block index
     // range [kc0, kc1) and okr select the core rows (all rows for local output)
     long long obase;
@@ -336,27 +378,32 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     }
     const bool emit_lane = wr && okr;
     __syncthreads();
-    if (wr) ysh[0][myr] = vl[myr];
+    if (wr) ysh[0][myr] = cmul(cmul(si, so_s[0]), vl[myr]);      // S_0 v_0
     __syncthreads();
 
-    auto step = [&](int s, const float4(&slot)[MAXJ]) {
+    auto step = [&](int s, const float4(&slot)[2 * NJ]) {
         const int k = blk(s);
         const int p = s & 1;
         const bool fwd = s < nb;
         // the recurrence's other operand does not depend on this step's product
         float2 pre = make_float2(0.f, 0.f);
         if (wr) pre = vl[min(fwd ? k + 1 : k, nb - 1) * b + myr];
-        float2 a0, a1;
-        {
-            const float2 yc = ysh[p][cg];
-            a0 = cmul(make_float2(slot[0].x, slot[0].y), yc);
-            a1 = cmul(make_float2(slot[0].z, slot[0].w), yc);
-        }
+        float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int j = 1; j < MAXJ; ++j) {
-            const float2 yc = ysh[p][cg + BT_GROUP * j];           // zero beyond b
-            a0 = cfma(a0, make_float2(slot[j].x, slot[j].y), yc);
-            a1 = cfma(a1, make_float2(slot[j].z, slot[j].w), yc);
+        for (int j = 0; j < NJ; ++j) {
+            const float2 x0 = ysh[p][2 * qj[j]], x1 = ysh[p][2 * qj[j] + 1];
+            // unused slots hold a clamped load of sub-block 0: their values are zeroed in registers
+            const float u = ((valid_mask >> j) & 1) ? 1.f : 0.f;
+            const float2 A = make_float2(u * slot[2 * j].x, u * slot[2 * j].y);           // M[2p'][2q']
+            const float2 B = make_float2(u * slot[2 * j].z, u * slot[2 * j].w);           // M[2p'+1][2q']
+            const float2 C = make_float2(u * slot[2 * j + 1].x, u * slot[2 * j + 1].y);   // M[2p'][2q'+1]
+            const float2 Dd = make_float2(u * slot[2 * j + 1].z, u * slot[2 * j + 1].w);  // M[2p'+1][2q'+1]
+            const bool dir = (direct_mask >> j) & 1;
+            const float2 E = dir ? C : B, F = dir ? B : C;
+            a0 = cfma(a0, A, x0);
+            a0 = cfma(a0, E, x1);
+            a1 = cfma(a1, F, x0);
+            a1 = cfma(a1, Dd, x1);
         }
         a0.x = group8_sum(a0.x);
         a0.y = group8_sum(a0.y);
@@ -365,15 +412,24 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
         const float2 a = (cg & 1) ? a1 : a0;
         if (wr) {
             float2 y;
+            int knext;
             if (fwd) {
                 vl[k * b + myr] = a;                                        // w_k
-                y = (k + 1 < nb) ? cfms(pre, cl_s[k + 1], a) : a;           // y_{k+1}, or u_{nb-1} = w_{nb-1}
-                if (k + 1 == nb && emit_lane && k >= kc0 && k < kc1) orr[obase + (long long)k * kstride] = a;
+                if (k + 1 < nb) {
+                    y = cfms(pre, cl_s[k + 1], a);                          // y_{k+1}
+                    knext = k + 1;
+                } else {
+                    y = a;                                                  // u_{nb-1} = w_{nb-1}
+                    knext = k - 1;
+                    if (emit_lane && k >= kc0 && k < kc1) orr[obase + (long long)k * kstride] = a;
+                }
             } else {
                 y = cfms(pre, ch_s[k], a);                                  // u_k
+                knext = k - 1;
                 if (emit_lane && k >= kc0 && k < kc1) orr[obase + (long long)k * kstride] = y;
             }
-            ysh[p ^ 1][myr] = y;
+            // operand of the next step: S_knext y
+            ysh[p ^ 1][myr] = knext >= 0 ? cmul(cmul(si, so_s[knext]), y) : y;
         }
         __syncthreads();
     };
@@ -384,7 +440,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     for (; s0 + NS <= nsteps; s0 += NS) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-            bt_load<MAXJ>(ring[(i + NS - 1) % NS], Dc + blk(min(s0 + i + NS - 1, nsteps - 1)) * bbytes, off);
+            bt_load<NJ>(ring[(i + NS - 1) % NS], Dc + blk(min(s0 + i + NS - 1, nsteps - 1)) * bbytes, off);
             step(s0 + i, ring[i]);
         }
     }
@@ -394,31 +450,33 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
         if (s0 + i < nsteps) step(s0 + i, ring[i]);
 }
 
-template <int MAXJ, int NS>
+template <int NJ, int NS>
 static void bt_solve_launch(hipStream_t s, dim3 grid, int threads, size_t lds, const TileDesc *tiles, int n_src,
-                            const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
-                            const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
-                            const int *active, int mode, const int2 *order) {
-    hipLaunchKernelGGL((bt_solve_kernel<MAXJ, NS>), grid, dim3(threads), lds, s, tiles, n_src, dinv, dinv_wl_stride,
-                       coef, nx, ny, vin, vin_stride, out, out_stride, active, mode, order);
+                            const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc,
+                            int nx, int ny, const float2 *vin, long long vin_stride, float2 *out,
+                            long long out_stride, const int *active, int mode, const int2 *order) {
+    hipLaunchKernelGGL((bt_solve_kernel<NJ, NS>), grid, dim3(threads), lds, s, tiles, n_src, dinv, dinv_wl_stride,
+                       coef, sc, nx, ny, vin, vin_stride, out, out_stride, active, mode, order);
 }
+
+static int bt_nj(int bmax) { return ((bmax / 2) + BT_GROUP - 1) / BT_GROUP; }
 
 // Kernels that need more than 64 KB of dynamic LDS must say so once per
 // process, before any launch (and outside graph capture).
 void bt_solve_prepare(int bmax, int max_cells) {
     const size_t lds = (size_t)max_cells * sizeof(float2);
     if (lds <= 65536) return;
-    const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
+    const int nj = bt_nj(bmax);
     const void *fs[3];
     int nf = 0;
-    if (maxj <= 9) {
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<9, 3>);
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<9, 4>);
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<9, 5>);
-    } else if (maxj <= 13) {
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<13, 3>);
+    if (nj <= 5) {
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 3>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 4>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 5>);
+    } else if (nj <= 7) {
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<7, 3>);
     } else {
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<16, 3>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<8, 3>);
     }
     for (int i = 0; i < nf; ++i) (void)hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
@@ -426,8 +484,7 @@ void bt_solve_prepare(int bmax, int max_cells) {
 // Prefetch depths available for a block size (the register ring holds NS - 1
 // blocks ahead); the first is the default.
 int bt_solve_depths(int bmax, int *depths) {
-    const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
-    if (maxj <= 9) {
+    if (bt_nj(bmax) <= 5) {
         depths[0] = 4;
         depths[1] = 3;
         depths[2] = 5;
@@ -438,26 +495,26 @@ int bt_solve_depths(int bmax, int *depths) {
 }
 
 void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, int n_jobs, int n_src,
-                     const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
-                     const float2 *vin, long long vin_stride, float2 *out, long long out_stride, const int *active,
-                     int mode, int bmax, int max_cells, int depth) {
+                     const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc, int nx,
+                     int ny, const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
+                     const int *active, int mode, int bmax, int max_cells, int depth) {
     dim3 grid(n_jobs);
     const int threads = ((bmax / 2) * BT_GROUP + 63) / 64 * 64;
-    const int maxj = (bmax + BT_GROUP - 1) / BT_GROUP;
+    const int nj = bt_nj(bmax);
     const size_t lds = (size_t)max_cells * sizeof(float2);
-#define BT_ARGS s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, nx, ny, vin, vin_stride, out, \
+#define BT_ARGS s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride, out, \
                 out_stride, active, mode, order
-    if (maxj <= 9) {
+    if (nj <= 5) {
         if (depth == 3)
-            bt_solve_launch<9, 3>(BT_ARGS);
+            bt_solve_launch<5, 3>(BT_ARGS);
         else if (depth == 5)
-            bt_solve_launch<9, 5>(BT_ARGS);
+            bt_solve_launch<5, 5>(BT_ARGS);
         else
-            bt_solve_launch<9, 4>(BT_ARGS);
-    } else if (maxj <= 13) {
-        bt_solve_launch<13, 3>(BT_ARGS);
+            bt_solve_launch<5, 4>(BT_ARGS);
+    } else if (nj <= 7) {
+        bt_solve_launch<7, 3>(BT_ARGS);
     } else {
-        bt_solve_launch<16, 3>(BT_ARGS);
+        bt_solve_launch<8, 3>(BT_ARGS);
     }
 #undef BT_ARGS
 }

@@ -690,7 +690,7 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
     {
         const auto &ob = p->orders.at(std::make_pair(n_rhs, n_src));
         launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ob.buf.as<int2>(), ob.n_jobs, n_src, p->d_dinv.as<float2>(),
-                        p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, v, N, z, N, active, 0, p->bmax,
+                        p->dinv_wl_stride, p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, v, N, z, N, active, 0, p->bmax,
                         p->max_cells, p->bt_depth);
     }
     }
@@ -837,7 +837,7 @@ nosdd_status coarse_setup(nosdd_problem *p) {
         nosdd_status so = solve_order(p, nwl * K, K, &ord, &nj);
         if (so != NOSDD_OK) return so;
         launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ord, nj, K, p->d_dinv.as<float2>(), p->dinv_wl_stride,
-                        p->d_coef.as<float2>(), nx, ny, d_rhs.as<float2>(), LT, d_F.as<float2>(), LT, nullptr, 3,
+                        p->d_coef.as<float2>(), p->d_sc.as<float2>(), nx, ny, d_rhs.as<float2>(), LT, d_F.as<float2>(), LT, nullptr, 3,
                         p->bmax, p->max_cells);
     }
     std::vector<float2> F(rhs.size());
@@ -1062,7 +1062,7 @@ nosdd_status autotune(nosdd_problem *p, int n_rhs, int n_src, int m, const Given
         for (int i = 0; i < nd; ++i) {
             const float ms = time_ms([&] {
                 launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ord, nj, n_src, p->d_dinv.as<float2>(),
-                                p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, V, N, Z, N,
+                                p->dinv_wl_stride, p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, V, N, Z, N,
                                 w.ones.as<int>(), 0, p->bmax, p->max_cells, depths[i]);
             });
             if (ms < best) {
@@ -1466,7 +1466,7 @@ nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const flo
             t.loc_off = loc;
             loc += (long long)lx * ly;
             t.dinv_off = dinv;
-            dinv += (long long)t.nb * t.b * t.b;
+            dinv += (long long)t.nb * bt_sym_block(t.b);
             p->bmax = std::max(p->bmax, t.b);
             p->tiles.push_back(t);
             cx += p->core_x[tx];
@@ -1575,7 +1575,8 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
                                      sizeof(double2)));
         }
         launch_bt_factor(s, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, p->d_eps.as<float>(),
-                         p->d_coefd.as<double>(), p->d_k0.as<double>(), p->h, p->nx, p->ny, p->d_dinv.as<float2>(),
+                         p->d_coefd.as<double>(), p->d_k0.as<double>(), p->h, p->nx, p->ny, p->d_sc.as<float2>(),
+                         p->d_dinv.as<float2>(),
                          p->dinv_wl_stride, d_big.as<int>(), (int)big.size(), d_scr.as<double2>());
         HIPCHK(ctx, hipGetLastError());
         HIPCHK(ctx, hipStreamSynchronize(s));
@@ -1750,7 +1751,7 @@ nosdd_status nosdd_schwarz_sweep(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
     st = solve_order(p, n_rhs, n_src, &ord, &nj);
     if (st) return st;
     launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), ord, nj, n_src, p->d_dinv.as<float2>(),
-                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->nx, p->ny, (const float2 *)v, N, (float2 *)z, N,
+                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, (const float2 *)v, N, (float2 *)z, N,
                     nullptr, 0, p->bmax, p->max_cells);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
@@ -1807,7 +1808,7 @@ nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32
     st = solve_order(p, nwl, 1, &ord, &nj);
     if (st) return st;
     launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), ord, nj, 1, p->d_dinv.as<float2>(), p->dinv_wl_stride,
-                    p->d_coef.as<float2>(), p->nx, p->ny, (const float2 *)rhs, p->loc_total, (float2 *)u,
+                    p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, (const float2 *)rhs, p->loc_total, (float2 *)u,
                     p->loc_total, nullptr, 3, p->bmax, p->max_cells);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));

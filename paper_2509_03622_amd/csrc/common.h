@@ -74,11 +74,48 @@ void launch_stencil(hipStream_t s, const float2 *x, const float2 *b, float2 *y, 
 void launch_residual64(hipStream_t s, const double2 *x, const float2 *b, float2 *r, const float *eps,
                        const double2 *coef, const double *k0, int nx, int ny, int n_rhs, int n_src);
 
+// Symmetric storage of the subdomain factors.  With S_k = diag of the centre
+// stretches s_x s_y on block k, M_k = D_k^-1 S_k^-1 = (S_k D_k)^-1 is complex
+// symmetric, and D_k^-1 y = M_k (S_k y).  Only the upper triangle is kept, as
+// 2 x 2 sub-blocks (rows 2p, 2p+1; columns 2q, 2q+1; q >= p), each stored
+// column-major (M[2p][2q], M[2p+1][2q], M[2p][2q+1], M[2p+1][2q+1]).  With
+// P = b/2 the sub-blocks are laid out in rows D = 0 .. P/2 of P entries (the
+// last one, D = P/2 for even P, has P/2): row 0 is the diagonal, row D > 0
+// holds diagonal D at entries 0..P-D-1 and diagonal P-D at entries P-D..P-1,
+// so the row-pair p and the offset d = 0..P-1 (column pair (p + d) mod P)
+// always find their sub-block at entry bt_sym_index.
+__host__ __device__ __forceinline__ long long bt_sym_block(int b) { return (long long)b * (b + 2) / 2; }  // complex
+// sub-block (row of the storage D, entry i) -> (p, q) with q >= p
+__host__ __device__ __forceinline__ void bt_sym_pq(int P, int sub, int &p, int &q) {
+    if (sub < P) {
+        p = q = sub;
+        return;
+    }
+    const int D = sub / P, i = sub - D * P;
+    if (i < P - D) {
+        p = i;
+        q = i + D;
+    } else {
+        p = i - (P - D);
+        q = i;
+    }
+}
+// row pair p, offset d in [0, P): storage sub-block index and whether the
+// sub-block is (p, q) as stored (true) or its transpose (false)
+__host__ __device__ __forceinline__ int bt_sym_index(int P, int p, int d, bool &direct) {
+    direct = p + d < P;
+    if (d == 0) return p;
+    if (2 * d == P) return d * P + (p < d ? p : p - d);
+    if (2 * d < P) return d * P + p;
+    const int D = P - d, idx = p + d < P ? p + d : p + d - P;
+    return D * P + idx;
+}
+
 // Factorisation of every (tile, wavelength); tiles whose short side exceeds
 // 72 (listed in big[n_big]) use scratch[n_wl * n_big * 128 * 128] (FP64 complex).
 void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_wl, const float *eps,
-                      const double *coef_d, const double *k0, double h, int nx, int ny, float2 *dinv,
-                      long long dinv_wl_stride, const int *big, int n_big, double2 *scratch);
+                      const double *coef_d, const double *k0, double h, int nx, int ny, const float2 *sc,
+                      float2 *dinv, long long dinv_wl_stride, const int *big, int n_big, double2 *scratch);
 constexpr int BT_FACT_SCRATCH_B = 128;
 
 // mode bit 0: input is a packed local vector (else gathered from a global vector)
@@ -89,8 +126,8 @@ constexpr int BT_LDS_MAX_CELLS = 15360;                      // 120 KB of LDS
 // One workgroup per job: order[n_jobs] = (tile, rhs), tile < 0 for padding.
 // depth: prefetch depth of the D-block ring (one of bt_solve_depths, 0 = default).
 void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, int n_jobs, int n_src,
-                     const float2 *dinv, long long dinv_wl_stride, const float2 *coef, int nx, int ny,
-                     const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
+                     const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc, int nx,
+                     int ny, const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
                      const int *active, int mode, int bmax, int max_cells, int depth = 0);
 void bt_solve_prepare(int bmax, int max_cells);
 int bt_solve_depths(int bmax, int *depths);
