@@ -290,7 +290,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
                                                        const int *__restrict__ active, int mode,
                                                        const int2 *__restrict__ order) {
     extern __shared__ float2 vl[];                    // [nb][b]: v_k, then w_k
-    __shared__ float2 ysh[2][BT_BMAX];
+    __shared__ float2 ysh[2][BT_BMAX + 2];            // + a zero pair read by unused offset slots
     __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX];
     const int2 job = order[blockIdx.x];               // (tile, rhs); tile < 0 pads the queue
     const int tile = job.x, rhs = job.y;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     // per offset: storage entry (byte offset within a block), transposed flag, operand pair
     unsigned off[NJ];
     int qj[NJ];
-    unsigned direct_mask = 0, valid_mask = 0;
+    unsigned direct_mask = 0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const int d = cg + BT_GROUP * j;
@@ -339,9 +339,8 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
         bool direct = true;
         const int sub = valid ? bt_sym_index(P, rp, d, direct) : 0;
         off[j] = (unsigned)sub * 32u;
-        qj[j] = valid ? (rp + d) % P : 0;
+        qj[j] = valid ? (rp + d) % P : BT_BMAX / 2;
         if (direct) direct_mask |= 1u << j;
-        if (valid) valid_mask |= 1u << j;
     }
     const char *Dc = reinterpret_cast<const char *>(D);
     float4 ring[NS][2 * NJ];
@@ -379,6 +378,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     const bool emit_lane = wr && okr;
     __syncthreads();
     if (wr) ysh[0][myr] = cmul(cmul(si, so_s[0]), vl[myr]);      // S_0 v_0
+    if (tid < 4) ysh[tid >> 1][BT_BMAX + (tid & 1)] = make_float2(0.f, 0.f);
     __syncthreads();
 
     auto step = [&](int s, const float4(&slot)[2 * NJ]) {
@@ -391,13 +391,12 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
         float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
+            // unused slots hold a clamped load of sub-block 0 and multiply the zero pair
             const float2 x0 = ysh[p][2 * qj[j]], x1 = ysh[p][2 * qj[j] + 1];
-            // unused slots hold a clamped load of sub-block 0: their values are zeroed in registers
-            const float u = ((valid_mask >> j) & 1) ? 1.f : 0.f;
-            const float2 A = make_float2(u * slot[2 * j].x, u * slot[2 * j].y);           // M[2p'][2q']
-            const float2 B = make_float2(u * slot[2 * j].z, u * slot[2 * j].w);           // M[2p'+1][2q']
-            const float2 C = make_float2(u * slot[2 * j + 1].x, u * slot[2 * j + 1].y);   // M[2p'][2q'+1]
-            const float2 Dd = make_float2(u * slot[2 * j + 1].z, u * slot[2 * j + 1].w);  // M[2p'+1][2q'+1]
+            const float2 A = make_float2(slot[2 * j].x, slot[2 * j].y);           // M[2p'][2q']
+            const float2 B = make_float2(slot[2 * j].z, slot[2 * j].w);           // M[2p'+1][2q']
+            const float2 C = make_float2(slot[2 * j + 1].x, slot[2 * j + 1].y);   // M[2p'][2q'+1]
+            const float2 Dd = make_float2(slot[2 * j + 1].z, slot[2 * j + 1].w);  // M[2p'+1][2q'+1]
             const bool dir = (direct_mask >> j) & 1;
             const float2 E = dir ? C : B, F = dir ? B : C;
             a0 = cfma(a0, A, x0);
