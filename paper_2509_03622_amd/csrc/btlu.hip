@@ -164,8 +164,10 @@ __device__ __forceinline__ void bt_factor_body(double2 *M, double2 *fcol, double
         // store the upper triangle of M_k = D_k^-1 S_k^-1 (symmetric), 2 x 2 sub-blocks
         float2 *dk = outw + (long long)k * blk;
         const float2 so = s_out[k];
+        const int nsub = (int)(blk >> 2);
         for (int e = tid; e < (int)blk; e += BT_FACT_THREADS) {
-            const int sub = e >> 2, comp = e & 3;
+            // e: half (first / second columns), sub-block, row within the pair
+            const int half = e >= 2 * nsub, sub = (e - half * 2 * nsub) >> 1, comp = (e & 1) | (half << 1);
             int bp, bq;
             bt_sym_pq(P, sub, bp, bq);
             const int r = 2 * bp + (comp & 1), c = 2 * bq + (comp >> 1);
@@ -254,14 +256,20 @@ constexpr int BT_GROUP = 8;
 // pair) read a valid entry instead and their products are zeroed at use.
 // Keeping every load unpredicated lets the compiler wait only for the oldest
 // slot of the ring.
+// The loads go through a buffer resource over the tile's factors: the
+// per-lane offset stays in a 32-bit register and the block offset in a
+// scalar register, so no address arithmetic runs per load.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t bt_rsrc(const void *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
 template <int NJ>
-__device__ __forceinline__ void bt_load(float4 (&slot)[2 * NJ], const char *__restrict__ blkbase,
-                                        const unsigned (&off)[NJ]) {
+__device__ __forceinline__ void bt_load(float4 (&slot)[2 * NJ], __amdgpu_buffer_rsrc_t rs, unsigned blkoff,
+                                        const unsigned (&off)[NJ], unsigned half) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const float4 *q = reinterpret_cast<const float4 *>(blkbase + off[j]);
-        slot[2 * j] = q[0];
-        slot[2 * j + 1] = q[1];
+        slot[2 * j] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off[j], blkoff, 0));
+        slot[2 * j + 1] =
+            __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, off[j], blkoff + half, 0));
     }
 }
 
@@ -269,15 +277,56 @@ __device__ __forceinline__ void bt_load(float4 (&slot)[2 * NJ], const char *__re
 // pairs, mirror the half-row of 8 lanes.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 constexpr int DPP_QUAD_XOR1 = 0xB1;       // quad_perm [1,0,3,2]
 constexpr int DPP_QUAD_XOR2 = 0x4E;       // quad_perm [2,3,0,1]
-constexpr int DPP_HALF_MIRROR = 0x141;    // row_half_mirror
-__device__ __forceinline__ float group8_sum(float v) {
-    v += dpp<DPP_QUAD_XOR1>(v);
-    v += dpp<DPP_QUAD_XOR2>(v);
-    return v + dpp<DPP_HALF_MIRROR>(v);
+constexpr int DPP_HALF_MIRROR = 0x141;    // row_half_mirror (lane i <-> 7 - i)
+
+// Sums of the two rows' partial products over the 8 lanes of a group, with
+// two values per lane instead of four: each lane keeps one row and sends the
+// other to its neighbour, then the kept sums are combined.  Lanes 4..7 keep
+// the opposite rows to lanes 0..3 so that the half-row mirror pairs equal
+// rows.  Lane 0 ends with row 2rp, lane 1 with row 2rp + 1.
+__device__ __forceinline__ float2 pair_sum8(float2 a0, float2 a1, bool keep1) {
+    float2 keep = keep1 ? a1 : a0;
+    const float2 send = keep1 ? a0 : a1;
+    keep.x += dpp<DPP_QUAD_XOR1>(send.x);
+    keep.y += dpp<DPP_QUAD_XOR1>(send.y);
+    keep.x += dpp<DPP_QUAD_XOR2>(keep.x);
+    keep.y += dpp<DPP_QUAD_XOR2>(keep.y);
+    keep.x += dpp<DPP_HALF_MIRROR>(keep.x);
+    keep.y += dpp<DPP_HALF_MIRROR>(keep.y);
+    return keep;
+}
+
+// One lane's share of M_k x: the sub-blocks of its offset slots (loaded in
+// `slot`, used directly or transposed) times the operand pairs in LDS;
+// returns the group's sums for rows 2rp (lane 0) and 2rp + 1 (lane 1).
+template <int NJ>
+__device__ __forceinline__ float2 bt_matvec(const float4 (&slot)[2 * NJ], const float2 *__restrict__ ysrc,
+                                            const int (&qj)[NJ], unsigned direct_mask, bool keep1) {
+    // even and odd slots accumulate separately: half the dependent chain length
+    float2 a0[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    float2 a1[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        // unused slots hold a clamped load of sub-block 0 and multiply the zero pair
+        const float4 x = *reinterpret_cast<const float4 *>(ysrc + 2 * qj[j]);
+        const float2 x0 = make_float2(x.x, x.y), x1 = make_float2(x.z, x.w);
+        const float2 A = make_float2(slot[2 * j].x, slot[2 * j].y);           // M[2p'][2q']
+        const float2 B = make_float2(slot[2 * j].z, slot[2 * j].w);           // M[2p'+1][2q']
+        const float2 C = make_float2(slot[2 * j + 1].x, slot[2 * j + 1].y);   // M[2p'][2q'+1]
+        const float2 Dd = make_float2(slot[2 * j + 1].z, slot[2 * j + 1].w);  // M[2p'+1][2q'+1]
+        const bool dir = (direct_mask >> j) & 1;
+        const float2 E = dir ? C : B, F = dir ? B : C;
+        a0[j & 1] = cfma(a0[j & 1], A, x0);
+        a0[j & 1] = cfma(a0[j & 1], E, x1);
+        a1[j & 1] = cfma(a1[j & 1], F, x0);
+        a1[j & 1] = cfma(a1[j & 1], Dd, x1);
+    }
+    return pair_sum8(make_float2(a0[0].x + a0[1].x, a0[0].y + a0[1].y),
+                     make_float2(a1[0].x + a1[1].x, a1[0].y + a1[1].y), keep1);
 }
 
 template <int NJ, int NS>
@@ -290,7 +339,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
                                                        const int *__restrict__ active, int mode,
                                                        const int2 *__restrict__ order) {
     extern __shared__ float2 vl[];                    // [nb][b]: v_k, then w_k
-    __shared__ float2 ysh[2][BT_BMAX + 2];            // + a zero pair read by unused offset slots
+    __shared__ __align__(16) float2 ysh[2][BT_BMAX + 2];   // + a zero pair read by unused offset slots
     __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX];
     const int2 job = order[blockIdx.x];               // (tile, rhs); tile < 0 pads the queue
     const int tile = job.x, rhs = job.y;
@@ -338,14 +387,15 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
         const bool valid = on && d < P;          // blocks narrower than the widest tile leave slots unused
         bool direct = true;
         const int sub = valid ? bt_sym_index(P, rp, d, direct) : 0;
-        off[j] = (unsigned)sub * 32u;
+        off[j] = (unsigned)sub * 16u;
         qj[j] = valid ? (rp + d) % P : BT_BMAX / 2;
         if (direct) direct_mask |= 1u << j;
     }
-    const char *Dc = reinterpret_cast<const char *>(D);
+    const __amdgpu_buffer_rsrc_t rs = bt_rsrc(D, (unsigned)(nb * bbytes));
+    const unsigned half = (unsigned)(bbytes >> 1);         // second columns of the sub-blocks
     float4 ring[NS][2 * NJ];
 #pragma unroll
-    for (int i = 0; i < NS - 1; ++i) bt_load<NJ>(ring[i], Dc + blk(min(i, nsteps - 1)) * bbytes, off);
+    for (int i = 0; i < NS - 1; ++i) bt_load<NJ>(ring[i], rs, (unsigned)(blk(min(i, nsteps - 1)) * bbytes), off, half);
 
     // lanes 0 and 1 of each group carry the recurrence for rows 2rp and 2rp + 1
     const int myr = 2 * rp + (cg & 1);
@@ -381,54 +431,27 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     if (tid < 4) ysh[tid >> 1][BT_BMAX + (tid & 1)] = make_float2(0.f, 0.f);
     __syncthreads();
 
+    const bool keep1 = ((cg ^ (cg >> 2)) & 1) != 0;
     auto step = [&](int s, const float4(&slot)[2 * NJ]) {
         const int k = blk(s);
         const int p = s & 1;
         const bool fwd = s < nb;
-        // the recurrence's other operand does not depend on this step's product
-        float2 pre = make_float2(0.f, 0.f);
-        if (wr) pre = vl[min(fwd ? k + 1 : k, nb - 1) * b + myr];
-        float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            // unused slots hold a clamped load of sub-block 0 and multiply the zero pair
-            const float2 x0 = ysh[p][2 * qj[j]], x1 = ysh[p][2 * qj[j] + 1];
-            const float2 A = make_float2(slot[2 * j].x, slot[2 * j].y);           // M[2p'][2q']
-            const float2 B = make_float2(slot[2 * j].z, slot[2 * j].w);           // M[2p'+1][2q']
-            const float2 C = make_float2(slot[2 * j + 1].x, slot[2 * j + 1].y);   // M[2p'][2q'+1]
-            const float2 Dd = make_float2(slot[2 * j + 1].z, slot[2 * j + 1].w);  // M[2p'+1][2q'+1]
-            const bool dir = (direct_mask >> j) & 1;
-            const float2 E = dir ? C : B, F = dir ? B : C;
-            a0 = cfma(a0, A, x0);
-            a0 = cfma(a0, E, x1);
-            a1 = cfma(a1, F, x0);
-            a1 = cfma(a1, Dd, x1);
-        }
-        a0.x = group8_sum(a0.x);
-        a0.y = group8_sum(a0.y);
-        a1.x = group8_sum(a1.x);
-        a1.y = group8_sum(a1.y);
-        const float2 a = (cg & 1) ? a1 : a0;
+        const bool turn = s == nb - 1;                // u_{nb-1} = w_{nb-1}
+        const int knext = fwd && !turn ? k + 1 : k - 1;
+        // everything the recurrence needs besides the product, read first:
+        // v_{k+1} (forward) or w_k (backward), the coupling, S_knext
+        float2 pre = make_float2(0.f, 0.f), cc = make_float2(0.f, 0.f), skn = make_float2(0.f, 0.f);
         if (wr) {
-            float2 y;
-            int knext;
-            if (fwd) {
-                vl[k * b + myr] = a;                                        // w_k
-                if (k + 1 < nb) {
-                    y = cfms(pre, cl_s[k + 1], a);                          // y_{k+1}
-                    knext = k + 1;
-                } else {
-                    y = a;                                                  // u_{nb-1} = w_{nb-1}
-                    knext = k - 1;
-                    if (emit_lane && k >= kc0 && k < kc1) orr[obase + (long long)k * kstride] = a;
-                }
-            } else {
-                y = cfms(pre, ch_s[k], a);                                  // u_k
-                knext = k - 1;
-                if (emit_lane && k >= kc0 && k < kc1) orr[obase + (long long)k * kstride] = y;
-            }
-            // operand of the next step: S_knext y
-            ysh[p ^ 1][myr] = knext >= 0 ? cmul(cmul(si, so_s[knext]), y) : y;
+            pre = vl[min(fwd ? k + 1 : k, nb - 1) * b + myr];
+            cc = fwd ? cl_s[min(k + 1, nb - 1)] : ch_s[k];
+            skn = cmul(si, so_s[max(knext, 0)]);
+        }
+        const float2 a = bt_matvec<NJ>(slot, ysh[p], qj, direct_mask, keep1);
+        if (wr) {
+            if (fwd) vl[k * b + myr] = a;                                   // w_k
+            const float2 y = turn ? a : cfms(pre, cc, a);                   // y_{k+1} or u_k
+            if ((!fwd || turn) && emit_lane && k >= kc0 && k < kc1) orr[obase + (long long)k * kstride] = y;
+            ysh[p ^ 1][myr] = knext >= 0 ? cmul(skn, y) : y;                // operand of the next step
         }
         __syncthreads();
     };
@@ -439,7 +462,8 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     for (; s0 + NS <= nsteps; s0 += NS) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-            bt_load<NJ>(ring[(i + NS - 1) % NS], Dc + blk(min(s0 + i + NS - 1, nsteps - 1)) * bbytes, off);
+            bt_load<NJ>(ring[(i + NS - 1) % NS], rs, (unsigned)(blk(min(s0 + i + NS - 1, nsteps - 1)) * bbytes), off,
+                        half);
             step(s0 + i, ring[i]);
         }
     }

@@ -77,8 +77,11 @@ void launch_residual64(hipStream_t s, const double2 *x, const float2 *b, float2 
 // Symmetric storage of the subdomain factors.  With S_k = diag of the centre
 // stretches s_x s_y on block k, M_k = D_k^-1 S_k^-1 = (S_k D_k)^-1 is complex
 // symmetric, and D_k^-1 y = M_k (S_k y).  Only the upper triangle is kept, as
-// 2 x 2 sub-blocks (rows 2p, 2p+1; columns 2q, 2q+1; q >= p), each stored
-// column-major (M[2p][2q], M[2p+1][2q], M[2p][2q+1], M[2p+1][2q+1]).  With
+// 2 x 2 sub-blocks (rows 2p, 2p+1; columns 2q, 2q+1; q >= p).  A block holds
+// n = P (P + 1) / 2 sub-blocks in two halves: first the first columns
+// (M[2p][2q], M[2p+1][2q]) of every sub-block, 16 bytes each, then their
+// second columns (M[2p][2q+1], M[2p+1][2q+1]), so that one 16-byte load per
+// lane over consecutive sub-blocks reads whole cache lines.  With
 // P = b/2 the sub-blocks are laid out in rows D = 0 .. P/2 of P entries (the
 // last one, D = P/2 for even P, has P/2): row 0 is the diagonal, row D > 0
 // holds diagonal D at entries 0..P-D-1 and diagonal P-D at entries P-D..P-1,
@@ -124,7 +127,7 @@ constexpr int BT_FACT_SCRATCH_B = 128;
 constexpr int BT_NBMAX = 256;                                // longest tile side
 constexpr int BT_LDS_MAX_CELLS = 15360;                      // 120 KB of LDS
 // One workgroup per job: order[n_jobs] = (tile, rhs), tile < 0 for padding.
-// depth: prefetch depth of the D-block ring (one of bt_solve_depths, 0 = default).
+// depth: prefetch depth of the factor-block ring (one of bt_solve_depths, 0 = default).
 void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, int n_jobs, int n_src,
                      const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc, int nx,
                      int ny, const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
