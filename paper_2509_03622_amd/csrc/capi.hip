@@ -1038,8 +1038,8 @@ nosdd_status autotune(nosdd_problem *p, int n_rhs, int n_src, int m, const Given
                     launch_cgs_dots(s, V, vstride, nv, wv, N, n_rhs, ones, part, c);
                     launch_cgs_update_dots(s, V, vstride, nv, wv, V + nv * vstride, N, n_rhs, ones,
                                            w.H.as<float2>(), m, nv - 1, part, c);
-                    launch_cgs_update(s, V, vstride, nv, V + nv * vstride, V + nv * vstride, N, n_rhs, ones,
-                                      w.H2.as<float2>(), m, nv - 1, part, c);
+                    launch_cgs_update_scale(s, V, vstride, nv, V + nv * vstride, V + nv * vstride, N, n_rhs, ones,
+                                            ones, w.H2.as<float2>(), m, nv - 1, w.inv_h.as<float>(), c);
                 });
                 if (ms < best) {
                     best = ms;
@@ -1203,7 +1203,8 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     const int *active = w.active.as<int>();
     // One Arnoldi step j: z_j = M^-1 v_j, w = A z_j, classical Gram-Schmidt
     // against v_0..v_j with a second pass where the DGKS test asks for it,
-    // Givens rotation and residual estimate, v_{j+1} = w / h_{j+1,j}.  Every
+    // Givens rotation and residual estimate (the second pass's norm from
+    // ||w'||^2 - ||h2||^2), v_{j+1} = w / h_{j+1,j} written by the last pass.  Every
     // argument is fixed for the solve, so the step can be captured in a graph.
     auto step = [&](hipStream_t st, int j, int n_live_) {
         float2 *Vj = V + j * vstride, *Vn = V + (j + 1) * vstride, *Zj = Z + j * vstride;
@@ -1218,9 +1219,8 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         // first-pass update with the second pass's dots taken from the same loads
         launch_cgs_update_dots(st, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, j, part, nb);
         launch_cgs_reduce(st, part, nb, j + 1, n_rhs, nullptr, j, 5, nullptr, ga);
-        launch_cgs_update(st, V, vstride, j + 1, Vn, Vn, N, n_rhs, ro, w.H2.as<float2>(), m, j, part, nb);
-        launch_cgs_reduce(st, part, nb, 0, n_rhs, ro, j, 4, nullptr, ga);
-        launch_scale(st, Vn, N, n_rhs, active, ih);
+        launch_cgs_update_scale(st, V, vstride, j + 1, Vn, Vn, N, n_rhs, active, ro, w.H2.as<float2>(), m, j, ih,
+                                nb);
     };
     {
         const int2 *ord = nullptr;

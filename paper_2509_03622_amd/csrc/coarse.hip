@@ -10,13 +10,15 @@
 
 namespace nosdd {
 
-// d[r][col] = sum_box conj(W[wl][col]) (v - w1), one workgroup per (col, rhs), FP64 sums.
-__global__ __launch_bounds__(256) void coarse_dot_kernel(const TileDesc *__restrict__ tiles, int kc,
+// d[r][col] = sum_box conj(W[wl][col]) (v - w1), one workgroup per (col, rhs), FP64 sums
+// (a box of about 66 x 66 cells: 1024 threads keep the per-thread loop short).
+constexpr int CD_THREADS = 1024;
+__global__ __launch_bounds__(CD_THREADS) void coarse_dot_kernel(const TileDesc *__restrict__ tiles, int kc,
                                                          const float2 *__restrict__ Wbox, long long wl_stride,
                                                          const float2 *__restrict__ v, const float2 *__restrict__ w1,
                                                          int nx, long long N, int n_src, int n_c,
                                                          const int *__restrict__ active, double2 *__restrict__ d) {
-    __shared__ double2 red[4];
+    __shared__ double2 red[CD_THREADS / 64];
     const int col = blockIdx.x, r = blockIdx.y;
     if (active && !active[r]) return;
     const int wl = r / n_src;
@@ -26,7 +28,7 @@ __global__ __launch_bounds__(256) void coarse_dot_kernel(const TileDesc *__restr
     const float2 *vr = v + r * N, *wr = w1 + r * N;
     double sx = 0.0, sy = 0.0;
     const int nbox = t.bw * t.bh;
-    for (int e = threadIdx.x; e < nbox; e += 256) {
+    for (int e = threadIdx.x; e < nbox; e += CD_THREADS) {
         const int by = e / t.bw, bx = e - by * t.bw;
         const long long g = (long long)(t.by0 + by) * nx + (t.bx0 + bx);
         const float2 tv = csub(vr[g], wr[g]);
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(256) void coarse_dot_kernel(const TileDesc *__restr
     __syncthreads();
     if (threadIdx.x == 0) {
         double2 s = red[0];
-        for (int i = 1; i < 4; ++i) s = zadd(s, red[i]);
+        for (int i = 1; i < CD_THREADS / 64; ++i) s = zadd(s, red[i]);
         d[(long long)r * n_c + col] = s;
     }
 }
@@ -50,39 +52,52 @@ __global__ __launch_bounds__(256) void coarse_dot_kernel(const TileDesc *__restr
 void launch_coarse_dot(hipStream_t s, const TileDesc *tiles, int n_c, int kc, const float2 *Wbox,
                        long long box_wl_stride, const float2 *v, const float2 *w1, int nx, long long N, int n_rhs,
                        int n_src, const int *active, double2 *d) {
-    hipLaunchKernelGGL(coarse_dot_kernel, dim3(n_c, n_rhs), dim3(256), 0, s, tiles, kc, Wbox, box_wl_stride, v, w1,
+    hipLaunchKernelGGL(coarse_dot_kernel, dim3(n_c, n_rhs), dim3(CD_THREADS), 0, s, tiles, kc, Wbox, box_wl_stride, v, w1,
                        nx, N, n_src, n_c, active, d);
 }
 
 // c[r] = G^-1 d[r] in FP64; G^-1 stored transposed (GinvT[wl][j][i] = Ginv[i][j])
-// so that consecutive outputs read contiguous entries.
-__global__ __launch_bounds__(256) void coarse_solve_kernel(const double2 *__restrict__ GinvT, int n_c,
-                                                           const double2 *__restrict__ d, float2 *__restrict__ c,
-                                                           int n_src, const int *__restrict__ active) {
-    __shared__ double2 ds[1024];
+// so that consecutive outputs read contiguous entries.  A workgroup owns 64
+// outputs; its four waves take interleaved quarters of the sum over j, with
+// several independent loads in flight per lane, and are combined in LDS in a
+// fixed order.
+constexpr int CS_OUT = 64, CS_SLICES = 4;
+__global__ __launch_bounds__(CS_OUT *CS_SLICES) void coarse_solve_kernel(const double2 *__restrict__ GinvT, int n_c,
+                                                                         const double2 *__restrict__ d,
+                                                                         float2 *__restrict__ c, int n_src,
+                                                                         const int *__restrict__ active) {
+    __shared__ double2 part[CS_SLICES][CS_OUT];
     const int r = blockIdx.y;
     if (active && !active[r]) return;
     const int wl = r / n_src;
     const double2 *dr = d + (long long)r * n_c;
-    for (int j = threadIdx.x; j < n_c && j < 1024; j += 256) ds[j] = dr[j];
-    __syncthreads();
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n_c) return;
-    const double2 *G = GinvT + (long long)wl * n_c * n_c;
-    double ax = 0.0, ay = 0.0;
-    for (int j = 0; j < n_c; ++j) {
-        const double2 g = G[(long long)j * n_c + i];
-        const double2 dv = j < 1024 ? ds[j] : dr[j];
-        ax += g.x * dv.x - g.y * dv.y;
-        ay += g.x * dv.y + g.y * dv.x;
+    const int lane = threadIdx.x % CS_OUT, sl = threadIdx.x / CS_OUT;
+    const int i = blockIdx.x * CS_OUT + lane;
+    const int ic = i < n_c ? i : n_c - 1;
+    const double2 *G = GinvT + (long long)wl * n_c * n_c + ic;
+    double ax[2] = {0.0, 0.0}, ay[2] = {0.0, 0.0};
+    int j = sl;
+#pragma unroll 4
+    for (; j < n_c; j += CS_SLICES) {
+        const double2 g = G[(long long)j * n_c];
+        const double2 dv = dr[j];
+        const int u = (j / CS_SLICES) & 1;
+        ax[u] += g.x * dv.x - g.y * dv.y;
+        ay[u] += g.x * dv.y + g.y * dv.x;
     }
-    c[(long long)r * n_c + i] = make_float2((float)ax, (float)ay);
+    part[sl][lane] = make_double2(ax[0] + ax[1], ay[0] + ay[1]);
+    __syncthreads();
+    if (sl == 0 && i < n_c) {
+        double2 s = part[0][lane];
+        for (int q = 1; q < CS_SLICES; ++q) s = make_double2(s.x + part[q][lane].x, s.y + part[q][lane].y);
+        c[(long long)r * n_c + i] = make_float2((float)s.x, (float)s.y);
+    }
 }
 
 void launch_coarse_solve(hipStream_t s, const double2 *GinvT, int n_c, const double2 *d, float2 *c, int n_rhs,
                          int n_src, const int *active) {
-    hipLaunchKernelGGL(coarse_solve_kernel, dim3((n_c + 255) / 256, n_rhs), dim3(256), 0, s, GinvT, n_c, d, c, n_src,
-                       active);
+    hipLaunchKernelGGL(coarse_solve_kernel, dim3((n_c + CS_OUT - 1) / CS_OUT, n_rhs), dim3(CS_OUT * CS_SLICES), 0, s,
+                       GinvT, n_c, d, c, n_src, active);
 }
 
 __device__ __forceinline__ float2 box_sum(const TileDesc &t, const float2 *base, int kc, const float2 *cc, int x,

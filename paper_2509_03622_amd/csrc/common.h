@@ -155,15 +155,15 @@ struct GivensArgs {
 };
 void launch_cgs_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, long long N,
                      int n_rhs, const int *gate, double2 *partial, int nblk);
-void launch_cgs_update(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
-                       long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col, double2 *partial,
-                       int nblk);
+// second pass and normalisation in one: v_{j+1} = (w - V h2) / h (reorth) or w / h
+void launch_cgs_update_scale(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
+                             long long N, int n_rhs, const int *active, const int *reorth, const float2 *Hc, int m,
+                             int col, const float *inv_h, int nblk);
 void launch_cgs_update_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
                             long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col,
                             double2 *partial, int nblk);
 void launch_cgs_reduce(hipStream_t s, const double2 *partial, int nblk, int nv, int n_rhs, const int *gate, int col,
                        int mode, double *norm_out, const GivensArgs &ga);
-void launch_scale(hipStream_t s, float2 *v, long long N, int n_rhs, const int *active, const float *sc);
 int nblk_for_update(long long N, int n_rhs);
 void launch_backsolve(hipStream_t s, const float2 *H, int ldh, int m, const float2 *gam, const int *kcyc,
                       float2 *y, int n_rhs);

@@ -169,58 +169,6 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_dots_kernel(const float2 *__re
     }
 }
 
-// Gram-Schmidt update pass:  dst = w - sum_{i<NV} Hc[r][i][col] V_i, with the
-// per-workgroup partial of ||dst||^2 written to slot KR_MAXV of `partial`.
-template <int NV, int U>
-__global__ __launch_bounds__(KR_THREADS) void cgs_update_kernel(const float2 *__restrict__ V, long long vstride,
-                                                                const float2 *w, float2 *dst, long long N,
-                                                                const int *__restrict__ gate,
-                                                                const float2 *__restrict__ Hc, int m, int col,
-                                                                double2 *__restrict__ partial, int nblk) {
-    __shared__ float2 hs[NV > 0 ? NV : 1];
-    __shared__ float red[KR_THREADS / 64];
-    const int r = blockIdx.y;
-    if (!gate[r]) return;
-    if (threadIdx.x < NV) hs[threadIdx.x] = Hc[((long long)r * (m + 1) + threadIdx.x) * m + col];
-    __syncthreads();
-    float2 hreg[NV > 0 ? NV : 1];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) hreg[i] = hs[i];
-    const float2 *wr = w + r * N;
-    float2 *dr = dst + r * N;
-    const float2 *Vr = V + r * N;
-    float fn = 0.f;
-    const long long stride = (long long)gridDim.x * KR_THREADS * U;
-    for (long long n0 = (long long)blockIdx.x * KR_THREADS * U + threadIdx.x; n0 < N; n0 += stride) {
-        float2 wv[U], vv[U][NV > 0 ? NV : 1];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const long long n = n0 + (long long)u * KR_THREADS;
-            const bool in = n < N;
-            wv[u] = in ? wr[n] : make_float2(0.f, 0.f);
-#pragma unroll
-            for (int i = 0; i < NV; ++i) vv[u][i] = in ? Vr[i * vstride + n] : make_float2(0.f, 0.f);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            float2 v = wv[u];
-#pragma unroll
-            for (int i = 0; i < NV; ++i) v = cfms(v, hreg[i], vv[u][i]);
-            const long long n = n0 + (long long)u * KR_THREADS;
-            if (n < N) dr[n] = v;
-            fn += cabs2(v);
-        }
-    }
-    fn = wave_sum_f(fn);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = fn;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int q = 0; q < KR_THREADS / 64; ++q) t += (double)red[q];
-        partial[((long long)r * nblk + blockIdx.x) * KR_SLOTS + KR_MAXV] = make_double2(t, 0.0);
-    }
-}
-
 // First-pass update fused with the second pass's dots: dst = w - sum_i Hc_i V_i,
 // and, from the same loads of V, per-workgroup partials of V_i^H dst (slots
 // i < NV) and of ||dst||^2 (slot KR_MAXV).  The second pass then needs one
@@ -284,9 +232,12 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float
 //   mode 2  first-pass norm: ||w'||^2; DGKS (||w'|| < 0.7 ||w|| asks for a
 //           second pass: reorth = 1), else the Givens step;
 //   mode 3  second-pass dots: h2 -> H2[:, col], H[:, col] += h2;
-//   mode 4  second-pass norm: ||w''||^2 and the Givens step;
+//   mode 4  norm ||.||^2 and the Givens step;
 //   mode 5  fused first-pass norm and second-pass dots: the DGKS test of mode 2,
-//           and where a second pass is due, the h2 bookkeeping of mode 3.
+//           and where a second pass is due, the h2 bookkeeping of mode 3 and the
+//           Givens step with ||w''||^2 = ||w'||^2 - ||h2||^2 (w'' = w' - V h2 and
+//           V^H w'' = 0 to working precision, so the norm is known before the
+//           second update runs; that update then writes v_{j+1} directly).
 constexpr int RED_THREADS = 1024;
 __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *__restrict__ partial, int nblk, int nv,
                                                                  const int *__restrict__ gate, int col, int mode,
@@ -334,14 +285,23 @@ __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *
                 givens_step(ga, r, col, n2);
             }
             break;
-        case 5:
+        case 5: {
             if (n2 >= 0.49 * ga.nw_pre[r]) {
                 ga.reorth[r] = 0;
                 givens_step(ga, r, col, n2);
                 break;
             }
             ga.reorth[r] = 1;
-            [[fallthrough]];
+            double h2n = 0.0;
+            for (int i = 0; i < nv; ++i) {
+                const float2 h = make_float2((float)vals[i].x, (float)vals[i].y);
+                ga.H2[((long long)r * (m + 1) + i) * m + col] = h;
+                Hr[i * m + col] = cadd(Hr[i * m + col], h);
+                h2n += vals[i].x * vals[i].x + vals[i].y * vals[i].y;
+            }
+            givens_step(ga, r, col, n2 > h2n ? n2 - h2n : 0.0);
+            break;
+        }
         case 3:
             for (int i = 0; i < nv; ++i) {
                 const float2 h = make_float2((float)vals[i].x, (float)vals[i].y);
@@ -380,22 +340,6 @@ void launch_cgs_dots(hipStream_t s, const float2 *V, long long vstride, int nv, 
     }
 }
 
-void launch_cgs_update(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
-                       long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col, double2 *partial,
-                       int nblk) {
-    dim3 grid(nblk, n_rhs);
-    switch (nv) {
-#define CASE(K)                                                                                                     \
-    case K:                                                                                                         \
-        hipLaunchKernelGGL((cgs_update_kernel<K, (K > 16 ? 2 : 1)>), grid, dim3(KR_THREADS), 0, s, V, vstride, w,  \
-                           dst, N, gate, Hc, m, col, partial, nblk);                                                \
-        break;
-        NOSDD_NV_CASES(CASE)
-#undef CASE
-        default: break;
-    }
-}
-
 void launch_cgs_update_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
                             long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col,
                             double2 *partial, int nblk) {
@@ -418,22 +362,73 @@ void launch_cgs_reduce(hipStream_t s, const double2 *partial, int nblk, int nv, 
                        norm_out, ga);
 }
 
-// v *= sc[r]  (normalise the new basis vector)
-__global__ void scale_kernel(float2 *v, long long N, const int *active, const float *sc) {
+// Second Gram-Schmidt pass fused with the normalisation:
+//   dst = (w - sum_{i<NV} Hc[r][i][col] V_i) * inv_h[r]   where reorth[r],
+//   dst = w * inv_h[r]                                    otherwise,
+// for the RHS still active (their h_{j+1,j} is already known, mode 5).
+template <int NV, int U>
+__global__ __launch_bounds__(KR_THREADS) void cgs_update_scale_kernel(const float2 *__restrict__ V, long long vstride,
+                                                                      const float2 *w, float2 *dst, long long N,
+                                                                      const int *__restrict__ active,
+                                                                      const int *__restrict__ reorth,
+                                                                      const float2 *__restrict__ Hc, int m, int col,
+                                                                      const float *__restrict__ inv_h) {
+    __shared__ float2 hs[NV > 0 ? NV : 1];
     const int r = blockIdx.y;
-    if (active && !active[r]) return;
-    const float f = sc[r];
-    float2 *vr = v + r * N;
-    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x)
-        vr[n] = cscale(vr[n], f);
+    if (!active[r]) return;
+    const float f = inv_h[r];
+    const float2 *wr = w + r * N;
+    float2 *dr = dst + r * N;
+    const long long stride = (long long)gridDim.x * KR_THREADS * U;
+    if (!reorth[r]) {
+        for (long long n = (long long)blockIdx.x * KR_THREADS + threadIdx.x; n < N;
+             n += (long long)gridDim.x * KR_THREADS)
+            dr[n] = cscale(wr[n], f);
+        return;
+    }
+    if (threadIdx.x < NV) hs[threadIdx.x] = Hc[((long long)r * (m + 1) + threadIdx.x) * m + col];
+    __syncthreads();
+    float2 hreg[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hreg[i] = hs[i];
+    const float2 *Vr = V + r * N;
+    for (long long n0 = (long long)blockIdx.x * KR_THREADS * U + threadIdx.x; n0 < N; n0 += stride) {
+        float2 wv[U], vv[U][NV > 0 ? NV : 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long n = n0 + (long long)u * KR_THREADS;
+            const bool in = n < N;
+            wv[u] = in ? wr[n] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) vv[u][i] = in ? Vr[i * vstride + n] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            float2 v = wv[u];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v = cfms(v, hreg[i], vv[u][i]);
+            const long long n = n0 + (long long)u * KR_THREADS;
+            if (n < N) dr[n] = cscale(v, f);
+        }
+    }
 }
 
-void launch_scale(hipStream_t s, float2 *v, long long N, int n_rhs, const int *active, const float *sc) {
-    const int nb = (int)(((N + 255) / 256) < 1024 ? (N + 255) / 256 : 1024);
-    hipLaunchKernelGGL(scale_kernel, dim3(nb, n_rhs), dim3(256), 0, s, v, N, active, sc);
+void launch_cgs_update_scale(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
+                             long long N, int n_rhs, const int *active, const int *reorth, const float2 *Hc, int m,
+                             int col, const float *inv_h, int nblk) {
+    dim3 grid(nblk, n_rhs);
+    switch (nv) {
+#define CASE(K)                                                                                                  \
+    case K:                                                                                                      \
+        hipLaunchKernelGGL((cgs_update_scale_kernel<K, (K > 16 ? 2 : 1)>), grid, dim3(KR_THREADS), 0, s, V,      \
+                           vstride, w, dst, N, active, reorth, Hc, m, col, inv_h);                               \
+        break;
+        NOSDD_NV_CASES(CASE)
+#undef CASE
+        default: break;
+    }
 }
 
-// y = R^-1 gamma for the first kcyc[r] columns (R upper triangular in H).
 __global__ void backsolve_kernel(const float2 *H, int m, const float2 *gam, const int *kcyc, float2 *y, int n_rhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_rhs) return;
