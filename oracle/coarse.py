@@ -113,6 +113,7 @@ class CoarseSpace:
         n = part.nx * part.ny
         cols = []
         self.tile_of_col = []
+        self.U_cols = []          # Robin data of each basis column on its tile's interface entries
         for i, (t, L) in enumerate(zip(part.tiles, locs)):
             if len(L.entries) == 0:
                 continue
@@ -133,10 +134,13 @@ class CoarseSpace:
                 V = np.eye(Kt, dtype=np.complex128)
             for l in range(k_coarse):
                 phi = np.zeros(n, dtype=np.complex128)
+                u = np.zeros(len(L.entries), dtype=np.complex128)
                 if l < Kt:          # fewer independent probes than k_coarse: zero column
                     L.prolong_core(F @ V[:, l], phi)
+                    u = X @ V[:, l]
                 cols.append(phi)
                 self.tile_of_col.append(i)
+                self.U_cols.append(u)
         # each basis field lives on one core: keep Phi and W = A Phi sparse
         self.Phi = (sp.csc_matrix(np.stack(cols, axis=1)) if cols
                     else sp.csc_matrix((n, 0), dtype=np.complex128))
