@@ -143,6 +143,32 @@ nosdd_status nosdd_solve_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_
                                 const nosdd_solve_opts *opts, nosdd_c32 *E_dev, float *resid_hist,
                                 int *iters, float *final_resid);
 
+/* The paper's own outer loop (Algorithm 3): stationary sweeps over the Robin
+ * data g of every subdomain's interface entries, starting from g = 0,
+ *   u_i = B_i^-1 (R_i b + inj(g_i)),  x = sum_i Rt_i^T u_i (core-only assembly),
+ *   g_new = Robin traces of x (Eq. 2 data),  e = g_new - g,
+ *   g <- m g + (1 - m) g_new [+ (m Q + (1 - m) T Q) z],
+ * with momentum m in [0, 1) and, when coarse is set (requires k_coarse > 0 at
+ * set-up), the Robin-space coarse correction of the Methods two-level
+ * subsection: z solves the normal equations of (I - T) Q z = e (T the
+ * Robin-to-Robin map, Q the rotated probe data of each subdomain's coarse
+ * columns), in FP64.  Stops when ||b - A x|| / ||b|| <= tol after a sweep or
+ * after max_iters sweeps.  Exact subdomain solves only (sub_solver 0). */
+typedef struct {
+    double momentum;
+    int coarse;
+    double tol;
+    int max_iters;
+} nosdd_paper_opts;
+/* J_dev and E_dev are device pointers on the context stream, laid out as in
+ * nosdd_solve_device; resid_hist[n_wl][n_src][max_iters] (-1 padded), iters
+ * (sweeps) and final_resid (relative residual after the last sweep) are host
+ * pointers (nullable).  Returns NOSDD_NOT_CONVERGED when some right-hand side
+ * did not reach tol; E_dev then holds its last sweep. */
+nosdd_status nosdd_solve_paper_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src,
+                                      const nosdd_paper_opts *opts, nosdd_c32 *E_dev, float *resid_hist,
+                                      int *iters, float *final_resid);
+
 /* ---- Steps of one Schwarz sweep, exposed for testing and composition. ----
  * All vectors are device pointers on the context stream, laid out
  * [n_wl][n_src][ny][nx]; n_src is the number of vectors per wavelength. */

@@ -93,6 +93,13 @@ struct nosdd_problem {
     int kc = 0, ktrial = 8, n_c = 0;
     long long box_wl_stride = 0;
     DevBuf d_phi, d_W, d_GinvT;
+    // Robin-data injection coefficients -a_pq tau_p per (wl, entry), and the
+    // Robin-space coarse space of the Algorithm 3 loop: (I - T) Q sparse by
+    // entry (Q, T Q values) and by column (M = Q - T Q), per wavelength, and
+    // the FP64 inverse (transposed) of M^H M
+    DevBuf d_injc;
+    int rc_nnz = 0;
+    DevBuf d_rc_rowptr, d_rc_rowcol, d_rc_q, d_rc_tq, d_rc_colptr, d_rc_colent, d_rc_colval, d_rc_GinvT;
     bool setup_done = false;
     int sub_solver = 0;
     Workspace ws;
@@ -849,6 +856,13 @@ nosdd_status coarse_setup(nosdd_problem *p) {
     std::vector<std::vector<cd>> Wd((size_t)nwl * nt);   // FP64 W boxes for G
     const int nc = p->n_c;
     std::vector<double2> ginv_dev((size_t)nwl * nc * nc);
+    // Robin-space coarse space (Algorithm 3 loop): per wavelength, the nonzeros
+    // (entry, column, Q value, T Q value) in column order
+    struct RcNz {
+        int e, col;
+        cd q, tq;
+    };
+    std::vector<std::vector<RcNz>> rcnz((size_t)nwl);
     for (int wi = 0; wi < nwl; ++wi) {
         const double k0 = 2.0 * M_PI / p->wl[wi];
         const auto &cf = p->coefd[wi];
@@ -924,6 +938,46 @@ nosdd_status coarse_setup(nosdd_problem *p) {
                 phi_h[(size_t)wi * box_total + t.box_off + e] = make_float2((float)phib[e].real(), (float)phib[e].imag());
                 W_h[(size_t)wi * box_total + t.box_off + e] = make_float2((float)wb[e].real(), (float)wb[e].imag());
             }
+            // Q: the rotated probe data on this tile's own entries; T Q: the Robin
+            // traces of the basis fields (core-only) on the neighbours' entries
+            // that touch this core
+            {
+                const auto &Xe = Xt[(size_t)wi * nt + ti];
+                const auto &own = p->tile_entries[ti];
+                for (int l = 0; l < kc; ++l) {
+                    const int col = ti * kc + l;
+                    const bool valid = l < std::min(kc, Kk);
+                    for (int e = 0; e < (int)own.size(); ++e) {
+                        cd u = 0;
+                        if (valid)
+                            for (int q = 0; q < Kk; ++q) u += Xe[(size_t)e * K + q] * Vv[(size_t)q * Kk + order[l]];
+                        rcnz[wi].push_back({t.tr_off + e, col, u, cd(0, 0)});
+                    }
+                    auto phv = [&](int x, int y) -> cd {
+                        if (!valid || x < t.cx0 || x >= t.cx1 || y < t.cy0 || y >= t.cy1) return cd(0, 0);
+                        return phib[(size_t)l * t.bw * t.bh + (size_t)(y - t.by0) * t.bw + (x - t.bx0)];
+                    };
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            if (!dx && !dy) continue;
+                            const int ntx = (ti % p->ncx) + dx, nty = (ti / p->ncx) + dy;
+                            if (ntx < 0 || ntx >= p->ncx || nty < 0 || nty >= p->ncy) continue;
+                            const int tj = nty * p->ncx + ntx;
+                            const TileDesc &u = p->tiles[tj];
+                            const auto &ent = p->tile_entries[tj];
+                            for (int e = 0; e < (int)ent.size(); ++e) {
+                                const int px = ent[e].x % nx, py = ent[e].x / nx, qx = ent[e].y % nx, qy = ent[e].y / nx;
+                                const bool inp = px >= t.cx0 && px < t.cx1 && py >= t.cy0 && py < t.cy1;
+                                const bool inq = qx >= t.cx0 && qx < t.cx1 && qy >= t.cy0 && qy < t.cy1;
+                                if (!inp && !inq) continue;
+                                const cd up = phv(px, py), uq = phv(qx, qy);
+                                const double kp = k0 * std::sqrt((double)p->eps[ent[e].x]);
+                                rcnz[wi].push_back({u.tr_off + e, col, cd(0, 0),
+                                                    (uq - up) / h + cd(0.0, 0.5 * kp) * (uq + up)});
+                            }
+                        }
+                }
+            }
             Wd[(size_t)wi * nt + ti] = std::move(wb);
         }
         // G = W^H W over overlapping boxes (neighbouring tiles only)
@@ -960,6 +1014,73 @@ nosdd_status coarse_setup(nosdd_problem *p) {
                 const cd g = Gi[(size_t)i * nc + j];
                 ginv_dev[(size_t)wi * nc * nc + (size_t)j * nc + i] = make_double2(g.real(), g.imag());
             }
+    }
+    {
+        // structure (identical for every wavelength: it is geometric) by entry and by column
+        const int ne = p->n_entries;
+        const auto &z0 = rcnz[0];
+        const int nnz = (int)z0.size();
+        p->rc_nnz = nnz;
+        std::vector<int> colptr(nc + 1, 0), rowptr(ne + 1, 0), colent(nnz), rowcol(nnz), perm(nnz);
+        for (int k = 0; k < nnz; ++k) {
+            colptr[z0[k].col + 1]++;
+            rowptr[z0[k].e + 1]++;
+            colent[k] = z0[k].e;
+        }
+        for (int c = 0; c < nc; ++c) colptr[c + 1] += colptr[c];
+        for (int e = 0; e < ne; ++e) rowptr[e + 1] += rowptr[e];
+        {
+            std::vector<int> fill(rowptr.begin(), rowptr.end() - 1);
+            for (int k = 0; k < nnz; ++k) perm[fill[z0[k].e]++] = k;      // row position -> column-order index
+        }
+        for (int k = 0; k < nnz; ++k) rowcol[k] = z0[perm[k]].col;
+        std::vector<float2> rq((size_t)nwl * nnz), rtq((size_t)nwl * nnz), cval((size_t)nwl * nnz);
+        std::vector<double2> rginv((size_t)nwl * nc * nc);
+        for (int wi = 0; wi < nwl; ++wi) {
+            const auto &zz = rcnz[wi];
+            for (int k = 0; k < nnz; ++k) {
+                const cd mv = zz[k].q - zz[k].tq;
+                cval[(size_t)wi * nnz + k] = make_float2((float)mv.real(), (float)mv.imag());
+                const RcNz &r = zz[perm[k]];
+                rq[(size_t)wi * nnz + k] = make_float2((float)r.q.real(), (float)r.q.imag());
+                rtq[(size_t)wi * nnz + k] = make_float2((float)r.tq.real(), (float)r.tq.imag());
+            }
+            // M^H M from the entries' nonzeros (M = Q - T Q), FP64
+            std::vector<cd> G((size_t)nc * nc, cd(0, 0));
+            for (int e = 0; e < ne; ++e)
+                for (int a = rowptr[e]; a < rowptr[e + 1]; ++a) {
+                    const RcNz &za = zz[perm[a]];
+                    const cd ma = std::conj(za.q - za.tq);
+                    for (int bb = rowptr[e]; bb < rowptr[e + 1]; ++bb) {
+                        const RcNz &zb = zz[perm[bb]];
+                        G[(size_t)za.col * nc + zb.col] += ma * (zb.q - zb.tq);
+                    }
+                }
+            for (int c = 0; c < nc; ++c)
+                if (std::abs(G[(size_t)c * nc + c]) == 0.0) G[(size_t)c * nc + c] = 1.0;   // zero column: z_c = 0
+            std::vector<cd> Gi;
+            if (!hpd_inverse(nc, G, Gi))
+                return fail(ctx, NOSDD_EBREAKDOWN, "Robin-space coarse matrix is not positive definite");
+            for (int j = 0; j < nc; ++j)
+                for (int i = 0; i < nc; ++i) {
+                    const cd g = Gi[(size_t)i * nc + j];
+                    rginv[(size_t)wi * nc * nc + (size_t)j * nc + i] = make_double2(g.real(), g.imag());
+                }
+        }
+        auto up = [&](DevBuf &d, const void *src, size_t bytes) -> hipError_t {
+            hipError_t er = d.ensure(std::max<size_t>(bytes, 16));
+            if (er != hipSuccess) return er;
+            return bytes ? hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+        };
+        HIPCHK(ctx, up(p->d_rc_rowptr, rowptr.data(), rowptr.size() * sizeof(int)));
+        HIPCHK(ctx, up(p->d_rc_rowcol, rowcol.data(), rowcol.size() * sizeof(int)));
+        HIPCHK(ctx, up(p->d_rc_colptr, colptr.data(), colptr.size() * sizeof(int)));
+        HIPCHK(ctx, up(p->d_rc_colent, colent.data(), colent.size() * sizeof(int)));
+        HIPCHK(ctx, up(p->d_rc_q, rq.data(), rq.size() * sizeof(float2)));
+        HIPCHK(ctx, up(p->d_rc_tq, rtq.data(), rtq.size() * sizeof(float2)));
+        HIPCHK(ctx, up(p->d_rc_colval, cval.data(), cval.size() * sizeof(float2)));
+        HIPCHK(ctx, up(p->d_rc_GinvT, rginv.data(), rginv.size() * sizeof(double2)));
+        HIPCHK(ctx, hipStreamSynchronize(s));
     }
     HIPCHK(ctx, p->d_phi.ensure(phi_h.size() * sizeof(float2)));
     HIPCHK(ctx, p->d_W.ensure(W_h.size() * sizeof(float2)));
@@ -1584,6 +1705,33 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
     bt_solve_prepare(p->bmax, p->max_cells);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
+    {
+        // Robin-data injection inj(g)_p = -a_pq tau_p g_p per (wavelength, entry)
+        const int ne = p->n_entries;
+        std::vector<float2> ic((size_t)nwl * std::max(ne, 1), make_float2(0.f, 0.f));
+        for (int wi = 0; wi < nwl; ++wi) {
+            const double k0 = 2.0 * M_PI / p->wl[wi];
+            const auto &cf = p->coefd[wi];
+            for (int ti = 0; ti < (int)p->tiles.size(); ++ti) {
+                const auto &ent = p->tile_entries[ti];
+                for (int e = 0; e < (int)ent.size(); ++e) {
+                    const int pc = ent[e].x, px = pc % p->nx, py = pc / p->nx;
+                    cd apq;
+                    switch (ent[e].z) {
+                        case SIDE_LEFT: apq = cf[px]; break;
+                        case SIDE_RIGHT: apq = cf[p->nx + px]; break;
+                        case SIDE_BOTTOM: apq = cf[2 * p->nx + py]; break;
+                        default: apq = cf[2 * p->nx + p->ny + py]; break;
+                    }
+                    const double kp = k0 * std::sqrt((double)p->eps[pc]);
+                    const cd v = -apq * (p->h / cd(1.0, 0.5 * kp * p->h));
+                    ic[(size_t)wi * ne + p->tiles[ti].tr_off + e] = make_float2((float)v.real(), (float)v.imag());
+                }
+            }
+        }
+        HIPCHK(ctx, p->d_injc.ensure(ic.size() * sizeof(float2)));
+        HIPCHK(ctx, hipMemcpy(p->d_injc.p, ic.data(), ic.size() * sizeof(float2), hipMemcpyHostToDevice));
+    }
     if (o->sub_solver == 1) {
         for (auto &t : p->tiles)
             if (t.x1 - t.x0 > 72 || t.y1 - t.y0 > 72 || t.x1 - t.x0 < 32 || t.y1 - t.y0 < 32)
@@ -1644,6 +1792,103 @@ nosdd_status nosdd_solve_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_
     if (st) return st;
     return solve_impl(p, (const float2 *)J_dev, n_src, o, (const float2 *)o->x0, (float2 *)E_dev, resid_hist, iters,
                       final_resid);
+}
+
+nosdd_status nosdd_solve_paper_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src, const nosdd_paper_opts *o,
+                                      nosdd_c32 *E_dev, float *resid_hist, int *iters, float *final_resid) {
+    nosdd_status st = check_problem(p, true);
+    if (st) return st;
+    nosdd_ctx *ctx = p->ctx;
+    if (!J_dev || !o || !E_dev || n_src <= 0) return fail(ctx, NOSDD_EINVAL, "null argument or n_src <= 0");
+    if (!(o->momentum >= 0.0 && o->momentum < 1.0)) return fail(ctx, NOSDD_EINVAL, "momentum must be in [0, 1)");
+    if (o->max_iters < 1 || !(o->tol > 0)) return fail(ctx, NOSDD_EINVAL, "invalid tolerance or max_iters");
+    if (p->sub_solver != 0) return fail(ctx, NOSDD_EINVAL, "the Algorithm 3 loop takes exact subdomain solves");
+    if (o->coarse && p->n_c == 0) return fail(ctx, NOSDD_EINVAL, "coarse correction requested without a coarse space");
+    hipStream_t s = ctx->stream;
+    const int n_wl = (int)p->wl.size(), n_rhs = n_wl * n_src, nt = (int)p->tiles.size();
+    const long long N = (long long)p->nx * p->ny, LT = p->loc_total;
+    const int ne = p->n_entries, nc = p->n_c;
+    DevBuf b, r, rhs, g, gn, d, z, part, nrm, act;
+    HIPCHK(ctx, b.ensure((size_t)n_rhs * N * sizeof(float2)));
+    HIPCHK(ctx, r.ensure((size_t)n_rhs * N * sizeof(float2)));
+    HIPCHK(ctx, rhs.ensure((size_t)n_rhs * LT * sizeof(float2)));
+    HIPCHK(ctx, g.ensure((size_t)n_rhs * std::max(ne, 1) * sizeof(float2)));
+    HIPCHK(ctx, gn.ensure((size_t)n_rhs * std::max(ne, 1) * sizeof(float2)));
+    HIPCHK(ctx, d.ensure((size_t)n_rhs * std::max(nc, 1) * sizeof(double2)));
+    HIPCHK(ctx, z.ensure((size_t)n_rhs * std::max(nc, 1) * sizeof(float2)));
+    HIPCHK(ctx, part.ensure((size_t)n_rhs * norm2_partials() * sizeof(double)));
+    HIPCHK(ctx, nrm.ensure((size_t)n_rhs * sizeof(double)));
+    HIPCHK(ctx, act.ensure((size_t)n_rhs * sizeof(int)));
+    const int2 *ord = nullptr;
+    int nj = 0;
+    st = solve_order(p, n_rhs, n_src, &ord, &nj);
+    if (st != NOSDD_OK) return st;
+    hipLaunchKernelGGL(make_rhs_kernel, dim3((unsigned)grid_blocks(N), n_rhs), dim3(256), 0, s, (const float2 *)J_dev,
+                       b.as<float2>(), p->d_k0f.as<float>(), N, n_src, 0);
+    HIPCHK(ctx, hipMemsetAsync(g.p, 0, (size_t)n_rhs * std::max(ne, 1) * sizeof(float2), s));
+    std::vector<double> n2(n_rhs), bn(n_rhs);
+    launch_norm2(s, b.as<float2>(), N, n_rhs, part.as<double>(), nrm.as<double>());
+    HIPCHK(ctx, hipMemcpyAsync(n2.data(), nrm.p, n_rhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    std::vector<int> active(n_rhs), it(n_rhs, 0);
+    std::vector<float> last(n_rhs, 0.f);
+    for (int q = 0; q < n_rhs; ++q) {
+        bn[q] = std::sqrt(n2[q]);
+        active[q] = bn[q] > 0.0 ? 1 : 0;
+    }
+    if (resid_hist)
+        for (size_t q = 0; q < (size_t)n_rhs * o->max_iters; ++q) resid_hist[q] = -1.f;
+    // zero sources: zero field, no sweeps
+    hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)grid_blocks(2LL * n_rhs * N)), dim3(256), 0, s, (float *)E_dev,
+                       2LL * n_rhs * N, 0.0f);
+    const float m = (float)o->momentum;
+    for (int k = 0; k < o->max_iters; ++k) {
+        int n_act = 0;
+        for (int q = 0; q < n_rhs; ++q) n_act += active[q];
+        if (!n_act) break;
+        HIPCHK(ctx, hipMemcpyAsync(act.p, active.data(), n_rhs * sizeof(int), hipMemcpyHostToDevice, s));
+        // sweep: local right-hand sides, subdomain solves, core-only assembly
+        launch_robin_rhs(s, p->d_tiles.as<TileDesc>(), nt, p->d_entries.as<int4>(), p->d_injc.as<float2>(), ne,
+                         b.as<float2>(), g.as<float2>(), rhs.as<float2>(), N, LT, p->nx, n_rhs, n_src, act.as<int>());
+        launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ord, nj, n_src, p->d_dinv.as<float2>(), p->dinv_wl_stride,
+                        p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, rhs.as<float2>(), LT,
+                        (float2 *)E_dev, N, act.as<int>(), 1, p->bmax, p->max_cells, p->bt_depth);
+        // ||b - A x|| after the sweep
+        launch_stencil(s, (const float2 *)E_dev, b.as<float2>(), r.as<float2>(), p->d_eps.as<float>(),
+                       p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->nx, p->ny, n_rhs, n_src, act.as<int>());
+        launch_norm2(s, r.as<float2>(), N, n_rhs, part.as<double>(), nrm.as<double>());
+        // data of the next sweep (used only by the RHS that stay active)
+        launch_robin_trace(s, p->d_entries.as<int4>(), ne, p->d_eps.as<float>(), p->d_k0f.as<float>(), (float)p->h,
+                           p->nx, p->ny, (const float2 *)E_dev, gn.as<float2>(), n_rhs, n_src);
+        if (o->coarse) {
+            launch_rc_dot(s, p->d_rc_colptr.as<int>(), p->d_rc_colent.as<int>(), p->d_rc_colval.as<float2>(),
+                          p->rc_nnz, nc, ne, g.as<float2>(), gn.as<float2>(), d.as<double2>(), n_rhs, n_src,
+                          act.as<int>());
+            launch_coarse_solve(s, p->d_rc_GinvT.as<double2>(), nc, d.as<double2>(), z.as<float2>(), n_rhs, n_src,
+                                act.as<int>());
+        }
+        launch_rc_update(s, p->d_rc_rowptr.as<int>(), p->d_rc_rowcol.as<int>(), p->d_rc_q.as<float2>(),
+                         p->d_rc_tq.as<float2>(), p->rc_nnz, ne, nc, g.as<float2>(), gn.as<float2>(), z.as<float2>(),
+                         m, o->coarse ? 1 : 0, n_rhs, n_src, act.as<int>());
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, hipMemcpyAsync(n2.data(), nrm.p, n_rhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        for (int q = 0; q < n_rhs; ++q) {
+            if (!active[q]) continue;
+            const float res = (float)(std::sqrt(n2[q]) / bn[q]);
+            if (resid_hist) resid_hist[(size_t)q * o->max_iters + k] = res;
+            it[q] = k + 1;
+            last[q] = res;
+            if (res <= o->tol) active[q] = 0;              // a NaN residual keeps iterating
+        }
+    }
+    bool all = true;
+    for (int q = 0; q < n_rhs; ++q) {
+        if (iters) iters[q] = it[q];
+        if (final_resid) final_resid[q] = last[q];
+        if (active[q]) all = false;
+    }
+    return all ? NOSDD_OK : NOSDD_NOT_CONVERGED;
 }
 
 nosdd_status nosdd_fom_gradient_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src, const int *focal,

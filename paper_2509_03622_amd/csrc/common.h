@@ -135,6 +135,18 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, in
 void bt_solve_prepare(int bmax, int max_cells);
 int bt_solve_depths(int bmax, int *depths);
 
+// Algorithm 3 loop (paperloop.hip)
+void launch_robin_rhs(hipStream_t s, const TileDesc *tiles, int n_tiles, const int4 *ent, const float2 *injc, int ne,
+                      const float2 *b, const float2 *g, float2 *rhs, long long N, long long LT, int nx, int n_rhs,
+                      int n_src, const int *active);
+void launch_rc_dot(hipStream_t s, const int *col_ptr, const int *col_ent, const float2 *col_val, int nnz, int nc,
+                   int ne, const float2 *g, const float2 *gn, double2 *d, int n_rhs, int n_src, const int *active);
+void launch_rc_update(hipStream_t s, const int *row_ptr, const int *row_col, const float2 *row_q,
+                      const float2 *row_tq, int nnz, int ne, int nc, float2 *g, const float2 *gn, const float2 *z,
+                      float m, int coarse, int n_rhs, int n_src, const int *active);
+void launch_norm2(hipStream_t s, const float2 *v, long long N, int n_rhs, double *part, double *out);
+int norm2_partials();
+
 void launch_robin_trace(hipStream_t s, const int4 *entries, int n_entries, const float *eps,
                         const float *k0, float h, int nx, int ny, const float2 *x, float2 *g,
                         int n_vec, int vec_per_wl);

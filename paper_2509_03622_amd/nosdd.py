@@ -19,7 +19,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -
           -5: "EBREAKDOWN", -6: "ENONFINITE", -7: "ENOWEIGHTS", -8: "ESTATE"}
 
 EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_problem_create",
-           "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device",
+           "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device", "nosdd_solve_paper_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
            "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_autotune", "nosdd_tuning",
@@ -43,6 +43,10 @@ class SetupOpts(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("x0", C.c_void_p)]
+
+
+class PaperOpts(C.Structure):
+    _fields_ = [("momentum", C.c_double), ("coarse", C.c_int), ("tol", C.c_double), ("max_iters", C.c_int)]
 
 
 class NosddError(RuntimeError):
@@ -72,6 +76,7 @@ def load(path=LIBPATH):
         "nosdd_problem_destroy": (None, [vp]),
         "nosdd_solve": (i, [vp, vp, i, C.POINTER(SolveOpts), vp, vp, vp, vp]),
         "nosdd_solve_device": (i, [vp, vp, i, C.POINTER(SolveOpts), vp, vp, vp, vp]),
+        "nosdd_solve_paper_device": (i, [vp, vp, i, C.POINTER(PaperOpts), vp, vp, vp, vp]),
         "nosdd_apply_operator": (i, [vp, vp, vp, vp, i]),
         "nosdd_schwarz_sweep": (i, [vp, vp, vp, i]),
         "nosdd_precond_apply": (i, [vp, vp, vp, vp, i]),
@@ -196,6 +201,18 @@ class Problem:
                                                hist.ctypes.data, iters.ctypes.data, fin.ctypes.data))
         del nr
         return E, hist, iters, fin, st
+
+    def solve_paper(self, J, E, momentum=0.0, coarse=False, tol=1e-6, max_iters=500):
+        """The paper's Algorithm 3 loop on device tensors (J [n_src][ny][nx],
+        E [n_wl][n_src][ny][nx] complex64); returns (hist, sweeps, final, status)."""
+        ns = J.shape[0]
+        hist = np.zeros((self.n_wl, ns, max(1, max_iters)), np.float32)
+        iters = np.zeros((self.n_wl, ns), np.int32)
+        fin = np.zeros((self.n_wl, ns), np.float32)
+        o = PaperOpts(momentum, 1 if coarse else 0, tol, max_iters)
+        st = self.ctx.check(self.L.nosdd_solve_paper_device(self.h, _ptr(J), ns, C.byref(o), _ptr(E),
+                                                            hist.ctypes.data, iters.ctypes.data, fin.ctypes.data))
+        return hist, iters, fin, st
 
     def solve_device(self, J, E, tol=1e-6, restart=30, max_iters=1000, x0=None):
         """Device tensors: J [n_src][ny][nx] complex64, E [n_wl][n_src][ny][nx] complex64."""
