@@ -111,6 +111,36 @@ def test_blocks512_four_wavelengths_full_size():
     ctx.close()
 
 
+def test_blocks512_algorithm3_loop_full_size():
+    """The paper's stationary loop on the same workload (momentum 0.3, which
+    it needs here: without momentum the sweeps diverge at 1.0, in the FP64
+    oracle too): the first 60 sweeps' residual history of the 1.0 wavelength
+    equals the oracle's, and every field reaches 1e-5 and lies within 5e-5 of
+    the direct solution."""
+    from oracle.paper_loop import paper_loop
+    from oracle.partition import build_local_problems
+    import torch
+    w = blocks_512()
+    ctx, P = _problem(w)
+    J = torch.from_numpy(w.J()).cuda()
+    E = torch.zeros((len(w.wavelengths), 1, w.ny, w.nx), dtype=torch.complex64, device="cuda")
+    hist, it, fin, st = P.solve_paper(J, E, momentum=0.3, tol=1e-5, max_iters=1500)
+    assert st == 0, (it, fin)
+    print("Algorithm 3 sweeps per wavelength", it.ravel().tolist())
+    Eh = host(E)
+    As = _operators(w)
+    for wi, lam in enumerate(w.wavelengths):
+        xs = solve_direct(As[wi], source_rhs(w.J()[0], lam))
+        assert rel(Eh[wi, 0].ravel(), xs) < 5e-5, (lam, rel(Eh[wi, 0].ravel(), xs))
+    wi = 1
+    part = Partition(w.nx, w.ny, w.core_x, w.core_y, w.overlap, w.npml)
+    locs = build_local_problems(part, As[wi], w.eps.astype(np.float64), w.wavelengths[wi], w.h)
+    x, n, h, g = paper_loop(locs, As[wi], source_rhs(w.J()[0], w.wavelengths[wi]), momentum=0.3, max_iters=60)
+    np.testing.assert_allclose(hist[wi, 0, :60], h, rtol=1e-3)
+    P.close()
+    ctx.close()
+
+
 def test_uneven_2048x1536_64_rhs_full_size():
     w = uneven_2048x1536()
     ctx, P = _problem(w)
