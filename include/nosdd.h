@@ -268,6 +268,14 @@ nosdd_status nosdd_tuning(const nosdd_problem *p, int out[6]);
  * Disabled, or while nosdd_profile is on: the same kernels are launched one
  * by one.  Results are bit-identical in both modes. */
 nosdd_status nosdd_graphs(nosdd_problem *p, int enable);
+/* Subdomain solves of the FGMRES preconditioner when a wavelength has at
+ * least 4 sources (and blocks are at most 112 cells wide): enabled (default),
+ * one workgroup per subdomain, wavelength and group of 32 (16 above 80-cell
+ * blocks) sources reads each factor block once and forms the block's products
+ * for the whole group as FP32 MFMA contractions; disabled, one workgroup per
+ * subdomain and source (the right-hand sides share the factor stream only
+ * through the caches).  Same arithmetic per product up to summation order. */
+nosdd_status nosdd_multi_source(nosdd_problem *p, int enable);
 
 /* Timing of the last solve (ms, GPU events): setup, total solve, iterations. */
 nosdd_status nosdd_last_timing(const nosdd_problem *p, double *setup_ms, double *solve_ms,

@@ -542,4 +542,230 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, in
 #undef BT_ARGS
 }
 
+// ----------------------------------------------------------- many sources
+// Sources that share a wavelength share every factor block, so a workgroup
+// takes one (subdomain, wavelength) and a group of NCOL sources: each block
+// M_k is read from HBM once, expanded in LDS into its real and imaginary
+// b x b parts (both triangles), and the step's products for all sources,
+// M_k (S_k Y) with Y the b x NCOL operand, run as FP32 MFMA contractions
+// (16 x 16 x 4):  Re = M_r Y_r + M_i (-Y_i),  Im = M_r Y_i + M_i Y_r.
+// The recurrence then runs elementwise over (row, source).  The gathered
+// right-hand sides, w_k and u_k live block-major in a packed workspace
+// (loc[rhs][tile cells]); the core cells are scattered at the end.
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+constexpr int BM_THREADS = 256;
+
+__host__ __device__ __forceinline__ int bm_rows(int b) { return (b + 15) & ~15; }   // MFMA row padding
+__host__ __device__ __forceinline__ int bm_kdim(int b) { return (b + 3) & ~3; }     // MFMA k padding
+int bt_multi_cols(int bmax) { return bmax <= 80 ? 32 : 16; }
+static size_t bm_lds_bytes(int bmax, int ncol) {
+    const int BR = bm_rows(bmax), BK = bm_kdim(bmax), LDM = BK + 1, LDX = ncol + 1;
+    return sizeof(float) * ((size_t)2 * BR * LDM + (size_t)3 * BK * LDX + (size_t)2 * BR * LDX);
+}
+
+template <int NCOL, int EMAX>
+__global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
+    const TileDesc *__restrict__ tiles, const int4 *__restrict__ jobs, int n_src, const float2 *__restrict__ dinv,
+    long long dinv_wl_stride, const float2 *__restrict__ coef, const float2 *__restrict__ sc, int nx, int ny,
+    const float2 *__restrict__ vin, long long vin_stride, float2 *__restrict__ out, long long out_stride,
+    const int *__restrict__ active, float2 *__restrict__ loc, long long LT) {
+    extern __shared__ float lds[];
+    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX], si_s[BT_BMAX];
+    __shared__ int colr[NCOL];                       // RHS index of each column, -1 when idle
+    const int4 job = jobs[blockIdx.x];               // (tile, wavelength, first source, sources)
+    if (job.x < 0) return;
+    const TileDesc t = tiles[job.x];
+    const int wl = job.y, s0 = job.z, ns = job.w;
+    const int b = t.b, nb = t.nb, P = b >> 1, tid = threadIdx.x;
+    const int BR = bm_rows(b), BK = bm_kdim(b), LDM = BK + 1, LDX = NCOL + 1;
+    float *Mr = lds, *Mi = Mr + BR * LDM;
+    float *Xr = Mi + BR * LDM, *Xi = Xr + BK * LDX, *Xn = Xi + BK * LDX;
+    float *Cr = Xn + BK * LDX, *Ci = Cr + BR * LDX;
+    if (tid < NCOL) {
+        const int r = wl * n_src + s0 + tid;
+        colr[tid] = (tid < ns && (!active || active[r])) ? r : -1;
+    }
+    const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
+    const float2 *cf = coef + wl * coef_stride(nx, ny);
+    const float2 *clo_a = t.tr ? cf : cf + 2 * nx;
+    const float2 *chi_a = t.tr ? cf + nx : cf + 2 * nx + ny;
+    const float2 *scw = sc + (long long)wl * (nx + ny);
+    const float2 *s_in = t.tr ? scw + nx + t.y0 : scw + t.x0;
+    const float2 *s_out = t.tr ? scw + t.x0 : scw + nx + t.y0;
+    const int base = t.tr ? t.x0 : t.y0;
+    for (int k = tid; k < nb; k += BM_THREADS) {
+        cl_s[k] = clo_a[base + k];
+        ch_s[k] = chi_a[base + k];
+        so_s[k] = s_out[k];
+    }
+    for (int i = tid; i < b; i += BM_THREADS) si_s[i] = s_in[i];
+    // zero the padding of the MFMA operands once (rows >= b of M, k >= b of M and Y)
+    for (int e = tid; e < BR * LDM; e += BM_THREADS) {
+        Mr[e] = 0.f;
+        Mi[e] = 0.f;
+    }
+    for (int e = tid; e < 3 * BK * LDX; e += BM_THREADS) Xr[e] = 0.f;
+    __syncthreads();
+    // gather R_i v block-major: loc[r][loc_off + k b + i]
+    for (int c = 0; c < ns; ++c) {
+        const int r = colr[c];
+        if (r < 0) continue;
+        const float2 *vr = vin + r * vin_stride;
+        float2 *lr = loc + r * LT + t.loc_off;
+        for (int e = tid; e < lx * ly; e += BM_THREADS) {
+            const int yy = e / lx, xx = e - yy * lx;
+            lr[t.tr ? xx * b + yy : e] = vr[(long long)(t.y0 + yy) * nx + (t.x0 + xx)];
+        }
+    }
+    // this thread's elements of a packed block and their two LDS positions
+    const long long blk = bt_sym_block(b);
+    const int nsub = (int)(blk >> 2);
+    const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
+    int o1[EMAX], o2[EMAX];
+#pragma unroll
+    for (int j = 0; j < EMAX; ++j) {
+        const int e = tid + j * BM_THREADS;
+        o1[j] = -1;
+        o2[j] = -1;
+        if (e < (int)blk) {
+            const int half = e >= 2 * nsub, sub = (e - half * 2 * nsub) >> 1, comp = (e & 1) | (half << 1);
+            int bp, bq;
+            bt_sym_pq(P, sub, bp, bq);
+            const int rr = 2 * bp + (comp & 1), cc = 2 * bq + (comp >> 1);
+            o1[j] = rr * LDM + cc;
+            o2[j] = cc * LDM + rr;
+        }
+    }
+    float2 mreg[EMAX];
+    auto fetch = [&](int k) {
+        const float2 *Dk = D + (long long)k * blk;
+#pragma unroll
+        for (int j = 0; j < EMAX; ++j) mreg[j] = o1[j] >= 0 ? Dk[tid + j * BM_THREADS] : make_float2(0.f, 0.f);
+    };
+    auto expand = [&]() {
+#pragma unroll
+        for (int j = 0; j < EMAX; ++j)
+            if (o1[j] >= 0) {
+                Mr[o1[j]] = mreg[j].x;
+                Mi[o1[j]] = mreg[j].y;
+                Mr[o2[j]] = mreg[j].x;
+                Mi[o2[j]] = mreg[j].y;
+            }
+    };
+    const int nsteps = 2 * nb - 1;
+    auto blk_of = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
+    fetch(0);
+    __syncthreads();                                  // gathered data visible
+    // operand of the first step: S_0 v_0
+    for (int e = tid; e < b * NCOL; e += BM_THREADS) {
+        const int i = e % b, c = e / b, r = colr[c];
+        float2 z = make_float2(0.f, 0.f);
+        if (r >= 0) z = cmul(cmul(si_s[i], so_s[0]), loc[r * LT + t.loc_off + i]);
+        Xr[i * LDX + c] = z.x;
+        Xi[i * LDX + c] = z.y;
+        Xn[i * LDX + c] = -z.y;
+    }
+    expand();
+    const int wave = tid >> 6, lane = tid & 63;
+    const int RT = BR / 16, nT = RT * (NCOL / 16);
+    for (int s = 0; s < nsteps; ++s) {
+        const int k = blk_of(s);
+        if (s + 1 < nsteps) fetch(blk_of(s + 1));
+        __syncthreads();                              // M_k and the operand are in LDS
+        for (int q = wave; q < nT; q += BM_THREADS / 64) {
+            const int rt = q % RT, ct = q / RT;
+            f32x4v accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+            const int arow = (rt * 16 + (lane & 15)) * LDM, bcol = ct * 16 + (lane & 15);
+            for (int kk = 0; kk < BK; kk += 4) {
+                const int ka = kk + (lane >> 4);
+                const float ar = Mr[arow + ka], ai = Mi[arow + ka];
+                const float yr = Xr[ka * LDX + bcol], yi = Xi[ka * LDX + bcol], yn = Xn[ka * LDX + bcol];
+                accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, yr, accR, 0, 0, 0);
+                accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, yn, accR, 0, 0, 0);
+                accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, yi, accI, 0, 0, 0);
+                accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, yr, accI, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = rt * 16 + 4 * (lane >> 4) + i;
+                Cr[row * LDX + bcol] = accR[i];
+                Ci[row * LDX + bcol] = accI[i];
+            }
+        }
+        __syncthreads();                              // products in LDS; M_k and the operand consumed
+        const bool fwd = s < nb, turn = s == nb - 1;
+        const int knext = fwd && !turn ? k + 1 : k - 1;
+        for (int e = tid; e < b * NCOL; e += BM_THREADS) {
+            const int i = e % b, c = e / b, r = colr[c];
+            float2 z = make_float2(0.f, 0.f);
+            if (r >= 0) {
+                float2 *lr = loc + r * LT + t.loc_off;
+                const float2 a = make_float2(Cr[i * LDX + c], Ci[i * LDX + c]);
+                float2 y;
+                if (fwd) {
+                    lr[k * b + i] = a;                                              // w_k
+                    y = turn ? a : cfms(lr[(k + 1) * b + i], cl_s[k + 1], a);        // y_{k+1} or u_{nb-1}
+                } else {
+                    y = cfms(lr[k * b + i], ch_s[k], a);                            // u_k
+                    lr[k * b + i] = y;
+                }
+                if (knext >= 0) z = cmul(cmul(si_s[i], so_s[knext]), y);
+            }
+            Xr[i * LDX + c] = z.x;
+            Xi[i * LDX + c] = z.y;
+            Xn[i * LDX + c] = -z.y;
+        }
+        if (s + 1 < nsteps) expand();
+    }
+    __syncthreads();
+    // core cells of u to the output
+    for (int c = 0; c < ns; ++c) {
+        const int r = colr[c];
+        if (r < 0) continue;
+        const float2 *lr = loc + r * LT + t.loc_off;
+        float2 *orr = out + r * out_stride;
+        const int cw = t.cx1 - t.cx0, chh = t.cy1 - t.cy0;
+        for (int e = tid; e < cw * chh; e += BM_THREADS) {
+            const int yy = e / cw, xx = e - yy * cw;
+            const int gx = t.cx0 + xx, gy = t.cy0 + yy;
+            const int lxx = gx - t.x0, lyy = gy - t.y0;
+            orr[(long long)gy * nx + gx] = lr[t.tr ? lxx * b + lyy : lyy * lx + lxx];
+        }
+    }
+}
+
+template <int NCOL, int EMAX>
+static void bt_multi_launch(hipStream_t s, int n_jobs, size_t lds, const TileDesc *tiles, const int4 *jobs, int n_src,
+                            const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc,
+                            int nx, int ny, const float2 *vin, long long vin_stride, float2 *out,
+                            long long out_stride, const int *active, float2 *loc, long long LT) {
+    hipLaunchKernelGGL((bt_solve_multi_kernel<NCOL, EMAX>), dim3(n_jobs), dim3(BM_THREADS), lds, s, tiles, jobs, n_src,
+                       dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride, out, out_stride, active, loc, LT);
+}
+
+void launch_bt_solve_multi(hipStream_t s, const TileDesc *tiles, const int4 *jobs, int n_jobs, int n_src,
+                           const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc, int nx,
+                           int ny, const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
+                           const int *active, float2 *loc, long long LT, int bmax) {
+    const int ncol = bt_multi_cols(bmax);
+    const size_t lds = bm_lds_bytes(bmax, ncol);
+    if (ncol == 32)
+        bt_multi_launch<32, 13>(s, n_jobs, lds, tiles, jobs, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin,
+                                vin_stride, out, out_stride, active, loc, LT);
+    else
+        bt_multi_launch<16, 33>(s, n_jobs, lds, tiles, jobs, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin,
+                                vin_stride, out, out_stride, active, loc, LT);
+}
+
+void bt_solve_multi_prepare(int bmax) {
+    const int ncol = bt_multi_cols(bmax);
+    const int lds = (int)bm_lds_bytes(bmax, ncol);
+    if (ncol == 32)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_multi_kernel<32, 13>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    else
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_multi_kernel<16, 33>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 }  // namespace nosdd

@@ -68,6 +68,7 @@ struct Workspace {
     long long N = 0;
     DevBuf x, b, V, Z, w, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, bnorm2, bnorm, beta2,
         iters, kcyc, active, want, ones, reorth, inv_h, flags, hist, cd_, cc_;
+    DevBuf loc;                                    // packed local vectors of the many-source solve
 };
 
 }  // namespace
@@ -125,11 +126,14 @@ struct nosdd_problem {
     struct OrderBuf {
         DevBuf buf;
         int n_jobs = 0;
+        DevBuf mbuf;                                 // many-source jobs (tile, wavelength, first source, sources)
+        int n_mjobs = 0;
     };
     std::map<std::pair<int, int>, OrderBuf> orders;
     // autotuned launch parameters (subdomain-solve prefetch depth; the Gram-Schmidt
     // grid lives in the workspace)
     bool use_autotune = true;
+    bool use_multi = true;                        // many-source solve (use_multi())
     int bt_depth = 0;
     bool bt_tuned = false;
     // one captured graph per Arnoldi step j of a restart cycle (replayed every cycle)
@@ -413,6 +417,7 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
         }
     }
     HIPCHK(ctx, w.hist.ensure((size_t)n_rhs * std::max(1, max_iters) * sizeof(float)));
+    HIPCHK(ctx, w.loc.ensure((size_t)n_rhs * p->loc_total * sizeof(float2)));
     const int nc = std::max(1, p->n_c);
     HIPCHK(ctx, w.cd_.ensure((size_t)n_rhs * nc * sizeof(double2)));
     HIPCHK(ctx, w.cc_.ensure((size_t)n_rhs * nc * sizeof(float2)));
@@ -649,6 +654,11 @@ nosdd_status ensure_nn(nosdd_problem *p, int n_rhs, int n_src) {
 // factorisation run on one XCD and share its L2.  Queues are padded with
 // (-1, -1) to equal length.  Built once per (n_rhs, n_src), outside any
 // graph capture.
+// Sources that share a wavelength are solved together (one factor stream,
+// MFMA products) from 4 sources per wavelength on, for blocks up to 112 wide
+// (LDS of the expanded block and operands).
+bool use_multi(const nosdd_problem *p, int n_src) { return n_src >= 4 && p->bmax <= 112 && p->use_multi; }
+
 nosdd_status solve_order(nosdd_problem *p, int n_rhs, int n_src, const int2 **order, int *n_jobs) {
     auto key = std::make_pair(n_rhs, n_src);
     auto it = p->orders.find(key);
@@ -675,11 +685,38 @@ nosdd_status solve_order(nosdd_problem *p, int n_rhs, int n_src, const int2 **or
         HIPCHK(p->ctx, ob.buf.ensure(ord.size() * sizeof(int2)));
         HIPCHK(p->ctx, hipMemcpy(ob.buf.p, ord.data(), ord.size() * sizeof(int2), hipMemcpyHostToDevice));
         ob.n_jobs = (int)ord.size();
+        if (use_multi(p, n_src)) {
+            // one job per (tile, wavelength, group of sources), largest tiles first
+            const int ncol = bt_multi_cols(p->bmax);
+            std::vector<int4> mj;
+            for (const auto &g : groups)
+                for (int s0 = 0; s0 < n_src; s0 += ncol) mj.push_back(make_int4(g.first, g.second, s0, std::min(ncol, n_src - s0)));
+            HIPCHK(p->ctx, ob.mbuf.ensure(mj.size() * sizeof(int4)));
+            HIPCHK(p->ctx, hipMemcpy(ob.mbuf.p, mj.data(), mj.size() * sizeof(int4), hipMemcpyHostToDevice));
+            ob.n_mjobs = (int)mj.size();
+        }
         it = p->orders.find(key);
     }
     *order = it->second.buf.as<int2>();
     *n_jobs = it->second.n_jobs;
     return NOSDD_OK;
+}
+
+// z = sum_i Rt_i^T B_i^-1 R_i v (exact local solves, global in and out) for
+// n_rhs vectors, n_src per wavelength; the launch queue must exist
+// (solve_order) and, for grouped sources, the workspace's packed local buffer.
+void local_sweep(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, int n_rhs, int n_src,
+                 const int *active) {
+    const long long N = (long long)p->nx * p->ny;
+    const auto &ob = p->orders.at(std::make_pair(n_rhs, n_src));
+    if (ob.n_mjobs > 0)
+        launch_bt_solve_multi(s, p->d_tiles.as<TileDesc>(), ob.mbuf.as<int4>(), ob.n_mjobs, n_src,
+                              p->d_dinv.as<float2>(), p->dinv_wl_stride, p->d_coef.as<float2>(), p->d_sc.as<float2>(),
+                              p->nx, p->ny, v, N, z, N, active, p->ws.loc.as<float2>(), p->loc_total, p->bmax);
+    else
+        launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ob.buf.as<int2>(), ob.n_jobs, n_src, p->d_dinv.as<float2>(),
+                        p->dinv_wl_stride, p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, v, N, z, N,
+                        active, 0, p->bmax, p->max_cells, p->bt_depth);
 }
 
 // z = M^-1 v (two-level), wout = A z.  v, z, wout: [n_rhs][N].
@@ -694,12 +731,7 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
                    p->max_cells, v, z, active, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(),
                    p->h, p->nx, p->ny, 0);
     } else
-    {
-        const auto &ob = p->orders.at(std::make_pair(n_rhs, n_src));
-        launch_bt_solve(s, p->d_tiles.as<TileDesc>(), ob.buf.as<int2>(), ob.n_jobs, n_src, p->d_dinv.as<float2>(),
-                        p->dinv_wl_stride, p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, v, N, z, N, active, 0, p->bmax,
-                        p->max_cells, p->bt_depth);
-    }
+    local_sweep(p, s, v, z, n_rhs, n_src, active);
     }
     if (wout == nullptr) return;
     {
@@ -1703,6 +1735,7 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
         HIPCHK(ctx, hipStreamSynchronize(s));
     }
     bt_solve_prepare(p->bmax, p->max_cells);
+    if (p->bmax <= 112) bt_solve_multi_prepare(p->bmax);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
     {
@@ -1995,9 +2028,9 @@ nosdd_status nosdd_schwarz_sweep(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
     int nj = 0;
     st = solve_order(p, n_rhs, n_src, &ord, &nj);
     if (st) return st;
-    launch_bt_solve(p->ctx->stream, p->d_tiles.as<TileDesc>(), ord, nj, n_src, p->d_dinv.as<float2>(),
-                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, (const float2 *)v, N, (float2 *)z, N,
-                    nullptr, 0, p->bmax, p->max_cells);
+    (void)N;
+    HIPCHK(p->ctx, p->ws.loc.ensure((size_t)n_rhs * p->loc_total * sizeof(float2)));
+    local_sweep(p, p->ctx->stream, (const float2 *)v, (float2 *)z, n_rhs, n_src, nullptr);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
     return NOSDD_OK;
@@ -2163,6 +2196,14 @@ nosdd_status nosdd_graphs(nosdd_problem *p, int enable) {
     if (!p) return NOSDD_EINVAL;
     p->use_graphs = enable != 0;
     if (!p->use_graphs) p->drop_graphs();
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_multi_source(nosdd_problem *p, int enable) {
+    if (!p) return NOSDD_EINVAL;
+    p->use_multi = enable != 0;
+    p->orders.clear();                            // launch queues are rebuilt with or without the grouped jobs
+    p->drop_graphs();
     return NOSDD_OK;
 }
 

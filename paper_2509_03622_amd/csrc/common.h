@@ -133,6 +133,16 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, in
                      int ny, const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
                      const int *active, int mode, int bmax, int max_cells, int depth = 0);
 void bt_solve_prepare(int bmax, int max_cells);
+// Many sources per wavelength: one workgroup per jobs[j] = (tile, wavelength,
+// first source, sources), bt_multi_cols(bmax) sources at most; the gathered
+// right-hand sides and intermediate blocks go through loc[n_rhs][LT] (packed
+// local layout, block-major within a tile).  Global input and core output.
+int bt_multi_cols(int bmax);
+void launch_bt_solve_multi(hipStream_t s, const TileDesc *tiles, const int4 *jobs, int n_jobs, int n_src,
+                           const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc, int nx,
+                           int ny, const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
+                           const int *active, float2 *loc, long long LT, int bmax);
+void bt_solve_multi_prepare(int bmax);
 int bt_solve_depths(int bmax, int *depths);
 
 // Algorithm 3 loop (paperloop.hip)

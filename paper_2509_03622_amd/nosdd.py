@@ -22,7 +22,7 @@ EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_p
            "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device", "nosdd_solve_paper_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
-           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_autotune", "nosdd_tuning",
+           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_multi_source", "nosdd_autotune", "nosdd_tuning",
            "nosdd_fom_gradient_device"]
 
 
@@ -90,6 +90,7 @@ def load(path=LIBPATH):
         "nosdd_kernel_times": (i, [vp, vp, vp, vp]),
         "nosdd_nn_apply": (i, [vp, vp, vp]),
         "nosdd_graphs": (i, [vp, i]),
+        "nosdd_multi_source": (i, [vp, i]),
         "nosdd_autotune": (i, [vp, i]),
         "nosdd_tuning": (i, [vp, vp]),
         "nosdd_fom_gradient_device": (i, [vp, vp, i, vp, i, C.POINTER(SolveOpts), C.POINTER(C.c_double), vp, vp]),
@@ -301,6 +302,10 @@ class Problem:
         self.ctx.check(self.L.nosdd_tuning(self.h, out.ctypes.data))
         return {"solve_prefetch_depth": int(out[0]), "gs_workgroups_per_rhs": out[1:5].tolist(),
                 "tuned_gram_schmidt": bool(out[5] & 1), "tuned_subdomain_solve": bool(out[5] & 2)}
+
+    def multi_source(self, enable=True):
+        """Solve the sources of a wavelength together (one factor stream, MFMA products) or one by one."""
+        return self.ctx.check(self.L.nosdd_multi_source(self.h, 1 if enable else 0))
 
     def graphs(self, enable=True):
         """Replay captured per-step HIP graphs (default) or launch kernels one by one."""
