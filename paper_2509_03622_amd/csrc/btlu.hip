@@ -553,23 +553,28 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, in
 // right-hand sides, w_k and u_k live block-major in a packed workspace
 // (loc[rhs][tile cells]); the core cells are scattered at the end.
 typedef float f32x4v __attribute__((ext_vector_type(4)));
-constexpr int BM_THREADS = 256;
+constexpr int BM_THREADS = 1024;
 
-__host__ __device__ __forceinline__ int bm_rows(int b) { return (b + 15) & ~15; }   // MFMA row padding
-__host__ __device__ __forceinline__ int bm_kdim(int b) { return (b + 3) & ~3; }     // MFMA k padding
+// LDS layout (b the tile's block size, padded to BP = 16 * ceil(b / 16) in rows and in k):
+//   M  [BP][BP + 2] float2 (re, im): the expanded block, row-major, k contiguous;
+//   X  3 x [NCOL][BP + 4] float: Re, Im and -Im of the operand S_k Y, source-major, k contiguous;
+//   C  2 x [BP][NCOL + 1] float: Re and Im of the products.
+// The MFMA lane groups (lane / 16) take contiguous quarters of k, so each lane
+// reads four k at once (16-byte LDS loads) for four consecutive MFMAs.
+__host__ __device__ __forceinline__ int bm_pad(int b) { return (b + 15) & ~15; }
 int bt_multi_cols(int bmax) { return bmax <= 80 ? 32 : 16; }
 static size_t bm_lds_bytes(int bmax, int ncol) {
-    const int BR = bm_rows(bmax), BK = bm_kdim(bmax), LDM = BK + 1, LDX = ncol + 1;
-    return sizeof(float) * ((size_t)2 * BR * LDM + (size_t)3 * BK * LDX + (size_t)2 * BR * LDX);
+    const int BP = bm_pad(bmax);
+    return sizeof(float) * ((size_t)2 * BP * (BP + 2) + (size_t)3 * ncol * (BP + 4) + (size_t)2 * BP * (ncol + 1));
 }
 
-template <int NCOL, int EMAX>
+template <int NCOL, int EMAX, int RMAX>
 __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
     const TileDesc *__restrict__ tiles, const int4 *__restrict__ jobs, int n_src, const float2 *__restrict__ dinv,
     long long dinv_wl_stride, const float2 *__restrict__ coef, const float2 *__restrict__ sc, int nx, int ny,
     const float2 *__restrict__ vin, long long vin_stride, float2 *__restrict__ out, long long out_stride,
     const int *__restrict__ active, float2 *__restrict__ loc, long long LT) {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX], si_s[BT_BMAX];
     __shared__ int colr[NCOL];                       // RHS index of each column, -1 when idle
     const int4 job = jobs[blockIdx.x];               // (tile, wavelength, first source, sources)
@@ -577,10 +582,10 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
     const TileDesc t = tiles[job.x];
     const int wl = job.y, s0 = job.z, ns = job.w;
     const int b = t.b, nb = t.nb, P = b >> 1, tid = threadIdx.x;
-    const int BR = bm_rows(b), BK = bm_kdim(b), LDM = BK + 1, LDX = NCOL + 1;
-    float *Mr = lds, *Mi = Mr + BR * LDM;
-    float *Xr = Mi + BR * LDM, *Xi = Xr + BK * LDX, *Xn = Xi + BK * LDX;
-    float *Cr = Xn + BK * LDX, *Ci = Cr + BR * LDX;
+    const int BP = bm_pad(b), LDM = BP + 2, LDK = BP + 4, LDC = NCOL + 1;
+    float2 *M = reinterpret_cast<float2 *>(lds);
+    float *Xr = lds + 2 * BP * LDM, *Xi = Xr + NCOL * LDK, *Xn = Xi + NCOL * LDK;
+    float *Cr = Xn + NCOL * LDK, *Ci = Cr + BP * LDC;
     if (tid < NCOL) {
         const int r = wl * n_src + s0 + tid;
         colr[tid] = (tid < ns && (!active || active[r])) ? r : -1;
@@ -599,12 +604,9 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
         so_s[k] = s_out[k];
     }
     for (int i = tid; i < b; i += BM_THREADS) si_s[i] = s_in[i];
-    // zero the padding of the MFMA operands once (rows >= b of M, k >= b of M and Y)
-    for (int e = tid; e < BR * LDM; e += BM_THREADS) {
-        Mr[e] = 0.f;
-        Mi[e] = 0.f;
-    }
-    for (int e = tid; e < 3 * BK * LDX; e += BM_THREADS) Xr[e] = 0.f;
+    // zero the padding of the MFMA operands once (rows and k >= b)
+    for (int e = tid; e < BP * LDM; e += BM_THREADS) M[e] = make_float2(0.f, 0.f);
+    for (int e = tid; e < 3 * NCOL * LDK; e += BM_THREADS) Xr[e] = 0.f;
     __syncthreads();
     // gather R_i v block-major: loc[r][loc_off + k b + i]
     for (int c = 0; c < ns; ++c) {
@@ -646,10 +648,8 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
 #pragma unroll
         for (int j = 0; j < EMAX; ++j)
             if (o1[j] >= 0) {
-                Mr[o1[j]] = mreg[j].x;
-                Mi[o1[j]] = mreg[j].y;
-                Mr[o2[j]] = mreg[j].x;
-                Mi[o2[j]] = mreg[j].y;
+                M[o1[j]] = mreg[j];
+                M[o2[j]] = mreg[j];
             }
     };
     const int nsteps = 2 * nb - 1;
@@ -661,59 +661,88 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
         const int i = e % b, c = e / b, r = colr[c];
         float2 z = make_float2(0.f, 0.f);
         if (r >= 0) z = cmul(cmul(si_s[i], so_s[0]), loc[r * LT + t.loc_off + i]);
-        Xr[i * LDX + c] = z.x;
-        Xi[i * LDX + c] = z.y;
-        Xn[i * LDX + c] = -z.y;
+        Xr[c * LDK + i] = z.x;
+        Xi[c * LDK + i] = z.y;
+        Xn[c * LDK + i] = -z.y;
     }
     expand();
     const int wave = tid >> 6, lane = tid & 63;
-    const int RT = BR / 16, nT = RT * (NCOL / 16);
+    const int RT = BP / 16, nT = RT * (NCOL / 16), KQ = BP / 4;
+    // this thread's (row, source) elements of the recurrence, fixed for all steps
+    int ri[RMAX], rc[RMAX];
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+        const int e = tid + j * BM_THREADS;
+        ri[j] = e < b * NCOL ? e % b : -1;
+        rc[j] = e < b * NCOL ? e / b : 0;
+    }
+    float2 pre[RMAX];                                 // v_{k+1} (forward) or w_k (backward) of this thread's elements
     for (int s = 0; s < nsteps; ++s) {
         const int k = blk_of(s);
+        const bool fwd = s < nb, turn = s == nb - 1;
         if (s + 1 < nsteps) fetch(blk_of(s + 1));
+        // the recurrence's other operands do not depend on this step's products: load them now
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) {
+            pre[j] = make_float2(0.f, 0.f);
+            const int r = colr[rc[j]];
+            if (ri[j] >= 0 && !turn && r >= 0) pre[j] = loc[r * LT + t.loc_off + (fwd ? k + 1 : k) * b + ri[j]];
+        }
         __syncthreads();                              // M_k and the operand are in LDS
         for (int q = wave; q < nT; q += BM_THREADS / 64) {
             const int rt = q % RT, ct = q / RT;
             f32x4v accR = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
-            const int arow = (rt * 16 + (lane & 15)) * LDM, bcol = ct * 16 + (lane & 15);
-            for (int kk = 0; kk < BK; kk += 4) {
-                const int ka = kk + (lane >> 4);
-                const float ar = Mr[arow + ka], ai = Mi[arow + ka];
-                const float yr = Xr[ka * LDX + bcol], yi = Xi[ka * LDX + bcol], yn = Xn[ka * LDX + bcol];
-                accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, yr, accR, 0, 0, 0);
-                accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, yn, accR, 0, 0, 0);
-                accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, yi, accI, 0, 0, 0);
-                accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, yr, accI, 0, 0, 0);
+            const int bcol = ct * 16 + (lane & 15), k0 = (lane >> 4) * KQ;
+            const float2 *arow = M + (rt * 16 + (lane & 15)) * LDM + k0;
+            const float *xr = Xr + bcol * LDK + k0, *xi = Xi + bcol * LDK + k0, *xn = Xn + bcol * LDK + k0;
+            for (int kk = 0; kk < KQ; kk += 4) {
+                const float4 a01 = *reinterpret_cast<const float4 *>(arow + kk);
+                const float4 a23 = *reinterpret_cast<const float4 *>(arow + kk + 2);
+                const float4 yr = *reinterpret_cast<const float4 *>(xr + kk);
+                const float4 yi = *reinterpret_cast<const float4 *>(xi + kk);
+                const float4 yn = *reinterpret_cast<const float4 *>(xn + kk);
+                const float ar[4] = {a01.x, a01.z, a23.x, a23.z}, ai[4] = {a01.y, a01.w, a23.y, a23.w};
+                const float vr[4] = {yr.x, yr.y, yr.z, yr.w}, vi[4] = {yi.x, yi.y, yi.z, yi.w};
+                const float vn[4] = {yn.x, yn.y, yn.z, yn.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[u], vr[u], accR, 0, 0, 0);
+                    accR = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[u], vn[u], accR, 0, 0, 0);
+                    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[u], vi[u], accI, 0, 0, 0);
+                    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[u], vr[u], accI, 0, 0, 0);
+                }
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = rt * 16 + 4 * (lane >> 4) + i;
-                Cr[row * LDX + bcol] = accR[i];
-                Ci[row * LDX + bcol] = accI[i];
+                Cr[row * LDC + bcol] = accR[i];
+                Ci[row * LDC + bcol] = accI[i];
             }
         }
         __syncthreads();                              // products in LDS; M_k and the operand consumed
-        const bool fwd = s < nb, turn = s == nb - 1;
         const int knext = fwd && !turn ? k + 1 : k - 1;
-        for (int e = tid; e < b * NCOL; e += BM_THREADS) {
-            const int i = e % b, c = e / b, r = colr[c];
+        const float2 cc = fwd ? cl_s[min(k + 1, nb - 1)] : ch_s[k];
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) {
+            if (ri[j] < 0) break;
+            const int i = ri[j], c = rc[j], r = colr[c];
             float2 z = make_float2(0.f, 0.f);
             if (r >= 0) {
                 float2 *lr = loc + r * LT + t.loc_off;
-                const float2 a = make_float2(Cr[i * LDX + c], Ci[i * LDX + c]);
+                const float2 a = make_float2(Cr[i * LDC + c], Ci[i * LDC + c]);
                 float2 y;
                 if (fwd) {
                     lr[k * b + i] = a;                                              // w_k
-                    y = turn ? a : cfms(lr[(k + 1) * b + i], cl_s[k + 1], a);        // y_{k+1} or u_{nb-1}
+                    y = turn ? a : cfms(pre[j], cc, a);                             // y_{k+1} or u_{nb-1}
                 } else {
-                    y = cfms(lr[k * b + i], ch_s[k], a);                            // u_k
+                    y = cfms(pre[j], cc, a);                                        // u_k
                     lr[k * b + i] = y;
                 }
                 if (knext >= 0) z = cmul(cmul(si_s[i], so_s[knext]), y);
             }
-            Xr[i * LDX + c] = z.x;
-            Xi[i * LDX + c] = z.y;
-            Xn[i * LDX + c] = -z.y;
+            Xr[c * LDK + i] = z.x;
+            Xi[c * LDK + i] = z.y;
+            Xn[c * LDK + i] = -z.y;
         }
         if (s + 1 < nsteps) expand();
     }
@@ -734,12 +763,12 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
     }
 }
 
-template <int NCOL, int EMAX>
+template <int NCOL, int EMAX, int RMAX>
 static void bt_multi_launch(hipStream_t s, int n_jobs, size_t lds, const TileDesc *tiles, const int4 *jobs, int n_src,
                             const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc,
                             int nx, int ny, const float2 *vin, long long vin_stride, float2 *out,
                             long long out_stride, const int *active, float2 *loc, long long LT) {
-    hipLaunchKernelGGL((bt_solve_multi_kernel<NCOL, EMAX>), dim3(n_jobs), dim3(BM_THREADS), lds, s, tiles, jobs, n_src,
+    hipLaunchKernelGGL((bt_solve_multi_kernel<NCOL, EMAX, RMAX>), dim3(n_jobs), dim3(BM_THREADS), lds, s, tiles, jobs, n_src,
                        dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride, out, out_stride, active, loc, LT);
 }
 
@@ -750,10 +779,10 @@ void launch_bt_solve_multi(hipStream_t s, const TileDesc *tiles, const int4 *job
     const int ncol = bt_multi_cols(bmax);
     const size_t lds = bm_lds_bytes(bmax, ncol);
     if (ncol == 32)
-        bt_multi_launch<32, 13>(s, n_jobs, lds, tiles, jobs, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin,
+        bt_multi_launch<32, 4, 3>(s, n_jobs, lds, tiles, jobs, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin,
                                 vin_stride, out, out_stride, active, loc, LT);
     else
-        bt_multi_launch<16, 33>(s, n_jobs, lds, tiles, jobs, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin,
+        bt_multi_launch<16, 9, 2>(s, n_jobs, lds, tiles, jobs, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin,
                                 vin_stride, out, out_stride, active, loc, LT);
 }
 
@@ -761,10 +790,10 @@ void bt_solve_multi_prepare(int bmax) {
     const int ncol = bt_multi_cols(bmax);
     const int lds = (int)bm_lds_bytes(bmax, ncol);
     if (ncol == 32)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_multi_kernel<32, 13>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_multi_kernel<32, 4, 3>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     else
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_multi_kernel<16, 33>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_multi_kernel<16, 9, 2>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
