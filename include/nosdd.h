@@ -38,6 +38,7 @@ extern "C" {
 #endif
 
 typedef struct { float re, im; } nosdd_c32;
+typedef struct { double re, im; } nosdd_c64;
 
 typedef enum {
     NOSDD_OK = 0,
@@ -142,6 +143,15 @@ nosdd_status nosdd_solve(nosdd_problem *p, const nosdd_c32 *J, int n_src,
 nosdd_status nosdd_solve_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src,
                                 const nosdd_solve_opts *opts, nosdd_c32 *E_dev, float *resid_hist,
                                 int *iters, float *final_resid);
+
+/* Same as nosdd_solve_device, with the field returned as the outer FGMRES's
+ * FP64 iterate (E64_dev, device, [n_wl][n_src][ny][nx] complex128) instead
+ * of its complex64 rounding: the iterate and every restart residual are FP64
+ * (refinement around FP32 Krylov cycles), so tolerances below single
+ * precision are reached and kept in the returned field. */
+nosdd_status nosdd_solve_device_c64(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src,
+                                    const nosdd_solve_opts *opts, nosdd_c64 *E64_dev, float *resid_hist,
+                                    int *iters, float *final_resid);
 
 /* The paper's own outer loop (Algorithm 3): stationary sweeps over the Robin
  * data g of every subdomain's interface entries, starting from g = 0,

@@ -66,7 +66,7 @@ struct Workspace {
     int nblk_b[4] = {0, 0, 0, 0}, nblk_max = 0;
     bool tuned = false;
     long long N = 0;
-    DevBuf x, b, V, Z, w, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, bnorm2, bnorm, beta2,
+    DevBuf x, b, b64, V, Z, w, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, bnorm2, bnorm, beta2,
         iters, kcyc, active, want, ones, reorth, inv_h, flags, hist, cd_, cc_;
     DevBuf loc;                                    // packed local vectors of the many-source solve
 };
@@ -313,6 +313,20 @@ __global__ void make_rhs_kernel(const float2 *J, float2 *b, const float *k0, lon
     }
 }
 
+// The same right-hand side in FP64 (-i omega J with omega in FP64), for the
+// residuals of the FP64 outer iterate.
+__global__ void make_rhs64_kernel(const float2 *J, double2 *b, const double *k0, long long N, int n_src,
+                                  int per_rhs) {
+    const int r = blockIdx.y;
+    const int wl = r / n_src, s = r - wl * n_src;
+    const double om = k0[wl];
+    const float2 *Jr = J + (per_rhs ? r : s) * N;
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long long)gridDim.x * blockDim.x) {
+        const float2 j = Jr[n];
+        b[r * N + n] = make_double2(om * j.y, -om * j.x);
+    }
+}
+
 __global__ void fill_f32_kernel(float *p, long long n, float v) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = v;
@@ -392,6 +406,7 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     const size_t vec = (size_t)n_rhs * N * sizeof(float2);
     HIPCHK(ctx, w.x.ensure(vec * 2));        // FP64 iterate
     HIPCHK(ctx, w.b.ensure(vec));
+    HIPCHK(ctx, w.b64.ensure(vec * 2));      // FP64 right-hand side of the restart residuals
     HIPCHK(ctx, w.w.ensure(vec));
     HIPCHK(ctx, w.V.ensure(vec * (m + 1)));
     HIPCHK(ctx, w.Z.ensure(vec * m));
@@ -1283,7 +1298,8 @@ nosdd_status ensure_graphs(nosdd_problem *p, int n_rhs, int n_src, int m, const 
 }
 
 nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const nosdd_solve_opts *o, const float2 *x0_dev,
-                        float2 *E_dev, float *resid_hist, int *iters_out, float *final_out, bool j_per_rhs = false) {
+                        float2 *E_dev, float *resid_hist, int *iters_out, float *final_out, bool j_per_rhs = false,
+                        double2 *E64_dev = nullptr) {
     nosdd_ctx *ctx = p->ctx;
     hipStream_t s = ctx->stream;
     const int nwl = (int)p->wl.size();
@@ -1329,6 +1345,8 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     const long long vstride = (long long)n_rhs * N;
     hipLaunchKernelGGL(make_rhs_kernel, dim3((unsigned)grid_blocks(N), n_rhs), dim3(256), 0, s, J_dev, b,
                        p->d_k0f.as<float>(), N, n_src, j_per_rhs ? 1 : 0);
+    hipLaunchKernelGGL(make_rhs64_kernel, dim3((unsigned)grid_blocks(N), n_rhs), dim3(256), 0, s, J_dev,
+                       w.b64.as<double2>(), p->d_k0.as<double>(), N, n_src, j_per_rhs ? 1 : 0);
     hipLaunchKernelGGL(widen_kernel, dim3((unsigned)grid_blocks(vstride)), dim3(256), 0, s, x0_dev, x, vstride);
     HIPCHK(ctx, hipMemsetAsync(w.iters.p, 0, n_rhs * sizeof(int), s));
     {
@@ -1403,7 +1421,7 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         // explicit residual r = b - A x (FP64) into w, beta^2
         {
         ProfScope ps(p, 1, n_rhs);
-        launch_residual64(s, x, b, wv, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->nx,
+        launch_residual64(s, x, w.b64.as<double2>(), wv, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->nx,
                           p->ny, n_rhs, n_src);
         }
         launch_cgs_dots(s, V, vstride, 0, wv, N, n_rhs, w.ones.as<int>(), w.partial.as<double2>(), w.nblk_b[0]);
@@ -1462,6 +1480,7 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     HIPCHK(ctx, hipGetLastError());
     if (E_dev)
         hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)grid_blocks(vstride)), dim3(256), 0, s, x, E_dev, vstride);
+    if (E64_dev) HIPCHK(ctx, hipMemcpyAsync(E64_dev, x, (size_t)vstride * sizeof(double2), hipMemcpyDeviceToDevice, s));
     HIPCHK(ctx, hipEventRecord(e1, s));
     HIPCHK(ctx, hipMemcpyAsync(iters.data(), w.iters.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
     if (resid_hist && o->max_iters > 0)
@@ -1825,6 +1844,14 @@ nosdd_status nosdd_solve_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_
     if (st) return st;
     return solve_impl(p, (const float2 *)J_dev, n_src, o, (const float2 *)o->x0, (float2 *)E_dev, resid_hist, iters,
                       final_resid);
+}
+
+nosdd_status nosdd_solve_device_c64(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src, const nosdd_solve_opts *o,
+                                    nosdd_c64 *E64_dev, float *resid_hist, int *iters, float *final_resid) {
+    nosdd_status st = validate_solve(p, J_dev, n_src, o, E64_dev);
+    if (st) return st;
+    return solve_impl(p, (const float2 *)J_dev, n_src, o, (const float2 *)o->x0, nullptr, resid_hist, iters,
+                      final_resid, false, (double2 *)E64_dev);
 }
 
 nosdd_status nosdd_solve_paper_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src, const nosdd_paper_opts *o,

@@ -71,7 +71,7 @@ void launch_stencil(hipStream_t s, const float2 *x, const float2 *b, float2 *y, 
                     const double2 *coef, const double *k0, int nx, int ny, int n_rhs, int n_src,
                     const int *active);
 
-void launch_residual64(hipStream_t s, const double2 *x, const float2 *b, float2 *r, const float *eps,
+void launch_residual64(hipStream_t s, const double2 *x, const double2 *b, float2 *r, const float *eps,
                        const double2 *coef, const double *k0, int nx, int ny, int n_rhs, int n_src);
 
 // Symmetric storage of the subdomain factors.  With S_k = diag of the centre

@@ -67,7 +67,7 @@ template <> __device__ __forceinline__ double2 zero_of<double2>() { return make_
 // stores, for outputs too large to stay in the last-level cache.
 template <typename XT, bool HAS_B, bool NT>
 __global__ __launch_bounds__(64 * ST_WAVES) void stencil_kernel(const XT *__restrict__ x,
-                                                                const float2 *__restrict__ b,
+                                                                const XT *__restrict__ b,
                                                                 float2 *__restrict__ y,
                                                                 const float *__restrict__ eps,
                                                                 const double2 *__restrict__ coef,
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(64 * ST_WAVES) void stencil_kernel(const XT *__rest
     const long long N = (long long)nx * ny;
     const XT *xr = x + rhs * N;
     float2 *yr = y + rhs * N;
-    const float2 *br = HAS_B ? b + rhs * N : nullptr;
+    const XT *br = HAS_B ? b + rhs * N : nullptr;
     const double2 *cf = coef + wl * coef_stride(nx, ny);
     const double2 *cxm = cf, *cxp = cf + nx, *cym = cf + 2 * nx, *cyp = cf + 2 * nx + ny;
     const double kk = k0v[wl] * k0v[wl];
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(64 * ST_WAVES) void stencil_kernel(const XT *__rest
 
     XT xv[ST_ROWS + 2], xh[ST_ROWS];
     float ev[ST_ROWS];
-    float2 bv[ST_ROWS] = {};
+    XT bv[ST_ROWS] = {};
 #pragma unroll
     for (int i = 0; i < ST_ROWS + 2; ++i) {
         const int iyc = min(max(iy0 - 1 + i, 0), ny - 1);
@@ -181,7 +181,7 @@ static dim3 stencil_grid(int nx, int ny, int n_rhs) {
 constexpr long long ST_STREAM_BYTES = 256LL << 20;
 
 template <typename XT, bool HAS_B>
-static void stencil_launch(hipStream_t s, const XT *x, const float2 *b, float2 *y, const float *eps,
+static void stencil_launch(hipStream_t s, const XT *x, const XT *b, float2 *y, const float *eps,
                            const double2 *coef, const double *k0, int nx, int ny, int n_rhs, int n_src,
                            const int *active) {
     const bool nt = (long long)nx * ny * n_rhs * (long long)sizeof(float2) > ST_STREAM_BYTES;
@@ -202,9 +202,10 @@ void launch_stencil(hipStream_t s, const float2 *x, const float2 *b, float2 *y, 
         stencil_launch<float2, false>(s, x, b, y, eps, coef, k0, nx, ny, n_rhs, n_src, active);
 }
 
-// r = b - A x with the iterate x kept in FP64 (mixed-precision refinement of
-// the outer iteration): the residual is formed in FP64 and rounded once.
-void launch_residual64(hipStream_t s, const double2 *x, const float2 *b, float2 *r, const float *eps,
+// r = b - A x with the iterate x and the right-hand side b kept in FP64
+// (mixed-precision refinement of the outer iteration): the residual is formed
+// in FP64 and rounded once.
+void launch_residual64(hipStream_t s, const double2 *x, const double2 *b, float2 *r, const float *eps,
                        const double2 *coef, const double *k0, int nx, int ny, int n_rhs, int n_src) {
     stencil_launch<double2, true>(s, x, b, r, eps, coef, k0, nx, ny, n_rhs, n_src, nullptr);
 }

@@ -19,7 +19,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -
           -5: "EBREAKDOWN", -6: "ENONFINITE", -7: "ENOWEIGHTS", -8: "ESTATE"}
 
 EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_problem_create",
-           "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device", "nosdd_solve_paper_device",
+           "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device", "nosdd_solve_device_c64", "nosdd_solve_paper_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
            "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_multi_source", "nosdd_autotune", "nosdd_tuning",
@@ -77,6 +77,7 @@ def load(path=LIBPATH):
         "nosdd_solve": (i, [vp, vp, i, C.POINTER(SolveOpts), vp, vp, vp, vp]),
         "nosdd_solve_device": (i, [vp, vp, i, C.POINTER(SolveOpts), vp, vp, vp, vp]),
         "nosdd_solve_paper_device": (i, [vp, vp, i, C.POINTER(PaperOpts), vp, vp, vp, vp]),
+        "nosdd_solve_device_c64": (i, [vp, vp, i, C.POINTER(SolveOpts), vp, vp, vp, vp]),
         "nosdd_apply_operator": (i, [vp, vp, vp, vp, i]),
         "nosdd_schwarz_sweep": (i, [vp, vp, vp, i]),
         "nosdd_precond_apply": (i, [vp, vp, vp, vp, i]),
@@ -202,6 +203,17 @@ class Problem:
                                                hist.ctypes.data, iters.ctypes.data, fin.ctypes.data))
         del nr
         return E, hist, iters, fin, st
+
+    def solve_device_c64(self, J, E64, tol=1e-6, restart=30, max_iters=1000, x0=None):
+        """As solve_device, with E64 [n_wl][n_src][ny][nx] complex128 receiving the FP64 iterate."""
+        ns = J.shape[0]
+        hist = np.zeros((self.n_wl, ns, max(1, max_iters)), np.float32)
+        iters = np.zeros((self.n_wl, ns), np.int32)
+        fin = np.zeros((self.n_wl, ns), np.float32)
+        o = SolveOpts(tol, restart, max_iters, _ptr(x0))
+        st = self.ctx.check(self.L.nosdd_solve_device_c64(self.h, _ptr(J), ns, C.byref(o), _ptr(E64),
+                                                          hist.ctypes.data, iters.ctypes.data, fin.ctypes.data))
+        return hist, iters, fin, st
 
     def solve_paper(self, J, E, momentum=0.0, coarse=False, tol=1e-6, max_iters=500):
         """The paper's Algorithm 3 loop on device tensors (J [n_src][ny][nx],
