@@ -340,7 +340,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
                                                        const int2 *__restrict__ order) {
     extern __shared__ float2 vl[];                    // [nb][b]: v_k, then w_k
     __shared__ __align__(16) float2 ysh[2][BT_BMAX + 2];   // + a zero pair read by unused offset slots
-    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX];
+    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX], si_s[BT_BMAX];
     const int2 job = order[blockIdx.x];               // (tile, rhs); tile < 0 pads the queue
     const int tile = job.x, rhs = job.y;
     if (tile < 0 || (active && !active[rhs])) return;
@@ -375,6 +375,10 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
         ch_s[k] = chi_a[base + k];
         so_s[k] = s_out[k];
     }
+    // the in-block scaling goes through LDS as well: a global load left in
+    // flight past the prefetch below would make every step's first use of it
+    // wait for the whole register ring
+    for (int k = tid; k < b; k += blockDim.x) si_s[k] = s_in[k];
     const int nsteps = 2 * nb - 1;
     auto blk = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
     // per offset: storage entry (byte offset within a block), transposed flag, operand pair
@@ -400,7 +404,6 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     // lanes 0 and 1 of each group carry the recurrence for rows 2rp and 2rp + 1
     const int myr = 2 * rp + (cg & 1);
     const bool wr = on && cg < 2;
-    const float2 si = wr ? s_in[myr] : make_float2(0.f, 0.f);
     // output index of row myr in block k: obase + k * kstride; the block index
     // range [kc0, kc1) and okr select the core rows (all rows for local output)
     long long obase;
@@ -427,6 +430,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     }
     const bool emit_lane = wr && okr;
     __syncthreads();
+    const float2 si = wr ? si_s[myr] : make_float2(0.f, 0.f);
     if (wr) ysh[0][myr] = cmul(cmul(si, so_s[0]), vl[myr]);      // S_0 v_0
     if (tid < 4) ysh[tid >> 1][BT_BMAX + (tid & 1)] = make_float2(0.f, 0.f);
     __syncthreads();
