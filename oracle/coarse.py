@@ -15,8 +15,9 @@ Algorithm 3, in this reading:
    whose interface ring is an L-shape).
 3. Homogeneous local solves F_l = B_i^-1 inj(x_l) (no source term).
 4. y_l = Robin traces of F_l on the interface rings of the neighbouring
-   subdomains (diagonal neighbours included), where those rings lie inside
-   the subdomain: the map x -> y is the Robin-to-Robin map.
+   subdomains (every subdomain whose ring or ghost nodes reach into this one,
+   diagonal neighbours included), where those rings lie inside the
+   subdomain: the map x -> y is the Robin-to-Robin map.
 5. Rayleigh-Ritz on (x, y) in its SVD form (the paper reports SVD works about
    as well as the eigen-decomposition): Y = U S V^H, the k_coarse right
    singular vectors with the largest singular values (slowest decaying
@@ -86,19 +87,13 @@ def neighbour_traces(part, locs, i, F_loc):
     """Robin traces of local fields F (columns) on neighbours' interface rings inside tile i."""
     t = part.tiles[i]
     rows = []
-    for dy in (-1, 0, 1):
-        for dx in (-1, 0, 1):
-            if dx == 0 and dy == 0:
-                continue
-            tj = part.tile_at(t.tx + dx, t.ty + dy)
-            if tj is None:
-                continue
-            Lj = locs[tj.ty * part.ncx + tj.tx]
-            for e, (p, q, side) in enumerate(Lj.entries):
-                if t.contains(*p) and t.contains(*q):
-                    up = F_loc[t.local_index(*p)]
-                    uq = F_loc[t.local_index(*q)]
-                    rows.append((uq - up) / Lj.h + 0.5j * Lj.kappa[e] * (uq + up))
+    for j in part.neighbours(i):
+        Lj = locs[j]
+        for e, (p, q, side) in enumerate(Lj.entries):
+            if t.contains(*p) and t.contains(*q):
+                up = F_loc[t.local_index(*p)]
+                uq = F_loc[t.local_index(*q)]
+                rows.append((uq - up) / Lj.h + 0.5j * Lj.kappa[e] * (uq + up))
     if not rows:
         return np.zeros((0, F_loc.shape[1]), dtype=np.complex128)
     return np.array(rows)

@@ -4,11 +4,14 @@ Oracle, test infrastructure only.  Follows the "partitioner" abstraction of the
 Methods section (two-level Schwarz subsection) and the subdomain boundary value
 problem of Eq. 2.
 
-Partition reading: the cores (lists ``core_x``, ``core_y``) tile the grid; each
-core is extended by ``ext = overlap // 2`` cells on every side that is not on
-the global boundary ("interface sides"), so neighbouring subdomains share
-``overlap`` cells.  The restricted (RAS) prolongation writes core cells only;
-the cores form a partition of unity.
+Partition reading: the cores tile the grid, either as the tensor product of
+the lists ``core_x`` and ``core_y`` or as any list of rectangles that covers
+every cell exactly once (``Partition.from_cores``: the partitioner abstraction
+allows arbitrary arrangements, e.g. a quad-tree, as long as the subdomains
+cover the domain); each core is extended by ``ext = overlap // 2`` cells on
+every side that is not on the global boundary ("interface sides"), so
+neighbouring subdomains share ``overlap`` cells.  The restricted (RAS)
+prolongation writes core cells only; the cores form a partition of unity.
 
 Robin transmission (Eq. 2 with the exp(+i omega t) convention, outward normal
 n, outgoing-absorbing sign):  g = du/dn + i kappa u,  kappa = k0 sqrt(eps).
@@ -77,37 +80,65 @@ class PartitionError(ValueError):
 
 
 class Partition:
-    """Rectangular arrangement of extended subdomains, tile index = ty*ncx + tx."""
+    """Overlapping extended subdomains over rectangular cores.
+
+    Tensor form (``core_x``, ``core_y``): tile index = ty*ncx + tx.  General
+    form (``from_cores``): tiles in the order of the core list, tx = ty = -1.
+    """
 
     def __init__(self, nx, ny, core_x, core_y, overlap, npml=0):
         core_x = [int(c) for c in core_x]
         core_y = [int(c) for c in core_y]
         if sum(core_x) != nx or sum(core_y) != ny:
             raise PartitionError("core sizes must sum to the grid size")
-        if overlap < 2 or overlap % 2:
-            raise PartitionError("overlap must be even and >= 2")
-        ext = overlap // 2
-        ncx, ncy = len(core_x), len(core_y)
-        if (ncx > 1 or ncy > 1) and ext + 1 > min(core_x + core_y):
-            raise PartitionError("ext + 1 must not exceed the smallest core")
-        self.nx, self.ny, self.ext, self.npml = nx, ny, ext, npml
-        self.ncx, self.ncy = ncx, ncy
+        if min(core_x + core_y) <= 0:
+            raise PartitionError("core sizes must be positive")
         xb = np.concatenate([[0], np.cumsum(core_x)])
         yb = np.concatenate([[0], np.cumsum(core_y)])
+        cores = [(int(xb[tx]), int(xb[tx + 1]), int(yb[ty]), int(yb[ty + 1]))
+                 for ty in range(len(core_y)) for tx in range(len(core_x))]
+        self.ncx, self.ncy = len(core_x), len(core_y)
+        self._build(nx, ny, cores, overlap, npml)
+        for k, t in enumerate(self.tiles):
+            t.ty, t.tx = divmod(k, self.ncx)
+
+    @classmethod
+    def from_cores(cls, nx, ny, cores, overlap, npml=0):
+        """Partition from an explicit list of cores (cx0, cx1, cy0, cy1), half-open."""
+        self = cls.__new__(cls)
+        self.ncx = self.ncy = None
+        self._build(nx, ny, [tuple(int(v) for v in c) for c in cores], overlap, npml)
+        return self
+
+    def _build(self, nx, ny, cores, overlap, npml):
+        if overlap < 2 or overlap % 2:
+            raise PartitionError("overlap must be even and >= 2")
+        if not cores:
+            raise PartitionError("empty partition")
+        ext = overlap // 2
+        owner = -np.ones((ny, nx), dtype=np.int64)
+        for k, (cx0, cx1, cy0, cy1) in enumerate(cores):
+            if not (0 <= cx0 < cx1 <= nx and 0 <= cy0 < cy1 <= ny):
+                raise PartitionError("a core is empty or leaves the grid")
+            if np.any(owner[cy0:cy1, cx0:cx1] >= 0):
+                raise PartitionError("cores overlap")
+            owner[cy0:cy1, cx0:cx1] = k
+        if np.any(owner < 0):
+            raise PartitionError("cores do not cover the grid")
+        if len(cores) > 1 and ext + 1 > min(min(c[1] - c[0], c[3] - c[2]) for c in cores):
+            raise PartitionError("ext + 1 must not exceed the smallest core")
+        self.nx, self.ny, self.ext, self.npml = nx, ny, ext, npml
+        self.owner = owner
         self.tiles = []
-        for ty in range(ncy):
-            for tx in range(ncx):
-                cx0, cx1, cy0, cy1 = xb[tx], xb[tx + 1], yb[ty], yb[ty + 1]
-                iface = {"left": tx > 0, "right": tx < ncx - 1,
-                         "bottom": ty > 0, "top": ty < ncy - 1}
-                x0 = cx0 - ext if iface["left"] else cx0
-                x1 = cx1 + ext if iface["right"] else cx1
-                y0 = cy0 - ext if iface["bottom"] else cy0
-                y1 = cy1 + ext if iface["top"] else cy1
-                t = Tile(tx, ty, int(cx0), int(cx1), int(cy0), int(cy1),
-                         int(x0), int(x1), int(y0), int(y1), iface)
-                self._validate_tile(t)
-                self.tiles.append(t)
+        for (cx0, cx1, cy0, cy1) in cores:
+            iface = {"left": cx0 > 0, "right": cx1 < nx, "bottom": cy0 > 0, "top": cy1 < ny}
+            x0 = cx0 - ext if iface["left"] else cx0
+            x1 = cx1 + ext if iface["right"] else cx1
+            y0 = cy0 - ext if iface["bottom"] else cy0
+            y1 = cy1 + ext if iface["top"] else cy1
+            t = Tile(-1, -1, cx0, cx1, cy0, cy1, x0, x1, y0, y1, iface)
+            self._validate_tile(t)
+            self.tiles.append(t)
 
     def _validate_tile(self, t):
         """No interface may sit inside the PML of its normal direction."""
@@ -125,9 +156,19 @@ class Partition:
                     raise PartitionError(f"interface y={yb} lies in the y-PML")
 
     def tile_at(self, tx, ty):
+        if self.ncx is None:
+            raise PartitionError("tile_at needs a tensor partition")
         if 0 <= tx < self.ncx and 0 <= ty < self.ncy:
             return self.tiles[ty * self.ncx + tx]
         return None
+
+    def neighbours(self, i):
+        """Tiles j != i whose extended rectangle grown by one cell (its ring's
+        ghost nodes) meets tile i's extended rectangle, in index order.  Every
+        interface entry that touches tile i belongs to one of them."""
+        t = self.tiles[i]
+        return [j for j, u in enumerate(self.tiles)
+                if j != i and u.x0 - 1 < t.x1 and t.x0 < u.x1 + 1 and u.y0 - 1 < t.y1 and t.y0 < u.y1 + 1]
 
     # ---------------------------------------------------------------- rings
     def ring_nodes(self, t):

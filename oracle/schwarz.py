@@ -18,12 +18,15 @@ from .partition import Partition, build_local_problems
 
 class SchwarzProblem:
     def __init__(self, eps, wavelength, h, npml, core_x, core_y, overlap,
-                 k_coarse=0, k_trial=8, pml_m=2, pml_lnR=-30.0, rotation="svd"):
+                 k_coarse=0, k_trial=8, pml_m=2, pml_lnR=-30.0, rotation="svd", cores=None):
         self.eps = np.asarray(eps, dtype=np.float64)
         ny, nx = self.eps.shape
         self.wavelength, self.h = wavelength, h
         self.A = assemble_A(self.eps, wavelength, h, npml, pml_m, pml_lnR)
-        self.part = Partition(nx, ny, core_x, core_y, overlap, npml)
+        if cores is not None:       # explicit core list (e.g. a quad-tree)
+            self.part = Partition.from_cores(nx, ny, cores, overlap, npml)
+        else:
+            self.part = Partition(nx, ny, core_x, core_y, overlap, npml)
         self.locs = build_local_problems(self.part, self.A, self.eps, wavelength, h)
         self.cs = None
         if k_coarse > 0:

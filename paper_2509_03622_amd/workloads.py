@@ -1,7 +1,7 @@
 """Seeded synthetic inputs shaped like the paper's workloads.
 
 This module only draws inputs (permittivity maps, source placements, partition
-lists); it holds none of the method's arithmetic, so both the HIP path and the
+lists, quad-tree core lists); it holds none of the method's arithmetic, so both the HIP path and the
 CPU oracle can take their inputs from it.  Each generator uses
 ``numpy.random.default_rng(seed)`` with a fixed draw order.
 
@@ -41,6 +41,7 @@ class Workload:
     pml_m: int = PML_M
     pml_lnR: float = PML_LNR
     notes: dict = field(default_factory=dict)
+    cores: list = None               # explicit cores (cx0, cx1, cy0, cy1); overrides core_x / core_y
 
     def J(self):
         """Current density [n_src][ny][nx] complex64, one unit cell per source."""
@@ -151,9 +152,80 @@ def random_small(seed, nx, ny, core_x, core_y, wavelengths=(1.0,), n_src=1, k_co
                     list(core_x), list(core_y), overlap=overlap, k_coarse=k_coarse, npml=npml)
 
 
+def _even_half(n):
+    return 2 * (n // 4)
+
+
+def quadtree_cores(nx, ny, eps, h, wavelength, max_size=5.0, min_core=16, max_core=64):
+    """Quad-tree partition of the grid (Methods, partitioner: a quadrant larger
+    than a threshold of about five wavelengths is decomposed into four).
+
+    The size of a quadrant is measured in local wavelengths, wavelength /
+    sqrt(max eps over the quadrant) with h per cell, so high-index regions are
+    refined further.  A quadrant is split while its longer side exceeds
+    max_size local wavelengths or max_core cells; it is split into four, or
+    into two along its longer side when the other side cannot be halved, as
+    long as every half keeps at least min_core cells.  Split points are even,
+    so even grids give even cores.  Returns the cores (cx0, cx1, cy0, cy1),
+    half-open, depth-first (lower-left, lower-right, upper-left, upper-right).
+    """
+    eps = np.asarray(eps)
+    out = []
+
+    def rec(x0, x1, y0, y1):
+        wx, wy = x1 - x0, y1 - y0
+        lam = wavelength / np.sqrt(float(eps[y0:y1, x0:x1].max()))
+        big = max(wx, wy) > max_core or max(wx, wy) * h > max_size * lam
+        hx, hy = _even_half(wx), _even_half(wy)
+        can_x = min(hx, wx - hx) >= min_core
+        can_y = min(hy, wy - hy) >= min_core
+        if not big or not (can_x or can_y):
+            out.append((x0, x1, y0, y1))
+            return
+        xs = [(x0, x0 + hx), (x0 + hx, x1)] if can_x else [(x0, x1)]
+        ys = [(y0, y0 + hy), (y0 + hy, y1)] if can_y else [(y0, y1)]
+        for (a0, a1) in ys:
+            for (b0, b1) in xs:
+                rec(b0, b1, a0, a1)
+
+    rec(0, nx, 0, ny)
+    return out
+
+
+def quadtree_512(seed=6):
+    """512 x 512, vacuum with a central 256 x 256 region of 16-cell blocks of
+    eps in [1, 8], 2 wavelengths {1.0, 1.2}, centre source, one coarse basis
+    per subdomain; quad-tree cores for the shorter wavelength: 64-cell cores
+    in vacuum, 32-cell cores over the high-index region."""
+    rng = np.random.default_rng(seed)
+    n = 512
+    eps = np.ones((n, n))
+    eps[128:384, 128:384] = np.kron(rng.uniform(1, 8, (16, 16)), np.ones((16, 16)))
+    cores = quadtree_cores(n, n, eps, H, 1.0)
+    return Workload("quadtree512_2wl_2level", n, n, eps.astype(np.float32), [1.0, 1.2], [(n // 2, n // 2)],
+                    [], [], k_coarse=1, cores=cores)
+
+
+def random_quadtree(seed, n=192, wavelengths=(1.0,), n_src=1, k_coarse=0, npml=NPML, hot=(48, 96, 48, 96)):
+    """Small quad-tree test problem: vacuum (eps 1.5) with one block of eps in
+    [6, 8] over hot = (x0, x1, y0, y1); the quad-tree refines the quadrant
+    that holds it (48-cell cores, 24-cell cores inside), which leaves
+    T-junctions between the refined quadrant and its neighbours."""
+    rng = np.random.default_rng(seed)
+    eps = np.full((n, n), 1.5)
+    x0, x1, y0, y1 = hot
+    eps[y0:y1, x0:x1] = np.kron(rng.uniform(6, 8, ((y1 - y0) // 8, (x1 - x0) // 8)), np.ones((8, 8)))
+    cores = quadtree_cores(n, n, eps, H, min(wavelengths), min_core=max(16, npml + 4), max_core=48)
+    src = [(int(rng.integers(npml + 2, n - npml - 2)), int(rng.integers(npml + 2, n - npml - 2)))
+           for _ in range(n_src)]
+    return Workload(f"quadtree{n}_s{seed}", n, n, eps.astype(np.float32), list(wavelengths), src, [], [],
+                    k_coarse=k_coarse, npml=npml, cores=cores)
+
+
 WORKLOADS = {
     "rect128": small_rectangles,
     "blocks512": blocks_512,
     "blocks1024": blocks_1024,
     "uneven2048": uneven_2048x1536,
+    "quadtree512": quadtree_512,
 }
