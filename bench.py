@@ -35,19 +35,34 @@ PROFILE_PMC = os.path.join(ROOT, "profiles", "bt_solve_blocks512_pmc.txt")
 NN_WEIGHTS = os.path.join(ROOT, "paper_2509_03622_amd", "weights", "fno_c64_m16_l4.bin")
 
 
-def tile_geometry(w):
-    """(lx, ly, core cells) of every extended subdomain, in tile order."""
-    ext = w.overlap // 2
-    out = []
+def core_list(w):
+    """The workload's cores (cx0, cx1, cy0, cy1) in tile order: its explicit list,
+    else the tensor product of core_x and core_y (row-major)."""
+    if w.cores is not None:
+        return [tuple(c) for c in w.cores]
     xs = np.concatenate([[0], np.cumsum(w.core_x)])
     ys = np.concatenate([[0], np.cumsum(w.core_y)])
-    for ty in range(len(w.core_y)):
-        for tx in range(len(w.core_x)):
-            lx = w.core_x[tx] + (ext if tx > 0 else 0) + (ext if tx < len(w.core_x) - 1 else 0)
-            ly = w.core_y[ty] + (ext if ty > 0 else 0) + (ext if ty < len(w.core_y) - 1 else 0)
-            out.append((lx, ly, w.core_x[tx] * w.core_y[ty]))
-    del xs, ys
+    return [(int(xs[tx]), int(xs[tx + 1]), int(ys[ty]), int(ys[ty + 1]))
+            for ty in range(len(w.core_y)) for tx in range(len(w.core_x))]
+
+
+def tile_geometry(w):
+    """(lx, ly, core cells) of every extended subdomain, in tile order: each core
+    grows by overlap/2 across every side that is not on the global boundary."""
+    ext = w.overlap // 2
+    out = []
+    for (cx0, cx1, cy0, cy1) in core_list(w):
+        lx = cx1 - cx0 + (ext if cx0 > 0 else 0) + (ext if cx1 < w.nx else 0)
+        ly = cy1 - cy0 + (ext if cy0 > 0 else 0) + (ext if cy1 < w.ny else 0)
+        out.append((lx, ly, (cx1 - cx0) * (cy1 - cy0)))
     return out
+
+
+def describe_cores(w):
+    sizes = sorted({(c[1] - c[0], c[3] - c[2]) for c in core_list(w)})
+    if w.cores is None:
+        return f"{len(w.core_x)}x{len(w.core_y)} of " + "/".join(str(v) for v in sorted(set(w.core_x + w.core_y)))
+    return f"{len(w.cores)} listed cores (" + ", ".join(f"{a}x{b}" for a, b in sizes) + ")"
 
 
 def local_solve_bytes(lx, ly, core):
@@ -129,13 +144,13 @@ def cpu_baseline(w, iters):
     lam = w.wavelengths[1] if len(w.wavelengths) > 1 else w.wavelengths[0]
     t0 = time.perf_counter()
     P = SchwarzProblem(w.eps, lam, w.h, w.npml, w.core_x, w.core_y, w.overlap, k_coarse=w.k_coarse,
-                       k_trial=w.k_trial)
+                       k_trial=w.k_trial, cores=w.cores)
     setup_s = time.perf_counter() - t0
     b = source_rhs(w.J()[0], lam)
     t0 = time.perf_counter()
     x, it, hist, res = fgmres(lambda u: P.A @ u, b, P.precond, tol=1e-6, restart=30, max_iters=iters)
     dt = time.perf_counter() - t0
-    n_tiles = len(w.core_x) * len(w.core_y)
+    n_tiles = len(core_list(w))
     if lim is not None:
         lim.unregister()
     return {"value": n_tiles * it / dt, "unit": "subdomain solves/s", "cores": 1, "kind": "oracle",
@@ -217,6 +232,10 @@ def main():
                     help="instead of the default line: the paper's Algorithm 3 loop (stationary Robin-data sweeps, "
                          "momentum, Robin-space coarse correction) against the FGMRES form, to 1e-5 on the default "
                          "workload")
+    ap.add_argument("--quadtree-compare", action="store_true",
+                    help="instead of the default line: the 512 x 512 quad-tree workload (64-cell cores in vacuum, "
+                         "32-cell cores over the high-index square) against uniform 64- and 32-cell partitions of "
+                         "the same problem, time to 1e-6")
     ap.add_argument("--nn-compare", action="store_true",
                     help="instead of the default line: exact-LU against NN-FGMRES subdomain solves, time to 1e-6 "
                          "on the 1024 x 1024 workload (16 x 16 subdomains)")
@@ -277,7 +296,8 @@ def main():
         torch.cuda.init()
         w = WORKLOADS[a.workload]()
         ctx = nosdd.Context(0, nosdd.torch_stream_handle())
-        P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+        P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m,
+                          w.pml_lnR, cores=w.cores)
         P.setup(k_coarse=max(w.k_coarse, 1), k_trial=w.k_trial)
         J = torch.from_numpy(w.J()).cuda()
         E = torch.zeros((len(w.wavelengths), len(w.sources), w.ny, w.nx), dtype=torch.complex64, device="cuda")
@@ -306,11 +326,42 @@ def main():
         print(json.dumps({"metric": "time to 1e-5 residual per global solve: Algorithm 3 loop vs FGMRES form",
                           "mode": "paper_vs_fgmres", "n_gpus": 1, "data": "synthetic", "dtype": "c64",
                           "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}",
-                                     "cores": f"{len(w.core_x)}x{len(w.core_y)} of 64", "overlap": w.overlap,
+                                     "cores": describe_cores(w), "overlap": w.overlap,
                                      "wavelengths": w.wavelengths, "k_coarse": max(w.k_coarse, 1), "tol": tol},
                           "rows": rows}), flush=True)
         P.close()
         ctx.close()
+        return
+    if a.quadtree_compare:
+        from paper_2509_03622_amd.workloads import quadtree_512
+        torch.cuda.init()
+        w = quadtree_512()
+        J = torch.from_numpy(w.J()).cuda()
+        rows = []
+        for name, cores, cx in (("quad-tree", w.cores, None), ("uniform 8 x 8 of 64", None, [64] * 8),
+                                ("uniform 16 x 16 of 32", None, [32] * 16)):
+            ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+            P = nosdd.Problem(ctx, w.eps, w.h, w.npml, cx, cx, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR,
+                              cores=cores)
+            t0 = time.perf_counter()
+            P.setup(k_coarse=w.k_coarse, k_trial=w.k_trial)
+            torch.cuda.synchronize()
+            setup_ms = 1e3 * (time.perf_counter() - t0)
+            E = torch.zeros((len(w.wavelengths), 1, w.ny, w.nx), dtype=torch.complex64, device="cuda")
+            dt, iters, fin, st, ms_k = timed_solve(torch, P, J, E, a.max_iters, reps=max(1, a.steps))
+            rows.append({"partition": name, "subdomains": P.sizes()[0], "status": int(st),
+                         "time_to_tol_ms": round(1e3 * dt, 2), "setup_ms": round(setup_ms, 1),
+                         "iterations_per_rhs": iters.ravel().tolist(),
+                         "final_rel_residual": [float(f"{v:.3e}") for v in fin.ravel()],
+                         "kernel_ms": dict(zip(("local_solve", "operator", "arnoldi", "coarse"), ms_k))})
+            print(f"[bench] {rows[-1]}", file=sys.stderr, flush=True)
+            P.close()
+            ctx.close()
+        print(json.dumps({"metric": "time to 1e-6 residual per global solve: quad-tree vs uniform partitions",
+                          "mode": "quadtree_vs_uniform", "n_gpus": 1, "data": "synthetic", "dtype": "c64",
+                          "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "overlap": w.overlap,
+                                     "wavelengths": w.wavelengths, "k_coarse": w.k_coarse, "tol": 1e-6},
+                          "rows": rows}), flush=True)
         return
     if a.nn_compare:
         torch.cuda.init()
@@ -350,7 +401,8 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     ctx = nosdd.Context(0, nosdd.torch_stream_handle())
-    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR,
+                      cores=w.cores)
     t0 = time.perf_counter()
     P.setup(k_coarse=w.k_coarse, k_trial=w.k_trial)
     torch.cuda.synchronize()
@@ -401,7 +453,7 @@ def main():
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_per_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
            "data": "synthetic",
-           "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "cores": f"{len(w.core_x)}x{len(w.core_y)} of 64",
+           "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "cores": describe_cores(w),
                       "overlap": w.overlap, "wavelengths": w.wavelengths, "sources": n_src,
                       "k_coarse": w.k_coarse, "subdomain_solver": "exact LU (block-Thomas)",
                       "restart": 30, "tol": 1e-6},

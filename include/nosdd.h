@@ -123,6 +123,22 @@ const char *nosdd_last_error(const nosdd_ctx *ctx);
 nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *grid, const float *eps,
                                   const nosdd_partition *part, const double *wavelengths,
                                   int n_wl, nosdd_problem **out);
+/* Create a problem over an explicit list of subdomain cores (Methods,
+ * "partitioner": any arrangement of subdomains that covers the domain, for
+ * instance a quad-tree whose quadrants are split while larger than about five
+ * wavelengths).  cores is a host array [n_cores][4] of half-open rectangles
+ * (cx0, cx1, cy0, cy1) in cells (copied); they must cover every cell exactly
+ * once.  Subdomain i is core i extended by overlap/2 cells across every side
+ * that is not on the global boundary, so a side may border several
+ * neighbours (T-junctions).  Same rules as nosdd_problem_create otherwise:
+ * overlap even and >= 2, overlap/2 + 1 <= every core side (with more than one
+ * core), no interface inside the PML of its normal direction, extended
+ * subdomains with an even short side <= 128 cells and a long side <= 256
+ * (NOSDD_EPARTITION otherwise; NOSDD_EINVAL for null pointers, n_cores <= 0
+ * or n_wl <= 0).  Every solve, sweep and set-up call works on it unchanged. */
+nosdd_status nosdd_problem_create_cores(nosdd_ctx *ctx, const nosdd_grid *grid, const float *eps,
+                                        const int *cores, int n_cores, int overlap,
+                                        const double *wavelengths, int n_wl, nosdd_problem **out);
 /* Build every per-wavelength subdomain factorisation, the coarse space and,
  * for sub_solver = 1, load the network.  Must precede any solve. */
 nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *opts);

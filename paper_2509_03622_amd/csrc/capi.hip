@@ -79,14 +79,15 @@ struct nosdd_problem {
     double h = 0.05, lnR = -30.0;
     std::vector<float> eps;
     std::vector<double> wl;
-    std::vector<int> core_x, core_y;
-    int ncx = 0, ncy = 0, overlap = 0, ext = 0;
+    int overlap = 0, ext = 0;
     std::vector<TileDesc> tiles;
+    std::vector<int> owner;                          // [ny][nx]: index of the core holding the cell
+    std::vector<std::vector<int>> nbrs;              // per tile: tiles whose ring reaches into it
     std::vector<std::vector<int4>> tile_entries;     // (p, q, side, 0) linear cell indices
     long long loc_total = 0, dinv_wl_stride = 0;
     int bmax = 0;
     std::vector<std::vector<cd>> coefd;             // per wl: cxm|cxp|cym|cyp
-    DevBuf d_eps, d_coef, d_coefd, d_k0sq, d_k0f, d_k0, d_tiles, d_dinv, d_entries, d_tox, d_toy;
+    DevBuf d_eps, d_coef, d_coefd, d_k0sq, d_k0f, d_k0, d_tiles, d_dinv, d_entries, d_owner;
     DevBuf d_sc;                                   // per wl: centre stretches s_x(nx) | s_y(ny)
     DevBuf adj_E, adj_mu, adj_J, adj_focal, adj_fom; // inverse-design gradient buffers
     int n_entries = 0;
@@ -760,9 +761,9 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
                           wout, p->nx, N, n_rhs, n_src, active, w.cd_.as<double2>());
         launch_coarse_solve(s, p->d_GinvT.as<double2>(), p->n_c, w.cd_.as<double2>(), w.cc_.as<float2>(), n_rhs, n_src,
                             active);
-        launch_coarse_update(s, p->d_tiles.as<TileDesc>(), p->ncx, p->ncy, p->d_tox.as<int>(), p->d_toy.as<int>(),
-                             p->kc, p->d_phi.as<float2>(), p->d_W.as<float2>(), p->box_wl_stride, 0,
-                             w.cc_.as<float2>(), p->n_c, z, wout, p->nx, p->ny, n_rhs, n_src, active);
+        launch_coarse_update(s, p->d_tiles.as<TileDesc>(), p->d_owner.as<int>(), p->kc, p->d_phi.as<float2>(),
+                             p->d_W.as<float2>(), p->box_wl_stride, w.cc_.as<float2>(), p->n_c, z, wout, p->nx, p->ny,
+                             n_rhs, n_src, active);
     }
 }
 
@@ -925,23 +926,17 @@ nosdd_status coarse_setup(nosdd_problem *p) {
             const int Kk = Kt[(size_t)wi * nt + ti];
             std::vector<cd> Y;
             int nrows = 0;
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    if (!dx && !dy) continue;
-                    const int ntx = (ti % p->ncx) + dx, nty = (ti / p->ncx) + dy;
-                    if (ntx < 0 || ntx >= p->ncx || nty < 0 || nty >= p->ncy) continue;
-                    const int tj = nty * p->ncx + ntx;
-                    for (const int4 &e : p->tile_entries[tj]) {
-                        const int px = e.x % nx, py = e.x / nx, qx = e.y % nx, qy = e.y / nx;
-                        if (px < t.x0 || px >= t.x1 || py < t.y0 || py >= t.y1) continue;
-                        if (qx < t.x0 || qx >= t.x1 || qy < t.y0 || qy >= t.y1) continue;
-                        const double kp = k0 * std::sqrt((double)p->eps[e.x]);
-                        for (int l = 0; l < Kk; ++l) {
-                            const cd up = Fv(l, px, py), uq = Fv(l, qx, qy);
-                            Y.push_back((uq - up) / h + cd(0.0, 0.5 * kp) * (uq + up));
-                        }
-                        ++nrows;
+            for (const int tj : p->nbrs[ti])
+                for (const int4 &e : p->tile_entries[tj]) {
+                    const int px = e.x % nx, py = e.x / nx, qx = e.y % nx, qy = e.y / nx;
+                    if (px < t.x0 || px >= t.x1 || py < t.y0 || py >= t.y1) continue;
+                    if (qx < t.x0 || qx >= t.x1 || qy < t.y0 || qy >= t.y1) continue;
+                    const double kp = k0 * std::sqrt((double)p->eps[e.x]);
+                    for (int l = 0; l < Kk; ++l) {
+                        const cd up = Fv(l, px, py), uq = Fv(l, qx, qy);
+                        Y.push_back((uq - up) / h + cd(0.0, 0.5 * kp) * (uq + up));
                     }
+                    ++nrows;
                 }
             // right singular vectors of Y = eigenvectors of Y^H Y, by decreasing eigenvalue
             std::vector<cd> YhY((size_t)Kk * Kk, cd(0, 0));
@@ -1004,25 +999,20 @@ nosdd_status coarse_setup(nosdd_problem *p) {
                         if (!valid || x < t.cx0 || x >= t.cx1 || y < t.cy0 || y >= t.cy1) return cd(0, 0);
                         return phib[(size_t)l * t.bw * t.bh + (size_t)(y - t.by0) * t.bw + (x - t.bx0)];
                     };
-                    for (int dy = -1; dy <= 1; ++dy)
-                        for (int dx = -1; dx <= 1; ++dx) {
-                            if (!dx && !dy) continue;
-                            const int ntx = (ti % p->ncx) + dx, nty = (ti / p->ncx) + dy;
-                            if (ntx < 0 || ntx >= p->ncx || nty < 0 || nty >= p->ncy) continue;
-                            const int tj = nty * p->ncx + ntx;
-                            const TileDesc &u = p->tiles[tj];
-                            const auto &ent = p->tile_entries[tj];
-                            for (int e = 0; e < (int)ent.size(); ++e) {
-                                const int px = ent[e].x % nx, py = ent[e].x / nx, qx = ent[e].y % nx, qy = ent[e].y / nx;
-                                const bool inp = px >= t.cx0 && px < t.cx1 && py >= t.cy0 && py < t.cy1;
-                                const bool inq = qx >= t.cx0 && qx < t.cx1 && qy >= t.cy0 && qy < t.cy1;
-                                if (!inp && !inq) continue;
-                                const cd up = phv(px, py), uq = phv(qx, qy);
-                                const double kp = k0 * std::sqrt((double)p->eps[ent[e].x]);
-                                rcnz[wi].push_back({u.tr_off + e, col, cd(0, 0),
-                                                    (uq - up) / h + cd(0.0, 0.5 * kp) * (uq + up)});
-                            }
+                    for (const int tj : p->nbrs[ti]) {
+                        const TileDesc &u = p->tiles[tj];
+                        const auto &ent = p->tile_entries[tj];
+                        for (int e = 0; e < (int)ent.size(); ++e) {
+                            const int px = ent[e].x % nx, py = ent[e].x / nx, qx = ent[e].y % nx, qy = ent[e].y / nx;
+                            const bool inp = px >= t.cx0 && px < t.cx1 && py >= t.cy0 && py < t.cy1;
+                            const bool inq = qx >= t.cx0 && qx < t.cx1 && qy >= t.cy0 && qy < t.cy1;
+                            if (!inp && !inq) continue;
+                            const cd up = phv(px, py), uq = phv(qx, qy);
+                            const double kp = k0 * std::sqrt((double)p->eps[ent[e].x]);
+                            rcnz[wi].push_back({u.tr_off + e, col, cd(0, 0),
+                                                (uq - up) / h + cd(0.0, 0.5 * kp) * (uq + up)});
                         }
+                    }
                 }
             }
             Wd[(size_t)wi * nt + ti] = std::move(wb);
@@ -1031,9 +1021,10 @@ nosdd_status coarse_setup(nosdd_problem *p) {
         std::vector<cd> G((size_t)nc * nc, cd(0, 0));
         for (int ti = 0; ti < nt; ++ti) {
             const TileDesc &a = p->tiles[ti];
-            for (int tj = 0; tj < nt; ++tj) {
+            std::vector<int> cand = p->nbrs[ti];
+            cand.push_back(ti);
+            for (const int tj : cand) {
                 const TileDesc &bt = p->tiles[tj];
-                if (std::abs(ti % p->ncx - tj % p->ncx) > 1 || std::abs(ti / p->ncx - tj / p->ncx) > 1) continue;
                 const int x0 = std::max(a.bx0, bt.bx0), x1 = std::min(a.bx0 + a.bw, bt.bx0 + bt.bw);
                 const int y0 = std::max(a.by0, bt.by0), y1 = std::min(a.by0 + a.bh, bt.by0 + bt.bh);
                 if (x0 >= x1 || y0 >= y1) continue;
@@ -1136,19 +1127,8 @@ nosdd_status coarse_setup(nosdd_problem *p) {
     HIPCHK(ctx, hipMemcpyAsync(p->d_W.p, W_h.data(), W_h.size() * sizeof(float2), hipMemcpyHostToDevice, s));
     HIPCHK(ctx, hipMemcpyAsync(p->d_GinvT.p, ginv_dev.data(), ginv_dev.size() * sizeof(double2), hipMemcpyHostToDevice,
                                s));
-    std::vector<int> tox(nx), toy(ny);
-    for (int i = 0, acc = 0; i < p->ncx; ++i) {
-        for (int x = 0; x < p->core_x[i]; ++x) tox[acc + x] = i;
-        acc += p->core_x[i];
-    }
-    for (int i = 0, acc = 0; i < p->ncy; ++i) {
-        for (int y = 0; y < p->core_y[i]; ++y) toy[acc + y] = i;
-        acc += p->core_y[i];
-    }
-    HIPCHK(ctx, p->d_tox.ensure(nx * sizeof(int)));
-    HIPCHK(ctx, p->d_toy.ensure(ny * sizeof(int)));
-    HIPCHK(ctx, hipMemcpyAsync(p->d_tox.p, tox.data(), nx * sizeof(int), hipMemcpyHostToDevice, s));
-    HIPCHK(ctx, hipMemcpyAsync(p->d_toy.p, toy.data(), ny * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, p->d_owner.ensure(p->owner.size() * sizeof(int)));
+    HIPCHK(ctx, hipMemcpyAsync(p->d_owner.p, p->owner.data(), p->owner.size() * sizeof(int), hipMemcpyHostToDevice, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     return NOSDD_OK;
 }
@@ -1550,100 +1530,108 @@ const char *nosdd_last_error(const nosdd_ctx *ctx) {
     return ctx->err.c_str();
 }
 
-nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const float *eps, const nosdd_partition *part,
-                                  const double *wavelengths, int n_wl, nosdd_problem **out) {
-    if (!ctx) return NOSDD_EINVAL;
-    if (!out || !g || !eps || !part || !wavelengths || n_wl <= 0) return fail(ctx, NOSDD_EINVAL, "null argument or n_wl <= 0");
-    *out = nullptr;
+// Problem over an explicit list of cores (cx0, cx1, cy0, cy1), half-open,
+// that covers every cell once: each core is extended by overlap/2 across every
+// side that is not on the global boundary.  Shared by the tensor-product
+// partition and the general (e.g. quad-tree) one.
+static nosdd_status problem_create_impl(nosdd_ctx *ctx, const nosdd_grid *g, const float *eps,
+                                        const std::vector<int4> &cores, int overlap, const double *wavelengths,
+                                        int n_wl, nosdd_problem **out) {
     if (g->nx < 4 || g->ny < 4 || !(g->h > 0) || g->npml < 0 || 2 * g->npml >= std::min(g->nx, g->ny) || g->pml_m < 0)
         return fail(ctx, NOSDD_EINVAL, "invalid grid");
     for (int i = 0; i < n_wl; ++i)
         if (!(wavelengths[i] > 0)) return fail(ctx, NOSDD_EINVAL, "wavelengths must be positive");
-    if (!part->core_x || !part->core_y || part->ncx <= 0 || part->ncy <= 0)
-        return fail(ctx, NOSDD_EPARTITION, "empty partition");
-    if (part->overlap < 2 || part->overlap % 2) return fail(ctx, NOSDD_EPARTITION, "overlap must be even and >= 2");
-    long long sx = 0, sy = 0;
+    if (cores.empty()) return fail(ctx, NOSDD_EPARTITION, "empty partition");
+    if (overlap < 2 || overlap % 2) return fail(ctx, NOSDD_EPARTITION, "overlap must be even and >= 2");
+    const int ext = overlap / 2;
+    const int gnx = g->nx, gny = g->ny;
+    std::vector<int> owner((size_t)gnx * gny, -1);
     int minc = 1 << 30;
-    for (int i = 0; i < part->ncx; ++i) {
-        if (part->core_x[i] <= 0) return fail(ctx, NOSDD_EPARTITION, "core sizes must be positive");
-        sx += part->core_x[i];
-        minc = std::min(minc, part->core_x[i]);
+    for (int k = 0; k < (int)cores.size(); ++k) {
+        const int4 c = cores[k];
+        if (!(0 <= c.x && c.x < c.y && c.y <= gnx && 0 <= c.z && c.z < c.w && c.w <= gny))
+            return fail(ctx, NOSDD_EPARTITION, "a core is empty or leaves the grid");
+        for (int y = c.z; y < c.w; ++y)
+            for (int x = c.x; x < c.y; ++x) {
+                int &o = owner[(size_t)y * gnx + x];
+                if (o >= 0) return fail(ctx, NOSDD_EPARTITION, "cores overlap");
+                o = k;
+            }
+        minc = std::min(minc, std::min(c.y - c.x, c.w - c.z));
     }
-    for (int i = 0; i < part->ncy; ++i) {
-        if (part->core_y[i] <= 0) return fail(ctx, NOSDD_EPARTITION, "core sizes must be positive");
-        sy += part->core_y[i];
-        minc = std::min(minc, part->core_y[i]);
-    }
-    if (sx != g->nx || sy != g->ny) return fail(ctx, NOSDD_EPARTITION, "core sizes must sum to the grid size");
-    const int ext = part->overlap / 2;
-    const int ntile = part->ncx * part->ncy;
-    if (ntile > 1 && ext + 1 > minc) return fail(ctx, NOSDD_EPARTITION, "overlap/2 + 1 exceeds a core");
-    for (int i = 0; i < g->nx * g->ny; ++i)
+    for (const int o : owner)
+        if (o < 0) return fail(ctx, NOSDD_EPARTITION, "cores do not cover the grid");
+    if (cores.size() > 1 && ext + 1 > minc) return fail(ctx, NOSDD_EPARTITION, "overlap/2 + 1 exceeds a core");
+    for (int i = 0; i < gnx * gny; ++i)
         if (!(std::isfinite(eps[i]))) return fail(ctx, NOSDD_EINVAL, "eps must be finite");
 
     nosdd_problem *p = new nosdd_problem();
     p->ctx = ctx;
-    p->nx = g->nx;
-    p->ny = g->ny;
+    p->nx = gnx;
+    p->ny = gny;
     p->h = g->h;
     p->npml = g->npml;
     p->pml_m = g->pml_m;
     p->lnR = g->pml_lnR;
-    p->eps.assign(eps, eps + (size_t)g->nx * g->ny);
+    p->eps.assign(eps, eps + (size_t)gnx * gny);
     p->wl.assign(wavelengths, wavelengths + n_wl);
-    p->core_x.assign(part->core_x, part->core_x + part->ncx);
-    p->core_y.assign(part->core_y, part->core_y + part->ncy);
-    p->ncx = part->ncx;
-    p->ncy = part->ncy;
-    p->overlap = part->overlap;
+    p->overlap = overlap;
     p->ext = ext;
+    p->owner = std::move(owner);
     // tiles
     long long loc = 0, dinv = 0;
-    int cy = 0;
-    for (int ty = 0; ty < p->ncy; ++ty) {
-        int cx = 0;
-        for (int tx = 0; tx < p->ncx; ++tx) {
-            TileDesc t{};
-            t.cx0 = cx;
-            t.cx1 = cx + p->core_x[tx];
-            t.cy0 = cy;
-            t.cy1 = cy + p->core_y[ty];
-            t.iface = (ty > 0 ? SIDE_BOTTOM : 0) | (tx < p->ncx - 1 ? SIDE_RIGHT : 0) |
-                      (ty < p->ncy - 1 ? SIDE_TOP : 0) | (tx > 0 ? SIDE_LEFT : 0);
-            t.x0 = (t.iface & SIDE_LEFT) ? t.cx0 - ext : t.cx0;
-            t.x1 = (t.iface & SIDE_RIGHT) ? t.cx1 + ext : t.cx1;
-            t.y0 = (t.iface & SIDE_BOTTOM) ? t.cy0 - ext : t.cy0;
-            t.y1 = (t.iface & SIDE_TOP) ? t.cy1 + ext : t.cy1;
-            const int n = p->npml;
-            auto bad_x = [&](int xb) { return xb < n || xb > p->nx - n - 1; };
-            auto bad_y = [&](int yb) { return yb < n || yb > p->ny - n - 1; };
-            if (((t.iface & SIDE_LEFT) && bad_x(t.x0)) || ((t.iface & SIDE_RIGHT) && bad_x(t.x1 - 1)) ||
-                ((t.iface & SIDE_BOTTOM) && bad_y(t.y0)) || ((t.iface & SIDE_TOP) && bad_y(t.y1 - 1))) {
-                delete p;
-                return fail(ctx, NOSDD_EPARTITION, "a subdomain interface lies inside the PML of its normal direction");
-            }
-            const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
-            t.tr = lx > ly ? 1 : 0;
-            t.b = std::min(lx, ly);
-            t.nb = std::max(lx, ly);
-            if (t.b % 2 || t.b > BT_FACT_SCRATCH_B) {
-                delete p;
-                return fail(ctx, NOSDD_EPARTITION, "extended subdomains need an even short side of at most 128 cells");
-            }
-            if (t.nb > BT_NBMAX || lx * ly > BT_LDS_MAX_CELLS) {
-                delete p;
-                return fail(ctx, NOSDD_EPARTITION, "an extended subdomain is too large for an LDS-resident solve");
-            }
-            p->max_cells = std::max(p->max_cells, lx * ly);
-            t.loc_off = loc;
-            loc += (long long)lx * ly;
-            t.dinv_off = dinv;
-            dinv += (long long)t.nb * bt_sym_block(t.b);
-            p->bmax = std::max(p->bmax, t.b);
-            p->tiles.push_back(t);
-            cx += p->core_x[tx];
+    for (const int4 &c : cores) {
+        TileDesc t{};
+        t.cx0 = c.x;
+        t.cx1 = c.y;
+        t.cy0 = c.z;
+        t.cy1 = c.w;
+        t.iface = (t.cy0 > 0 ? SIDE_BOTTOM : 0) | (t.cx1 < gnx ? SIDE_RIGHT : 0) | (t.cy1 < gny ? SIDE_TOP : 0) |
+                  (t.cx0 > 0 ? SIDE_LEFT : 0);
+        t.x0 = (t.iface & SIDE_LEFT) ? t.cx0 - ext : t.cx0;
+        t.x1 = (t.iface & SIDE_RIGHT) ? t.cx1 + ext : t.cx1;
+        t.y0 = (t.iface & SIDE_BOTTOM) ? t.cy0 - ext : t.cy0;
+        t.y1 = (t.iface & SIDE_TOP) ? t.cy1 + ext : t.cy1;
+        const int n = p->npml;
+        auto bad_x = [&](int xb) { return xb < n || xb > p->nx - n - 1; };
+        auto bad_y = [&](int yb) { return yb < n || yb > p->ny - n - 1; };
+        if (((t.iface & SIDE_LEFT) && bad_x(t.x0)) || ((t.iface & SIDE_RIGHT) && bad_x(t.x1 - 1)) ||
+            ((t.iface & SIDE_BOTTOM) && bad_y(t.y0)) || ((t.iface & SIDE_TOP) && bad_y(t.y1 - 1))) {
+            delete p;
+            return fail(ctx, NOSDD_EPARTITION, "a subdomain interface lies inside the PML of its normal direction");
         }
-        cy += p->core_y[ty];
+        const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
+        t.tr = lx > ly ? 1 : 0;
+        t.b = std::min(lx, ly);
+        t.nb = std::max(lx, ly);
+        if (t.b % 2 || t.b > BT_FACT_SCRATCH_B) {
+            delete p;
+            return fail(ctx, NOSDD_EPARTITION, "extended subdomains need an even short side of at most 128 cells");
+        }
+        if (t.nb > BT_NBMAX || lx * ly > BT_LDS_MAX_CELLS) {
+            delete p;
+            return fail(ctx, NOSDD_EPARTITION, "an extended subdomain is too large for an LDS-resident solve");
+        }
+        p->max_cells = std::max(p->max_cells, lx * ly);
+        t.loc_off = loc;
+        loc += (long long)lx * ly;
+        t.dinv_off = dinv;
+        dinv += (long long)t.nb * bt_sym_block(t.b);
+        p->bmax = std::max(p->bmax, t.b);
+        p->tiles.push_back(t);
+    }
+    // neighbours: tiles whose extended rectangle grown by one cell (the ghost
+    // nodes of its ring) meets this tile's, in index order; every interface
+    // entry that touches a tile belongs to one of them
+    const int nt = (int)p->tiles.size();
+    p->nbrs.assign(nt, {});
+    for (int i = 0; i < nt; ++i) {
+        const TileDesc &t = p->tiles[i];
+        for (int j = 0; j < nt; ++j) {
+            const TileDesc &u = p->tiles[j];
+            if (j != i && u.x0 - 1 < t.x1 && t.x0 < u.x1 + 1 && u.y0 - 1 < t.y1 && t.y0 < u.y1 + 1)
+                p->nbrs[i].push_back(j);
+        }
     }
     p->loc_total = loc;
     p->dinv_wl_stride = dinv;
@@ -1714,6 +1702,42 @@ nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const flo
     }
     *out = p;
     return NOSDD_OK;
+}
+
+nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *g, const float *eps, const nosdd_partition *part,
+                                  const double *wavelengths, int n_wl, nosdd_problem **out) {
+    if (!ctx) return NOSDD_EINVAL;
+    if (!out || !g || !eps || !part || !wavelengths || n_wl <= 0) return fail(ctx, NOSDD_EINVAL, "null argument or n_wl <= 0");
+    *out = nullptr;
+    if (!part->core_x || !part->core_y || part->ncx <= 0 || part->ncy <= 0)
+        return fail(ctx, NOSDD_EPARTITION, "empty partition");
+    long long sx = 0, sy = 0;
+    for (int i = 0; i < part->ncx; ++i) {
+        if (part->core_x[i] <= 0) return fail(ctx, NOSDD_EPARTITION, "core sizes must be positive");
+        sx += part->core_x[i];
+    }
+    for (int i = 0; i < part->ncy; ++i) {
+        if (part->core_y[i] <= 0) return fail(ctx, NOSDD_EPARTITION, "core sizes must be positive");
+        sy += part->core_y[i];
+    }
+    if (sx != g->nx || sy != g->ny) return fail(ctx, NOSDD_EPARTITION, "core sizes must sum to the grid size");
+    std::vector<int4> cores;
+    for (int ty = 0, cy = 0; ty < part->ncy; cy += part->core_y[ty++])
+        for (int tx = 0, cx = 0; tx < part->ncx; cx += part->core_x[tx++])
+            cores.push_back(make_int4(cx, cx + part->core_x[tx], cy, cy + part->core_y[ty]));
+    return problem_create_impl(ctx, g, eps, cores, part->overlap, wavelengths, n_wl, out);
+}
+
+nosdd_status nosdd_problem_create_cores(nosdd_ctx *ctx, const nosdd_grid *g, const float *eps, const int *cores,
+                                        int n_cores, int overlap, const double *wavelengths, int n_wl,
+                                        nosdd_problem **out) {
+    if (!ctx) return NOSDD_EINVAL;
+    if (!out || !g || !eps || !cores || !wavelengths || n_wl <= 0 || n_cores <= 0)
+        return fail(ctx, NOSDD_EINVAL, "null argument, n_cores <= 0 or n_wl <= 0");
+    *out = nullptr;
+    std::vector<int4> cv((size_t)n_cores);
+    for (int k = 0; k < n_cores; ++k) cv[k] = make_int4(cores[4 * k], cores[4 * k + 1], cores[4 * k + 2], cores[4 * k + 3]);
+    return problem_create_impl(ctx, g, eps, cv, overlap, wavelengths, n_wl, out);
 }
 
 nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {

@@ -109,10 +109,13 @@ __device__ __forceinline__ float2 box_sum(const TileDesc &t, const float2 *base,
     return s;
 }
 
-// z += Phi c (owner core), w += W c (owner box and the four side neighbours' boxes)
-__global__ __launch_bounds__(256) void coarse_update_kernel(const TileDesc *__restrict__ tiles, int ncx, int ncy,
-                                                            const int *__restrict__ tile_of_x,
-                                                            const int *__restrict__ tile_of_y, int kc,
+// z += Phi c (owner core), w += W c (owner box and the boxes of the cores
+// across each side of the cell: W = A Phi vanishes on a box's corner cells,
+// so only the owners of the four side neighbours can contribute, and they
+// are distinct from each other and from the cell's own core).  owner[y][x]
+// is the index of the core holding (x, y), for any arrangement of cores.
+__global__ __launch_bounds__(256) void coarse_update_kernel(const TileDesc *__restrict__ tiles,
+                                                            const int *__restrict__ owner, int kc,
                                                             const float2 *__restrict__ Phibox,
                                                             const float2 *__restrict__ Wbox, long long wl_stride,
                                                             const float2 *__restrict__ c, int n_c, float2 *__restrict__ z,
@@ -124,42 +127,40 @@ __global__ __launch_bounds__(256) void coarse_update_kernel(const TileDesc *__re
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x >= nx || y >= ny) return;
-    const int tx = tile_of_x[x], ty = tile_of_y[y];
-    const TileDesc t = tiles[ty * ncx + tx];
+    const long long cell = (long long)y * nx + x;
+    const int own = owner[cell];
+    const TileDesc t = tiles[own];
     const float2 *cr = c + (long long)r * n_c;
     const float2 *Pb = Phibox + wl * wl_stride;
     const float2 *Wb = Wbox + wl * wl_stride;
-    const long long g = (long long)r * nx * ny + (long long)y * nx + x;
-    const int own = ty * ncx + tx;
+    const long long g = (long long)r * nx * ny + cell;
     z[g] = cadd(z[g], box_sum(t, Pb, kc, cr + own * kc, x, y));
     float2 acc = box_sum(t, Wb, kc, cr + own * kc, x, y);
-    if (x == t.cx0 && tx > 0) {
-        const int nb = ty * ncx + tx - 1;
+    if (x == t.cx0 && x > 0) {
+        const int nb = owner[cell - 1];
         acc = cadd(acc, box_sum(tiles[nb], Wb, kc, cr + nb * kc, x, y));
     }
-    if (x == t.cx1 - 1 && tx + 1 < ncx) {
-        const int nb = ty * ncx + tx + 1;
+    if (x == t.cx1 - 1 && x + 1 < nx) {
+        const int nb = owner[cell + 1];
         acc = cadd(acc, box_sum(tiles[nb], Wb, kc, cr + nb * kc, x, y));
     }
-    if (y == t.cy0 && ty > 0) {
-        const int nb = (ty - 1) * ncx + tx;
+    if (y == t.cy0 && y > 0) {
+        const int nb = owner[cell - nx];
         acc = cadd(acc, box_sum(tiles[nb], Wb, kc, cr + nb * kc, x, y));
     }
-    if (y == t.cy1 - 1 && ty + 1 < ncy) {
-        const int nb = (ty + 1) * ncx + tx;
+    if (y == t.cy1 - 1 && y + 1 < ny) {
+        const int nb = owner[cell + nx];
         acc = cadd(acc, box_sum(tiles[nb], Wb, kc, cr + nb * kc, x, y));
     }
     w[g] = cadd(w[g], acc);
 }
 
-void launch_coarse_update(hipStream_t s, const TileDesc *tiles, int ncx, int ncy, const int *tile_of_x,
-                          const int *tile_of_y, int kc, const float2 *Phibox, const float2 *Wbox,
-                          long long box_wl_stride, long long box_total, const float2 *c, int n_c, float2 *z, float2 *w,
+void launch_coarse_update(hipStream_t s, const TileDesc *tiles, const int *owner, int kc, const float2 *Phibox,
+                          const float2 *Wbox, long long box_wl_stride, const float2 *c, int n_c, float2 *z, float2 *w,
                           int nx, int ny, int n_rhs, int n_src, const int *active) {
-    (void)box_total;
     dim3 grid((nx + 63) / 64, (ny + 3) / 4, n_rhs);
-    hipLaunchKernelGGL(coarse_update_kernel, grid, dim3(64, 4), 0, s, tiles, ncx, ncy, tile_of_x, tile_of_y, kc, Phibox,
-                       Wbox, box_wl_stride, c, n_c, z, w, nx, ny, n_src, active);
+    hipLaunchKernelGGL(coarse_update_kernel, grid, dim3(64, 4), 0, s, tiles, owner, kc, Phibox, Wbox, box_wl_stride,
+                       c, n_c, z, w, nx, ny, n_src, active);
 }
 
 }  // namespace nosdd

@@ -200,10 +200,9 @@ void launch_coarse_dot(hipStream_t s, const TileDesc *tiles, int n_c, int kc, co
                        int n_src, const int *active, double2 *d);
 void launch_coarse_solve(hipStream_t s, const double2 *GinvT, int n_c, const double2 *d, float2 *c, int n_rhs,
                          int n_src, const int *active);
-void launch_coarse_update(hipStream_t s, const TileDesc *tiles, int ncx, int ncy, const int *tile_of_x,
-                          const int *tile_of_y, int kc, const float2 *Phibox, const float2 *Wbox,
-                          long long box_wl_stride, long long box_total, const float2 *c, int n_c, float2 *z,
-                          float2 *w, int nx, int ny, int n_rhs, int n_src, const int *active);
+void launch_coarse_update(hipStream_t s, const TileDesc *tiles, const int *owner, int kc, const float2 *Phibox,
+                          const float2 *Wbox, long long box_wl_stride, const float2 *c, int n_c, float2 *z, float2 *w,
+                          int nx, int ny, int n_rhs, int n_src, const int *active);
 
 // ------------------------------------------------------------ neural subdomain solver
 // One sample = one (subdomain, RHS) pair: tile geometry and where its vectors live.

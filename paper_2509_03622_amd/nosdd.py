@@ -19,6 +19,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -
           -5: "EBREAKDOWN", -6: "ENONFINITE", -7: "ENOWEIGHTS", -8: "ESTATE"}
 
 EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_problem_create",
+           "nosdd_problem_create_cores",
            "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device", "nosdd_solve_device_c64", "nosdd_solve_paper_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
@@ -72,6 +73,7 @@ def load(path=LIBPATH):
         "nosdd_ctx_destroy": (None, [vp]),
         "nosdd_last_error": (C.c_char_p, [vp]),
         "nosdd_problem_create": (i, [vp, C.POINTER(Grid), vp, C.POINTER(PartitionSpec), vp, i, C.POINTER(vp)]),
+        "nosdd_problem_create_cores": (i, [vp, C.POINTER(Grid), vp, vp, i, i, vp, i, C.POINTER(vp)]),
         "nosdd_problem_setup": (i, [vp, C.POINTER(SetupOpts)]),
         "nosdd_problem_destroy": (None, [vp]),
         "nosdd_solve": (i, [vp, vp, i, C.POINTER(SolveOpts), vp, vp, vp, vp]),
@@ -152,19 +154,28 @@ class Context:
 class Problem:
     """A grid, permittivity map, partition and wavelength set (one operator per wavelength)."""
 
-    def __init__(self, ctx: Context, eps, h, npml, core_x, core_y, overlap, wavelengths, pml_m=2, pml_lnR=-30.0):
+    def __init__(self, ctx: Context, eps, h, npml, core_x, core_y, overlap, wavelengths, pml_m=2, pml_lnR=-30.0,
+                 cores=None):
+        """core_x, core_y: tensor-product partition; or cores: an explicit list of
+        (cx0, cx1, cy0, cy1) rectangles covering the grid (core_x, core_y ignored)."""
         self.ctx, self.L = ctx, ctx.L
         eps = np.ascontiguousarray(eps, dtype=np.float32)
         self.ny, self.nx = eps.shape
         self.wavelengths = [float(w) for w in wavelengths]
         g = Grid(self.nx, self.ny, float(h), int(npml), int(pml_m), float(pml_lnR))
-        cx = (C.c_int * len(core_x))(*core_x)
-        cy = (C.c_int * len(core_y))(*core_y)
-        part = PartitionSpec(cx, len(core_x), cy, len(core_y), int(overlap))
         wl = np.ascontiguousarray(self.wavelengths, dtype=np.float64)
         hp = C.c_void_p()
-        ctx.check(self.L.nosdd_problem_create(ctx.h, C.byref(g), eps.ctypes.data, C.byref(part), wl.ctypes.data,
-                                              len(wl), C.byref(hp)))
+        if cores is not None:
+            cv = np.ascontiguousarray(np.asarray(cores, dtype=np.int32).reshape(-1, 4))
+            ctx.check(self.L.nosdd_problem_create_cores(ctx.h, C.byref(g), eps.ctypes.data, cv.ctypes.data,
+                                                        cv.shape[0], int(overlap), wl.ctypes.data, len(wl),
+                                                        C.byref(hp)))
+        else:
+            cx = (C.c_int * len(core_x))(*core_x)
+            cy = (C.c_int * len(core_y))(*core_y)
+            part = PartitionSpec(cx, len(core_x), cy, len(core_y), int(overlap))
+            ctx.check(self.L.nosdd_problem_create(ctx.h, C.byref(g), eps.ctypes.data, C.byref(part),
+                                                  wl.ctypes.data, len(wl), C.byref(hp)))
         self.h = hp
         self.n_wl = len(wl)
         ctx._problems.add(self)

@@ -17,7 +17,8 @@ def make_gpu_problem(w: Workload, k_coarse=None, k_trial=None):
     import torch
     from paper_2509_03622_amd import nosdd
     ctx = nosdd.Context(0, nosdd.torch_stream_handle())
-    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+    P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR,
+                      cores=w.cores)
     P.setup(k_coarse=w.k_coarse if k_coarse is None else k_coarse, k_trial=k_trial or w.k_trial)
     torch.cuda.synchronize()
     return ctx, P
