@@ -176,7 +176,7 @@ def timed_solve(torch, P, J, E, max_iters, reps=1):
     return dt, iters, fin, st, [round(float(v) / reps, 2) for v in ms_k]
 
 
-def nn_compare(torch, nosdd, workload, configs, max_iters):
+def nn_compare(torch, nosdd, workload, configs, max_iters, weights=NN_WEIGHTS):
     """Time to a 1e-6 residual of the exact-LU form and of the NN-FGMRES form
     (BF16 network inside FP32 inner FGMRES) on the same problem and GPU."""
     from paper_2509_03622_amd.workloads import WORKLOADS
@@ -192,7 +192,7 @@ def nn_compare(torch, nosdd, workload, configs, max_iters):
         if solver == "lu":
             P.setup(k_coarse=kc, k_trial=w.k_trial)
         else:
-            P.setup(k_coarse=kc, k_trial=w.k_trial, sub_solver=1, nn_weights=NN_WEIGHTS, inner_max=steps,
+            P.setup(k_coarse=kc, k_trial=w.k_trial, sub_solver=1, nn_weights=weights, inner_max=steps,
                     inner_tol=tol)
         torch.cuda.synchronize()
         setup_ms = 1e3 * (time.perf_counter() - t0)
@@ -239,6 +239,9 @@ def main():
     ap.add_argument("--nn-compare", action="store_true",
                     help="instead of the default line: exact-LU against NN-FGMRES subdomain solves, time to 1e-6 "
                          "on the 1024 x 1024 workload (16 x 16 subdomains)")
+    ap.add_argument("--weights", default=NN_WEIGHTS, help="--nn-compare: network weights file")
+    ap.add_argument("--nn-quick", action="store_true",
+                    help="--nn-compare: only exact LU and two NN-FGMRES settings, all with one coarse function")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
@@ -365,17 +368,21 @@ def main():
         return
     if a.nn_compare:
         torch.cuda.init()
-        configs = [(kc, "lu", 0, 0.0) for kc in (0, 1)]
-        configs += [(kc, "nn", n, t) for kc in (1, 0) for n, t in ((1, 0.1), (2, 0.1), (4, 0.1), (4, 0.01),
-                                                                 (8, 0.01))]
-        w, rows = nn_compare(torch, nosdd, "blocks1024", configs, max_iters=3000)
+        if a.nn_quick:
+            configs = [(1, "lu", 0, 0.0), (1, "nn", 2, 0.1), (1, "nn", 4, 0.01)]
+        else:
+            configs = [(kc, "lu", 0, 0.0) for kc in (0, 1)]
+            configs += [(kc, "nn", n, t) for kc in (1, 0) for n, t in ((1, 0.1), (2, 0.1), (4, 0.1), (4, 0.01),
+                                                                     (8, 0.01))]
+        w, rows = nn_compare(torch, nosdd, "blocks1024", configs, max_iters=3000, weights=a.weights)
         lu = min((r for r in rows if r["solver"] == "lu" and r["status"] == 0), key=lambda r: r["time_to_tol_ms"])
         nn = [r for r in rows if r["solver"] == "nn" and r["status"] == 0]
         best = min(nn, key=lambda r: r["time_to_tol_ms"]) if nn else None
         print(json.dumps({"metric": METRIC, "mode": "nn_vs_lu", "n_gpus": 1, "data": "synthetic",
                           "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "cores": "16x16 of 64",
                                      "overlap": w.overlap, "wavelengths": w.wavelengths, "tol": 1e-6,
-                                     "network": "FNO C=64, 16 modes, 4 layers, BF16 MFMA, FP32 accumulation"},
+                                     "network": "FNO C=64, 16 modes, 4 layers, BF16 MFMA, FP32 accumulation",
+                                     "weights": os.path.basename(a.weights)},
                           "best_lu_ms": lu["time_to_tol_ms"],
                           "best_nn_ms": best["time_to_tol_ms"] if best else None,
                           "nn_over_lu_time": round(best["time_to_tol_ms"] / lu["time_to_tol_ms"], 3) if best else None,

@@ -7,6 +7,15 @@ c_r ||b - B x_j||^2 + c_d ||x_j - y||^2 (relative, per sample) is
 back-propagated and the optimizer steps, then the Krylov quantities (basis,
 preconditioned directions, Hessenberg entries) are detached.
 
+``--scheme fixed-point`` trains with the fixed-point recurrence instead
+(Algorithm 2): from x = 0, N times e = M(r), x <- x + e, r = b - B x, the
+same loss, an optimizer step, and the residual fed to the next step is
+detached and clipped.  Clipping reading: every complex entry of r whose
+magnitude exceeds th_clip * rms(b) (per sample) is scaled down to that
+magnitude with its phase kept; the fixed-point recurrence diverges on these
+indefinite problems while the network is still poor, and the clip bounds
+what it is fed.
+
 The data are exactly solved subdomain problems written by the oracle's
 training-set script (an .npz of eps, wavelength, right-hand side and solution
 per subdomain position of a 3 x 3 partition of a 192 x 192 grid, cores of 64,
@@ -27,6 +36,7 @@ lift_w[C][9], lift_b[C], per layer R_re[2m][m][C][C], R_im[2m][m][C][C],
 W[C][C], b[C], then proj1_w[128][C], proj1_b[128], proj2_w[2][128], proj2_b[2].
 
 Usage: python -m paper_2509_03622_amd.fno_train --data tiles.npz --out weights.bin [--minutes 15]
+       [--scheme fixed-point --clip 4]
 """
 from __future__ import annotations
 
@@ -207,6 +217,31 @@ def write_weights(model, path):
             f.write(bf16_bits(p).tobytes())
 
 
+def read_weights(model, path):
+    """Load a weights file written by write_weights into a model of the same shape."""
+    import torch
+    with open(path, "rb") as f:
+        if f.read(8) != MAGIC:
+            raise ValueError(f"{path}: not a weights file")
+        ver, C, m, L, in_ch, hidden, dt = struct.unpack("<7i", f.read(28))
+        if (ver, C, m, L, in_ch, hidden, dt) != (1, model.C, model.m, model.L, IN_CH, HIDDEN, 1):
+            raise ValueError(f"{path}: header {(ver, C, m, L, in_ch, hidden, dt)} does not match the model")
+        raw = np.frombuffer(f.read(), dtype=np.uint16)
+    params = [model.lift_w, model.lift_b]
+    for l in range(model.L):
+        params += [model.Rr[l], model.Ri[l], model.W[l], model.b[l]]
+    params += [model.p1w, model.p1b, model.p2w, model.p2b]
+    off = 0
+    with torch.no_grad():
+        for p in params:
+            n = p.numel()
+            vals = (raw[off:off + n].astype(np.uint32) << 16).view(np.float32).reshape(tuple(p.shape))
+            p.copy_(torch.from_numpy(vals.copy()))
+            off += n
+    if off != raw.size:
+        raise ValueError(f"{path}: {raw.size - off} trailing values")
+
+
 def round_model_to_bf16(model):
     import torch
     with torch.no_grad():
@@ -291,6 +326,40 @@ def fgmres_train_step(model, opt, coef, aux, b, y, N, c_r=1.0, c_d=0.1):
     return hist
 
 
+def clip_residual(r, b, th_clip):
+    """Entries of r with |r| > th_clip * rms(b) (per sample) scaled to that magnitude, phase kept."""
+    import torch
+    rms = torch.sqrt(torch.mean(torch.abs(b) ** 2, dim=(-1, -2)))
+    lim = (th_clip * rms)[:, None, None]
+    mag = torch.abs(r)
+    scale = torch.where(mag > lim, lim / torch.clamp(mag, min=torch.finfo(mag.dtype).tiny), torch.ones_like(mag))
+    return r * scale
+
+
+def fixed_point_train_step(model, opt, coef, aux, b, y, N, th_clip, c_r=1.0, c_d=0.1):
+    """One batch of the fixed-point training (Algorithm 2); returns per-step relative residuals."""
+    import torch
+    nrm = lambda a: torch.sqrt(torch.sum(torch.abs(a) ** 2, dim=(-1, -2)))
+    bn = nrm(b)
+    yn = nrm(y)
+    x = torch.zeros_like(b)
+    r = b
+    hist = []
+    for j in range(N):
+        opt.zero_grad(set_to_none=True)
+        x = x + model(r, aux)                 # earlier updates carry no graph (detached below)
+        res = b - apply_op(coef, x)
+        rel_r = nrm(res) / bn
+        loss = c_r * torch.mean(rel_r ** 2) + c_d * torch.mean((nrm(x - y) / yn) ** 2)
+        loss.backward()
+        torch.nn.utils.clip_grad_norm_(model.parameters(), 1.0)
+        opt.step()
+        hist.append(rel_r.detach().mean().item())
+        x = x.detach()
+        r = clip_residual(res.detach(), b, th_clip)
+    return hist
+
+
 def evaluate(model, data, rng, steps=30, n=32):
     """NN-FGMRES on held-out samples: residual after step 1, and steps to 1e-6 (float32)."""
     import torch
@@ -327,6 +396,21 @@ def evaluate(model, data, rng, steps=30, n=32):
     return float(np.median(res[0])), float(np.median(first)), res
 
 
+def evaluate_many(model, data, seed, batches=8, n=32, steps=30):
+    """evaluate() over several held-out batches drawn from a fixed seed, pooled:
+    median residual after 1, 2, 4, 8 and 16 NN-FGMRES steps, and the median
+    number of steps to 1e-3 and to 1e-5 (steps + 1 when not reached)."""
+    rng = np.random.default_rng(seed)
+    res = np.concatenate([evaluate(model, data, rng, steps, n)[2] for _ in range(batches)], axis=1)
+    out = {"samples": res.shape[1]}
+    for k in (1, 2, 4, 8, 16):
+        out[f"res_after_{k}"] = float(np.median(res[k - 1]))
+    for t in (1e-3, 1e-5):
+        below = res <= t
+        out[f"steps_to_{t:g}"] = float(np.median(np.where(below.any(0), below.argmax(0) + 1, steps + 1)))
+    return out
+
+
 def main():
     import torch
     ap = argparse.ArgumentParser()
@@ -340,11 +424,24 @@ def main():
     ap.add_argument("--modes", type=int, default=16)
     ap.add_argument("--layers", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--scheme", choices=("fgmres", "fixed-point"), default="fgmres",
+                    help="recurrent FGMRES training (Algorithm 1) or fixed-point training with clipping (Algorithm 2)")
+    ap.add_argument("--clip", type=float, default=4.0,
+                    help="fixed-point scheme: clip threshold th_clip, in units of rms(b) per sample")
+    ap.add_argument("--eval", nargs="+", metavar="WEIGHTS",
+                    help="only evaluate these weights files on the same held-out batches (no training)")
     a = ap.parse_args()
     dev = torch.device("cuda" if torch.cuda.is_available() else "cpu")
     torch.manual_seed(a.seed)
     rng = np.random.default_rng(a.seed)
     data = Data(a.data, dev)
+    if a.eval:
+        for path in a.eval:
+            model = build_model(a.width, a.modes, a.layers).to(dev)
+            read_weights(model, path)
+            ev = evaluate_many(model, data, seed=12345)
+            print(f"[fno_train] eval {path}: " + ", ".join(f"{k} {v:.3g}" for k, v in ev.items()), flush=True)
+        return
     model = build_model(a.width, a.modes, a.layers).to(dev)
     opt = torch.optim.Adam(model.parameters(), lr=a.lr)
     t0 = time.time()
@@ -356,7 +453,10 @@ def main():
         for g in opt.param_groups:
             g["lr"] = a.lr * (0.02 + 0.98 * 0.5 * (1 + math.cos(math.pi * frac)))
         coef, aux, b, y = data.batch(rng, a.batch)
-        hist = fgmres_train_step(model, opt, coef, aux, b, y, a.recurrence)
+        if a.scheme == "fgmres":
+            hist = fgmres_train_step(model, opt, coef, aux, b, y, a.recurrence)
+        else:
+            hist = fixed_point_train_step(model, opt, coef, aux, b, y, a.recurrence, a.clip)
         it += 1
         if time.time() - last > 30:
             last = time.time()
@@ -365,7 +465,7 @@ def main():
     round_model_to_bf16(model)
     write_weights(model, a.out)
     r1, steps, _ = evaluate(model, data, rng)
-    print(f"[fno_train] done: {it} batches; held-out median residual after 1 step {r1:.3e}, "
+    print(f"[fno_train] done ({a.scheme}): {it} batches; held-out median residual after 1 step {r1:.3e}, "
           f"median steps to 1e-6 {steps:.0f}; weights -> {a.out}", flush=True)
 
 

@@ -54,3 +54,86 @@ def test_trainer_operator_equals_oracle_local_matrix(tile):
     coef = ft.local_operator(tile, lam, eps[t.y0:t.y1, t.x0:t.x1])
     out = ft.apply_op(torch.from_numpy(coef)[None], torch.from_numpy(u)[None])[0].numpy()
     assert np.linalg.norm(out - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_weights_file_reads_back_exactly(tmp_path):
+    torch.manual_seed(1)
+    model = ft.build_model(C=8, modes=4, layers=2)
+    with torch.no_grad():
+        for p in model.parameters():
+            p.add_(0.05 * torch.randn_like(p))
+    ft.round_model_to_bf16(model)
+    path = os.path.join(tmp_path, "w.bin")
+    ft.write_weights(model, path)
+    other = ft.build_model(C=8, modes=4, layers=2)
+    ft.read_weights(other, path)
+    for p, q in zip(model.parameters(), other.parameters()):
+        assert torch.equal(p, q)
+    with pytest.raises(ValueError):
+        ft.read_weights(ft.build_model(C=8, modes=4, layers=3), path)
+
+
+def test_residual_clip_keeps_phase_and_bounds_magnitude():
+    b = torch.full((1, 2, 2), 2.0 + 0j, dtype=torch.complex128)           # rms(b) = 2
+    r = torch.tensor([[[3 + 4j, 0.5j], [-10.0 + 0j, 1 - 1j]]], dtype=torch.complex128)
+    out = ft.clip_residual(r, b, 1.5)                                      # limit 3
+    exp = torch.tensor([[[0.6 * (3 + 4j), 0.5j], [-3.0 + 0j, 1 - 1j]]], dtype=torch.complex128)
+    assert torch.allclose(out, exp, rtol=0, atol=1e-15)
+
+
+class _Scaled(torch.nn.Module):
+    """M(r) = a r: the fixed-point recurrence becomes a Richardson iteration."""
+
+    def __init__(self, a):
+        super().__init__()
+        self.a = torch.nn.Parameter(torch.tensor(a, dtype=torch.complex128))
+
+    def forward(self, r, aux):
+        return self.a * r
+
+
+def _diag_problem(d, c, n=4):
+    coef = torch.zeros((1, 5, n, n), dtype=torch.complex128)
+    coef[:, 4] = d                                                          # B = d I
+    b = torch.full((1, n, n), c, dtype=torch.complex128)
+    return coef, b, b / d
+
+
+def test_fixed_point_step_is_richardson_without_clipping():
+    """B = d I, M(r) = a r, frozen weights: r_j = (1 - a d)^j b, so the relative
+    residual after step j is |1 - a d|^j."""
+    d, a, c = 2.0 - 0.5j, 0.3 + 0.1j, 1.0 + 2.0j
+    coef, b, y = _diag_problem(d, c)
+    model = _Scaled(a)
+    opt = torch.optim.SGD(model.parameters(), lr=0.0)
+    hist = ft.fixed_point_train_step(model, opt, coef, None, b, y, 5, th_clip=1e9)
+    q = abs(1 - a * d)
+    np.testing.assert_allclose(hist, [q ** j for j in range(1, 6)], rtol=1e-12)
+
+
+def test_fixed_point_step_clips_the_residual_it_feeds_back():
+    """A diverging Richardson step (|1 - a d| = 2.5 > th = 1.5): the residual fed
+    to step 2 is clipped to th rms(b) with its phase, so r_2 = (1 - a d) b -
+    a d th (1 - a d)/|1 - a d| b and the reported residual is not clipped."""
+    d, a, c, th = 1.0 + 0j, 3.5 + 0j, 0.5 - 1.5j, 1.5
+    coef, b, y = _diag_problem(d, c)
+    model = _Scaled(a)
+    opt = torch.optim.SGD(model.parameters(), lr=0.0)
+    hist = ft.fixed_point_train_step(model, opt, coef, None, b, y, 2, th_clip=th)
+    q = 1 - a * d
+    r2 = q - a * d * th * q / abs(q)
+    np.testing.assert_allclose(hist, [abs(q), abs(r2)], rtol=1e-12)
+
+
+def test_fixed_point_training_reduces_the_loss():
+    """With the weights free, a few batches of the fixed-point recurrence move
+    a towards 1/d (each step's graph ends at its own optimizer step)."""
+    d, c = 2.0 + 0j, 1.0 + 0j
+    coef, b, y = _diag_problem(d, c)
+    model = _Scaled(0.1 + 0j)
+    opt = torch.optim.SGD(model.parameters(), lr=0.05)
+    first = ft.fixed_point_train_step(model, opt, coef, None, b, y, 3, th_clip=4.0)
+    for _ in range(20):
+        last = ft.fixed_point_train_step(model, opt, coef, None, b, y, 3, th_clip=4.0)
+    assert last[0] < 0.5 * first[0]
+    assert abs(model.a.item() - 0.5) < abs(0.1 - 0.5)
