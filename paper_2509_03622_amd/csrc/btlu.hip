@@ -240,7 +240,10 @@ void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_w
 // d the groups of a wave read consecutive entries of one storage row, so the
 // loads coalesce.  The 8 lanes' partial sums are combined with three DPP
 // steps and lanes 0 and 1 of the group run the recurrence for rows 2rp and
-// 2rp + 1.
+// 2rp + 1.  A workgroup of more than four waves puts two waves on one SIMD;
+// when its last wave would be at most half full (P mod 8 <= 4), that wave
+// takes its row pairs with 16 lanes each (offsets d = cg + 16 j, one more
+// DPP step), so that the SIMD it shares carries fewer offset slots.
 //
 // Only the M stream touches HBM inside the recurrence: the subdomain RHS is
 // gathered into LDS up front (block-major, [k][r]), w_k overwrites v_k in
@@ -251,6 +254,8 @@ void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_w
 // a register ring.
 constexpr int BT_BMAX = 128;
 constexpr int BT_GROUP = 8;
+// offset slots per lane of the 16-lane tail wave (blocks up to 80 wide: at most 40 row pairs)
+constexpr int bt_tail_nj(int nj) { return nj <= 5 ? 3 : 0; }
 
 // Unconditional loads: lanes without a sub-block (offset d >= P, or no row
 // pair) read a valid entry instead and their products are zeroed at use.
@@ -283,12 +288,17 @@ constexpr int DPP_QUAD_XOR1 = 0xB1;       // quad_perm [1,0,3,2]
 constexpr int DPP_QUAD_XOR2 = 0x4E;       // quad_perm [2,3,0,1]
 constexpr int DPP_HALF_MIRROR = 0x141;    // row_half_mirror (lane i <-> 7 - i)
 
-// Sums of the two rows' partial products over the 8 lanes of a group, with
-// two values per lane instead of four: each lane keeps one row and sends the
-// other to its neighbour, then the kept sums are combined.  Lanes 4..7 keep
-// the opposite rows to lanes 0..3 so that the half-row mirror pairs equal
-// rows.  Lane 0 ends with row 2rp, lane 1 with row 2rp + 1.
-__device__ __forceinline__ float2 pair_sum8(float2 a0, float2 a1, bool keep1) {
+constexpr int DPP_ROW_MIRROR = 0x140;     // row_mirror (lane i <-> 15 - i)
+
+// Sums of the two rows' partial products over the G = 8 or 16 lanes of a
+// group, with two values per lane instead of four: each lane keeps one row
+// and sends the other to its neighbour, then the kept sums are combined.
+// Lanes 4..7 keep the opposite rows to lanes 0..3 so that the half-row mirror
+// pairs equal rows; the pattern is symmetric under i <-> 7 - i, so with 16
+// lanes the row mirror pairs equal rows too.  Lane 0 ends with row 2rp,
+// lane 1 with row 2rp + 1.
+template <int G>
+__device__ __forceinline__ float2 pair_sum(float2 a0, float2 a1, bool keep1) {
     float2 keep = keep1 ? a1 : a0;
     const float2 send = keep1 ? a0 : a1;
     keep.x += dpp<DPP_QUAD_XOR1>(send.x);
@@ -297,13 +307,17 @@ __device__ __forceinline__ float2 pair_sum8(float2 a0, float2 a1, bool keep1) {
     keep.y += dpp<DPP_QUAD_XOR2>(keep.y);
     keep.x += dpp<DPP_HALF_MIRROR>(keep.x);
     keep.y += dpp<DPP_HALF_MIRROR>(keep.y);
+    if (G == 16) {
+        keep.x += dpp<DPP_ROW_MIRROR>(keep.x);
+        keep.y += dpp<DPP_ROW_MIRROR>(keep.y);
+    }
     return keep;
 }
 
 // One lane's share of M_k x: the sub-blocks of its offset slots (loaded in
 // `slot`, used directly or transposed) times the operand pairs in LDS;
 // returns the group's sums for rows 2rp (lane 0) and 2rp + 1 (lane 1).
-template <int NJ>
+template <int NJ, int G>
 __device__ __forceinline__ float2 bt_matvec(const float4 (&slot)[2 * NJ], const float2 *__restrict__ ysrc,
                                             const int (&qj)[NJ], unsigned direct_mask, bool keep1) {
     // even and odd slots accumulate separately: half the dependent chain length
@@ -325,60 +339,22 @@ __device__ __forceinline__ float2 bt_matvec(const float4 (&slot)[2 * NJ], const 
         a1[j & 1] = cfma(a1[j & 1], F, x0);
         a1[j & 1] = cfma(a1[j & 1], Dd, x1);
     }
-    return pair_sum8(make_float2(a0[0].x + a0[1].x, a0[0].y + a0[1].y),
-                     make_float2(a1[0].x + a1[1].x, a1[0].y + a1[1].y), keep1);
+    return pair_sum<G>(make_float2(a0[0].x + a0[1].x, a0[0].y + a0[1].y),
+                       make_float2(a1[0].x + a1[1].x, a1[0].y + a1[1].y), keep1);
 }
 
-template <int NJ, int NS>
-__global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restrict__ tiles, int n_src,
-                                                       const float2 *__restrict__ dinv, long long dinv_wl_stride,
-                                                       const float2 *__restrict__ coef,
-                                                       const float2 *__restrict__ sc, int nx, int ny,
-                                                       const float2 *__restrict__ vin, long long vin_stride,
-                                                       float2 *__restrict__ out, long long out_stride,
-                                                       const int *__restrict__ active, int mode,
-                                                       const int2 *__restrict__ order) {
-    extern __shared__ float2 vl[];                    // [nb][b]: v_k, then w_k
-    __shared__ __align__(16) float2 ysh[2][BT_BMAX + 2];   // + a zero pair read by unused offset slots
-    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX], si_s[BT_BMAX];
-    const int2 job = order[blockIdx.x];               // (tile, rhs); tile < 0 pads the queue
-    const int tile = job.x, rhs = job.y;
-    if (tile < 0 || (active && !active[rhs])) return;
-    const int wl = rhs / n_src;
-    const TileDesc t = tiles[tile];
+// The recurrence of one wave: G lanes per row pair, NJ offset slots per lane,
+// the factor blocks prefetched NS - 1 steps ahead.  Every wave of the
+// workgroup runs the same steps and barriers; only the lane mapping differs.
+template <int NJ, int NS, int G>
+__device__ __forceinline__ void bt_run(const TileDesc &t, int rp, int cg, int tid, const float2 *__restrict__ D,
+                                       long long bbytes, int nx, bool local_out, float2 *__restrict__ orr,
+                                       float2 *__restrict__ vl, float2 (*ysh)[BT_BMAX + 2],
+                                       const float2 *__restrict__ cl_s, const float2 *__restrict__ ch_s,
+                                       const float2 *__restrict__ so_s, const float2 *__restrict__ si_s) {
     const int b = t.b, nb = t.nb, P = b >> 1;
-    const int tid = threadIdx.x;
-    const int rp = tid / BT_GROUP, cg = tid - rp * BT_GROUP;
+    const int lx = t.x1 - t.x0;
     const bool on = rp < P;
-    const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
-    const long long bbytes = bt_sym_block(b) * (long long)sizeof(float2);
-    const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
-    const float2 *cf = coef + wl * coef_stride(nx, ny);
-    const float2 *clo_a = t.tr ? cf : cf + 2 * nx;               // cxm or cym
-    const float2 *chi_a = t.tr ? cf + nx : cf + 2 * nx + ny;      // cxp or cyp
-    const float2 *scw = sc + (long long)wl * (nx + ny);
-    const float2 *s_in = t.tr ? scw + nx + t.y0 : scw + t.x0;     // along the block
-    const float2 *s_out = t.tr ? scw + t.x0 : scw + nx + t.y0;    // across blocks
-    const int base = t.tr ? t.x0 : t.y0;
-    const bool local_in = mode & 1, local_out = mode & 2;
-    const float2 *vr = vin + rhs * vin_stride + (local_in ? t.loc_off : 0);
-    float2 *orr = out + rhs * out_stride + (local_out ? t.loc_off : 0);
-
-    // gather R_i v (row-major over the tile, coalesced) into block-major LDS
-    for (int e = tid; e < lx * ly; e += blockDim.x) {
-        const int yy = e / lx, xx = e - yy * lx;
-        const float2 val = local_in ? vr[e] : vr[(long long)(t.y0 + yy) * nx + (t.x0 + xx)];
-        vl[t.tr ? xx * b + yy : e] = val;
-    }
-    for (int k = tid; k < nb; k += blockDim.x) {
-        cl_s[k] = clo_a[base + k];
-        ch_s[k] = chi_a[base + k];
-        so_s[k] = s_out[k];
-    }
-    // the in-block scaling goes through LDS as well: a global load left in
-    // flight past the prefetch below would make every step's first use of it
-    // wait for the whole register ring
-    for (int k = tid; k < b; k += blockDim.x) si_s[k] = s_in[k];
     const int nsteps = 2 * nb - 1;
     auto blk = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
     // per offset: storage entry (byte offset within a block), transposed flag, operand pair
@@ -387,7 +363,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     unsigned direct_mask = 0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const int d = cg + BT_GROUP * j;
+        const int d = cg + G * j;
         const bool valid = on && d < P;          // blocks narrower than the widest tile leave slots unused
         bool direct = true;
         const int sub = valid ? bt_sym_index(P, rp, d, direct) : 0;
@@ -435,7 +411,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     if (tid < 4) ysh[tid >> 1][BT_BMAX + (tid & 1)] = make_float2(0.f, 0.f);
     __syncthreads();
 
-    const bool keep1 = ((cg ^ (cg >> 2)) & 1) != 0;
+    const bool keep1 = (((cg & 7) ^ ((cg & 7) >> 2)) & 1) != 0;
     auto step = [&](int s, const float4(&slot)[2 * NJ]) {
         const int k = blk(s);
         const int p = s & 1;
@@ -450,7 +426,7 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
             cc = fwd ? cl_s[min(k + 1, nb - 1)] : ch_s[k];
             skn = cmul(si, so_s[max(knext, 0)]);
         }
-        const float2 a = bt_matvec<NJ>(slot, ysh[p], qj, direct_mask, keep1);
+        const float2 a = bt_matvec<NJ, G>(slot, ysh[p], qj, direct_mask, keep1);
         if (wr) {
             if (fwd) vl[k * b + myr] = a;                                   // w_k
             const float2 y = turn ? a : cfms(pre, cc, a);                   // y_{k+1} or u_k
@@ -477,12 +453,75 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
         if (s0 + i < nsteps) step(s0 + i, ring[i]);
 }
 
+template <int NJ, int NS, int NJT>
+__global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restrict__ tiles, int n_src,
+                                                       const float2 *__restrict__ dinv, long long dinv_wl_stride,
+                                                       const float2 *__restrict__ coef,
+                                                       const float2 *__restrict__ sc, int nx, int ny,
+                                                       const float2 *__restrict__ vin, long long vin_stride,
+                                                       float2 *__restrict__ out, long long out_stride,
+                                                       const int *__restrict__ active, int mode,
+                                                       const int2 *__restrict__ order) {
+    extern __shared__ float2 vl[];                    // [nb][b]: v_k, then w_k
+    __shared__ __align__(16) float2 ysh[2][BT_BMAX + 2];   // + a zero pair read by unused offset slots
+    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX], si_s[BT_BMAX];
+    const int2 job = order[blockIdx.x];               // (tile, rhs); tile < 0 pads the queue
+    const int tile = job.x, rhs = job.y;
+    if (tile < 0 || (active && !active[rhs])) return;
+    const int wl = rhs / n_src;
+    const TileDesc t = tiles[tile];
+    const int b = t.b, nb = t.nb, P = b >> 1;
+    const int tid = threadIdx.x;
+    const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
+    const long long bbytes = bt_sym_block(b) * (long long)sizeof(float2);
+    const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
+    const float2 *cf = coef + wl * coef_stride(nx, ny);
+    const float2 *clo_a = t.tr ? cf : cf + 2 * nx;               // cxm or cym
+    const float2 *chi_a = t.tr ? cf + nx : cf + 2 * nx + ny;      // cxp or cyp
+    const float2 *scw = sc + (long long)wl * (nx + ny);
+    const float2 *s_in = t.tr ? scw + nx + t.y0 : scw + t.x0;     // along the block
+    const float2 *s_out = t.tr ? scw + t.x0 : scw + nx + t.y0;    // across blocks
+    const int base = t.tr ? t.x0 : t.y0;
+    const bool local_in = mode & 1, local_out = mode & 2;
+    const float2 *vr = vin + rhs * vin_stride + (local_in ? t.loc_off : 0);
+    float2 *orr = out + rhs * out_stride + (local_out ? t.loc_off : 0);
+
+    // gather R_i v (row-major over the tile, coalesced) into block-major LDS
+    for (int e = tid; e < lx * ly; e += blockDim.x) {
+        const int yy = e / lx, xx = e - yy * lx;
+        const float2 val = local_in ? vr[e] : vr[(long long)(t.y0 + yy) * nx + (t.x0 + xx)];
+        vl[t.tr ? xx * b + yy : e] = val;
+    }
+    for (int k = tid; k < nb; k += blockDim.x) {
+        cl_s[k] = clo_a[base + k];
+        ch_s[k] = chi_a[base + k];
+        so_s[k] = s_out[k];
+    }
+    // the in-block scaling goes through LDS as well: a global load left in
+    // flight past the prefetch below would make every step's first use of it
+    // wait for the whole register ring
+    for (int k = tid; k < b; k += blockDim.x) si_s[k] = s_in[k];
+    // waves of 8-lane groups; when the last wave holds at most four row pairs
+    // (it is then at most half full), it takes them with 16-lane groups
+    // instead, so that it carries fewer offset slots per lane than the full
+    // waves (the SIMD that runs it runs two waves)
+    const int full = P >> 3, rest = P & 7;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (NJT > 0 && rest > 0 && rest <= 4 && wave == full) {
+        const int l = tid - 64 * full;
+        bt_run<(NJT > 0 ? NJT : 1), NS, 16>(t, 8 * full + (l >> 4), l & 15, tid, D, bbytes, nx, local_out, orr, vl,
+                                          ysh, cl_s, ch_s, so_s, si_s);
+    } else {
+        bt_run<NJ, NS, 8>(t, tid >> 3, tid & 7, tid, D, bbytes, nx, local_out, orr, vl, ysh, cl_s, ch_s, so_s, si_s);
+    }
+}
+
 template <int NJ, int NS>
 static void bt_solve_launch(hipStream_t s, dim3 grid, int threads, size_t lds, const TileDesc *tiles, int n_src,
                             const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc,
                             int nx, int ny, const float2 *vin, long long vin_stride, float2 *out,
                             long long out_stride, const int *active, int mode, const int2 *order) {
-    hipLaunchKernelGGL((bt_solve_kernel<NJ, NS>), grid, dim3(threads), lds, s, tiles, n_src, dinv, dinv_wl_stride,
+    hipLaunchKernelGGL((bt_solve_kernel<NJ, NS, bt_tail_nj(NJ)>), grid, dim3(threads), lds, s, tiles, n_src, dinv, dinv_wl_stride,
                        coef, sc, nx, ny, vin, vin_stride, out, out_stride, active, mode, order);
 }
 
@@ -497,13 +536,13 @@ void bt_solve_prepare(int bmax, int max_cells) {
     const void *fs[3];
     int nf = 0;
     if (nj <= 5) {
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 3>);
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 4>);
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 5>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 3, bt_tail_nj(5)>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 4, bt_tail_nj(5)>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 5, bt_tail_nj(5)>);
     } else if (nj <= 7) {
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<7, 3>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<7, 3, bt_tail_nj(7)>);
     } else {
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<8, 3>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<8, 3, bt_tail_nj(8)>);
     }
     for (int i = 0; i < nf; ++i) (void)hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
