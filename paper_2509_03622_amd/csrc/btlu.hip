@@ -254,8 +254,9 @@ void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_w
 // a register ring.
 constexpr int BT_BMAX = 128;
 constexpr int BT_GROUP = 8;
-// offset slots per lane of the 16-lane tail wave (blocks up to 80 wide: at most 40 row pairs)
-constexpr int bt_tail_nj(int nj) { return nj <= 5 ? 3 : 0; }
+// offset slots per lane of the 16-lane tail wave: ceil(P / 16) for the
+// widest block of each offset-slot instance (80, 112 and 128 cells)
+constexpr int bt_tail_nj(int nj) { return nj <= 5 ? 3 : 4; }
 
 // Unconditional loads: lanes without a sub-block (offset d >= P, or no row
 // pair) read a valid entry instead and their products are zeroed at use.
