@@ -302,6 +302,16 @@ nosdd_status nosdd_graphs(nosdd_problem *p, int enable);
  * subdomain and source (the right-hand sides share the factor stream only
  * through the caches).  Same arithmetic per product up to summation order. */
 nosdd_status nosdd_multi_source(nosdd_problem *p, int enable);
+/* Second Gram-Schmidt pass of the outer FGMRES (both forms orthogonalise
+ * twice against the basis; flexible GMRES, Algorithm 1 recurrence): enabled
+ * (default), the second pass's correction and the normalisation of each new
+ * basis vector are kept in a small triangular FP64 map from the stored
+ * vectors to the orthonormal basis, so a step makes two passes over the
+ * vectors (dots; update fused with the second dots) and the preconditioner
+ * is applied to the stored vector; disabled, the second pass runs where the
+ * Daniel-Gragg-Kaufman-Stewart test asks for it and a third pass writes the
+ * normalised vector.  Same Krylov space in exact arithmetic. */
+nosdd_status nosdd_stored_basis(nosdd_problem *p, int enable);
 
 /* Timing of the last solve (ms, GPU events): setup, total solve, iterations. */
 nosdd_status nosdd_last_timing(const nosdd_problem *p, double *setup_ms, double *solve_ms,

@@ -66,6 +66,7 @@ struct Workspace {
     int nblk_b[4] = {0, 0, 0, 0}, nblk_max = 0;
     bool tuned = false;
     long long N = 0;
+    DevBuf T, G1, scale;                           // stored-basis Gram-Schmidt (T: FP64 [rhs][m+1][m+1])
     DevBuf x, b, b64, V, Z, w, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, bnorm2, bnorm, beta2,
         iters, kcyc, active, want, ones, reorth, inv_h, flags, hist, cd_, cc_;
     DevBuf loc;                                    // packed local vectors of the many-source solve
@@ -135,6 +136,7 @@ struct nosdd_problem {
     // grid lives in the workspace)
     bool use_autotune = true;
     bool use_multi = true;                        // many-source solve (use_multi())
+    bool stored_basis = true;                     // Gram-Schmidt second pass in coefficient space
     int bt_depth = 0;
     bool bt_tuned = false;
     // one captured graph per Arnoldi step j of a restart cycle (replayed every cycle)
@@ -415,6 +417,9 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     const size_t hsz = (size_t)n_rhs * (m + 1) * m * sizeof(float2);
     HIPCHK(ctx, w.H.ensure(hsz));
     HIPCHK(ctx, w.H2.ensure(hsz));
+    HIPCHK(ctx, w.G1.ensure(hsz));
+    HIPCHK(ctx, w.T.ensure((size_t)n_rhs * (m + 1) * (m + 1) * sizeof(double2)));
+    HIPCHK(ctx, w.scale.ensure((size_t)n_rhs * sizeof(float)));
     HIPCHK(ctx, w.cs.ensure((size_t)n_rhs * m * sizeof(float)));
     HIPCHK(ctx, w.sn.ensure((size_t)n_rhs * m * sizeof(float2)));
     HIPCHK(ctx, w.gam.ensure((size_t)n_rhs * (m + 1) * sizeof(float2)));
@@ -1186,8 +1191,9 @@ nosdd_status autotune(nosdd_problem *p, int n_rhs, int n_src, int m, const Given
                     launch_cgs_dots(s, V, vstride, nv, wv, N, n_rhs, ones, part, c);
                     launch_cgs_update_dots(s, V, vstride, nv, wv, V + nv * vstride, N, n_rhs, ones,
                                            w.H.as<float2>(), m, nv - 1, part, c);
-                    launch_cgs_update_scale(s, V, vstride, nv, V + nv * vstride, V + nv * vstride, N, n_rhs, ones,
-                                            ones, w.H2.as<float2>(), m, nv - 1, w.inv_h.as<float>(), c);
+                    if (!p->stored_basis)
+                        launch_cgs_update_scale(s, V, vstride, nv, V + nv * vstride, V + nv * vstride, N, n_rhs,
+                                                ones, ones, w.H2.as<float2>(), m, nv - 1, w.inv_h.as<float>(), c);
                 });
                 if (ms < best) {
                     best = ms;
@@ -1314,6 +1320,9 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     ga.hist_ld = std::max(1, o->max_iters);
     ga.inv_h = w.inv_h.as<float>();
     ga.flags = w.flags.as<int>();
+    ga.T = w.T.as<double2>();
+    ga.G1 = w.G1.as<float2>();
+    ga.scale = w.scale.as<float>();
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
@@ -1352,11 +1361,16 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     nosdd_status result = NOSDD_OK;
     int total_outer = 0;
     const int *active = w.active.as<int>();
-    // One Arnoldi step j: z_j = M^-1 v_j, w = A z_j, classical Gram-Schmidt
-    // against v_0..v_j with a second pass where the DGKS test asks for it,
-    // Givens rotation and residual estimate (the second pass's norm from
-    // ||w'||^2 - ||h2||^2), v_{j+1} = w / h_{j+1,j} written by the last pass.  Every
-    // argument is fixed for the solve, so the step can be captured in a graph.
+    // One Arnoldi step j: z_j = M^-1 v_j, w = A z_j, two passes of classical
+    // Gram-Schmidt against the basis, Givens rotation and residual estimate.
+    // Stored-basis form (default): the first pass's dots, then its update fused
+    // with the second pass's dots; the second pass's correction and the
+    // normalisation enter the triangular map T from stored vectors to the
+    // orthonormal basis instead of a third pass over the vectors.  The other
+    // form runs the second pass where the DGKS test asks for it and writes
+    // v_{j+1} = (w' - V h2) / h_{j+1,j} with a third pass.  Every argument is
+    // fixed for the solve, so the step can be captured in a graph.
+    const bool stored_basis = p->stored_basis;
     auto step = [&](hipStream_t st, int j, int n_live_) {
         float2 *Vj = V + j * vstride, *Vn = V + (j + 1) * vstride, *Zj = Z + j * vstride;
         precond(p, st, Vj, Zj, wv, n_src, n_rhs, active, n_live_);
@@ -1366,6 +1380,13 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         const float *ih = w.inv_h.as<float>();
         const int nb = w.nblk_b[cgs_bucket(j + 1)];
         launch_cgs_dots(st, V, vstride, j + 1, wv, N, n_rhs, active, part, nb);
+        if (stored_basis) {
+            launch_cgs_reduce(st, part, nb, j + 1, n_rhs, active, j, 6, nullptr, ga);
+            launch_cgs_update_dots(st, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.G1.as<float2>(), m, j, part,
+                                   nb, w.scale.as<float>());
+            launch_cgs_reduce(st, part, nb, j + 1, n_rhs, active, j, 7, nullptr, ga);
+            return;
+        }
         launch_cgs_reduce(st, part, nb, j + 1, n_rhs, active, j, 1, nullptr, ga);
         // first-pass update with the second pass's dots taken from the same loads
         launch_cgs_update_dots(st, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.H.as<float2>(), m, j, part, nb);
@@ -2255,6 +2276,14 @@ nosdd_status nosdd_multi_source(nosdd_problem *p, int enable) {
     p->use_multi = enable != 0;
     p->orders.clear();                            // launch queues are rebuilt with or without the grouped jobs
     p->drop_graphs();
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_stored_basis(nosdd_problem *p, int enable) {
+    if (!p) return NOSDD_EINVAL;
+    p->stored_basis = enable != 0;
+    p->drop_graphs();                             // the captured steps launch different kernels
+    p->ws.tuned = false;                          // and the Gram-Schmidt grid is timed on those kernels
     return NOSDD_OK;
 }
 

@@ -174,6 +174,12 @@ struct GivensArgs {
     int *active; int *iters; int *kcyc; int max_iters;
     float *hist; int hist_ld;
     float *inv_h; int *flags;         // flags bit 0 converged, bit 1 breakdown, bit 2 budget
+    // stored-basis form of the two-pass Gram-Schmidt (modes 6 and 7): the
+    // orthonormal basis is V = Vs T with Vs the stored vectors and T upper
+    // triangular, T[r][k][i] at T + (r*(m+1) + k)*(m+1) + i (FP64); G1 holds the
+    // first-pass coefficients on the stored vectors (layout of H); scale the
+    // factor the first-pass update applies to the vector it stores
+    double2 *T; float2 *G1; float *scale;
 };
 void launch_cgs_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, long long N,
                      int n_rhs, const int *gate, double2 *partial, int nblk);
@@ -183,7 +189,7 @@ void launch_cgs_update_scale(hipStream_t s, const float2 *V, long long vstride, 
                              int col, const float *inv_h, int nblk);
 void launch_cgs_update_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
                             long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col,
-                            double2 *partial, int nblk);
+                            double2 *partial, int nblk, const float *scale = nullptr);
 void launch_cgs_reduce(hipStream_t s, const double2 *partial, int nblk, int nv, int n_rhs, const int *gate, int col,
                        int mode, double *norm_out, const GivensArgs &ga);
 int nblk_for_update(long long N, int n_rhs);

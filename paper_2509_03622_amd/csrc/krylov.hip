@@ -178,11 +178,13 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float
                                                                      const float2 *w, float2 *dst, long long N,
                                                                      const int *__restrict__ gate,
                                                                      const float2 *__restrict__ Hc, int m, int col,
-                                                                     double2 *__restrict__ partial, int nblk) {
+                                                                     double2 *__restrict__ partial, int nblk,
+                                                                     const float *__restrict__ scale) {
     __shared__ float2 hs[NV > 0 ? NV : 1];
     __shared__ double2 red[(KR_THREADS / 64) * KR_SLOTS];
     const int r = blockIdx.y;
     if (!gate[r]) return;
+    const float sf = scale ? scale[r] : 1.f;
     if (threadIdx.x < NV) hs[threadIdx.x] = Hc[((long long)r * (m + 1) + threadIdx.x) * m + col];
     __syncthreads();
     const float2 *wr = w + r * N;
@@ -200,6 +202,7 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float
         for (int i = 0; i < NV; ++i) vv[i] = Vr[i * vstride + n];
 #pragma unroll
         for (int i = 0; i < NV; ++i) v = cfms(v, hs[i], vv[i]);
+        v = cscale(v, sf);
         dr[n] = v;
         fn += cabs2(v);
 #pragma unroll
@@ -237,8 +240,95 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float
 //           and where a second pass is due, the h2 bookkeeping of mode 3 and the
 //           Givens step with ||w''||^2 = ||w'||^2 - ||h2||^2 (w'' = w' - V h2 and
 //           V^H w'' = 0 to working precision, so the norm is known before the
-//           second update runs; that update then writes v_{j+1} directly).
+//           second update runs; that update then writes v_{j+1} directly);
+//   modes 6, 7  the two passes on the stored basis (stored_basis_step).
 constexpr int RED_THREADS = 1024;
+
+// Two-pass classical Gram-Schmidt on the stored basis (modes 6 and 7).  The
+// orthonormal basis is V = Vs T (Vs the stored vectors, T upper triangular,
+// FP64), so dots against V are T^H times dots against Vs, and an update by V h
+// is an update by Vs (T h).  Step j, with w = A z_j:
+//   mode 6  d = Vs^H w, ||w||^2:  h1 = T^H d -> H[:, j];  coefficients T h1 on
+//           the stored vectors -> G1[:, j];  the first-pass update will store
+//           s (w - V h1) with s = 1/sqrt(max(||w||^2 - ||h1||^2, 1e-20 ||w||^2))
+//           (any scale is exact, T records it; this one keeps the stored
+//           vectors near unit norm);
+//   mode 7  d = Vs^H s w', ||s w'||^2:  h2 = T^H d / s (the second pass),
+//           H[:, j] += h2, h^2 = ||w'||^2 - ||h2||^2 (V^H w'' = 0), and
+//           v_{j+1} = (w' - V h2)/h enters T as its column j+1:
+//           T[k][j+1] = -(T h2)_k / h (k <= j), T[j+1][j+1] = 1/(s h);
+//           then the Givens step with h^2.
+// The second pass thus costs no pass over the vectors: the stored vector is
+// never rewritten, and the preconditioner of the next step is applied to it
+// (flexible GMRES takes any direction z; the relation A Z = V H holds with V
+// the orthonormal basis above).
+__device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode, int r, const GivensArgs &ga) {
+    __shared__ double2 hv[KR_SLOTS];
+    __shared__ double sh_s, sh_h;
+    const int m = ga.m, ld = m + 1;
+    double2 *Tr = ga.T + (long long)r * ld * ld;
+    float2 *Hr = ga.H + (long long)r * (m + 1) * m;
+    const int t = threadIdx.x;
+    if (mode == 6 && col == 0 && t == 0) Tr[0] = make_double2(1.0, 0.0);       // v_0 is stored normalised
+    __syncthreads();
+    const double inv_s = mode == 7 ? 1.0 / (double)ga.scale[r] : 1.0;
+    // h = T^H d (column i of T has entries k <= i)
+    if (t < nv) {
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k <= t; ++k) {
+            const double2 a = Tr[k * ld + t], d = vals[k];
+            sx += a.x * d.x + a.y * d.y;
+            sy += a.x * d.y - a.y * d.x;
+        }
+        hv[t] = make_double2(sx * inv_s, sy * inv_s);
+    }
+    __syncthreads();
+    if (t == 0) {
+        double hn = 0.0;
+        for (int i = 0; i < nv; ++i) hn += hv[i].x * hv[i].x + hv[i].y * hv[i].y;
+        if (mode == 6) {
+            const double n2 = vals[KR_MAXV].x;
+            ga.nw_pre_w[r] = n2;
+            const double e = n2 - hn;
+            ga.scale[r] = n2 > 0.0 ? (float)(1.0 / sqrt(e > 1e-20 * n2 ? e : 1e-20 * n2)) : 1.f;
+        } else {
+            const double n2 = vals[KR_MAXV].x * inv_s * inv_s;
+            const double e = n2 > hn ? n2 - hn : 0.0;
+            sh_h = e;
+            sh_s = (double)ga.scale[r];
+        }
+    }
+    __syncthreads();
+    if (mode == 6) {
+        if (t < nv) Hr[t * m + col] = make_float2((float)hv[t].x, (float)hv[t].y);
+        // coefficients on the stored vectors: g_k = sum_{i >= k} T[k][i] h1_i
+        if (t < nv) {
+            double gx = 0.0, gy = 0.0;
+            for (int i = t; i < nv; ++i) {
+                const double2 a = Tr[t * ld + i], h = hv[i];
+                gx += a.x * h.x - a.y * h.y;
+                gy += a.x * h.y + a.y * h.x;
+            }
+            ga.G1[((long long)r * (m + 1) + t) * m + col] = make_float2((float)gx, (float)gy);
+        }
+        return;
+    }
+    const double hsq = sh_h, h = sqrt(hsq), sc = sh_s;
+    if (t < nv) {
+        Hr[t * m + col] = cadd(Hr[t * m + col], make_float2((float)hv[t].x, (float)hv[t].y));
+        double gx = 0.0, gy = 0.0;
+        for (int i = t; i < nv; ++i) {
+            const double2 a = Tr[t * ld + i], q = hv[i];
+            gx += a.x * q.x - a.y * q.y;
+            gy += a.x * q.y + a.y * q.x;
+        }
+        Tr[t * ld + col + 1] = h > 0.0 ? make_double2(-gx / h, -gy / h) : make_double2(0.0, 0.0);
+    }
+    if (t == 0) Tr[(col + 1) * ld + col + 1] = h > 0.0 ? make_double2(1.0 / (sc * h), 0.0) : make_double2(0.0, 0.0);
+    __syncthreads();
+    if (t == 0) givens_step(ga, r, col, hsq);
+}
+
 __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *__restrict__ partial, int nblk, int nv,
                                                                  const int *__restrict__ gate, int col, int mode,
                                                                  double *__restrict__ norm_out, GivensArgs ga) {
@@ -249,7 +339,7 @@ __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *
         return;
     }
     if (gate && !gate[r]) return;
-    const int ns = (mode == 1 || mode == 3 || mode == 5) ? nv : 0;
+    const int ns = (mode == 1 || mode == 3 || mode == 5 || mode == 6 || mode == 7) ? nv : 0;
     const double2 *pr = partial + (long long)r * nblk * KR_SLOTS;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int v = wid; v <= ns; v += RED_THREADS / 64) {
@@ -265,6 +355,10 @@ __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *
         if (lane == 0) vals[slot] = make_double2(sx, sy);
     }
     __syncthreads();
+    if (mode == 6 || mode == 7) {
+        stored_basis_step(vals, nv, col, mode, r, ga);
+        return;
+    }
     if (threadIdx.x != 0) return;
     const double n2 = vals[KR_MAXV].x;
     const int m = ga.m;
@@ -342,13 +436,13 @@ void launch_cgs_dots(hipStream_t s, const float2 *V, long long vstride, int nv, 
 
 void launch_cgs_update_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, float2 *dst,
                             long long N, int n_rhs, const int *gate, const float2 *Hc, int m, int col,
-                            double2 *partial, int nblk) {
+                            double2 *partial, int nblk, const float *scale) {
     dim3 grid(nblk, n_rhs);
     switch (nv) {
 #define CASE(K)                                                                                                     \
     case K:                                                                                                         \
         hipLaunchKernelGGL((cgs_update_dots_kernel<K>), grid, dim3(KR_THREADS), 0, s, V, vstride, w, dst, N, gate,  \
-                           Hc, m, col, partial, nblk);                                                              \
+                           Hc, m, col, partial, nblk, scale);                                                       \
         break;
         NOSDD_NV_CASES(CASE)
 #undef CASE

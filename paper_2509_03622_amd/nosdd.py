@@ -23,7 +23,7 @@ EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_p
            "nosdd_problem_setup", "nosdd_problem_destroy", "nosdd_solve", "nosdd_solve_device", "nosdd_solve_device_c64", "nosdd_solve_paper_device",
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
-           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_multi_source", "nosdd_autotune", "nosdd_tuning",
+           "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_multi_source", "nosdd_stored_basis", "nosdd_autotune", "nosdd_tuning",
            "nosdd_fom_gradient_device"]
 
 
@@ -94,6 +94,7 @@ def load(path=LIBPATH):
         "nosdd_nn_apply": (i, [vp, vp, vp]),
         "nosdd_graphs": (i, [vp, i]),
         "nosdd_multi_source": (i, [vp, i]),
+        "nosdd_stored_basis": (i, [vp, i]),
         "nosdd_autotune": (i, [vp, i]),
         "nosdd_tuning": (i, [vp, vp]),
         "nosdd_fom_gradient_device": (i, [vp, vp, i, vp, i, C.POINTER(SolveOpts), C.POINTER(C.c_double), vp, vp]),
@@ -329,6 +330,10 @@ class Problem:
     def multi_source(self, enable=True):
         """Solve the sources of a wavelength together (one factor stream, MFMA products) or one by one."""
         return self.ctx.check(self.L.nosdd_multi_source(self.h, 1 if enable else 0))
+
+    def stored_basis(self, enable=True):
+        """Second Gram-Schmidt pass in coefficient space (two passes per step) or as a third pass."""
+        return self.ctx.check(self.L.nosdd_stored_basis(self.h, 1 if enable else 0))
 
     def graphs(self, enable=True):
         """Replay captured per-step HIP graphs (default) or launch kernels one by one."""
