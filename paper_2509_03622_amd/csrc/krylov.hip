@@ -264,19 +264,27 @@ constexpr int RED_THREADS = 1024;
 // the orthonormal basis above).
 __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode, int r, const GivensArgs &ga) {
     __shared__ double2 hv[KR_SLOTS];
+    __shared__ double2 Ts[KR_MAXV][KR_MAXV];       // the leading nv x nv block of T (upper triangle)
     __shared__ double sh_s, sh_h;
     const int m = ga.m, ld = m + 1;
     double2 *Tr = ga.T + (long long)r * ld * ld;
     float2 *Hr = ga.H + (long long)r * (m + 1) * m;
     const int t = threadIdx.x;
-    if (mode == 6 && col == 0 && t == 0) Tr[0] = make_double2(1.0, 0.0);       // v_0 is stored normalised
+    // stage T in LDS with whole-workgroup loads (the triangular products below
+    // would otherwise walk its columns with one dependent global load per term)
+    for (int e = t; e < nv * nv; e += blockDim.x) {
+        const int k = e / nv, i = e - k * nv;
+        Ts[k][i] = (mode == 6 && col == 0) ? make_double2(1.0, 0.0)        // v_0 is stored normalised
+                   : (k <= i ? Tr[k * ld + i] : make_double2(0.0, 0.0));
+    }
+    if (mode == 6 && col == 0 && t == 0) Tr[0] = make_double2(1.0, 0.0);
     __syncthreads();
     const double inv_s = mode == 7 ? 1.0 / (double)ga.scale[r] : 1.0;
     // h = T^H d (column i of T has entries k <= i)
     if (t < nv) {
         double sx = 0.0, sy = 0.0;
         for (int k = 0; k <= t; ++k) {
-            const double2 a = Tr[k * ld + t], d = vals[k];
+            const double2 a = Ts[k][t], d = vals[k];
             sx += a.x * d.x + a.y * d.y;
             sy += a.x * d.y - a.y * d.x;
         }
@@ -305,7 +313,7 @@ __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode
         if (t < nv) {
             double gx = 0.0, gy = 0.0;
             for (int i = t; i < nv; ++i) {
-                const double2 a = Tr[t * ld + i], h = hv[i];
+                const double2 a = Ts[t][i], h = hv[i];
                 gx += a.x * h.x - a.y * h.y;
                 gy += a.x * h.y + a.y * h.x;
             }
@@ -318,7 +326,7 @@ __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode
         Hr[t * m + col] = cadd(Hr[t * m + col], make_float2((float)hv[t].x, (float)hv[t].y));
         double gx = 0.0, gy = 0.0;
         for (int i = t; i < nv; ++i) {
-            const double2 a = Tr[t * ld + i], q = hv[i];
+            const double2 a = Ts[t][i], q = hv[i];
             gx += a.x * q.x - a.y * q.y;
             gy += a.x * q.y + a.y * q.x;
         }
