@@ -165,7 +165,7 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_dots_kernel(const float2 *__re
     if (i < NV || i == KR_MAXV) {
         double2 s = red[i];
         for (int wv = 1; wv < KR_THREADS / 64; ++wv) s = zadd(s, red[wv * KR_SLOTS + i]);
-        pr[(long long)blockIdx.x * KR_SLOTS + i] = s;
+        pr[(long long)i * nblk + blockIdx.x] = s;            // slot-major: the reduction reads rows
     }
 }
 
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float
     if (i < NV || i == KR_MAXV) {
         double2 s = red[i];
         for (int q = 1; q < KR_THREADS / 64; ++q) s = zadd(s, red[q * KR_SLOTS + i]);
-        pr[(long long)blockIdx.x * KR_SLOTS + i] = s;
+        pr[(long long)i * nblk + blockIdx.x] = s;            // slot-major: the reduction reads rows
     }
 }
 
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *
         const int slot = v < ns ? v : KR_MAXV;
         double sx = 0.0, sy = 0.0;
         for (int bk = lane; bk < nblk; bk += 64) {
-            const double2 q = pr[(long long)bk * KR_SLOTS + slot];
+            const double2 q = pr[(long long)slot * nblk + bk];
             sx += q.x;
             sy += q.y;
         }
