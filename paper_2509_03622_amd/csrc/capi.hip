@@ -67,6 +67,7 @@ struct Workspace {
     bool tuned = false;
     long long N = 0;
     DevBuf T, G1, scale;                           // stored-basis Gram-Schmidt (T: FP64 [rhs][m+1][m+1])
+    DevBuf cstep, cy;                              // coarse coefficients per step [m][rhs][n_c], their y-sum
     DevBuf x, b, b64, V, Z, w, partial, H, H2, cs, sn, gam, y, nw_pre, nw_post, bnorm2, bnorm, beta2,
         iters, kcyc, active, want, ones, reorth, inv_h, flags, hist, cd_, cc_;
     DevBuf loc;                                    // packed local vectors of the many-source solve
@@ -442,6 +443,8 @@ nosdd_status ensure_ws(nosdd_problem *p, int n_rhs, int m, int max_iters) {
     const int nc = std::max(1, p->n_c);
     HIPCHK(ctx, w.cd_.ensure((size_t)n_rhs * nc * sizeof(double2)));
     HIPCHK(ctx, w.cc_.ensure((size_t)n_rhs * nc * sizeof(float2)));
+    HIPCHK(ctx, w.cstep.ensure((size_t)m * n_rhs * nc * sizeof(float2)));
+    HIPCHK(ctx, w.cy.ensure((size_t)n_rhs * nc * sizeof(double2)));
     return NOSDD_OK;
 }
 
@@ -740,9 +743,11 @@ void local_sweep(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, in
                         active, 0, p->bmax, p->max_cells, p->bt_depth);
 }
 
-// z = M^-1 v (two-level), wout = A z.  v, z, wout: [n_rhs][N].
+// z = M^-1 v (two-level), wout = A z.  v, z, wout: [n_rhs][N].  With c_store
+// the coarse coefficients go there and z keeps only the one-level part (the
+// caller adds Phi c later); wout is the full A z either way.
 void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2 *wout, int n_src, int n_rhs,
-             const int *active, int n_live) {
+             const int *active, int n_live, float2 *c_store = nullptr) {
     Workspace &w = p->ws;
     const long long N = (long long)p->nx * p->ny;
     {
@@ -764,10 +769,10 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
         ProfScope ps(p, 3, n_live);
         launch_coarse_dot(s, p->d_tiles.as<TileDesc>(), p->n_c, p->kc, p->d_W.as<float2>(), p->box_wl_stride, v,
                           wout, p->nx, N, n_rhs, n_src, active, w.cd_.as<double2>());
-        launch_coarse_solve(s, p->d_GinvT.as<double2>(), p->n_c, w.cd_.as<double2>(), w.cc_.as<float2>(), n_rhs, n_src,
-                            active);
+        float2 *cc = c_store ? c_store : w.cc_.as<float2>();
+        launch_coarse_solve(s, p->d_GinvT.as<double2>(), p->n_c, w.cd_.as<double2>(), cc, n_rhs, n_src, active);
         launch_coarse_update(s, p->d_tiles.as<TileDesc>(), p->d_owner.as<int>(), p->kc, p->d_phi.as<float2>(),
-                             p->d_W.as<float2>(), p->box_wl_stride, w.cc_.as<float2>(), p->n_c, z, wout, p->nx, p->ny,
+                             p->d_W.as<float2>(), p->box_wl_stride, cc, p->n_c, c_store ? nullptr : z, wout, p->nx, p->ny,
                              n_rhs, n_src, active);
     }
 }
@@ -1373,7 +1378,8 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     const bool stored_basis = p->stored_basis;
     auto step = [&](hipStream_t st, int j, int n_live_) {
         float2 *Vj = V + j * vstride, *Vn = V + (j + 1) * vstride, *Zj = Z + j * vstride;
-        precond(p, st, Vj, Zj, wv, n_src, n_rhs, active, n_live_);
+        precond(p, st, Vj, Zj, wv, n_src, n_rhs, active, n_live_,
+                p->n_c > 0 ? w.cstep.as<float2>() + (size_t)j * n_rhs * p->n_c : nullptr);
         ProfScope arn(p, 2, n_live_);
         double2 *part = w.partial.as<double2>();
         const int *ro = w.reorth.as<int>();
@@ -1477,6 +1483,10 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         }
         launch_backsolve(s, w.H.as<float2>(), m, m, w.gam.as<float2>(), w.kcyc.as<int>(), w.y.as<float2>(), n_rhs);
         launch_xupdate(s, x, Z, vstride, w.y.as<float2>(), m, w.kcyc.as<int>(), N, n_rhs);
+        if (p->n_c > 0)
+            launch_coarse_cycle_end(s, x, p->d_tiles.as<TileDesc>(), p->d_owner.as<int>(), p->kc,
+                                    p->d_phi.as<float2>(), p->box_wl_stride, w.cstep.as<float2>(), w.y.as<float2>(), m,
+                                    w.kcyc.as<int>(), p->n_c, w.cy.as<double2>(), p->nx, p->ny, n_rhs, n_src);
     }
     HIPCHK(ctx, hipGetLastError());
     if (E_dev)

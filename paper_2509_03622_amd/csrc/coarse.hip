@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void coarse_update_kernel(const TileDesc *__re
     const float2 *Pb = Phibox + wl * wl_stride;
     const float2 *Wb = Wbox + wl * wl_stride;
     const long long g = (long long)r * nx * ny + cell;
-    z[g] = cadd(z[g], box_sum(t, Pb, kc, cr + own * kc, x, y));
+    if (z) z[g] = cadd(z[g], box_sum(t, Pb, kc, cr + own * kc, x, y));     // null: Phi c deferred to the cycle end
     float2 acc = box_sum(t, Wb, kc, cr + own * kc, x, y);
     if (x == t.cx0 && x > 0) {
         const int nb = owner[cell - 1];
@@ -161,6 +161,62 @@ void launch_coarse_update(hipStream_t s, const TileDesc *tiles, const int *owner
     dim3 grid((nx + 63) / 64, (ny + 3) / 4, n_rhs);
     hipLaunchKernelGGL(coarse_update_kernel, grid, dim3(64, 4), 0, s, tiles, owner, kc, Phibox, Wbox, box_wl_stride,
                        c, n_c, z, w, nx, ny, n_src, active);
+}
+
+// Deferred coarse part of the preconditioned directions: within a restart
+// cycle z_j = z1_j + Phi c_j keeps only z1_j and stores c_j, and the cycle's
+// update x += sum_j y_j z_j takes the coarse part as x += Phi (sum_j y_j c_j).
+// cy[r][col] = sum_{j < kcyc[r]} y[r][j] c_j[r][col] (FP64), then x += Phi cy
+// on every core.
+__global__ __launch_bounds__(256) void coarse_cy_kernel(const float2 *__restrict__ C, long long cstride,
+                                                        const float2 *__restrict__ y, int m,
+                                                        const int *__restrict__ kcyc, int n_c,
+                                                        double2 *__restrict__ cy) {
+    const int r = blockIdx.y, col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= n_c) return;
+    const int k = kcyc[r];
+    double sx = 0.0, sy = 0.0;
+    for (int j = 0; j < k; ++j) {
+        const float2 a = y[r * m + j], c = C[j * cstride + (long long)r * n_c + col];
+        sx += (double)a.x * c.x - (double)a.y * c.y;
+        sy += (double)a.x * c.y + (double)a.y * c.x;
+    }
+    cy[(long long)r * n_c + col] = make_double2(sx, sy);
+}
+
+__global__ __launch_bounds__(256) void coarse_x_kernel(double2 *__restrict__ x, const TileDesc *__restrict__ tiles,
+                                                       const int *__restrict__ owner, int kc,
+                                                       const float2 *__restrict__ Phibox, long long wl_stride,
+                                                       const double2 *__restrict__ cy, int n_c, int nx, int ny,
+                                                       int n_src, const int *__restrict__ kcyc) {
+    const int r = blockIdx.z;
+    if (kcyc[r] == 0) return;
+    const int xx = blockIdx.x * 64 + threadIdx.x, yy = blockIdx.y * 4 + threadIdx.y;
+    if (xx >= nx || yy >= ny) return;
+    const long long cell = (long long)yy * nx + xx;
+    const int own = owner[cell];
+    const TileDesc t = tiles[own];
+    const float2 *Pb = Phibox + (r / n_src) * wl_stride + t.box_off;
+    const int e = (yy - t.by0) * t.bw + (xx - t.bx0);
+    const long long colstride = (long long)t.bw * t.bh;
+    const double2 *c = cy + (long long)r * n_c + (long long)own * kc;
+    double sx = 0.0, sy = 0.0;
+    for (int l = 0; l < kc; ++l) {
+        const float2 ph = Pb[l * colstride + e];
+        sx += (double)ph.x * c[l].x - (double)ph.y * c[l].y;
+        sy += (double)ph.x * c[l].y + (double)ph.y * c[l].x;
+    }
+    double2 &xv = x[(long long)r * nx * ny + cell];
+    xv = make_double2(xv.x + sx, xv.y + sy);
+}
+
+void launch_coarse_cycle_end(hipStream_t s, double2 *x, const TileDesc *tiles, const int *owner, int kc,
+                             const float2 *Phibox, long long box_wl_stride, const float2 *C, const float2 *y, int m,
+                             const int *kcyc, int n_c, double2 *cy, int nx, int ny, int n_rhs, int n_src) {
+    hipLaunchKernelGGL(coarse_cy_kernel, dim3((n_c + 255) / 256, n_rhs), dim3(256), 0, s, C, (long long)n_rhs * n_c, y,
+                       m, kcyc, n_c, cy);
+    hipLaunchKernelGGL(coarse_x_kernel, dim3((nx + 63) / 64, (ny + 3) / 4, n_rhs), dim3(64, 4), 0, s, x, tiles, owner,
+                       kc, Phibox, box_wl_stride, cy, n_c, nx, ny, n_src, kcyc);
 }
 
 }  // namespace nosdd

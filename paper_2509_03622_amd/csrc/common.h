@@ -209,6 +209,9 @@ void launch_coarse_solve(hipStream_t s, const double2 *GinvT, int n_c, const dou
 void launch_coarse_update(hipStream_t s, const TileDesc *tiles, const int *owner, int kc, const float2 *Phibox,
                           const float2 *Wbox, long long box_wl_stride, const float2 *c, int n_c, float2 *z, float2 *w,
                           int nx, int ny, int n_rhs, int n_src, const int *active);
+void launch_coarse_cycle_end(hipStream_t s, double2 *x, const TileDesc *tiles, const int *owner, int kc,
+                             const float2 *Phibox, long long box_wl_stride, const float2 *C, const float2 *y, int m,
+                             const int *kcyc, int n_c, double2 *cy, int nx, int ny, int n_rhs, int n_src);
 
 // ------------------------------------------------------------ neural subdomain solver
 // One sample = one (subdomain, RHS) pair: tile geometry and where its vectors live.

@@ -64,6 +64,10 @@ def test_core_list_is_bitwise_the_tensor_partition():
         Q.precond_apply(dev(v), z, Az, 2)
         outs.append((host(z), host(Az)))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    # the autotuner times the Gram-Schmidt grid per problem, and a different
+    # grid sums the dots in another order: fixed launch parameters for both
+    P.autotune(False)
+    P2.autotune(False)
     E1, h1, it1, f1, s1 = P.solve(w.J(), tol=1e-6, max_iters=600)
     E2, h2, it2, f2, s2 = P2.solve(w.J(), tol=1e-6, max_iters=600)
     assert s1 == 0 and s2 == 0
