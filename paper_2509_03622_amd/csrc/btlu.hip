@@ -347,7 +347,12 @@ __device__ __forceinline__ float2 bt_matvec(const float4 (&slot)[2 * NJ], const 
 // The recurrence of one wave: G lanes per row pair, NJ offset slots per lane,
 // the factor blocks prefetched NS - 1 steps ahead.  Every wave of the
 // workgroup runs the same steps and barriers; only the lane mapping differs.
-template <int NJ, int NS, int G>
+// U = 0: each lane loads its own sub-blocks into a register ring (every
+// off-diagonal sub-block is then fetched by two groups).  U > 0: the
+// workgroup copies each block once, U 16-byte chunks per thread, through a
+// register ring into one of two LDS stages behind vl, and the lanes read
+// their sub-blocks from there (half the vector-memory instructions).
+template <int NJ, int NS, int G, int U>
 __device__ __forceinline__ void bt_run(const TileDesc &t, int rp, int cg, int tid, const float2 *__restrict__ D,
                                        long long bbytes, int nx, bool local_out, float2 *__restrict__ orr,
                                        float2 *__restrict__ vl, float2 (*ysh)[BT_BMAX + 2],
@@ -374,9 +379,35 @@ __device__ __forceinline__ void bt_run(const TileDesc &t, int rp, int cg, int ti
     }
     const __amdgpu_buffer_rsrc_t rs = bt_rsrc(D, (unsigned)(nb * bbytes));
     const unsigned half = (unsigned)(bbytes >> 1);         // second columns of the sub-blocks
-    float4 ring[NS][2 * NJ];
+    constexpr int RW = U > 0 ? U : 2 * NJ;                 // ring entries per thread and block
+    float4 ring[NS][RW];
+    // staged form: chunk tid + u * nthr of the block (clamped: surplus threads
+    // re-read the last chunk and store nothing)
+    const int nthr = blockDim.x, nchunk = (int)(bbytes >> 4), SZ = (nchunk + 63) & ~63;
+    float4 *stg = reinterpret_cast<float4 *>(vl + nb * b);
+    unsigned coff[U > 0 ? U : 1];
 #pragma unroll
-    for (int i = 0; i < NS - 1; ++i) bt_load<NJ>(ring[i], rs, (unsigned)(blk(min(i, nsteps - 1)) * bbytes), off, half);
+    for (int u = 0; u < (U > 0 ? U : 1); ++u) coff[u] = (unsigned)min(tid + u * nthr, nchunk - 1) * 16u;
+    auto load = [&](float4 (&rr)[RW], int s) {
+        const unsigned bo = (unsigned)(blk(min(s, nsteps - 1)) * bbytes);
+        if constexpr (U > 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                rr[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, coff[u], bo, 0));
+        } else {
+            bt_load<NJ>(rr, rs, bo, off, half);
+        }
+    };
+    auto stage = [&](const float4 (&rr)[RW], int st) {
+        if constexpr (U > 0) {
+            float4 *dst = stg + st * SZ;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (tid + u * nthr < nchunk) dst[tid + u * nthr] = rr[u];
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < NS - 1; ++i) load(ring[i], i);
 
     // lanes 0 and 1 of each group carry the recurrence for rows 2rp and 2rp + 1
     const int myr = 2 * rp + (cg & 1);
@@ -406,6 +437,7 @@ __device__ __forceinline__ void bt_run(const TileDesc &t, int rp, int cg, int ti
         okr = t.x0 + myr >= t.cx0 && t.x0 + myr < t.cx1;
     }
     const bool emit_lane = wr && okr;
+    stage(ring[0], 0);
     __syncthreads();
     const float2 si = wr ? si_s[myr] : make_float2(0.f, 0.f);
     if (wr) ysh[0][myr] = cmul(cmul(si, so_s[0]), vl[myr]);      // S_0 v_0
@@ -413,7 +445,19 @@ __device__ __forceinline__ void bt_run(const TileDesc &t, int rp, int cg, int ti
     __syncthreads();
 
     const bool keep1 = (((cg & 7) ^ ((cg & 7) >> 2)) & 1) != 0;
-    auto step = [&](int s, const float4(&slot)[2 * NJ]) {
+    auto step = [&](int s, const float4(&regs)[RW]) {
+        float4 slot[2 * NJ];
+        if constexpr (U > 0) {
+            const float4 *sb = stg + (s & 1) * SZ;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                slot[2 * j] = sb[off[j] >> 4];
+                slot[2 * j + 1] = sb[(off[j] + half) >> 4];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2 * NJ; ++q) slot[q] = regs[q];
+        }
         const int k = blk(s);
         const int p = s & 1;
         const bool fwd = s < nb;
@@ -437,24 +481,30 @@ __device__ __forceinline__ void bt_run(const TileDesc &t, int rp, int cg, int ti
         __syncthreads();
     };
 
-    // steady state: step s uses ring[s % NS] and refills the slot of step s - 1
-    // with the block of step s + NS - 1 (clamped at the end: a re-read)
+    // steady state: step s refills the ring entry of step s - 1 with the block
+    // of step s + NS - 1 (clamped at the end: a re-read); the register form
+    // then uses ring[s % NS], the staged form first stores block s + 1 (loaded
+    // NS - 2 steps ago) into LDS stage (s + 1) & 1 and reads block s from stage
+    // s & 1, the step's closing barrier publishing the new stage
     int s0 = 0;
     for (; s0 + NS <= nsteps; s0 += NS) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-            bt_load<NJ>(ring[(i + NS - 1) % NS], rs, (unsigned)(blk(min(s0 + i + NS - 1, nsteps - 1)) * bbytes), off,
-                        half);
+            load(ring[(i + NS - 1) % NS], s0 + i + NS - 1);
+            stage(ring[(i + 1) % NS], (s0 + i + 1) & 1);
             step(s0 + i, ring[i]);
         }
     }
     // tail: fewer than NS steps left, their blocks are already in the ring
 #pragma unroll
     for (int i = 0; i < NS - 1; ++i)
-        if (s0 + i < nsteps) step(s0 + i, ring[i]);
+        if (s0 + i < nsteps) {
+            stage(ring[(i + 1) % NS], (s0 + i + 1) & 1);
+            step(s0 + i, ring[i]);
+        }
 }
 
-template <int NJ, int NS, int NJT>
+template <int NJ, int NS, int NJT, int U>
 __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restrict__ tiles, int n_src,
                                                        const float2 *__restrict__ dinv, long long dinv_wl_stride,
                                                        const float2 *__restrict__ coef,
@@ -510,46 +560,73 @@ __global__ __launch_bounds__(512) void bt_solve_kernel(const TileDesc *__restric
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (NJT > 0 && rest > 0 && rest <= 4 && wave == full) {
         const int l = tid - 64 * full;
-        bt_run<(NJT > 0 ? NJT : 1), NS, 16>(t, 8 * full + (l >> 4), l & 15, tid, D, bbytes, nx, local_out, orr, vl,
+        bt_run<(NJT > 0 ? NJT : 1), NS, 16, U>(t, 8 * full + (l >> 4), l & 15, tid, D, bbytes, nx, local_out, orr, vl,
                                           ysh, cl_s, ch_s, so_s, si_s);
     } else {
-        bt_run<NJ, NS, 8>(t, tid >> 3, tid & 7, tid, D, bbytes, nx, local_out, orr, vl, ysh, cl_s, ch_s, so_s, si_s);
+        bt_run<NJ, NS, 8, U>(t, tid >> 3, tid & 7, tid, D, bbytes, nx, local_out, orr, vl, ysh, cl_s, ch_s, so_s, si_s);
     }
 }
 
-template <int NJ, int NS>
+template <int NJ, int NS, int U>
 static void bt_solve_launch(hipStream_t s, dim3 grid, int threads, size_t lds, const TileDesc *tiles, int n_src,
                             const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc,
                             int nx, int ny, const float2 *vin, long long vin_stride, float2 *out,
                             long long out_stride, const int *active, int mode, const int2 *order) {
-    hipLaunchKernelGGL((bt_solve_kernel<NJ, NS, bt_tail_nj(NJ)>), grid, dim3(threads), lds, s, tiles, n_src, dinv, dinv_wl_stride,
-                       coef, sc, nx, ny, vin, vin_stride, out, out_stride, active, mode, order);
+    hipLaunchKernelGGL((bt_solve_kernel<NJ, NS, bt_tail_nj(NJ), U>), grid, dim3(threads), lds, s, tiles, n_src, dinv,
+                       dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride, out, out_stride, active, mode, order);
 }
 
 static int bt_nj(int bmax) { return ((bmax / 2) + BT_GROUP - 1) / BT_GROUP; }
+static int bt_threads(int bmax) { return ((bmax / 2) * BT_GROUP + 63) / 64 * 64; }
+
+// Dynamic LDS of the solve: the gathered subdomain (max_cells complex values)
+// and, in the staged form, two stages of the widest block's 16-byte chunks.
+static size_t bt_lds_bytes(int bmax, int max_cells, bool staged) {
+    size_t l = (size_t)max_cells * sizeof(float2);
+    if (staged) l += 2 * (size_t)(((bmax * (bmax + 2) / 4) + 63) & ~63) * 16;
+    return l;
+}
+constexpr size_t BT_DYN_LDS_MAX = 150 * 1024;     // 160 KB per CU, less the static arrays
+
+// Chunks per thread of the staged form (4, 5 or 6), or 0 for the register
+// form: blocks up to 80 cells whose two stages fit in LDS beside the subdomain.
+static int bt_stage_u(int bmax, int max_cells) {
+    if (bt_nj(bmax) > 5) return 0;
+    const int nthr = bt_threads(bmax);
+    const int u = (bmax * (bmax + 2) / 4 + nthr - 1) / nthr;
+    if (u > 6 || bt_lds_bytes(bmax, max_cells, true) > BT_DYN_LDS_MAX) return 0;
+    return u < 4 ? 4 : u;
+}
 
 // Kernels that need more than 64 KB of dynamic LDS must say so once per
 // process, before any launch (and outside graph capture).
 void bt_solve_prepare(int bmax, int max_cells) {
-    const size_t lds = (size_t)max_cells * sizeof(float2);
+    const int u = bt_stage_u(bmax, max_cells);
+    const size_t lds = bt_lds_bytes(bmax, max_cells, u > 0);
     if (lds <= 65536) return;
     const int nj = bt_nj(bmax);
     const void *fs[3];
     int nf = 0;
-    if (nj <= 5) {
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 3, bt_tail_nj(5)>);
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 4, bt_tail_nj(5)>);
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 5, bt_tail_nj(5)>);
+    if (u == 4) {
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 4, bt_tail_nj(5), 4>);
+    } else if (u == 5) {
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 4, bt_tail_nj(5), 5>);
+    } else if (u == 6) {
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 4, bt_tail_nj(5), 6>);
+    } else if (nj <= 5) {
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 3, bt_tail_nj(5), 0>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 4, bt_tail_nj(5), 0>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<5, 5, bt_tail_nj(5), 0>);
     } else if (nj <= 7) {
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<7, 3, bt_tail_nj(7)>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<7, 3, bt_tail_nj(7), 0>);
     } else {
-        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<8, 3, bt_tail_nj(8)>);
+        fs[nf++] = reinterpret_cast<const void *>(&bt_solve_kernel<8, 3, bt_tail_nj(8), 0>);
     }
     for (int i = 0; i < nf; ++i) (void)hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 // Prefetch depths available for a block size (the register ring holds NS - 1
-// blocks ahead); the first is the default.
+// blocks ahead); the first is the default.  The staged form always runs depth 4.
 int bt_solve_depths(int bmax, int *depths) {
     if (bt_nj(bmax) <= 5) {
         depths[0] = 4;
@@ -566,22 +643,29 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, in
                      int ny, const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
                      const int *active, int mode, int bmax, int max_cells, int depth) {
     dim3 grid(n_jobs);
-    const int threads = ((bmax / 2) * BT_GROUP + 63) / 64 * 64;
+    const int threads = bt_threads(bmax);
     const int nj = bt_nj(bmax);
-    const size_t lds = (size_t)max_cells * sizeof(float2);
+    const int u = bt_stage_u(bmax, max_cells);
+    const size_t lds = bt_lds_bytes(bmax, max_cells, u > 0);
 #define BT_ARGS s, grid, threads, lds, tiles, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride, out, \
                 out_stride, active, mode, order
-    if (nj <= 5) {
+    if (u == 4) {
+        bt_solve_launch<5, 4, 4>(BT_ARGS);
+    } else if (u == 5) {
+        bt_solve_launch<5, 4, 5>(BT_ARGS);
+    } else if (u == 6) {
+        bt_solve_launch<5, 4, 6>(BT_ARGS);
+    } else if (nj <= 5) {
         if (depth == 3)
-            bt_solve_launch<5, 3>(BT_ARGS);
+            bt_solve_launch<5, 3, 0>(BT_ARGS);
         else if (depth == 5)
-            bt_solve_launch<5, 5>(BT_ARGS);
+            bt_solve_launch<5, 5, 0>(BT_ARGS);
         else
-            bt_solve_launch<5, 4>(BT_ARGS);
+            bt_solve_launch<5, 4, 0>(BT_ARGS);
     } else if (nj <= 7) {
-        bt_solve_launch<7, 3>(BT_ARGS);
+        bt_solve_launch<7, 3, 0>(BT_ARGS);
     } else {
-        bt_solve_launch<8, 3>(BT_ARGS);
+        bt_solve_launch<8, 3, 0>(BT_ARGS);
     }
 #undef BT_ARGS
 }
