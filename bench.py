@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -75,10 +76,11 @@ def local_solve_bytes(lx, ly, core):
 
 
 def kernel_hash():
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2509_03622_amd", "csrc", "btlu.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+    """Hash of the subdomain-solve source without its // comments and blank
+    lines: a change of code, not of commentary, invalidates the stored counters."""
+    with open(os.path.join(ROOT, "paper_2509_03622_amd", "csrc", "btlu.hip"), encoding="utf-8") as f:
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in f.read().splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln).encode()).hexdigest()[:16]
 
 
 def read_traffic(units_per_launch):

@@ -233,12 +233,15 @@ void launch_bt_factor(hipStream_t s, const TileDesc *tiles, int n_tiles, int n_w
 // ------------------------------------------------------------------ solve
 // Thread layout per (subdomain, RHS) workgroup: lane group rp (8 lanes) owns
 // rows 2rp, 2rp+1 of every block; lane cg of the group takes the column pairs
-// q = (rp + d) mod P for the offsets d = cg + 8 j.  For each it loads one 2 x 2
+// q = (rp + d) mod P for the offsets d = cg + 8 j.  For each it takes one 2 x 2
 // sub-block of M_k (two float4), directly (q >= rp) or as the transpose of the
-// stored sub-block (q, rp); every off-diagonal sub-block is therefore read by
-// two groups in the same step, once from HBM and once from cache.  For a fixed
-// d the groups of a wave read consecutive entries of one storage row, so the
-// loads coalesce.  The 8 lanes' partial sums are combined with three DPP
+// stored sub-block (q, rp), so every off-diagonal sub-block is used by two
+// groups in the same step.  Blocks up to 80 cells are copied once per step
+// into LDS by the whole workgroup and the lanes read their sub-blocks there
+// (staged form); wider blocks are loaded by each lane from global memory, a
+// sub-block then coming once from HBM and once from cache.  For a fixed d the
+// groups of a wave read consecutive entries of one storage row, so the loads
+// coalesce.  The 8 lanes' partial sums are combined with three DPP
 // steps and lanes 0 and 1 of the group run the recurrence for rows 2rp and
 // 2rp + 1.  A workgroup of more than four waves puts two waves on one SIMD;
 // when its last wave would be at most half full (P mod 8 <= 4), that wave
