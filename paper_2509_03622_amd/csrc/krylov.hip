@@ -61,24 +61,28 @@ __device__ __forceinline__ void block_sum(double2 (&acc)[NV], int nv, double2 *r
 }
 
 // One Givens step for RHS r (column j of H holds h_{0..j,j}; ||w'||^2 = nw).
-__device__ void givens_step(const GivensArgs &a, int r, int j, double nw) {
+// The column and the earlier rotations are read through `col`, `csr`, `snr`
+// (global memory, or LDS copies made by the calling workgroup), and the
+// rotated column is written to H.
+template <typename HC, typename CS, typename SN>
+__device__ void givens_core(const GivensArgs &a, int r, int j, double nw, HC col, CS csr, SN snr) {
     const int m = a.m;
     float2 *Hr = a.H + (long long)r * (m + 1) * m;
     const float hn = (float)sqrt(nw);
-    Hr[(j + 1) * m + j] = make_float2(hn, 0.f);
+    col(j + 1) = make_float2(hn, 0.f);
     float *cs = a.cs + r * m;
     float2 *sn = a.sn + r * m;
     for (int i = 0; i < j; ++i) {
-        const float2 hi = Hr[i * m + j], hi1 = Hr[(i + 1) * m + j];
-        const float c = cs[i];
-        const float2 s = sn[i];
+        const float2 hi = col(i), hi1 = col(i + 1);
+        const float c = csr(i);
+        const float2 s = snr(i);
         // t = c hi + s hi1 ; hi1' = -conj(s) hi + c hi1
         const float2 t = make_float2(c * hi.x + s.x * hi1.x - s.y * hi1.y, c * hi.y + s.x * hi1.y + s.y * hi1.x);
         const float2 u = make_float2(-(s.x * hi.x + s.y * hi.y) + c * hi1.x, -(s.x * hi.y - s.y * hi.x) + c * hi1.y);
-        Hr[i * m + j] = t;
-        Hr[(i + 1) * m + j] = u;
+        col(i) = t;
+        col(i + 1) = u;
     }
-    const float2 av = Hr[j * m + j], bv = Hr[(j + 1) * m + j];
+    const float2 av = col(j), bv = col(j + 1);
     const float aa = sqrtf(cabs2(av));
     float c;
     float2 s;
@@ -93,8 +97,9 @@ __device__ void givens_step(const GivensArgs &a, int r, int j, double nw) {
     }
     cs[j] = c;
     sn[j] = s;
-    Hr[j * m + j] = make_float2(c * av.x + s.x * bv.x - s.y * bv.y, c * av.y + s.x * bv.y + s.y * bv.x);
-    Hr[(j + 1) * m + j] = make_float2(0.f, 0.f);
+    col(j) = make_float2(c * av.x + s.x * bv.x - s.y * bv.y, c * av.y + s.x * bv.y + s.y * bv.x);
+    col(j + 1) = make_float2(0.f, 0.f);
+    for (int i = 0; i <= j + 1; ++i) Hr[i * m + j] = col(i);
     float2 *g = a.gam + r * (m + 1);
     const float2 gj = g[j];
     g[j + 1] = make_float2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
@@ -112,6 +117,15 @@ __device__ void givens_step(const GivensArgs &a, int r, int j, double nw) {
     a.flags[r] = fl;
     a.inv_h[r] = hn > 0.f ? 1.f / hn : 0.f;
     if (fl) a.active[r] = 0;
+}
+
+__device__ void givens_step(const GivensArgs &a, int r, int j, double nw) {
+    float2 *Hr = a.H + (long long)r * (a.m + 1) * a.m;
+    const float *cs = a.cs + r * a.m;
+    const float2 *sn = a.sn + r * a.m;
+    const int m = a.m;
+    givens_core(a, r, j, nw, [&](int i) -> float2 & { return Hr[i * m + j]; }, [&](int i) { return cs[i]; },
+                [&](int i) { return sn[i]; });
 }
 
 // Gram-Schmidt dots pass: per-workgroup partials of h_i = V_i^H w (i < NV) and
@@ -322,8 +336,16 @@ __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode
         return;
     }
     const double hsq = sh_h, h = sqrt(hsq), sc = sh_s;
+    // the Givens step runs on LDS copies of the column and of the earlier
+    // rotations (one dependent LDS access per rotation instead of a global round trip)
+    __shared__ float2 hcol[KR_SLOTS], snl[KR_MAXV];
+    __shared__ float csl[KR_MAXV];
+    if (t < col) {
+        csl[t] = ga.cs[r * m + t];
+        snl[t] = ga.sn[r * m + t];
+    }
     if (t < nv) {
-        Hr[t * m + col] = cadd(Hr[t * m + col], make_float2((float)hv[t].x, (float)hv[t].y));
+        hcol[t] = cadd(Hr[t * m + col], make_float2((float)hv[t].x, (float)hv[t].y));
         double gx = 0.0, gy = 0.0;
         for (int i = t; i < nv; ++i) {
             const double2 a = Ts[t][i], q = hv[i];
@@ -334,7 +356,9 @@ __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode
     }
     if (t == 0) Tr[(col + 1) * ld + col + 1] = h > 0.0 ? make_double2(1.0 / (sc * h), 0.0) : make_double2(0.0, 0.0);
     __syncthreads();
-    if (t == 0) givens_step(ga, r, col, hsq);
+    if (t == 0)
+        givens_core(ga, r, col, hsq, [&](int i) -> float2 & { return hcol[i]; }, [&](int i) { return csl[i]; },
+                    [&](int i) { return snl[i]; });
 }
 
 __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *__restrict__ partial, int nblk, int nv,
