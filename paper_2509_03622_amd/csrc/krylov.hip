@@ -312,7 +312,8 @@ __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode
             const double n2 = vals[KR_MAXV].x;
             ga.nw_pre_w[r] = n2;
             const double e = n2 - hn;
-            ga.scale[r] = n2 > 0.0 ? (float)(1.0 / sqrt(e > 1e-20 * n2 ? e : 1e-20 * n2)) : 1.f;
+            // clamped so that a vanishing w (a breakdown, stopped by the Givens step) cannot overflow FP32
+            ga.scale[r] = n2 > 0.0 ? (float)fmin(1.0 / sqrt(e > 1e-20 * n2 ? e : 1e-20 * n2), 1e30) : 1.f;
         } else {
             const double n2 = vals[KR_MAXV].x * inv_s * inv_s;
             const double e = n2 > hn ? n2 - hn : 0.0;
