@@ -1654,14 +1654,29 @@ static nosdd_status problem_create_impl(nosdd_ctx *ctx, const nosdd_grid *g, con
     // neighbours: tiles whose extended rectangle grown by one cell (the ghost
     // nodes of its ring) meets this tile's, in index order; every interface
     // entry that touches a tile belongs to one of them
+    // (candidates: the owners of the cells within ext + 1 of the extended
+    // tile, since a neighbour's extended tile grown by one lies within ext + 1
+    // of its core; linear in the grid, whatever the number of cores)
     const int nt = (int)p->tiles.size();
     p->nbrs.assign(nt, {});
+    std::vector<int> seen(nt, -1);
     for (int i = 0; i < nt; ++i) {
         const TileDesc &t = p->tiles[i];
-        for (int j = 0; j < nt; ++j) {
+        const int gx0 = std::max(t.x0 - ext - 1, 0), gx1 = std::min(t.x1 + ext + 1, gnx);
+        const int gy0 = std::max(t.y0 - ext - 1, 0), gy1 = std::min(t.y1 + ext + 1, gny);
+        std::vector<int> cand;
+        for (int y = gy0; y < gy1; ++y)
+            for (int x = gx0; x < gx1; ++x) {
+                const int j = p->owner[(size_t)y * gnx + x];
+                if (j != i && seen[j] != i) {
+                    seen[j] = i;
+                    cand.push_back(j);
+                }
+            }
+        std::sort(cand.begin(), cand.end());
+        for (const int j : cand) {
             const TileDesc &u = p->tiles[j];
-            if (j != i && u.x0 - 1 < t.x1 && t.x0 < u.x1 + 1 && u.y0 - 1 < t.y1 && t.y0 < u.y1 + 1)
-                p->nbrs[i].push_back(j);
+            if (u.x0 - 1 < t.x1 && t.x0 < u.x1 + 1 && u.y0 - 1 < t.y1 && t.y0 < u.y1 + 1) p->nbrs[i].push_back(j);
         }
     }
     p->loc_total = loc;

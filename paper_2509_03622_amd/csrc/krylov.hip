@@ -556,26 +556,39 @@ void launch_cgs_update_scale(hipStream_t s, const float2 *V, long long vstride, 
     }
 }
 
-__global__ void backsolve_kernel(const float2 *H, int m, const float2 *gam, const int *kcyc, float2 *y, int n_rhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rhs) return;
+// y = R^-1 gamma for the k x k upper triangle of the rotated H, one workgroup
+// per RHS: the triangle and gamma are staged in LDS, then one thread runs the
+// substitution in the usual order (no dependent global round trips).
+__global__ __launch_bounds__(64) void backsolve_kernel(const float2 *H, int m, const float2 *gam, const int *kcyc,
+                                                       float2 *y) {
+    __shared__ float2 Hs[KR_MAXV][KR_MAXV + 1];
+    __shared__ float2 gs[KR_MAXV], ys[KR_MAXV];
+    const int r = blockIdx.x;
     const int k = kcyc[r];
     const float2 *Hr = H + (long long)r * (m + 1) * m;
-    const float2 *g = gam + r * (m + 1);
-    float2 *yr = y + r * m;
-    for (int i = k - 1; i >= 0; --i) {
-        float2 s = g[i];
-        for (int l = i + 1; l < k; ++l) s = cfms(s, Hr[i * m + l], yr[l]);
-        const float2 d = Hr[i * m + i];
-        const float dd = cabs2(d);
-        yr[i] = make_float2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd);
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        const int i = e / k, l = e - i * k;
+        if (l >= i) Hs[i][l] = Hr[i * m + l];
     }
+    if (threadIdx.x < k) gs[threadIdx.x] = gam[r * (m + 1) + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = k - 1; i >= 0; --i) {
+            float2 s = gs[i];
+            for (int l = i + 1; l < k; ++l) s = cfms(s, Hs[i][l], ys[l]);
+            const float2 d = Hs[i][i];
+            const float dd = cabs2(d);
+            ys[i] = make_float2((s.x * d.x + s.y * d.y) / dd, (s.y * d.x - s.x * d.y) / dd);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < k) y[r * m + threadIdx.x] = ys[threadIdx.x];
 }
 
 void launch_backsolve(hipStream_t s, const float2 *H, int ldh, int m, const float2 *gam, const int *kcyc, float2 *y,
                       int n_rhs) {
     (void)ldh;
-    hipLaunchKernelGGL(backsolve_kernel, dim3((n_rhs + 63) / 64), dim3(64), 0, s, H, m, gam, kcyc, y, n_rhs);
+    hipLaunchKernelGGL(backsolve_kernel, dim3(n_rhs), dim3(64), 0, s, H, m, gam, kcyc, y);
 }
 
 // x += sum_{i < kcyc[r]} y_i Z_i  (x in FP64; the FP32 products are accumulated in FP64)
