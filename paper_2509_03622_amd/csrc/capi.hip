@@ -145,6 +145,7 @@ struct nosdd_problem {
     std::vector<hipGraphExec_t> gexec;
     std::vector<long long> gkey;
     int *h_flags = nullptr;                       // pinned: active flags of steps of either parity
+    int *d_flags = nullptr;                       // the same memory as seen from the device
     int h_flags_n = 0;
     hipEvent_t gev[2] = {nullptr, nullptr};
     void drop_graphs() {
@@ -1253,6 +1254,7 @@ nosdd_status ensure_graphs(nosdd_problem *p, int n_rhs, int n_src, int m, const 
         p->h_flags = nullptr;
         p->h_flags_n = 0;
         HIPCHK(ctx, hipHostMalloc((void **)&p->h_flags, 2 * (size_t)n_rhs * sizeof(int), hipHostMallocDefault));
+        HIPCHK(ctx, hipHostGetDevicePointer((void **)&p->d_flags, p->h_flags, 0));
         p->h_flags_n = n_rhs;
         ++g_alloc_gen;
     }
@@ -1271,9 +1273,12 @@ nosdd_status ensure_graphs(nosdd_problem *p, int n_rhs, int n_src, int m, const 
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-        step(cs, j, n_rhs);
-        hipError_t e = hipMemcpyAsync(p->h_flags + (j & 1) * n_rhs, w.active.p, n_rhs * sizeof(int),
-                                      hipMemcpyDeviceToHost, cs);
+        // the host reads the step's active flags from pinned memory: written by
+        // the step's last reduction in the stored-basis form, copied otherwise
+        step(cs, j, n_rhs, p->stored_basis ? p->d_flags + (j & 1) * n_rhs : nullptr);
+        hipError_t e = p->stored_basis ? hipSuccess
+                                       : hipMemcpyAsync(p->h_flags + (j & 1) * n_rhs, w.active.p, n_rhs * sizeof(int),
+                                                        hipMemcpyDeviceToHost, cs);
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -1325,6 +1330,7 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     ga.hist_ld = std::max(1, o->max_iters);
     ga.inv_h = w.inv_h.as<float>();
     ga.flags = w.flags.as<int>();
+    ga.host_flags = nullptr;
     ga.T = w.T.as<double2>();
     ga.G1 = w.G1.as<float2>();
     ga.scale = w.scale.as<float>();
@@ -1376,7 +1382,7 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     // v_{j+1} = (w' - V h2) / h_{j+1,j} with a third pass.  Every argument is
     // fixed for the solve, so the step can be captured in a graph.
     const bool stored_basis = p->stored_basis;
-    auto step = [&](hipStream_t st, int j, int n_live_) {
+    auto step = [&](hipStream_t st, int j, int n_live_, int *host_flags = nullptr) {
         float2 *Vj = V + j * vstride, *Vn = V + (j + 1) * vstride, *Zj = Z + j * vstride;
         precond(p, st, Vj, Zj, wv, n_src, n_rhs, active, n_live_,
                 p->n_c > 0 ? w.cstep.as<float2>() + (size_t)j * n_rhs * p->n_c : nullptr);
@@ -1390,7 +1396,9 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
             launch_cgs_reduce(st, part, nb, j + 1, n_rhs, active, j, 6, nullptr, ga);
             launch_cgs_update_dots(st, V, vstride, j + 1, wv, Vn, N, n_rhs, active, w.G1.as<float2>(), m, j, part,
                                    nb, w.scale.as<float>());
-            launch_cgs_reduce(st, part, nb, j + 1, n_rhs, active, j, 7, nullptr, ga);
+            GivensArgs g7 = ga;
+            g7.host_flags = host_flags;
+            launch_cgs_reduce(st, part, nb, j + 1, n_rhs, active, j, 7, nullptr, g7);
             return;
         }
         launch_cgs_reduce(st, part, nb, j + 1, n_rhs, active, j, 1, nullptr, ga);

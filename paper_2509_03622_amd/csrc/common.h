@@ -180,6 +180,7 @@ struct GivensArgs {
     // first-pass coefficients on the stored vectors (layout of H); scale the
     // factor the first-pass update applies to the vector it stores
     double2 *T; float2 *G1; float *scale;
+    int *host_flags;                  // nullable: pinned host copy of active[] written by the last reduction of a step
 };
 void launch_cgs_dots(hipStream_t s, const float2 *V, long long vstride, int nv, const float2 *w, long long N,
                      int n_rhs, const int *gate, double2 *partial, int nblk);

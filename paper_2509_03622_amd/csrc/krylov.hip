@@ -357,9 +357,11 @@ __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode
     }
     if (t == 0) Tr[(col + 1) * ld + col + 1] = h > 0.0 ? make_double2(1.0 / (sc * h), 0.0) : make_double2(0.0, 0.0);
     __syncthreads();
-    if (t == 0)
+    if (t == 0) {
         givens_core(ga, r, col, hsq, [&](int i) -> float2 & { return hcol[i]; }, [&](int i) { return csl[i]; },
                     [&](int i) { return snl[i]; });
+        if (ga.host_flags) ga.host_flags[r] = ga.active[r];     // read by the host once the step has completed
+    }
 }
 
 __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *__restrict__ partial, int nblk, int nv,
@@ -371,7 +373,10 @@ __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *
         if (threadIdx.x == 0) ga.reorth[r] = 0;
         return;
     }
-    if (gate && !gate[r]) return;
+    if (gate && !gate[r]) {
+        if (mode == 7 && ga.host_flags && threadIdx.x == 0) ga.host_flags[r] = 0;
+        return;
+    }
     const int ns = (mode == 1 || mode == 3 || mode == 5 || mode == 6 || mode == 7) ? nv : 0;
     const double2 *pr = partial + (long long)r * nblk * KR_SLOTS;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
