@@ -125,3 +125,28 @@ def test_autotuned_launch_parameters_keep_the_result():
     assert np.linalg.norm(E1 - E0) <= 2e-6 * np.linalg.norm(E0)
     P.close()
     ctx.close()
+
+
+def test_single_subdomain_is_an_exact_solve():
+    """One subdomain covering the grid (no interfaces, no Robin data, no coarse
+    space): the preconditioner is the exact inverse, so FGMRES converges in one
+    iteration, Algorithm 3 in one sweep, both to the direct solution."""
+    import torch
+    from gpu_common import make_gpu_problem, rel
+    from oracle.fdfd import assemble_A, solve_direct, source_rhs
+    w = random_small(44, 64, 64, [64], [64], wavelengths=(1.0, 1.3), npml=8, k_coarse=1)
+    ctx, P = make_gpu_problem(w)
+    assert P.sizes()[2] == 0 and P.sizes()[3] == 0          # no interface entries, no coarse columns
+    E, hist, it, fin, st = P.solve(w.J(), tol=1e-6, max_iters=50)
+    assert st == 0 and np.all(it == 1), it
+    J = torch.from_numpy(w.J()).cuda()
+    E2 = torch.zeros((2, 1, 64, 64), dtype=torch.complex64, device="cuda")
+    hist2, it2, fin2, st2 = P.solve_paper(J, E2, tol=1e-5, max_iters=5)
+    assert st2 == 0 and np.all(it2 == 1), it2
+    E2 = E2.cpu().numpy()
+    for wi, lam in enumerate(w.wavelengths):
+        xs = solve_direct(assemble_A(w.eps, lam, w.h, w.npml), source_rhs(w.J()[0], lam))
+        assert rel(E[wi, 0].ravel(), xs) < 1e-5
+        assert rel(E2[wi, 0].ravel(), xs) < 1e-5
+    P.close()
+    ctx.close()
