@@ -160,3 +160,15 @@ def test_quadtree_paper_loop(qt):
     assert rel(0.3 * g + 0.7 * gn + rc.correction(gn - g, 0.3), gs) < 1e-10
     x, n, hist, g = paper_loop(P.locs, P.A, b, momentum=0.3, coarse=rc, tol=1e-6, max_iters=300)
     assert n < 300 and hist[-1] <= 1e-6 and rel(x, xs) < 1e-5
+
+
+def test_quadtree_two_way_split_worked_by_hand():
+    """160 x 32 vacuum, cores of at most 48 cells and halves of at least 16:
+    the root splits four ways into 80 x 16 quadrants; those are still longer
+    than 48 but their 16-cell height cannot be halved, so each splits in two
+    along x into 40 x 16 leaves."""
+    from paper_2509_03622_amd.workloads import quadtree_cores
+    cores = quadtree_cores(160, 32, np.ones((32, 160)), 0.05, 1.0, min_core=16, max_core=48)
+    assert cores == [(0, 40, 0, 16), (40, 80, 0, 16), (80, 120, 0, 16), (120, 160, 0, 16),
+                     (0, 40, 16, 32), (40, 80, 16, 32), (80, 120, 16, 32), (120, 160, 16, 32)]
+    Partition.from_cores(160, 32, cores, 8, npml=0)
