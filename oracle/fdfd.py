@@ -94,7 +94,7 @@ def point_source(nx, ny, ix=None, iy=None):
 
 
 def solve_direct(A, b):
-    """x* = A^-1 b by sparse LU (SuperLU), the judge of every field."""
+    """x* = A^-1 b by sparse LU (SuperLU), the reference for every field."""
     lu = spla.splu(A.tocsc())
     if b.ndim == 1:
         return lu.solve(b)

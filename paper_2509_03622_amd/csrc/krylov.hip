@@ -257,6 +257,7 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float
 //           second update runs; that update then writes v_{j+1} directly);
 //   modes 6, 7  the two passes on the stored basis (stored_basis_step).
 constexpr int RED_THREADS = 1024;
+static_assert(KR_MAXV * KR_MAXV <= RED_THREADS && KR_MAXV <= 64, "one thread per entry of T, one wave for ||h||^2");
 
 // Two-pass classical Gram-Schmidt on the stored basis (modes 6 and 7).  The
 // orthonormal basis is V = Vs T (Vs the stored vectors, T upper triangular,
@@ -276,7 +277,35 @@ constexpr int RED_THREADS = 1024;
 // never rewritten, and the preconditioner of the next step is applied to it
 // (flexible GMRES takes any direction z; the relation A Z = V H holds with V
 // the orthonormal basis above).
-__device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode, int r, const GivensArgs &ga) {
+// The operands of the step that do not depend on this step's dots (entry e =
+// threadIdx.x of the leading nv x nv block of T, and for mode 7 the earlier
+// rotations and the first-pass column of H), loaded before the partial sums
+// so that their latency overlaps that of the reduction.
+struct StepOperands {
+    double2 t;
+    float cs;
+    float2 sn, hc;
+};
+__device__ __forceinline__ StepOperands stored_basis_operands(int nv, int col, int mode, int r, const GivensArgs &ga) {
+    const int m = ga.m, ld = m + 1, t = threadIdx.x;
+    StepOperands o = {make_double2(0.0, 0.0), 1.f, make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    if (t < nv * nv) {
+        const int k = t / nv, i = t - k * nv;
+        o.t = (mode == 6 && col == 0) ? make_double2(1.0, 0.0)            // v_0 is stored normalised
+              : (k <= i ? ga.T[(long long)r * ld * ld + k * ld + i] : make_double2(0.0, 0.0));
+    }
+    if (mode == 7) {
+        if (t < col) {
+            o.cs = ga.cs[r * m + t];
+            o.sn = ga.sn[r * m + t];
+        }
+        if (t < nv) o.hc = ga.H[(long long)r * (m + 1) * m + t * m + col];
+    }
+    return o;
+}
+
+__device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode, int r, const GivensArgs &ga,
+                                  const StepOperands &op) {
     __shared__ double2 hv[KR_SLOTS];
     __shared__ double2 Ts[KR_MAXV][KR_MAXV];       // the leading nv x nv block of T (upper triangle)
     __shared__ double sh_s, sh_h;
@@ -284,13 +313,8 @@ __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode
     double2 *Tr = ga.T + (long long)r * ld * ld;
     float2 *Hr = ga.H + (long long)r * (m + 1) * m;
     const int t = threadIdx.x;
-    // stage T in LDS with whole-workgroup loads (the triangular products below
-    // would otherwise walk its columns with one dependent global load per term)
-    for (int e = t; e < nv * nv; e += blockDim.x) {
-        const int k = e / nv, i = e - k * nv;
-        Ts[k][i] = (mode == 6 && col == 0) ? make_double2(1.0, 0.0)        // v_0 is stored normalised
-                   : (k <= i ? Tr[k * ld + i] : make_double2(0.0, 0.0));
-    }
+    // T staged in LDS (the triangular products below walk its columns)
+    if (t < nv * nv) Ts[t / nv][t % nv] = op.t;
     if (mode == 6 && col == 0 && t == 0) Tr[0] = make_double2(1.0, 0.0);
     __syncthreads();
     const double inv_s = mode == 7 ? 1.0 / (double)ga.scale[r] : 1.0;
@@ -305,16 +329,15 @@ __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode
         hv[t] = make_double2(sx * inv_s, sy * inv_s);
     }
     __syncthreads();
-    if (t == 0) {
-        double hn = 0.0;
-        for (int i = 0; i < nv; ++i) hn += hv[i].x * hv[i].x + hv[i].y * hv[i].y;
-        if (mode == 6) {
+    if (t < 64) {                                     // nv <= KR_MAXV <= 64: one wave sums ||h||^2
+        const double hn = wave_sum(t < nv ? hv[t].x * hv[t].x + hv[t].y * hv[t].y : 0.0);
+        if (t == 0 && mode == 6) {
             const double n2 = vals[KR_MAXV].x;
             ga.nw_pre_w[r] = n2;
             const double e = n2 - hn;
             // clamped so that a vanishing w (a breakdown, stopped by the Givens step) cannot overflow FP32
             ga.scale[r] = n2 > 0.0 ? (float)fmin(1.0 / sqrt(e > 1e-20 * n2 ? e : 1e-20 * n2), 1e30) : 1.f;
-        } else {
+        } else if (t == 0) {
             const double n2 = vals[KR_MAXV].x * inv_s * inv_s;
             const double e = n2 > hn ? n2 - hn : 0.0;
             sh_h = e;
@@ -342,11 +365,11 @@ __device__ void stored_basis_step(const double2 *vals, int nv, int col, int mode
     __shared__ float2 hcol[KR_SLOTS], snl[KR_MAXV];
     __shared__ float csl[KR_MAXV];
     if (t < col) {
-        csl[t] = ga.cs[r * m + t];
-        snl[t] = ga.sn[r * m + t];
+        csl[t] = op.cs;
+        snl[t] = op.sn;
     }
     if (t < nv) {
-        hcol[t] = cadd(Hr[t * m + col], make_float2((float)hv[t].x, (float)hv[t].y));
+        hcol[t] = cadd(op.hc, make_float2((float)hv[t].x, (float)hv[t].y));
         double gx = 0.0, gy = 0.0;
         for (int i = t; i < nv; ++i) {
             const double2 a = Ts[t][i], q = hv[i];
@@ -378,6 +401,9 @@ __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *
         return;
     }
     const int ns = (mode == 1 || mode == 3 || mode == 5 || mode == 6 || mode == 7) ? nv : 0;
+    const bool sb = mode == 6 || mode == 7;
+    StepOperands op;
+    if (sb) op = stored_basis_operands(nv, col, mode, r, ga);
     const double2 *pr = partial + (long long)r * nblk * KR_SLOTS;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int v = wid; v <= ns; v += RED_THREADS / 64) {
@@ -393,8 +419,8 @@ __global__ __launch_bounds__(RED_THREADS) void cgs_reduce_kernel(const double2 *
         if (lane == 0) vals[slot] = make_double2(sx, sy);
     }
     __syncthreads();
-    if (mode == 6 || mode == 7) {
-        stored_basis_step(vals, nv, col, mode, r, ga);
+    if (sb) {
+        stored_basis_step(vals, nv, col, mode, r, ga, op);
         return;
     }
     if (threadIdx.x != 0) return;
