@@ -59,7 +59,8 @@ typedef struct nosdd_problem nosdd_problem;
 /* Grid: nx * ny cells of size h; a PML of npml cells on every side with
  * conductivity profile sigma(d) = sigma_max d^pml_m and ideal reflection
  * exp(pml_lnR) (Methods, UPML equations).  Defaults used by the benchmarks:
- * h = 0.05, npml = 12, pml_m = 2, pml_lnR = -30. */
+ * h = 0.05, npml = 12, pml_m = 2, pml_lnR = -30.  nx, ny >= 4 and
+ * nx * ny < 2^29 (NOSDD_EINVAL otherwise). */
 typedef struct {
     int nx, ny;
     double h;

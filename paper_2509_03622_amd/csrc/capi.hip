@@ -1578,6 +1578,8 @@ static nosdd_status problem_create_impl(nosdd_ctx *ctx, const nosdd_grid *g, con
                                         int n_wl, nosdd_problem **out) {
     if (g->nx < 4 || g->ny < 4 || !(g->h > 0) || g->npml < 0 || 2 * g->npml >= std::min(g->nx, g->ny) || g->pml_m < 0)
         return fail(ctx, NOSDD_EINVAL, "invalid grid");
+    if ((long long)g->nx * g->ny >= (1LL << 29))          // byte offsets within a vector stay 32-bit
+        return fail(ctx, NOSDD_EINVAL, "grid too large: at most 2^29 - 1 cells");
     for (int i = 0; i < n_wl; ++i)
         if (!(wavelengths[i] > 0)) return fail(ctx, NOSDD_EINVAL, "wavelengths must be positive");
     if (cores.empty()) return fail(ctx, NOSDD_EPARTITION, "empty partition");

@@ -129,39 +129,53 @@ __device__ void givens_step(const GivensArgs &a, int r, int j, double nw) {
 }
 
 // Gram-Schmidt dots pass: per-workgroup partials of h_i = V_i^H w (i < NV) and
-// ||w||^2 (slot KR_MAXV), summed by cgs_reduce_kernel.
-template <int NV, int U>
+// ||w||^2 (slot KR_MAXV), summed by cgs_reduce_kernel.  Software-pipelined:
+// the NV + 1 loads of a thread's next cell are issued before the products of
+// the current one, so every wave keeps a cell's worth of loads in flight
+// through its arithmetic.  Byte offsets within a vector are 32-bit (grids
+// have fewer than 2^29 cells), so the loads take the vector bases as scalars.
+template <int NV>
 __global__ __launch_bounds__(KR_THREADS) void cgs_dots_kernel(const float2 *__restrict__ V, long long vstride,
                                                               const float2 *__restrict__ w, long long N,
                                                               const int *__restrict__ gate,
                                                               double2 *__restrict__ partial, int nblk) {
     __shared__ double2 red[(KR_THREADS / 64) * KR_SLOTS];
+    constexpr int NA = NV > 0 ? NV : 1;
     const int r = blockIdx.y;
     if (!gate[r]) return;
-    const float2 *wr = w + r * N;
-    const float2 *Vr = V + r * N;
-    float2 facc[NV > 0 ? NV : 1];
+    const char *wb = reinterpret_cast<const char *>(w + r * N);
+    const char *vb = reinterpret_cast<const char *>(V + r * N);
+    float2 facc[NA];
 #pragma unroll
     for (int i = 0; i < NV; ++i) facc[i] = make_float2(0.f, 0.f);
     float fn = 0.f;
-    // U cells per thread per trip, all loads of a trip issued before any use
-    const long long stride = (long long)gridDim.x * KR_THREADS * U;
-    for (long long n0 = (long long)blockIdx.x * KR_THREADS * U + threadIdx.x; n0 < N; n0 += stride) {
-        float2 wv[U], vv[U][NV > 0 ? NV : 1];
+    // cells past the end load as zeros, which add nothing
+    auto load = [&](float2 &wv, float2 (&vv)[NA], long long n) {
+        if (n < N) {
+            const unsigned off = (unsigned)n * 8u;
+            wv = *reinterpret_cast<const float2 *>(wb + off);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const long long n = n0 + (long long)u * KR_THREADS;
-            const bool in = n < N;
-            wv[u] = in ? wr[n] : make_float2(0.f, 0.f);
+            for (int i = 0; i < NV; ++i) vv[i] = *reinterpret_cast<const float2 *>(vb + i * vstride * 8 + off);
+        } else {
+            wv = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int i = 0; i < NV; ++i) vv[u][i] = in ? Vr[i * vstride + n] : make_float2(0.f, 0.f);
+            for (int i = 0; i < NV; ++i) vv[i] = make_float2(0.f, 0.f);
         }
+    };
+    auto use = [&](const float2 &wv, const float2 (&vv)[NA]) {
+        fn += cabs2(wv);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            fn += cabs2(wv[u]);
-#pragma unroll
-            for (int i = 0; i < NV; ++i) facc[i] = cfma_conj(facc[i], vv[u][i], wv[u]);
-        }
+        for (int i = 0; i < NV; ++i) facc[i] = cfma_conj(facc[i], vv[i], wv);
+    };
+    const long long stride = (long long)gridDim.x * KR_THREADS;
+    long long n = (long long)blockIdx.x * KR_THREADS + threadIdx.x;
+    float2 wa, va[NA], wn, vn[NA];
+    load(wa, va, n);
+    for (; n < N; n += 2 * stride) {
+        load(wn, vn, n + stride);
+        use(wa, va);
+        load(wa, va, n + 2 * stride);
+        use(wn, vn);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -489,8 +503,8 @@ void launch_cgs_dots(hipStream_t s, const float2 *V, long long vstride, int nv, 
     switch (nv) {
 #define CASE(K)                                                                                                  \
     case K:                                                                                                      \
-        hipLaunchKernelGGL((cgs_dots_kernel<K, (K > 16 ? 2 : 1)>), grid, dim3(KR_THREADS), 0, s, V, vstride, w, N, \
-                           gate, partial, nblk);                                                                 \
+        hipLaunchKernelGGL((cgs_dots_kernel<K>), grid, dim3(KR_THREADS), 0, s, V, vstride, w, N, gate, partial,    \
+                           nblk);                                                                                \
         break;
         NOSDD_NV_CASES(CASE)
 #undef CASE
