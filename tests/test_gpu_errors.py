@@ -31,6 +31,22 @@ def test_invalid_partitions_are_rejected():
     assert e.value.status == -1
 
 
+def test_grid_beyond_the_cell_limit_is_rejected():
+    # 2^15 x 2^14 = 2^29 cells, the smallest grid past the limit; rejected before eps is read
+    import ctypes as C
+    nosdd, ctx = _ctx()
+    L = ctx.L
+    eps = np.ones(16, np.float32)
+    g = nosdd.Grid(1 << 15, 1 << 14, 0.05, 12, 2, -30.0)
+    cx, cy = (C.c_int * 1)(1 << 15), (C.c_int * 1)(1 << 14)
+    part = nosdd.PartitionSpec(cx, 1, cy, 1, 8)
+    wl = np.ones(1, np.float64)
+    hp = C.c_void_p()
+    st = L.nosdd_problem_create(ctx.h, C.byref(g), eps.ctypes.data, C.byref(part), wl.ctypes.data, 1, C.byref(hp))
+    assert st == -1 and not hp.value
+    assert b"too large" in L.nosdd_last_error(ctx.h)
+
+
 def test_solve_before_setup_and_missing_weights():
     nosdd, ctx = _ctx()
     w = random_small(40, 128, 128, [64, 64], [64, 64])
