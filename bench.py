@@ -246,7 +246,7 @@ def main():
                     help="--nn-compare: only exact LU and two NN-FGMRES settings, all with one coarse function")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported "
               "(the path would shard over right-hand sides and subdomain slabs)", file=sys.stderr)
         sys.exit(2)
 
