@@ -220,7 +220,8 @@ def main():
     ap.add_argument("--max-iters", type=int, default=4000,
                     help="outer iteration cap per solve (a small cap shortens profiling runs; the line then "
                          "reports the solves as not converged)")
-    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--cpu-iters", type=int, default=200,
+                    help="outer iterations of the CPU oracle timed for cpu_baseline (about 12 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="accepted for compatibility; fields are checked by the tests")
     ap.add_argument("--no-stencil", action="store_true", help="skip the operator/residual roofline measurement")
