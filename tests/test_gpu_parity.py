@@ -7,7 +7,9 @@ Tolerances (complex64 arithmetic against complex128):
   factors formed in FP64; measured ~4e-7 on the hardest tiles);
 * whole solves: field within 1e-5 of the direct solution when the oracle's
   own FP64 Schwarz-FGMRES at the same tolerance is within 5e-6 of it, and
-  iteration counts within one of the oracle's.
+  iteration counts within one of the oracle's, also for restart lengths 7
+  and 31 (the largest Krylov dimension, with a full cycle before the
+  restart).
 """
 import numpy as np
 import pytest
@@ -154,6 +156,30 @@ def test_rect128_solve_matches_direct_and_oracle_iterations():
     h = hist[0, 0, :iters[0, 0]]
     np.testing.assert_allclose(h[:10], np.array(hist_o[:10]), rtol=2e-3)
     assert np.all(hist[0, 0, iters[0, 0]:] == -1)
+
+
+@pytest.mark.parametrize("restart", [7, 31])
+def test_restart_lengths_match_oracle(restart):
+    # 31 is the largest Krylov dimension the library takes: this one-level
+    # problem needs 48 iterations, so a whole cycle runs the Gram-Schmidt
+    # passes over 31 basis vectors before the restart
+    w = random_small(61, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.0,), npml=12, block=16)
+    ctx, P = make_gpu_problem(w, k_coarse=0)
+    E, hist, iters, fin, st = P.solve(w.J(), tol=1e-6, restart=restart, max_iters=1000)
+    assert st == 0
+    lam = w.wavelengths[0]
+    A = assemble_A(w.eps, lam, w.h, w.npml)
+    xs = solve_direct(A, source_rhs(w.J()[0], lam))
+    op = SchwarzProblem(w.eps, lam, w.h, w.npml, w.core_x, w.core_y, w.overlap)
+    xo, it_o, hist_o, res_o = op.solve(w.J()[0], tol=1e-6, restart=restart)
+    print(f"restart {restart}: GPU {int(iters[0, 0])} iterations, oracle {it_o}")
+    assert it_o > restart
+    assert rel(E[0, 0].ravel(), xs) < 1e-5
+    assert abs(int(iters[0, 0]) - it_o) <= 1
+    assert fin[0, 0] <= 1e-6
+    np.testing.assert_allclose(hist[0, 0, :10], np.array(hist_o[:10]), rtol=2e-3)
+    P.close()
+    ctx.close()
 
 
 def test_batched_wavelengths_and_sources_two_level():
