@@ -102,7 +102,10 @@ typedef struct {
 
 /* Outer flexible GMRES(restart) on A x = b, right-preconditioned by the
  * two-level Schwarz sweep.  Stops when ||b - A x|| / ||b|| <= tol (checked on
- * an explicit residual) or after max_iters preconditioner applications.
+ * an explicit residual) or after max_iters preconditioner applications; a
+ * right-hand side whose explicit residual did not decrease over a whole
+ * restart cycle is stopped early (stagnation: the solve then returns
+ * NOSDD_NOT_CONVERGED and nosdd_last_error says so).
  * x0 (nullable) is an initial guess laid out like E_out. */
 typedef struct {
     double tol;
@@ -120,7 +123,9 @@ void nosdd_ctx_destroy(nosdd_ctx *ctx);                /* NULL is accepted */
 const char *nosdd_last_error(const nosdd_ctx *ctx);
 
 /* Create a problem (destroy it before its context): eps is a host [ny][nx] real permittivity map (copied);
- * wavelengths[n_wl] are solved together, one operator per wavelength. */
+ * every entry must be finite and positive, since the Robin condition's local wavenumber k0 sqrt(eps) is
+ * taken real (NOSDD_EINVAL otherwise); wavelengths[n_wl] are solved together, one operator per
+ * wavelength. */
 nosdd_status nosdd_problem_create(nosdd_ctx *ctx, const nosdd_grid *grid, const float *eps,
                                   const nosdd_partition *part, const double *wavelengths,
                                   int n_wl, nosdd_problem **out);
@@ -146,7 +151,11 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *opts)
 void nosdd_problem_destroy(nosdd_problem *p);          /* NULL is accepted */
 
 /* Solve for n_src current densities J[n_src][ny][nx] (host) at every
- * wavelength.  Outputs (host): E_out[n_wl][n_src][ny][nx];
+ * wavelength: E = A^-1 (-i omega J) with A the Eq. 1 operator, by flexible
+ * GMRES(restart) preconditioned by one two-level Schwarz sweep per iteration
+ * (the Algorithm 3 loop body: subdomain Robin solves of Eq. 2 with exact LU
+ * or the Algorithm 1 network-preconditioned inner solver, then the coarse
+ * correction of the Methods two-level subsection).  Outputs (host): E_out[n_wl][n_src][ny][nx];
  * resid_hist[n_wl][n_src][max_iters] relative residual estimate after each
  * preconditioner application, -1 padded (nullable); iters[n_wl][n_src]
  * preconditioner applications (nullable); final_resid[n_wl][n_src] explicit
@@ -154,8 +163,9 @@ void nosdd_problem_destroy(nosdd_problem *p);          /* NULL is accepted */
 nosdd_status nosdd_solve(nosdd_problem *p, const nosdd_c32 *J, int n_src,
                          const nosdd_solve_opts *opts, nosdd_c32 *E_out, float *resid_hist,
                          int *iters, float *final_resid);
-/* Same as nosdd_solve, but J, x0 and E_out are device pointers, ordered on
- * the context stream; resid_hist, iters and final_resid stay host pointers.
+/* Same as nosdd_solve (Eq. 1 solved by the Algorithm 3 sweep inside
+ * flexible GMRES), but J, x0 and E_out are device pointers, ordered on the
+ * context stream; resid_hist, iters and final_resid stay host pointers.
  * This is the call whose time the benchmark reports (inputs resident in HBM). */
 nosdd_status nosdd_solve_device(nosdd_problem *p, const nosdd_c32 *J_dev, int n_src,
                                 const nosdd_solve_opts *opts, nosdd_c32 *E_dev, float *resid_hist,
@@ -313,6 +323,19 @@ nosdd_status nosdd_multi_source(nosdd_problem *p, int enable);
  * Daniel-Gragg-Kaufman-Stewart test asks for it and a third pass writes the
  * normalised vector.  Same Krylov space in exact arithmetic. */
 nosdd_status nosdd_stored_basis(nosdd_problem *p, int enable);
+
+/* Exact-LU fallback of the neural subdomain solver.  Every subdomain is
+ * factorised at set-up whatever the subdomain solver, so in each sweep of a
+ * problem set up with sub_solver = 1 an inner NN-FGMRES solve (one subdomain,
+ * one right-hand side) whose recurrence meets a NaN or Inf, or whose final
+ * residual estimate is not below 0.99 of its right-hand side's norm (the
+ * network did not reduce the subdomain residual), is replaced by the exact
+ * block-Thomas solve of that subdomain in the same sweep (Algorithm 1 leaves
+ * the inner solve's quality to the network; exact subdomain LU is the solver
+ * the network approximates).  *count receives the number of such
+ * replacements since the current or last solve began (sweeps and local
+ * solves outside a solve add to it); 0 for sub_solver = 0. */
+nosdd_status nosdd_fallback_count(const nosdd_problem *p, long long *count);
 
 /* Timing of the last solve (ms, GPU events): setup, total solve, iterations. */
 nosdd_status nosdd_last_timing(const nosdd_problem *p, double *setup_ms, double *solve_ms,

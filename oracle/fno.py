@@ -66,13 +66,34 @@ def idft_truncated(X, Lx, Ly, m):
     return out
 
 
-def fourier_block(u, R, W, bias, m, act=True):
-    """One block: act(W u + b + F^-1(R . F(u))).  R [2m][m][Cin][Cout] complex."""
+def round_bf16(a):
+    """Round to the nearest bfloat16 (ties to even) through float32, returned as float64.
+
+    Used only by the BF16 emulation of the forward pass: a matrix-core
+    product with BF16 operands and FP32 accumulation sees exactly these
+    operand values."""
+    a = np.asarray(a)
+    if np.iscomplexobj(a):
+        return round_bf16(a.real) + 1j * round_bf16(a.imag)
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
+
+
+def fourier_block(u, R, W, bias, m, act=True, bf16=False):
+    """One block: act(W u + b + F^-1(R . F(u))).  R [2m][m][Cin][Cout] complex.
+
+    bf16: the operands of the two channel mixes (the truncated spectrum X
+    before R, the activations u before W) are rounded to bfloat16, as a
+    matrix-core implementation with BF16 operands sees them; the transforms,
+    sums and bias stay exact."""
     C, Ly, Lx = u.shape
     X = dft_truncated(u, m)
+    if bf16:
+        X = round_bf16(X)
     Y = np.einsum("ikq,kqio->okq", X, R)
     spec = idft_truncated(Y, Lx, Ly, m)
-    pw = np.einsum("oi,iyx->oyx", W, u) + bias[:, None, None]
+    pw = np.einsum("oi,iyx->oyx", W, round_bf16(u) if bf16 else u) + bias[:, None, None]
     out = pw + spec
     return leaky(out) if act else out
 
@@ -91,8 +112,14 @@ def build_inputs(v, eps, k0h, inv_sx, inv_sy, ring_mask):
     return np.stack(ch).astype(np.float64), s
 
 
-def fno_forward(weights, v, eps, k0h, inv_sx, inv_sy, ring_mask):
-    """Apply the network to one local residual v [Ly][Lx]; returns e [Ly][Lx] complex."""
+def fno_forward(weights, v, eps, k0h, inv_sx, inv_sy, ring_mask, bf16=False):
+    """Apply the network to one local residual v [Ly][Lx]; returns e [Ly][Lx] complex.
+
+    bf16=True is the emulation of a BF16 matrix-core forward pass: the
+    operands of every learned channel mix (spectral mix, 1x1 mix, first
+    projection) are rounded to bfloat16 before the product, everything else
+    is exact (the lift, the transforms and the last projection are not
+    matrix-core products)."""
     wt = {k: np.asarray(a, dtype=np.float64) if not np.iscomplexobj(a) else np.asarray(a, np.complex128)
           for k, a in weights.items()}
     m = int(weights["modes"])
@@ -102,8 +129,9 @@ def fno_forward(weights, v, eps, k0h, inv_sx, inv_sy, ring_mask):
         return np.zeros_like(v, dtype=np.complex128)
     u = np.einsum("oi,iyx->oyx", wt["lift_w"], x) + wt["lift_b"][:, None, None]
     for l in range(nl):
-        u = fourier_block(u, wt[f"R{l}"], wt[f"W{l}"], wt[f"b{l}"], m, act=(l < nl - 1))
-    p = leaky(np.einsum("oi,iyx->oyx", wt["proj1_w"], u) + wt["proj1_b"][:, None, None])
+        u = fourier_block(u, wt[f"R{l}"], wt[f"W{l}"], wt[f"b{l}"], m, act=(l < nl - 1), bf16=bf16)
+    p = leaky(np.einsum("oi,iyx->oyx", wt["proj1_w"], round_bf16(u) if bf16 else u)
+              + wt["proj1_b"][:, None, None])
     o = np.einsum("oi,iyx->oyx", wt["proj2_w"], p) + wt["proj2_b"][:, None, None]
     return (o[0] + 1j * o[1]) * s
 

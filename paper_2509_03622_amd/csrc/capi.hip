@@ -115,6 +115,7 @@ struct nosdd_problem {
     int smp_rhs = 0;                              // samples built for this many RHS
     DevBuf nn_Vin, nn_Zin, nn_w, nn_beta, nn_vs, nn_os, nn_cs, nn_sact, nn_kstep, nn_gam, nn_H, nn_sn, nn_act0, nn_act1,
         nn_spec, nn_X, nn_Y;
+    DevBuf nn_fb, nn_fborder, nn_fbcount;          // exact-LU fallback of failed inner solves
     NnWork nw;
     double setup_ms = 0.0, solve_ms = 0.0;
     int last_iters = 0;
@@ -177,6 +178,17 @@ nosdd_status fail(nosdd_ctx *ctx, nosdd_status s, const std::string &msg) {
     if (ctx) ctx->err = msg;
     return s;
 }
+
+// Timing events and pinned host memory of one call, released on every return path.
+struct CallResources {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int *h_pinned = nullptr;
+    ~CallResources() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (h_pinned) (void)hipHostFree(h_pinned);
+    }
+};
 
 // ---------------------------------------------------------------- PML / stencil
 // s(q) = 1 - i sigma_hat d(q)^m,  sigma_hat = (m+1)(-lnR) / (2 k0 npml h),
@@ -645,6 +657,12 @@ nosdd_status ensure_nn(nosdd_problem *p, int n_rhs, int n_src) {
     HIPCHK(ctx, p->nn_spec.ensure(actb));
     HIPCHK(ctx, p->nn_X.ensure((size_t)512 * S * 128 * 4));
     HIPCHK(ctx, p->nn_Y.ensure((size_t)512 * S * 128 * 4));
+    HIPCHK(ctx, p->nn_fb.ensure((size_t)S * sizeof(int)));
+    HIPCHK(ctx, p->nn_fborder.ensure((size_t)S * sizeof(int2)));
+    if (!p->nn_fbcount.p) {
+        HIPCHK(ctx, p->nn_fbcount.ensure(sizeof(unsigned)));
+        HIPCHK(ctx, hipMemset(p->nn_fbcount.p, 0, sizeof(unsigned)));
+    }
     NnWork &nw = p->nw;
     nw.net = &p->net;
     nw.smp = p->d_smp.as<FnoSample>();
@@ -669,7 +687,25 @@ nosdd_status ensure_nn(nosdd_problem *p, int n_rhs, int n_src) {
     nw.spec = p->nn_spec.as<float>();
     nw.X = p->nn_X.as<float>();
     nw.Y = p->nn_Y.as<float>();
+    nw.fb = p->nn_fb.as<int>();
+    nw.fb_order = p->nn_fborder.as<int2>();
+    nw.fb_count = p->nn_fbcount.as<unsigned>();
     return NOSDD_OK;
+}
+
+// Inner NN-FGMRES on every (tile, RHS) sample, then the exact block-Thomas
+// solve of the samples it queued as failed (global or subdomain-local vectors
+// as in nn_precond; n_rhs * n_tiles fallback jobs, most of them empty).
+void nn_sweep(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, int n_rhs, int n_src, const int *active,
+              int local) {
+    const long long N = (long long)p->nx * p->ny;
+    const int nt = (int)p->tiles.size();
+    nn_precond(s, p->nw, p->d_tiles.as<TileDesc>(), nt, n_rhs, n_src, p->loc_total, p->max_cells, v, z, active,
+               p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->h, p->nx, p->ny, local);
+    const long long stride = local ? p->loc_total : N;
+    launch_bt_solve(s, p->d_tiles.as<TileDesc>(), p->nw.fb_order, n_rhs * nt, n_src, p->d_dinv.as<float2>(),
+                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, v, stride, z, stride,
+                    active, local ? 3 : 0, p->bmax, p->max_cells, p->bt_depth);
 }
 
 // Launch queue of the batched subdomain solve.  Jobs (tile, rhs) are grouped by
@@ -754,9 +790,7 @@ void precond(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, float2
     {
     ProfScope ps(p, 0, (long long)n_live * (long long)p->tiles.size());
     if (p->sub_solver == 1) {
-        nn_precond(s, p->nw, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), n_rhs, n_src, p->loc_total,
-                   p->max_cells, v, z, active, p->d_eps.as<float>(), p->d_coefd.as<double2>(), p->d_k0.as<double>(),
-                   p->h, p->nx, p->ny, 0);
+        nn_sweep(p, s, v, z, n_rhs, n_src, active, 0);
     } else
     local_sweep(p, s, v, z, n_rhs, n_src, active);
     }
@@ -1164,9 +1198,10 @@ nosdd_status autotune(nosdd_problem *p, int n_rhs, int n_src, int m, const Given
     const long long N = w.N;
     const long long vstride = (long long)n_rhs * N;
     float2 *V = w.V.as<float2>(), *wv = w.w.as<float2>(), *Z = w.Z.as<float2>();
-    hipEvent_t e0, e1;
-    HIPCHK(ctx, hipEventCreate(&e0));
-    HIPCHK(ctx, hipEventCreate(&e1));
+    CallResources res;
+    HIPCHK(ctx, hipEventCreate(&res.e0));
+    HIPCHK(ctx, hipEventCreate(&res.e1));
+    hipEvent_t e0 = res.e0, e1 = res.e1;
     auto time_ms = [&](auto &&launch) -> float {
         float t[3];
         launch();                                      // warm
@@ -1233,8 +1268,6 @@ nosdd_status autotune(nosdd_problem *p, int n_rhs, int n_src, int m, const Given
         p->bt_depth = pick;
         p->bt_tuned = true;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     HIPCHK(ctx, hipGetLastError());
     return NOSDD_OK;
 }
@@ -1334,10 +1367,10 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     ga.T = w.T.as<double2>();
     ga.G1 = w.G1.as<float2>();
     ga.scale = w.scale.as<float>();
-    hipEvent_t e0, e1;
-    HIPCHK(ctx, hipEventCreate(&e0));
-    HIPCHK(ctx, hipEventCreate(&e1));
-    HIPCHK(ctx, hipEventRecord(e0, s));
+    CallResources res;
+    HIPCHK(ctx, hipEventCreate(&res.e0));
+    HIPCHK(ctx, hipEventCreate(&res.e1));
+    HIPCHK(ctx, hipEventRecord(res.e0, s));
 
     double2 *x = w.x.as<double2>();
     float2 *b = w.b.as<float2>(), *V = w.V.as<float2>(), *Z = w.Z.as<float2>(),
@@ -1349,6 +1382,7 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
                        w.b64.as<double2>(), p->d_k0.as<double>(), N, n_src, j_per_rhs ? 1 : 0);
     hipLaunchKernelGGL(widen_kernel, dim3((unsigned)grid_blocks(vstride)), dim3(256), 0, s, x0_dev, x, vstride);
     HIPCHK(ctx, hipMemsetAsync(w.iters.p, 0, n_rhs * sizeof(int), s));
+    if (p->nn_fbcount.p) HIPCHK(ctx, hipMemsetAsync(p->nn_fbcount.p, 0, sizeof(unsigned), s));
     {
         const long long nh = (long long)n_rhs * std::max(1, o->max_iters);
         hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)grid_blocks(nh)), dim3(256), 0, s, w.hist.as<float>(), nh,
@@ -1367,8 +1401,13 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
 
     std::vector<int> iters(n_rhs, 0), want(n_rhs), act(n_rhs);
     std::vector<double> final_res(n_rhs, 0.0);
-    int *h_act = nullptr;
-    HIPCHK(ctx, hipHostMalloc((void **)&h_act, n_rhs * sizeof(int) * 2, hipHostMallocDefault));
+    // stagnation: a right-hand side whose explicit residual did not decrease
+    // over a whole restart cycle is stopped (status NOT_CONVERGED)
+    std::vector<double> prev_res(n_rhs, 0.0);
+    std::vector<char> ran(n_rhs, 0), stalled(n_rhs, 0);
+    int n_stalled = 0;
+    HIPCHK(ctx, hipHostMalloc((void **)&res.h_pinned, n_rhs * sizeof(int) * 2, hipHostMallocDefault));
+    int *h_act = res.h_pinned;
     nosdd_status result = NOSDD_OK;
     int total_outer = 0;
     const int *active = w.active.as<int>();
@@ -1412,25 +1451,16 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         const int2 *ord = nullptr;
         int nj = 0;
         nosdd_status so = solve_order(p, n_rhs, n_src, &ord, &nj);
-        if (so != NOSDD_OK) {
-            (void)hipHostFree(h_act);
-            return so;
-        }
+        if (so != NOSDD_OK) return so;
     }
     if (p->use_autotune) {
         nosdd_status ts = autotune(p, n_rhs, n_src, m, ga);
-        if (ts != NOSDD_OK) {
-            (void)hipHostFree(h_act);
-            return ts;
-        }
+        if (ts != NOSDD_OK) return ts;
     }
     const bool graphs = p->use_graphs && !p->prof;
     if (graphs) {
         nosdd_status gs = ensure_graphs(p, n_rhs, n_src, m, o, step);
-        if (gs != NOSDD_OK) {
-            (void)hipHostFree(h_act);
-            return gs;
-        }
+        if (gs != NOSDD_OK) return gs;
     }
     for (;;) {
         // explicit residual r = b - A x (FP64) into w, beta^2
@@ -1449,7 +1479,13 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
             const double rel = bn2[r] > 0 ? std::sqrt(beta2[r] / bn2[r]) : 0.0;
             final_res[r] = rel;
             if (!std::isfinite(rel)) return fail(ctx, NOSDD_ENONFINITE, "non-finite residual");
-            want[r] = (rel > o->tol && iters[r] < o->max_iters && bn2[r] > 0) ? 1 : 0;
+            if (ran[r] && !stalled[r] && rel > o->tol && rel >= prev_res[r]) {
+                stalled[r] = 1;
+                ++n_stalled;
+            }
+            want[r] = (!stalled[r] && rel > o->tol && iters[r] < o->max_iters && bn2[r] > 0) ? 1 : 0;
+            ran[r] = (char)want[r];
+            prev_res[r] = rel;
             any |= want[r];
         }
         if (!any) break;
@@ -1500,17 +1536,14 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
     if (E_dev)
         hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)grid_blocks(vstride)), dim3(256), 0, s, x, E_dev, vstride);
     if (E64_dev) HIPCHK(ctx, hipMemcpyAsync(E64_dev, x, (size_t)vstride * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    HIPCHK(ctx, hipEventRecord(e1, s));
+    HIPCHK(ctx, hipEventRecord(res.e1, s));
     HIPCHK(ctx, hipMemcpyAsync(iters.data(), w.iters.p, n_rhs * sizeof(int), hipMemcpyDeviceToHost, s));
     if (resid_hist && o->max_iters > 0)
         HIPCHK(ctx, hipMemcpyAsync(resid_hist, w.hist.p, (size_t)n_rhs * std::max(1, o->max_iters) * sizeof(float),
                                    hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipHostFree(h_act);
+    (void)hipEventElapsedTime(&ms, res.e0, res.e1);
     if (p->prof) prof_flush(p);
     p->solve_ms = ms;
     p->last_iters = total_outer;
@@ -1519,6 +1552,9 @@ nosdd_status solve_impl(nosdd_problem *p, const float2 *J_dev, int n_src, const 
         if (final_out) final_out[r] = (float)final_res[r];
         if (final_res[r] > o->tol) result = NOSDD_NOT_CONVERGED;
     }
+    if (n_stalled > 0)
+        ctx->err = std::to_string(n_stalled) + " right-hand side(s) stopped early: the explicit residual did not "
+                                                "decrease over a whole restart cycle";
     return result;
 }
 
@@ -1603,8 +1639,9 @@ static nosdd_status problem_create_impl(nosdd_ctx *ctx, const nosdd_grid *g, con
     for (const int o : owner)
         if (o < 0) return fail(ctx, NOSDD_EPARTITION, "cores do not cover the grid");
     if (cores.size() > 1 && ext + 1 > minc) return fail(ctx, NOSDD_EPARTITION, "overlap/2 + 1 exceeds a core");
+    // the Robin wavenumber kappa = k0 sqrt(eps) is real only for eps > 0
     for (int i = 0; i < gnx * gny; ++i)
-        if (!(std::isfinite(eps[i]))) return fail(ctx, NOSDD_EINVAL, "eps must be finite");
+        if (!(std::isfinite(eps[i]) && eps[i] > 0.f)) return fail(ctx, NOSDD_EINVAL, "eps must be finite and positive");
 
     nosdd_problem *p = new nosdd_problem();
     p->ctx = ctx;
@@ -1808,10 +1845,10 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
     if (o->sub_solver == 1 && (o->inner_max < 1 || o->inner_max > 8 || !(o->inner_tol >= 0.f)))
         return fail(ctx, NOSDD_EINVAL, "inner_max must be in [1, 8] and inner_tol >= 0");
     hipStream_t s = ctx->stream;
-    hipEvent_t e0, e1;
-    HIPCHK(ctx, hipEventCreate(&e0));
-    HIPCHK(ctx, hipEventCreate(&e1));
-    HIPCHK(ctx, hipEventRecord(e0, s));
+    CallResources res;
+    HIPCHK(ctx, hipEventCreate(&res.e0));
+    HIPCHK(ctx, hipEventCreate(&res.e1));
+    HIPCHK(ctx, hipEventRecord(res.e0, s));
     const int nwl = (int)p->wl.size();
     HIPCHK(ctx, p->d_dinv.ensure((size_t)nwl * p->dinv_wl_stride * sizeof(float2)));
     {
@@ -1887,12 +1924,10 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
         st = coarse_setup(p);
         if (st) return st;
     }
-    HIPCHK(ctx, hipEventRecord(e1, s));
-    HIPCHK(ctx, hipEventSynchronize(e1));
+    HIPCHK(ctx, hipEventRecord(res.e1, s));
+    HIPCHK(ctx, hipEventSynchronize(res.e1));
     float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)hipEventElapsedTime(&ms, res.e0, res.e1);
     p->setup_ms = ms;
     p->sub_solver = o->sub_solver;
     p->setup_done = true;
@@ -2181,9 +2216,7 @@ nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32
     if (p->sub_solver == 1) {
         st = ensure_nn(p, nwl, 1);
         if (st) return st;
-        nn_precond(p->ctx->stream, p->nw, p->d_tiles.as<TileDesc>(), (int)p->tiles.size(), nwl, 1, p->loc_total,
-                   p->max_cells, (const float2 *)rhs, (float2 *)u, nullptr, p->d_eps.as<float>(),
-                   p->d_coefd.as<double2>(), p->d_k0.as<double>(), p->h, p->nx, p->ny, 1);
+        nn_sweep(p, p->ctx->stream, (const float2 *)rhs, (float2 *)u, nwl, 1, nullptr, 1);
         HIPCHK(p->ctx, hipGetLastError());
         HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
         return NOSDD_OK;
@@ -2329,6 +2362,17 @@ nosdd_status nosdd_kernel_times(const nosdd_problem *p, double ms[4], long long 
         if (launches) launches[i] = p->prof_launch[i];
         if (units) units[i] = p->prof_units[i];
     }
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_fallback_count(const nosdd_problem *p, long long *count) {
+    if (!p || !count) return NOSDD_EINVAL;
+    *count = 0;
+    if (!p->nn_fbcount.p) return NOSDD_OK;
+    unsigned c = 0;
+    HIPCHK(p->ctx, hipMemcpyAsync(&c, p->nn_fbcount.p, sizeof(unsigned), hipMemcpyDeviceToHost, p->ctx->stream));
+    HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    *count = c;
     return NOSDD_OK;
 }
 

@@ -252,7 +252,18 @@ struct NnWork {
     float2 *gam = nullptr, *H = nullptr, *sn = nullptr;
     const float *aux = nullptr;                               // [wl][7][loc_total]
     float *act0 = nullptr, *act1 = nullptr, *spec = nullptr, *X = nullptr, *Y = nullptr;
+    // exact-LU fallback: per-sample failure flag, the fallback job queue
+    // (tile, rhs) per sample ((-1, -1) where the inner solve is kept) and a
+    // running count of fallen-back samples
+    int *fb = nullptr;
+    int2 *fb_order = nullptr;
+    unsigned *fb_count = nullptr;
 };
+
+// An inner solve whose final residual estimate is not below this fraction of
+// its right-hand side's norm, or that meets a non-finite value, is replaced
+// by the exact subdomain LU solve in the same sweep.
+constexpr float NN_FALLBACK_RATIO = 0.99f;
 
 // Inverse-design gradient (adjoint.hip).  sc: per wavelength [s_x(nx) | s_y(ny)]
 // centre stretches; focal: (ix, iy) cells.
@@ -264,6 +275,9 @@ void launch_adjoint_grad(hipStream_t s, const float2 *E, const float2 *mu, long 
 // Inner NN-FGMRES on every (tile, RHS) sample.  local == 0: v and z are
 // global [n_rhs][N] vectors (gather over the extended subdomain, core-only
 // scatter); local != 0: v and z are subdomain-local [n_rhs][loc_total].
+// Samples that fail (see NN_FALLBACK_RATIO) leave z untouched and are listed
+// in nw.fb_order for an exact block-Thomas solve (launch_bt_solve over
+// n_rhs * n_tiles jobs) that the caller issues next.
 void nn_precond(hipStream_t st, const NnWork &nw, const TileDesc *tiles, int n_tiles, int n_rhs, int n_src,
                 long long loc_total, int max_cells, const float2 *v, float2 *z, const int *active, const float *eps,
                 const double2 *coef, const double *k0, double h, int nx, int ny, int local);

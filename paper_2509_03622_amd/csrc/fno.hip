@@ -14,8 +14,12 @@
 // and the per-mode complex mix R -- run on MFMA in BF16 with FP32
 // accumulation (v_mfma_f32_32x32x8_bf16): R is applied as the real 128 x 128
 // form of the complex 64 x 64 mix to (Re X_c, Im X_c) interleaved per
-// channel.  The truncated DFTs are separable FP32 sums in LDS with twiddle
-// tables precomputed per subdomain side.
+// channel.  The truncated DFTs are four batched FP32 MFMA contractions
+// (v_mfma_f32_32x32x2f32) against twiddle tables built on the host in FP64
+// per subdomain side: the y-transform first (it keeps 16 of the ly
+// frequencies), then the x-transform of those 16 rows, and the inverse in the
+// reverse order with the Hermitian weights of the real inverse folded into
+// its last table.
 #include "common.h"
 
 namespace nosdd {

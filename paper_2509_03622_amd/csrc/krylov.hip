@@ -1,9 +1,15 @@
 // Flexible GMRES building blocks (Algorithm 1 recurrence, batched over RHS).
 //
-// Orthogonalisation is classical Gram-Schmidt with one selective second pass
-// (Daniel-Gragg-Kaufman-Stewart test ||w'|| < 0.7 ||w||): with j basis vectors
-// a pass reads j+1 vectors for the dots and j+1 for the update and writes one,
-// so the Arnoldi traffic per step is about 8 (2 j + 5) bytes per cell.
+// Orthogonalisation is classical Gram-Schmidt applied twice.  Default
+// (stored-basis) form: the dots of pass one, then pass one's update fused with
+// pass two's dots; the second pass's correction and the normalisation are kept
+// in an upper-triangular FP64 map T from the stored vectors to the orthonormal
+// basis (dots against the basis are T^H times dots against the stored
+// vectors), so no third pass rewrites the new vector and a step moves about
+// 8 (2 j + 5) bytes per cell with j basis vectors.  Alternative form: the
+// second pass runs where the Daniel-Gragg-Kaufman-Stewart test
+// ||w'|| < 0.7 ||w|| asks for it, and a third pass writes the normalised
+// vector (about 8 (3 j + 8) bytes per cell).
 // Reductions are two-stage and fixed-order (no atomics): per-workgroup
 // partials in FP64, then one workgroup per RHS sums them, so results are
 // bit-reproducible run to run.

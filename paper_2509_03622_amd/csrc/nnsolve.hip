@@ -8,6 +8,10 @@
 //   u_i = Z_k y_k, and the core of u_i is written to the global vector.
 // The network always sees a unit-norm residual (its input scaling and output
 // scaling follow from the rms of a unit vector over the subdomain).
+// A sample whose recurrence meets a non-finite value, or whose final residual
+// estimate |gamma_k| / beta is not below NN_FALLBACK_RATIO, writes nothing and
+// is queued for the exact LU solve of its subdomain (the factors exist for
+// every subdomain), which the caller launches right after.
 #include <cmath>
 
 #include "common.h"
@@ -54,7 +58,7 @@ __global__ __launch_bounds__(256) void loc_start_kernel(const TileDesc *__restri
                                                         const int *__restrict__ active, float *__restrict__ beta,
                                                         float *__restrict__ vscale, float *__restrict__ oscale,
                                                         int *__restrict__ sact, int *__restrict__ kstep,
-                                                        float2 *__restrict__ gam, int maxk) {
+                                                        float2 *__restrict__ gam, int maxk, int *__restrict__ fb) {
     __shared__ double red[4];
     const int s = blockIdx.x;
     const int rhs = s / n_tiles, t = s - rhs * n_tiles;
@@ -76,6 +80,7 @@ __global__ __launch_bounds__(256) void loc_start_kernel(const TileDesc *__restri
         oscale[s] = 1.f / sqrtf((float)n);
         sact[s] = (on && b > 0) ? 1 : 0;
         kstep[s] = 0;
+        fb[s] = 0;
         for (int i = 0; i <= maxk; ++i) gam[s * (maxk + 1) + i] = make_float2(0.f, 0.f);
         gam[s * (maxk + 1)] = make_float2((float)b, 0.f);
     }
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(256) void loc_arnoldi_kernel(const TileDesc *__rest
                                                           float2 *__restrict__ H, float *__restrict__ cs,
                                                           float2 *__restrict__ sn, float2 *__restrict__ gam,
                                                           const float *__restrict__ beta, int *__restrict__ sact,
-                                                          int *__restrict__ kstep) {
+                                                          int *__restrict__ kstep, int *__restrict__ fb) {
     __shared__ double red[4];
     __shared__ double2 hs[NN_MAXK + 1];
     const int s = blockIdx.x;
@@ -208,7 +213,12 @@ __global__ __launch_bounds__(256) void loc_arnoldi_kernel(const TileDesc *__rest
     g[k] = make_float2(c * gj.x, c * gj.y);
     kstep[s] = k + 1;
     const float res = sqrtf(cabs2(g[k + 1])) / beta[s];
-    if (res <= tol || hn == 0.0) sact[s] = 0;
+    if (!(res <= 3.0e38f)) {              // NaN or Inf: stop and hand the sample to the exact solve
+        sact[s] = 0;
+        fb[s] = 1;
+    } else if (res <= tol || hn == 0.0) {
+        sact[s] = 0;
+    }
 }
 
 // u_i = Z y (y = R^-1 gamma over kstep columns); core cells -> global z, or
@@ -218,17 +228,29 @@ __global__ __launch_bounds__(256) void loc_finish_kernel(const TileDesc *__restr
                                                          const float2 *__restrict__ Zin, int maxk,
                                                          const float2 *__restrict__ H, const float2 *__restrict__ gam,
                                                          const int *__restrict__ kstep, const int *__restrict__ active,
-                                                         float2 *__restrict__ zout, long long N, int nx, int local) {
+                                                         float2 *__restrict__ zout, long long N, int nx, int local,
+                                                         const float *__restrict__ beta, const int *__restrict__ fb,
+                                                         int2 *__restrict__ fb_order, unsigned *__restrict__ fb_count) {
     __shared__ float2 y[NN_MAXK];
+    __shared__ int failed;
     const int s = blockIdx.x;
     const int rhs = s / n_tiles, t = s - rhs * n_tiles;
-    if (active && !active[rhs]) return;
+    if (active && !active[rhs]) {
+        if (threadIdx.x == 0) fb_order[s] = make_int2(-1, -1);
+        return;
+    }
     const TileDesc T = tiles[t];
     const int lx = T.x1 - T.x0, n = lx * (T.y1 - T.y0);
     const int k = kstep[s];
     if (threadIdx.x == 0) {
         const float2 *Hs = H + (long long)s * (maxk + 1) * maxk;
         const float2 *g = gam + s * (maxk + 1);
+        // no reduction of the subdomain residual, or a non-finite value: exact solve instead
+        const float fin = k > 0 ? sqrtf(cabs2(g[k])) / beta[s] : 0.f;
+        const int bad = fb[s] || !(fin < NN_FALLBACK_RATIO);
+        failed = bad;
+        fb_order[s] = bad ? make_int2(t, rhs) : make_int2(-1, -1);
+        if (bad) atomicAdd(fb_count, 1u);
         for (int i = k - 1; i >= 0; --i) {
             float2 acc = g[i];
             for (int l = i + 1; l < k; ++l) acc = cfms(acc, Hs[i * maxk + l], y[l]);
@@ -239,6 +261,7 @@ __global__ __launch_bounds__(256) void loc_finish_kernel(const TileDesc *__restr
         }
     }
     __syncthreads();
+    if (failed) return;
     const long long off = rhs * loc_total + T.loc_off;
     for (int c = threadIdx.x; c < n; c += 256) {
         const int yy = c / lx, xx = c - yy * lx;
@@ -263,17 +286,18 @@ void nn_precond(hipStream_t st, const NnWork &nw, const TileDesc *tiles, int n_t
     hipLaunchKernelGGL(loc_gather_kernel, dim3(cblk, S), dim3(256), 0, st, tiles, n_tiles, v, N, nx, loc_total, nw.Vin,
                        active, local);
     hipLaunchKernelGGL(loc_start_kernel, dim3(S), dim3(256), 0, st, tiles, n_tiles, loc_total, nw.Vin, active, nw.beta,
-                       nw.vscale, nw.oscale, nw.sact, nw.kstep, nw.gam, nw.maxk);
+                       nw.vscale, nw.oscale, nw.sact, nw.kstep, nw.gam, nw.maxk, nw.fb);
     for (int k = 0; k < nw.steps; ++k) {
         fno_forward(st, *nw.net, nw.smp, nw.sact, S, max_cells, nw.Vin + k * vstride, nw.vscale, nw.oscale, nw.aux,
                     loc_total, nw.act0, nw.act1, nw.spec, nw.X, nw.Y, nw.Zin + k * vstride);
         hipLaunchKernelGGL(loc_stencil_kernel, dim3(cblk, S), dim3(256), 0, st, tiles, n_tiles, n_src, loc_total,
                            nw.Zin + k * vstride, nw.w, eps, coef, k0, h, nx, ny, nw.sact);
         hipLaunchKernelGGL(loc_arnoldi_kernel, dim3(S), dim3(256), 0, st, tiles, n_tiles, loc_total, vstride, nw.Vin,
-                           nw.w, k, nw.maxk, nw.tol, nw.H, nw.cs, nw.sn, nw.gam, nw.beta, nw.sact, nw.kstep);
+                           nw.w, k, nw.maxk, nw.tol, nw.H, nw.cs, nw.sn, nw.gam, nw.beta, nw.sact, nw.kstep, nw.fb);
     }
     hipLaunchKernelGGL(loc_finish_kernel, dim3(S), dim3(256), 0, st, tiles, n_tiles, loc_total, vstride, nw.Zin,
-                       nw.maxk, nw.H, nw.gam, nw.kstep, active, z, N, nx, local);
+                       nw.maxk, nw.H, nw.gam, nw.kstep, active, z, N, nx, local, nw.beta, nw.fb, nw.fb_order,
+                       nw.fb_count);
 }
 
 // vscale = 1/rms(v_s), oscale = rms(v_s) per sample (rms over the subdomain's cells)

@@ -24,7 +24,7 @@ EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_p
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
            "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_multi_source", "nosdd_stored_basis", "nosdd_autotune", "nosdd_tuning",
-           "nosdd_fom_gradient_device"]
+           "nosdd_fom_gradient_device", "nosdd_fallback_count"]
 
 
 class Grid(C.Structure):
@@ -98,6 +98,7 @@ def load(path=LIBPATH):
         "nosdd_autotune": (i, [vp, i]),
         "nosdd_tuning": (i, [vp, vp]),
         "nosdd_fom_gradient_device": (i, [vp, vp, i, vp, i, C.POINTER(SolveOpts), C.POINTER(C.c_double), vp, vp]),
+        "nosdd_fallback_count": (i, [vp, C.POINTER(ll)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -350,6 +351,12 @@ class Problem:
         self.ctx.check(self.L.nosdd_kernel_times(self.h, ms.ctypes.data, la.ctypes.data, un.ctypes.data))
         return ms, la, un
 
+    def fallback_count(self):
+        """Inner NN-FGMRES solves replaced by the exact subdomain LU solve since the last solve began."""
+        c = C.c_longlong()
+        self.ctx.check(self.L.nosdd_fallback_count(self.h, C.byref(c)))
+        return int(c.value)
+
     def last_timing(self):
         s, v, i = C.c_double(), C.c_double(), C.c_int()
         self.ctx.check(self.L.nosdd_last_timing(self.h, C.byref(s), C.byref(v), C.byref(i)))
@@ -383,7 +390,13 @@ def _fom_function():
             torch.cuda.synchronize()
             P.close()
             ctx.close()
+            if st != OK:
+                # a gradient from fields that did not reach tol is not the gradient of the FoM
+                raise NosddError(st, "forward or adjoint solve stopped at max_iters "
+                                     f"(outer iterations forward {iters[0].ravel().tolist()}, "
+                                     f"adjoint {iters[1].ravel().tolist()})")
             ctx_.save_for_backward(grad.to(eps.device))
+            ctx_.iters = iters
             return torch.tensor(fom, dtype=torch.float64, device=eps.device)
 
         @staticmethod
@@ -396,5 +409,7 @@ def _fom_function():
 
 def figure_of_merit(eps, J, focal, spec):
     """Differentiable FoM(eps) (see FomGradient); spec holds the grid and partition:
-    h, npml, core_x, core_y, overlap, wavelengths (and optionally k_coarse, tol, max_iters)."""
+    h, npml, core_x, core_y, overlap, wavelengths (and optionally k_coarse, tol, max_iters).
+    Raises NosddError (status NOT_CONVERGED) when the forward or the adjoint solve
+    stops at max_iters before reaching tol."""
     return _fom_function().apply(eps, J, focal, spec)

@@ -75,3 +75,14 @@ def test_autograd_wrapper_returns_the_library_gradient():
     f.backward()
     assert abs(float(f.detach()) - fom) <= 1e-6 * fom
     assert rel(e.grad.cpu().numpy(), g) < 1e-6
+
+
+def test_autograd_wrapper_raises_when_a_solve_stops_at_max_iters():
+    """A gradient from fields that did not reach tol is refused, with both iteration counts."""
+    import torch
+    from paper_2509_03622_amd import nosdd
+    eps, J, focal, spec, rng = design_case(63)
+    spec = dict(spec, max_iters=5)
+    e = torch.from_numpy(eps).cuda().requires_grad_(True)
+    with pytest.raises(nosdd.NosddError, match="NOT_CONVERGED"):
+        nosdd.figure_of_merit(e, torch.from_numpy(J).cuda(), focal, spec)

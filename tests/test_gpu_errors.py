@@ -24,11 +24,12 @@ def test_invalid_partitions_are_rejected():
     with pytest.raises(nosdd.NosddError) as e:
         nosdd.Problem(ctx, eps, 0.05, 12, [64, 64], [64, 64], 7, [1.0])     # odd overlap
     assert e.value.status == -4
-    bad = eps.copy()
-    bad[3, 3] = np.nan
-    with pytest.raises(nosdd.NosddError) as e:
-        nosdd.Problem(ctx, bad, 0.05, 12, [64, 64], [64, 64], 8, [1.0])
-    assert e.value.status == -1
+    for v in (np.nan, 0.0, -2.0):               # kappa = k0 sqrt(eps) must be real
+        bad = eps.copy()
+        bad[3, 3] = v
+        with pytest.raises(nosdd.NosddError) as e:
+            nosdd.Problem(ctx, bad, 0.05, 12, [64, 64], [64, 64], 8, [1.0])
+        assert e.value.status == -1
 
 
 def test_grid_beyond_the_cell_limit_is_rejected():

@@ -1,9 +1,10 @@
 """GPU parity of the neural subdomain path, through the C ABI.
 
 * One network application (BF16 MFMA channel mixes with FP32 accumulation,
-  FP32 truncated DFTs) against the oracle's NumPy forward pass in FP64 on the
-  same BF16 weights: relative L2 error per subdomain below 3e-2 (BF16 rounding
-  of activations at every layer).
+  FP32 truncated DFTs) against the oracle's NumPy forward pass on the same
+  BF16 weights: relative L2 error per subdomain below 2e-2 against FP64
+  arithmetic and below 1e-3 against the oracle's BF16 emulation (operands of
+  the matrix-core products rounded where the kernels round them).
 * The inner NN-FGMRES (Algorithm 1, inference branch) on every subdomain
   against the oracle's FP64 flexible GMRES preconditioned by the oracle's
   forward pass: same iterate to 5e-2 (BF16 network), same residual reached,
@@ -64,38 +65,59 @@ def _problem(w, weights, steps=2, tol=0.1):
     return ctx, P
 
 
-def test_network_application_matches_oracle(random_weights):
-    w = random_small(31, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.1,), npml=12, block=16)
-    ctx, P = _problem(w, random_weights)
+def _ring_mask(tile):
+    mask = np.zeros((tile.ly, tile.lx))
+    if tile.iface["left"]:
+        mask[:, 0] = 1
+    if tile.iface["right"]:
+        mask[:, -1] = 1
+    if tile.iface["bottom"]:
+        mask[0, :] = 1
+    if tile.iface["top"]:
+        mask[-1, :] = 1
+    return mask
+
+
+@pytest.mark.parametrize("case", ["3x3_of_64", "ragged"])
+def test_network_application_matches_oracle(case, random_weights):
+    """Per subdomain: within 2e-2 (relative L2) of the FP64 forward pass on the
+    same weights, and within 1e-3 of its BF16 emulation (the operands of every
+    matrix-core product rounded to bfloat16 as the kernels round them).
+    Tile shapes: 68x68 corners, 68x72 and 72x68 edges, 72x72 interior (3 x 3
+    cores of 64), and ragged 36..72-cell sides (cores 32, 44, 60, 56)."""
+    if case == "3x3_of_64":
+        w = random_small(31, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.1,), npml=12, block=16)
+    else:
+        w = random_small(35, 192, 160, [32, 44, 60, 56], [40, 64, 56], wavelengths=(0.9,), npml=12, block=8)
+    ctx, P = _problem(w, _weights(random_weights))
     nt, lc, ne, nc = P.sizes()
     rng = np.random.default_rng(5)
     v = rng.standard_normal((1, lc)) + 1j * rng.standard_normal((1, lc))
     e = dev(np.zeros_like(v))
     P.nn_apply(dev(v), e)
     e = host(e)[0]
-    wt = load_weights(random_weights)
+    wt = load_weights(_weights(random_weights))
     lam = w.wavelengths[0]
     k0 = 2 * np.pi / lam
-    sc, _ = pml_stretch(w.nx, w.npml, w.pml_m, w.pml_lnR, k0, w.h)
+    scx, _ = pml_stretch(w.nx, w.npml, w.pml_m, w.pml_lnR, k0, w.h)
+    scy, _ = pml_stretch(w.ny, w.npml, w.pml_m, w.pml_lnR, k0, w.h)
     part = Partition(w.nx, w.ny, w.core_x, w.core_y, w.overlap, w.npml)
-    worst = 0.0
+    worst64 = worst16 = 0.0
+    shapes = set()
     for t, tile in enumerate(part.tiles):
         off = P.tile_info(t)[8]
         n = tile.lx * tile.ly
         vt = v[0, off:off + n].reshape(tile.ly, tile.lx)
-        mask = np.zeros((tile.ly, tile.lx))
-        if tile.iface["left"]:
-            mask[:, 0] = 1
-        if tile.iface["right"]:
-            mask[:, -1] = 1
-        if tile.iface["bottom"]:
-            mask[0, :] = 1
-        if tile.iface["top"]:
-            mask[-1, :] = 1
-        ref = fno_forward(wt, vt, w.eps[tile.y0:tile.y1, tile.x0:tile.x1].astype(np.float64), k0 * w.h,
-                          1 / sc[tile.x0:tile.x1], 1 / sc[tile.y0:tile.y1], mask)
-        worst = max(worst, rel(e[off:off + n].reshape(tile.ly, tile.lx), ref))
-    assert worst < 3e-2, worst
+        args = (vt, w.eps[tile.y0:tile.y1, tile.x0:tile.x1].astype(np.float64), k0 * w.h,
+                1 / scx[tile.x0:tile.x1], 1 / scy[tile.y0:tile.y1], _ring_mask(tile))
+        et = e[off:off + n].reshape(tile.ly, tile.lx)
+        r64 = rel(et, fno_forward(wt, *args))
+        r16 = rel(et, fno_forward(wt, *args, bf16=True))
+        worst64, worst16 = max(worst64, r64), max(worst16, r16)
+        shapes.add((tile.ly, tile.lx))
+    print(f"{case}: shapes {sorted(shapes)}; worst vs FP64 {worst64:.2e}, vs BF16 emulation {worst16:.2e}")
+    assert worst64 < 2e-2, worst64
+    assert worst16 < 1e-3, worst16
 
 
 @pytest.mark.parametrize("steps,tol", [(4, 0.0), (8, 0.9)])
@@ -160,7 +182,48 @@ def test_nn_fgmres_solve_reaches_direct_solution():
     A = assemble_A(w.eps, 1.0, w.h, w.npml)
     xs = solve_direct(A, source_rhs(w.J()[0], 1.0))
     assert rel(E[0, 0].ravel(), xs) < 1e-5
+    # the trained network reduces every subdomain residual: no exact-LU fallback
+    assert P.fallback_count() == 0
     print("NN-FGMRES outer iterations", int(iters[0, 0]))
+
+
+def _nan_weights(path, out):
+    """A copy of a weights file whose lift bias is NaN (every network output is NaN)."""
+    raw = bytearray(open(path, "rb").read())
+    off = 8 + 7 * 4 + 2 * 64 * 9                 # magic, header, lift weights (bf16)
+    for i in range(64):
+        raw[off + 2 * i:off + 2 * i + 2] = (0x7FC0).to_bytes(2, "little")
+    with open(out, "wb") as f:
+        f.write(bytes(raw))
+    return out
+
+
+def test_nan_network_falls_back_to_exact_lu(tmp_path):
+    """Every inner solve meets NaN and is replaced by the exact subdomain solve
+    in the same sweep: the solve reaches the direct solution with the exact-LU
+    form's iteration count, and the fallback count says so."""
+    if not os.path.exists(TRAINED):
+        pytest.skip("trained weights not present")
+    path = _nan_weights(TRAINED, str(tmp_path / "nan.bin"))
+    w = random_small(32, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.0,), npml=12, k_coarse=1, block=16)
+    ctx, P = _problem(w, path, steps=4, tol=1e-2)
+    E, hist, iters, fin, st = P.solve(w.J(), tol=1e-6, restart=30, max_iters=1500)
+    n_fb = P.fallback_count()
+    it = int(iters[0, 0])
+    assert st == 0, (iters, fin)
+    A = assemble_A(w.eps, 1.0, w.h, w.npml)
+    xs = solve_direct(A, source_rhs(w.J()[0], 1.0))
+    assert rel(E[0, 0].ravel(), xs) < 1e-5
+    # every sweep replaces each of the 9 inner solves, except those whose
+    # subdomain right-hand side is exactly zero (the first sweeps, before the
+    # point source's residual has spread to every subdomain)
+    assert 9 * (it - 3) <= n_fb <= 9 * it, (n_fb, it)
+    from paper_2509_03622_amd import nosdd
+    P2 = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+    P2.setup(k_coarse=w.k_coarse, k_trial=w.k_trial)
+    E2, hist2, iters2, fin2, st2 = P2.solve(w.J(), tol=1e-6, restart=30, max_iters=1500)
+    print(f"NaN network: {it} outer iterations, {n_fb} fallbacks; exact LU form {int(iters2[0, 0])}")
+    assert abs(int(iters2[0, 0]) - it) <= 1
 
 
 def test_outer_bookkeeping_with_random_network(random_weights):

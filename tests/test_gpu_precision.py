@@ -81,3 +81,23 @@ def test_nn_fgmres_reaches_1e9():
     err = _check_field(w, 1.0, E[0, 0], fin[0, 0], 1e-9)
     assert err < 1e-6
     _check_fp64(w, 1.0, P, 1e-9)
+
+
+def test_stagnation_stops_the_solve_early():
+    """A tolerance below what the FP64 iterate can reach (rounding of the
+    operator itself) makes the explicit residual stop decreasing; the solve
+    then ends after one cycle without progress instead of running to
+    max_iters, and says so."""
+    import torch
+    w = small_rectangles()
+    ctx, P = make_gpu_problem(w)
+    J = torch.from_numpy(w.J()).cuda()
+    E64 = torch.zeros((1, 1, w.ny, w.nx), dtype=torch.complex128, device="cuda")
+    max_iters = 20000
+    hist, it, fin, st = P.solve_device_c64(J, E64, tol=1e-18, max_iters=max_iters)
+    msg = ctx.L.nosdd_last_error(ctx.h).decode()
+    print(f"stopped after {int(it[0, 0])} iterations at {float(fin[0, 0]):.2e}: {msg}")
+    assert st == 1
+    assert int(it[0, 0]) < max_iters // 4
+    assert "did not decrease" in msg
+    assert float(fin[0, 0]) < 1e-9

@@ -78,3 +78,20 @@ def test_zero_input_zero_output_and_scale_equivariance():
     e1 = fno_forward(w, v, eps, 0.3, isx, isy, mask)
     e2 = fno_forward(w, 5.0 * v, eps, 0.3, isx, isy, mask)
     np.testing.assert_allclose(e2, 5.0 * e1, rtol=1e-12)      # the rms normalisation
+
+
+def test_bf16_rounding_matches_torch_bfloat16():
+    """The emulation's rounding equals torch's float32 -> bfloat16 conversion
+    (round to nearest, ties to even), ties and signs included."""
+    import torch
+    from oracle.fno import round_bf16
+    rng = np.random.default_rng(3)
+    x = (rng.standard_normal(20000) * 10.0 ** rng.uniform(-8, 8, 20000)).astype(np.float32)
+    # exact ties: a bfloat16 value plus half an ulp, with even and odd last bits
+    base = rng.integers(0x3000, 0x5000, 2000).astype(np.uint32) << 16       # finite bfloat16 values
+    ties = (base | 0x8000).view(np.float32)
+    x = np.concatenate([x, ties, -ties, np.float32([0.0, -0.0, 1.0, 3.0e38])])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(round_bf16(x), ref)
+    z = x[:100] + 1j * x[100:200]
+    np.testing.assert_array_equal(round_bf16(z), ref[:100] + 1j * ref[100:200])
