@@ -222,6 +222,25 @@ nosdd_status nosdd_schwarz_sweep(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
  * c = G^-1 W^H (v - A z1) (coarse correction, FP64 solve). Az nullable. */
 nosdd_status nosdd_precond_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *z, nosdd_c32 *Az,
                                  int n_src);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * two-level preconditioner as nosdd_precond_apply for a problem set up with
+ * exact subdomain solves (sub_solver 0), z = z1 + Phi c and Az = A z
+ * (Az required), computed without any allocation.  The job queue of the
+ * subdomain solves and the coarse coefficients (FP64 W^H t and c) live in a
+ * fixed per-device scratch array of NOSDD_NOALLOC_SCRATCH_BYTES inside the
+ * library, whose device address is looked up when a context is created on
+ * that device; a batch needs 8 n_tiles n_rhs + 24 n_rhs n_coarse bytes (each
+ * part rounded up to 256), n_rhs = n_wl * n_src, and larger batches are
+ * rejected with NOSDD_EINVAL before any work is issued.  The subdomain solves
+ * always use the one-source kernel.  Nothing is synchronised: the work is
+ * ordered on the context stream.  Every call on one GPU shares that GPU's
+ * scratch (which keeps the last call's contents; every entry is written
+ * before it is read), so calls that overlap on one device race.
+ * NOSDD_ESTATE before set-up or with sub_solver 1. */
+#define NOSDD_NOALLOC_SCRATCH_BYTES (16u << 20)
+nosdd_status nosdd_precond_apply_noalloc(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *z, nosdd_c32 *Az,
+                                         int n_src);
 /* Subdomain solves on subdomain-local vectors with the configured sub-solver:
  * for tile t (index ty*ncx+tx) and wavelength wl, u = B_{t,wl}^-1 rhs.
  * sub_solver 0: exact block-Thomas LU.  sub_solver 1: the inner NN-FGMRES of

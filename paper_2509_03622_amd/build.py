@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnosdd.so")
-SOURCES = ["stencil.hip", "btlu.hip", "krylov.hip", "coarse.hip", "fno.hip", "nnsolve.hip", "adjoint.hip", "paperloop.hip", "capi.hip"]
+SOURCES = ["stencil.hip", "btlu.hip", "krylov.hip", "coarse.hip", "fno.hip", "nnsolve.hip", "adjoint.hip", "paperloop.hip", "noalloc.hip", "capi.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are kept out of every code object on purpose.

@@ -1577,6 +1577,8 @@ nosdd_status nosdd_ctx_create(int hip_device, void *hip_stream, nosdd_ctx **out)
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return NOSDD_EINVAL;
     if (hipSetDevice(hip_device) != hipSuccess) return NOSDD_EHIP;
+    // device address of this GPU's fixed scratch (nosdd_precond_apply_noalloc)
+    if (noalloc_scratch_init(hip_device) != hipSuccess) return NOSDD_EHIP;
     nosdd_ctx *c = new nosdd_ctx();
     c->device = hip_device;
     if (hip_stream) {
@@ -2205,6 +2207,50 @@ nosdd_status nosdd_precond_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32
     precond(p, p->ctx->stream, (const float2 *)v, (float2 *)z, w, n_src, n_rhs, nullptr, n_rhs);
     HIPCHK(p->ctx, hipGetLastError());
     HIPCHK(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    return NOSDD_OK;
+}
+
+nosdd_status nosdd_precond_apply_noalloc(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *z, nosdd_c32 *Az,
+                                         int n_src) {
+    static_assert(NOALLOC_SCRATCH_BYTES == NOSDD_NOALLOC_SCRATCH_BYTES, "scratch size differs from the header");
+    nosdd_status st = check_problem(p, true);
+    if (st) return st;
+    if (!v || !z || !Az || n_src <= 0) return fail(p->ctx, NOSDD_EINVAL, "null argument or n_src <= 0");
+    if (p->sub_solver != 0)
+        return fail(p->ctx, NOSDD_ESTATE, "the allocation-free sweep takes exact subdomain solves (sub_solver 0)");
+    const long long nt = (long long)p->tiles.size(), n_rhs = (long long)p->wl.size() * n_src;
+    const long long nc = p->n_c;
+    auto up = [](long long b) { return (b + 255) / 256 * 256; };
+    const long long q_bytes = up(nt * n_rhs * (long long)sizeof(int2));
+    const long long d_bytes = up(n_rhs * nc * (long long)sizeof(double2));
+    const long long c_bytes = up(n_rhs * nc * (long long)sizeof(float2));
+    if (n_rhs > (1 << 20) || q_bytes + d_bytes + c_bytes > (long long)NOALLOC_SCRATCH_BYTES)
+        return fail(p->ctx, NOSDD_EINVAL,
+                    "batch too large for the fixed scratch: needs " + std::to_string(q_bytes + d_bytes + c_bytes) +
+                        " bytes, at most " + std::to_string((long long)NOALLOC_SCRATCH_BYTES));
+    char *scr = static_cast<char *>(noalloc_scratch(p->ctx->device));
+    if (!scr) return fail(p->ctx, NOSDD_ESTATE, "no scratch address for this device");
+    int2 *order = reinterpret_cast<int2 *>(scr);
+    double2 *cd = reinterpret_cast<double2 *>(scr + q_bytes);
+    float2 *cc = reinterpret_cast<float2 *>(scr + q_bytes + d_bytes);
+    hipStream_t s = p->ctx->stream;
+    const long long N = (long long)p->nx * p->ny;
+    // every entry of the queue, d and c is written before it is read: nothing to clear
+    launch_noalloc_queue(s, order, (int)nt, (int)n_rhs);
+    launch_bt_solve(s, p->d_tiles.as<TileDesc>(), order, (int)(nt * n_rhs), n_src, p->d_dinv.as<float2>(),
+                    p->dinv_wl_stride, p->d_coef.as<float2>(), p->d_sc.as<float2>(), p->nx, p->ny, (const float2 *)v, N,
+                    (float2 *)z, N, nullptr, 0, p->bmax, p->max_cells, p->bt_depth);
+    launch_stencil(s, (const float2 *)z, nullptr, (float2 *)Az, p->d_eps.as<float>(), p->d_coefd.as<double2>(),
+                   p->d_k0.as<double>(), p->nx, p->ny, (int)n_rhs, n_src, nullptr);
+    if (nc > 0) {
+        launch_coarse_dot(s, p->d_tiles.as<TileDesc>(), p->n_c, p->kc, p->d_W.as<float2>(), p->box_wl_stride,
+                          (const float2 *)v, (const float2 *)Az, p->nx, N, (int)n_rhs, n_src, nullptr, cd);
+        launch_coarse_solve(s, p->d_GinvT.as<double2>(), p->n_c, cd, cc, (int)n_rhs, n_src, nullptr);
+        launch_coarse_update(s, p->d_tiles.as<TileDesc>(), p->d_owner.as<int>(), p->kc, p->d_phi.as<float2>(),
+                             p->d_W.as<float2>(), p->box_wl_stride, cc, p->n_c, (float2 *)z, (float2 *)Az, p->nx, p->ny,
+                             (int)n_rhs, n_src, nullptr);
+    }
+    HIPCHK(p->ctx, hipGetLastError());
     return NOSDD_OK;
 }
 

@@ -260,6 +260,14 @@ struct NnWork {
     unsigned *fb_count = nullptr;
 };
 
+// Fixed per-device scratch of the entry point that allocates nothing (noalloc.hip):
+// init looks the array's device address up on `device` (once; done at context
+// creation), noalloc_scratch returns it (nullptr before init).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;
+hipError_t noalloc_scratch_init(int device);
+void *noalloc_scratch(int device);
+void launch_noalloc_queue(hipStream_t s, int2 *order, int n_tiles, int n_rhs);
+
 // An inner solve whose final residual estimate is not below this fraction of
 // its right-hand side's norm, or that meets a non-finite value, is replaced
 // by the exact subdomain LU solve in the same sweep.

@@ -24,7 +24,7 @@ EXPORTS = ["nosdd_ctx_create", "nosdd_ctx_destroy", "nosdd_last_error", "nosdd_p
            "nosdd_apply_operator", "nosdd_schwarz_sweep", "nosdd_precond_apply", "nosdd_local_solve",
            "nosdd_robin_trace", "nosdd_tile_info", "nosdd_sizes", "nosdd_last_timing", "nosdd_coarse_basis",
            "nosdd_profile", "nosdd_kernel_times", "nosdd_nn_apply", "nosdd_graphs", "nosdd_multi_source", "nosdd_stored_basis", "nosdd_autotune", "nosdd_tuning",
-           "nosdd_fom_gradient_device", "nosdd_fallback_count"]
+           "nosdd_fom_gradient_device", "nosdd_fallback_count", "nosdd_precond_apply_noalloc"]
 
 
 class Grid(C.Structure):
@@ -99,6 +99,7 @@ def load(path=LIBPATH):
         "nosdd_tuning": (i, [vp, vp]),
         "nosdd_fom_gradient_device": (i, [vp, vp, i, vp, i, C.POINTER(SolveOpts), C.POINTER(C.c_double), vp, vp]),
         "nosdd_fallback_count": (i, [vp, C.POINTER(ll)]),
+        "nosdd_precond_apply_noalloc": (i, [vp, vp, vp, vp, i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -260,6 +261,10 @@ class Problem:
 
     def precond_apply(self, v, z, Az=None, n_src=1):
         return self.ctx.check(self.L.nosdd_precond_apply(self.h, _ptr(v), _ptr(z), _ptr(Az), n_src))
+
+    def precond_apply_noalloc(self, v, z, Az, n_src=1):
+        """Two-level preconditioner without any device allocation (fixed library scratch)."""
+        return self.ctx.check(self.L.nosdd_precond_apply_noalloc(self.h, _ptr(v), _ptr(z), _ptr(Az), n_src))
 
     def local_solve(self, rhs, u):
         return self.ctx.check(self.L.nosdd_local_solve(self.h, _ptr(rhs), _ptr(u)))
