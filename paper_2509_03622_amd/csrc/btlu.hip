@@ -26,6 +26,8 @@
 // which carries the neighbours' Robin traces by the Robin identity) and the
 // core-only scatter (restricted additive Schwarz prolongation) are fused into
 // the same kernel.
+#include <algorithm>
+
 #include "common.h"
 
 namespace nosdd {
@@ -675,16 +677,24 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, in
 
 // ----------------------------------------------------------- many sources
 // Sources that share a wavelength share every factor block, so a workgroup
-// takes one (subdomain, wavelength) and a group of NCOL sources: each block
-// M_k is read from HBM once, expanded in LDS into its real and imaginary
-// b x b parts (both triangles), and the step's products for all sources,
-// M_k (S_k Y) with Y the b x NCOL operand, run as FP32 MFMA contractions
-// (16 x 16 x 4):  Re = M_r Y_r + M_i (-Y_i),  Im = M_r Y_i + M_i Y_r.
+// takes one (subdomain, wavelength) and a group of sources: each block M_k is
+// read from HBM once, expanded in LDS into its real and imaginary b x b parts
+// (both triangles), and the step's products for all sources, M_k (S_k Y) with
+// Y the b x NCOL operand, run as FP32 MFMA contractions (16 x 16 x 4):
+//   Re = M_r Y_r + M_i (-Y_i),  Im = M_r Y_i + M_i Y_r.
 // The recurrence then runs elementwise over (row, source).  The gathered
 // right-hand sides, w_k and u_k live block-major in a packed workspace
 // (loc[rhs][tile cells]); the core cells are scattered at the end.
+// The group width follows the tile: 32 sources for blocks up to 80 cells,
+// 16 above (LDS), so one launch serves mixed tile sizes and the common
+// 72-wide tiles stream each factor block once per wavelength.
+// Every global load of the step loop is unpredicated (clamped addresses), so
+// the compiler counts them exactly: factor blocks are fetched two steps ahead
+// into a two-slot register ring and the recurrence operands one step ahead,
+// and a step waits only for the loads it consumes.
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 constexpr int BM_THREADS = 1024;
+constexpr int BM_NARROW = 80;                  // widest block of the 32-source form
 
 // LDS layout (b the tile's block size, padded to BP = 16 * ceil(b / 16) in rows and in k):
 //   M  [BP][BP + 2] float2 (re, im): the expanded block, row-major, k contiguous;
@@ -693,32 +703,34 @@ constexpr int BM_THREADS = 1024;
 // The MFMA lane groups (lane / 16) take contiguous quarters of k, so each lane
 // reads four k at once (16-byte LDS loads) for four consecutive MFMAs.
 __host__ __device__ __forceinline__ int bm_pad(int b) { return (b + 15) & ~15; }
-int bt_multi_cols(int bmax) { return bmax <= 80 ? 32 : 16; }
-static size_t bm_lds_bytes(int bmax, int ncol) {
-    const int BP = bm_pad(bmax);
+__host__ __device__ __forceinline__ int bm_cols(int b) { return b <= BM_NARROW ? 32 : 16; }
+int bt_multi_cols(int b) { return bm_cols(b); }
+static size_t bm_lds_class(int b, int ncol) {
+    const int BP = bm_pad(b);
     return sizeof(float) * ((size_t)2 * BP * (BP + 2) + (size_t)3 * ncol * (BP + 4) + (size_t)2 * BP * (ncol + 1));
+}
+// dynamic LDS of a launch whose widest block is bmax (either group form may run)
+static size_t bm_lds_bytes(int bmax) {
+    if (bmax <= BM_NARROW) return bm_lds_class(bmax, 32);
+    return std::max(bm_lds_class(BM_NARROW, 32), bm_lds_class(bmax, 16));
 }
 
 template <int NCOL, int EMAX, int RMAX>
-__global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
-    const TileDesc *__restrict__ tiles, const int4 *__restrict__ jobs, int n_src, const float2 *__restrict__ dinv,
-    long long dinv_wl_stride, const float2 *__restrict__ coef, const float2 *__restrict__ sc, int nx, int ny,
-    const float2 *__restrict__ vin, long long vin_stride, float2 *__restrict__ out, long long out_stride,
-    const int *__restrict__ active, float2 *__restrict__ loc, long long LT) {
-    extern __shared__ __align__(16) float lds[];
-    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX], si_s[BT_BMAX];
-    __shared__ int colr[NCOL];                       // RHS index of each column, -1 when idle
-    const int4 job = jobs[blockIdx.x];               // (tile, wavelength, first source, sources)
-    if (job.x < 0) return;
-    const TileDesc t = tiles[job.x];
-    const int wl = job.y, s0 = job.z, ns = job.w;
+__device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int ns, int n_src,
+                                         const float2 *__restrict__ dinv, long long dinv_wl_stride,
+                                         const float2 *__restrict__ coef, const float2 *__restrict__ sc, int nx, int ny,
+                                         const float2 *__restrict__ vin, long long vin_stride, float2 *__restrict__ out,
+                                         long long out_stride, const int *__restrict__ active, float2 *__restrict__ loc,
+                                         long long LT, float *lds, float2 *cl_s, float2 *ch_s, float2 *so_s,
+                                         float2 *si_s, int *colr) {
     const int b = t.b, nb = t.nb, P = b >> 1, tid = threadIdx.x;
     const int BP = bm_pad(b), LDM = BP + 2, LDK = BP + 4, LDC = NCOL + 1;
     float2 *M = reinterpret_cast<float2 *>(lds);
     float *Xr = lds + 2 * BP * LDM, *Xi = Xr + NCOL * LDK, *Xn = Xi + NCOL * LDK;
     float *Cr = Xn + NCOL * LDK, *Ci = Cr + BP * LDC;
+    const int rfirst = wl * n_src + s0;               // a valid right-hand side of this job (clamped loads)
     if (tid < NCOL) {
-        const int r = wl * n_src + s0 + tid;
+        const int r = rfirst + tid;
         colr[tid] = (tid < ns && (!active || active[r])) ? r : -1;
     }
     const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
@@ -750,14 +762,16 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
             lr[t.tr ? xx * b + yy : e] = vr[(long long)(t.y0 + yy) * nx + (t.x0 + xx)];
         }
     }
-    // this thread's elements of a packed block and their two LDS positions
+    // this thread's elements of a packed block: a clamped (always valid) load
+    // index and the two LDS positions of the element (-1: nothing to store)
     const long long blk = bt_sym_block(b);
     const int nsub = (int)(blk >> 2);
     const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
-    int o1[EMAX], o2[EMAX];
+    int gi[EMAX], o1[EMAX], o2[EMAX];
 #pragma unroll
     for (int j = 0; j < EMAX; ++j) {
         const int e = tid + j * BM_THREADS;
+        gi[j] = e < (int)blk ? e : (int)blk - 1;
         o1[j] = -1;
         o2[j] = -1;
         if (e < (int)blk) {
@@ -769,24 +783,47 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
             o2[j] = cc * LDM + rr;
         }
     }
-    float2 mreg[EMAX];
-    auto fetch = [&](int k) {
-        const float2 *Dk = D + (long long)k * blk;
+    // this thread's (row, source) elements of the recurrence, fixed for all
+    // steps, and their workspace rows (clamped to a valid source when idle)
+    int ri[RMAX], rc[RMAX];
+    const float2 *prow[RMAX];
 #pragma unroll
-        for (int j = 0; j < EMAX; ++j) mreg[j] = o1[j] >= 0 ? Dk[tid + j * BM_THREADS] : make_float2(0.f, 0.f);
+    for (int j = 0; j < RMAX; ++j) {
+        const int e = tid + j * BM_THREADS;
+        const bool valid = e < b * NCOL;
+        ri[j] = valid ? e % b : -1;
+        rc[j] = valid ? e / b : 0;
+        const int r = colr[rc[j]];
+        prow[j] = loc + (long long)(r >= 0 ? r : rfirst) * LT + t.loc_off + (valid ? e % b : 0);
+    }
+    const int nsteps = 2 * nb - 1;
+    auto blk_of = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
+    auto fetch = [&](int s, float2(&dst)[EMAX]) {
+        const float2 *Dk = D + (long long)blk_of(s < nsteps ? s : nsteps - 1) * blk;
+#pragma unroll
+        for (int j = 0; j < EMAX; ++j) dst[j] = Dk[gi[j]];
     };
-    auto expand = [&]() {
+    auto expand = [&](const float2(&src)[EMAX]) {
 #pragma unroll
         for (int j = 0; j < EMAX; ++j)
             if (o1[j] >= 0) {
-                M[o1[j]] = mreg[j];
-                M[o2[j]] = mreg[j];
+                M[o1[j]] = src[j];
+                M[o2[j]] = src[j];
             }
     };
-    const int nsteps = 2 * nb - 1;
-    auto blk_of = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
-    fetch(0);
+    // v_{k+1} (forward) or w_k (backward) for step s
+    auto load_pre = [&](int s, float2(&dst)[RMAX]) {
+        const int sc_ = s < nsteps ? s : nsteps - 1;
+        const int k = blk_of(sc_);
+        const int kk = sc_ < nb ? (k + 1 < nb ? k + 1 : nb - 1) : k;
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) dst[j] = prow[j][(long long)kk * b];
+    };
     __syncthreads();                                  // gathered data visible
+    float2 ra[EMAX], rb[EMAX], pre_c[RMAX], pre_n[RMAX];
+    fetch(0, ra);
+    fetch(1, rb);
+    load_pre(0, pre_c);
     // operand of the first step: S_0 v_0
     for (int e = tid; e < b * NCOL; e += BM_THREADS) {
         const int i = e % b, c = e / b, r = colr[c];
@@ -796,29 +833,15 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
         Xi[c * LDK + i] = z.y;
         Xn[c * LDK + i] = -z.y;
     }
-    expand();
+    expand(ra);
     const int wave = tid >> 6, lane = tid & 63;
     const int RT = BP / 16, nT = RT * (NCOL / 16), KQ = BP / 4;
-    // this thread's (row, source) elements of the recurrence, fixed for all steps
-    int ri[RMAX], rc[RMAX];
-#pragma unroll
-    for (int j = 0; j < RMAX; ++j) {
-        const int e = tid + j * BM_THREADS;
-        ri[j] = e < b * NCOL ? e % b : -1;
-        rc[j] = e < b * NCOL ? e / b : 0;
-    }
-    float2 pre[RMAX];                                 // v_{k+1} (forward) or w_k (backward) of this thread's elements
-    for (int s = 0; s < nsteps; ++s) {
+    // one block step: block s is expanded in M (it came from cur), block s + 1 waits in nxt
+    auto step = [&](int s, float2(&cur)[EMAX], float2(&nxt)[EMAX]) {
         const int k = blk_of(s);
         const bool fwd = s < nb, turn = s == nb - 1;
-        if (s + 1 < nsteps) fetch(blk_of(s + 1));
-        // the recurrence's other operands do not depend on this step's products: load them now
-#pragma unroll
-        for (int j = 0; j < RMAX; ++j) {
-            pre[j] = make_float2(0.f, 0.f);
-            const int r = colr[rc[j]];
-            if (ri[j] >= 0 && !turn && r >= 0) pre[j] = loc[r * LT + t.loc_off + (fwd ? k + 1 : k) * b + ri[j]];
-        }
+        fetch(s + 2, cur);
+        load_pre(s + 1, pre_n);
         __syncthreads();                              // M_k and the operand are in LDS
         for (int q = wave; q < nT; q += BM_THREADS / 64) {
             const int rt = q % RT, ct = q / RT;
@@ -864,9 +887,9 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
                 float2 y;
                 if (fwd) {
                     lr[k * b + i] = a;                                              // w_k
-                    y = turn ? a : cfms(pre[j], cc, a);                             // y_{k+1} or u_{nb-1}
+                    y = turn ? a : cfms(pre_c[j], cc, a);                           // y_{k+1} or u_{nb-1}
                 } else {
-                    y = cfms(pre[j], cc, a);                                        // u_k
+                    y = cfms(pre_c[j], cc, a);                                      // u_k
                     lr[k * b + i] = y;
                 }
                 if (knext >= 0) z = cmul(cmul(si_s[i], so_s[knext]), y);
@@ -875,7 +898,13 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
             Xi[c * LDK + i] = z.y;
             Xn[c * LDK + i] = -z.y;
         }
-        if (s + 1 < nsteps) expand();
+#pragma unroll
+        for (int j = 0; j < RMAX; ++j) pre_c[j] = pre_n[j];
+        if (s + 1 < nsteps) expand(nxt);
+    };
+    for (int s = 0; s < nsteps; s += 2) {
+        step(s, ra, rb);
+        if (s + 1 < nsteps) step(s + 1, rb, ra);
     }
     __syncthreads();
     // core cells of u to the output
@@ -894,38 +923,38 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
     }
 }
 
-template <int NCOL, int EMAX, int RMAX>
-static void bt_multi_launch(hipStream_t s, int n_jobs, size_t lds, const TileDesc *tiles, const int4 *jobs, int n_src,
-                            const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc,
-                            int nx, int ny, const float2 *vin, long long vin_stride, float2 *out,
-                            long long out_stride, const int *active, float2 *loc, long long LT) {
-    hipLaunchKernelGGL((bt_solve_multi_kernel<NCOL, EMAX, RMAX>), dim3(n_jobs), dim3(BM_THREADS), lds, s, tiles, jobs, n_src,
-                       dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride, out, out_stride, active, loc, LT);
+// jobs[j] = (tile, wavelength, first source, sources), at most bm_cols(b) sources
+__global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
+    const TileDesc *__restrict__ tiles, const int4 *__restrict__ jobs, int n_src, const float2 *__restrict__ dinv,
+    long long dinv_wl_stride, const float2 *__restrict__ coef, const float2 *__restrict__ sc, int nx, int ny,
+    const float2 *__restrict__ vin, long long vin_stride, float2 *__restrict__ out, long long out_stride,
+    const int *__restrict__ active, float2 *__restrict__ loc, long long LT) {
+    extern __shared__ __align__(16) float lds[];
+    __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX], si_s[BT_BMAX];
+    __shared__ int colr[32];                          // RHS index of each column, -1 when idle
+    const int4 job = jobs[blockIdx.x];
+    if (job.x < 0) return;
+    const TileDesc t = tiles[job.x];
+    if (t.b <= BM_NARROW)
+        bm_solve<32, 4, 3>(t, job.y, job.z, job.w, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride,
+                           out, out_stride, active, loc, LT, lds, cl_s, ch_s, so_s, si_s, colr);
+    else
+        bm_solve<16, 7, 2>(t, job.y, job.z, job.w, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride,
+                           out, out_stride, active, loc, LT, lds, cl_s, ch_s, so_s, si_s, colr);
 }
 
 void launch_bt_solve_multi(hipStream_t s, const TileDesc *tiles, const int4 *jobs, int n_jobs, int n_src,
                            const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc, int nx,
                            int ny, const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
                            const int *active, float2 *loc, long long LT, int bmax) {
-    const int ncol = bt_multi_cols(bmax);
-    const size_t lds = bm_lds_bytes(bmax, ncol);
-    if (ncol == 32)
-        bt_multi_launch<32, 4, 3>(s, n_jobs, lds, tiles, jobs, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin,
-                                vin_stride, out, out_stride, active, loc, LT);
-    else
-        bt_multi_launch<16, 9, 2>(s, n_jobs, lds, tiles, jobs, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin,
-                                vin_stride, out, out_stride, active, loc, LT);
+    hipLaunchKernelGGL(bt_solve_multi_kernel, dim3(n_jobs), dim3(BM_THREADS), bm_lds_bytes(bmax), s, tiles, jobs,
+                       n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride, out, out_stride, active, loc,
+                       LT);
 }
 
 void bt_solve_multi_prepare(int bmax) {
-    const int ncol = bt_multi_cols(bmax);
-    const int lds = (int)bm_lds_bytes(bmax, ncol);
-    if (ncol == 32)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_multi_kernel<32, 4, 3>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    else
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_multi_kernel<16, 9, 2>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&bt_solve_multi_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bm_lds_bytes(bmax));
 }
 
 }  // namespace nosdd

@@ -109,7 +109,11 @@ struct nosdd_problem {
     Workspace ws;
     // neural subdomain solver
     FnoDevice net;
-    DevBuf d_net, d_aux, d_smp;
+    DevBuf d_net, d_aux, d_smp, d_mod;
+    // modulation path of the modulated network (host copy, FP32 values of the
+    // BF16 weights): conv 3x3 7 -> mod_ch, pool to mod_pool^2, FC -> mod_hidden, FC -> layers x 512 x 2
+    int mod_ch = 0, mod_pool = 0, mod_hidden = 0;
+    std::vector<float> mod_cw, mod_cb, mod_f1w, mod_f1b, mod_f2w, mod_f2b;
     int nn_steps = 2, max_cells = 0;
     float nn_tol = 0.1f;
     int smp_rhs = 0;                              // samples built for this many RHS
@@ -482,19 +486,28 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(ctx, NOSDD_ENOWEIGHTS, std::string("cannot open weights file ") + path);
     char magic[8];
-    int32_t hdr[7];
-    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "NOSDDFNO", 8) != 0 || std::fread(hdr, 4, 7, f) != 7) {
+    int32_t hdr[7], hdr2[4] = {0, 0, 0, 0};
+    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "NOSDDFNO", 8) != 0 || std::fread(hdr, 4, 7, f) != 7 ||
+        (hdr[0] == 2 && std::fread(hdr2, 4, 4, f) != 4)) {
         std::fclose(f);
         return fail(ctx, NOSDD_ENOWEIGHTS, "not a network weights file");
     }
     const int C = hdr[1], m = hdr[2], L = hdr[3], in_ch = hdr[4], hid = hdr[5];
-    if (hdr[0] != 1 || hdr[6] != 1 || C != 64 || m != 16 || in_ch != 9 || hid != 128 || L < 1 || L > 16) {
+    const int ver = hdr[0], rank = hdr2[0], mch = hdr2[1], mpool = hdr2[2], mhid = hdr2[3];
+    if ((ver != 1 && ver != 2) || hdr[6] != 1 || C != 64 || m != 16 || in_ch != 9 || hid != 128 || L < 1 || L > 16 ||
+        (ver == 2 && (rank < 1 || rank > 256 || mch < 1 || mch > 64 || mpool < 1 || mpool > 16 || mhid < 1 ||
+                      mhid > 1024))) {
         std::fclose(f);
         return fail(ctx, NOSDD_ENOWEIGHTS, "weights file must hold a bf16 network of width 64, 16 modes, 9 inputs, "
-                                           "projection 128");
+                                           "projection 128 (version 1 plain, version 2 modulated low-rank)");
     }
-    const size_t per_layer = 2ull * (2 * m) * m * C * C + (size_t)C * C + C;
-    const size_t total = (size_t)C * in_ch + C + L * per_layer + (size_t)hid * C + hid + 2ull * hid + 2;
+    const size_t spec_per_layer = ver == 1 ? 2ull * (2 * m) * m * C * C
+                                           : 2ull * (2 * m) * m * rank + 2ull * rank * C * C;
+    const size_t per_layer = spec_per_layer + (size_t)C * C + C;
+    const size_t mod_total = ver == 1 ? 0
+                                      : (size_t)mch * 7 * 9 + mch + (size_t)mhid * mch * mpool * mpool + mhid +
+                                            (size_t)L * 2 * m * m * 2 * mhid + (size_t)L * 2 * m * m * 2;
+    const size_t total = (size_t)C * in_ch + C + L * per_layer + (size_t)hid * C + hid + 2ull * hid + 2 + mod_total;
     std::vector<uint16_t> w(total);
     const size_t got = std::fread(w.data(), 2, total, f);
     const bool extra = std::fgetc(f) != EOF;
@@ -511,8 +524,40 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
     const int nmodes = 2 * m * m;
     std::vector<uint16_t> R((size_t)L * nmodes * 128 * 128), Wb((size_t)L * C * C);
     std::vector<float> bias((size_t)L * C);
+    std::vector<uint16_t> lr_expanded;                    // version 2: R = A B per layer, rounded to bf16
     for (int l = 0; l < L; ++l) {
-        const uint16_t *rr = &w[pos];
+        if (ver == 2) {
+            // R[k][i][o] = sum_r A[k][r] B[r][i][o] (complex), in FP64, then rounded
+            std::vector<double> Ar(nmodes * (size_t)rank), Ai(nmodes * (size_t)rank), Br((size_t)rank * C * C),
+                Bi((size_t)rank * C * C);
+            for (size_t i = 0; i < Ar.size(); ++i) Ar[i] = f32_of_bf16(w[pos + i]);
+            pos += Ar.size();
+            for (size_t i = 0; i < Ai.size(); ++i) Ai[i] = f32_of_bf16(w[pos + i]);
+            pos += Ai.size();
+            for (size_t i = 0; i < Br.size(); ++i) Br[i] = f32_of_bf16(w[pos + i]);
+            pos += Br.size();
+            for (size_t i = 0; i < Bi.size(); ++i) Bi[i] = f32_of_bf16(w[pos + i]);
+            pos += Bi.size();
+            lr_expanded.assign(2ull * nmodes * C * C, 0);
+            std::vector<double> re((size_t)C * C), im((size_t)C * C);
+            for (int md = 0; md < nmodes; ++md) {
+                std::fill(re.begin(), re.end(), 0.0);
+                std::fill(im.begin(), im.end(), 0.0);
+                for (int r = 0; r < rank; ++r) {
+                    const double a = Ar[(size_t)md * rank + r], b = Ai[(size_t)md * rank + r];
+                    const double *br = &Br[(size_t)r * C * C], *bi = &Bi[(size_t)r * C * C];
+                    for (int e = 0; e < C * C; ++e) {
+                        re[e] += a * br[e] - b * bi[e];
+                        im[e] += a * bi[e] + b * br[e];
+                    }
+                }
+                for (int e = 0; e < C * C; ++e) {
+                    lr_expanded[(size_t)md * C * C + e] = bf16_of((float)re[e]);
+                    lr_expanded[(size_t)nmodes * C * C + (size_t)md * C * C + e] = bf16_of((float)im[e]);
+                }
+            }
+        }
+        const uint16_t *rr = ver == 2 ? lr_expanded.data() : &w[pos];
         const uint16_t *ri = rr + (size_t)nmodes * C * C;
         for (int md = 0; md < nmodes; ++md) {
             uint16_t *dst = &R[((size_t)l * nmodes + md) * 128 * 128];
@@ -527,7 +572,7 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
                     dst[(2 * i + 1) * 128 + 2 * o + 1] = a;
                 }
         }
-        pos += 2ull * nmodes * C * C;
+        if (ver == 1) pos += 2ull * nmodes * C * C;
         std::memcpy(&Wb[(size_t)l * C * C], &w[pos], (size_t)C * C * 2);
         pos += (size_t)C * C;
         for (int o = 0; o < C; ++o) bias[(size_t)l * C + o] = f32_of_bf16(w[pos + o]);
@@ -536,6 +581,18 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
     std::vector<uint16_t> p1w(w.begin() + pos, w.begin() + pos + (size_t)hid * C);
     pos += (size_t)hid * C;
     std::vector<float> p1b = f32s(hid), p2w = f32s(2ull * hid), p2b = f32s(2);
+    p->mod_ch = p->mod_pool = p->mod_hidden = 0;
+    if (ver == 2) {
+        p->mod_ch = mch;
+        p->mod_pool = mpool;
+        p->mod_hidden = mhid;
+        p->mod_cw = f32s((size_t)mch * 7 * 9);
+        p->mod_cb = f32s(mch);
+        p->mod_f1w = f32s((size_t)mhid * mch * mpool * mpool);
+        p->mod_f1b = f32s(mhid);
+        p->mod_f2w = f32s((size_t)L * nmodes * 2 * mhid);
+        p->mod_f2b = f32s((size_t)L * nmodes * 2);
+    }
     // truncated-DFT twiddle tables for every subdomain side L <= 72 (FP64 on the host)
     std::vector<float2> tw((size_t)FNO_TW_UNIT * FNO_MAXL * (FNO_MAXL + 1) / 2);
     for (int L = 1; L <= FNO_MAXL; ++L) {
@@ -615,6 +672,63 @@ nosdd_status build_aux(nosdd_problem *p) {
     }
     HIPCHK(ctx, p->d_aux.ensure(aux.size() * 4));
     HIPCHK(ctx, hipMemcpyAsync(p->d_aux.p, aux.data(), aux.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    p->net.mod = nullptr;
+    if (p->mod_ch > 0) {
+        // modulation tensors of the modulated network, one set per (wavelength,
+        // subdomain): they depend on the auxiliary channels only (Fig. 2
+        // modulation path), so they are formed once here, in FP64
+        const int nt = (int)p->tiles.size(), L = p->net.layers, mc = p->mod_ch, P = p->mod_pool, mh = p->mod_hidden;
+        const int nout = L * FNO_MODES_TOTAL * 2;
+        std::vector<float2> mod((size_t)nwl * nt * L * FNO_MODES_TOTAL);
+        std::vector<double> h, pool((size_t)mc * P * P), fh(mh);
+        for (int wi = 0; wi < nwl; ++wi)
+            for (int ti = 0; ti < nt; ++ti) {
+                const TileDesc &t = p->tiles[ti];
+                const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
+                auto a = [&](int k, int y, int x) -> double {
+                    if (x < 0 || x >= lx || y < 0 || y >= ly) return 0.0;
+                    return aux[((size_t)wi * 7 + k) * LT + t.loc_off + (long long)y * lx + x];
+                };
+                h.assign((size_t)mc * ly * lx, 0.0);
+                for (int c = 0; c < mc; ++c)
+                    for (int y = 0; y < ly; ++y)
+                        for (int x = 0; x < lx; ++x) {
+                            double acc = p->mod_cb[c];
+                            for (int k = 0; k < 7; ++k)
+                                for (int dy = 0; dy < 3; ++dy)
+                                    for (int dx = 0; dx < 3; ++dx)
+                                        acc += (double)p->mod_cw[((c * 7 + k) * 3 + dy) * 3 + dx] * a(k, y + dy - 1, x + dx - 1);
+                            h[((size_t)c * ly + y) * lx + x] = acc >= 0 ? acc : 0.01 * acc;
+                        }
+                for (int c = 0; c < mc; ++c)
+                    for (int py = 0; py < P; ++py)
+                        for (int px = 0; px < P; ++px) {
+                            const int y0 = py * ly / P, y1 = (py + 1) * ly / P, x0 = px * lx / P, x1 = (px + 1) * lx / P;
+                            double acc = 0.0;
+                            for (int y = y0; y < y1; ++y)
+                                for (int x = x0; x < x1; ++x) acc += h[((size_t)c * ly + y) * lx + x];
+                            pool[((size_t)c * P + py) * P + px] = acc / ((double)(y1 - y0) * (x1 - x0));
+                        }
+                for (int j = 0; j < mh; ++j) {
+                    double acc = p->mod_f1b[j];
+                    for (int k = 0; k < mc * P * P; ++k) acc += (double)p->mod_f1w[(size_t)j * mc * P * P + k] * pool[k];
+                    fh[j] = acc >= 0 ? acc : 0.01 * acc;
+                }
+                float2 *out = &mod[((size_t)wi * nt + ti) * L * FNO_MODES_TOTAL];
+                for (int n = 0; n < nout / 2; ++n) {
+                    double re = p->mod_f2b[2 * n], im = p->mod_f2b[2 * n + 1];
+                    for (int j = 0; j < mh; ++j) {
+                        re += (double)p->mod_f2w[(size_t)(2 * n) * mh + j] * fh[j];
+                        im += (double)p->mod_f2w[(size_t)(2 * n + 1) * mh + j] * fh[j];
+                    }
+                    out[n] = make_float2((float)(1.0 + re), (float)im);      // n = (layer, kx, ky)
+                }
+            }
+        HIPCHK(ctx, p->d_mod.ensure(mod.size() * sizeof(float2)));
+        HIPCHK(ctx, hipMemcpyAsync(p->d_mod.p, mod.data(), mod.size() * sizeof(float2), hipMemcpyHostToDevice,
+                                   ctx->stream));
+        p->net.mod = p->d_mod.as<float2>();
+    }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return NOSDD_OK;
 }
@@ -635,6 +749,8 @@ nosdd_status ensure_nn(nosdd_problem *p, int n_rhs, int n_src) {
                 q.ly = T.y1 - T.y0;
                 q.cell_off = (long long)r * LT + T.loc_off;
                 q.aux_off = (long long)(r / n_src) * 7 * LT + T.loc_off;
+                q.mod_idx = (r / n_src) * nt + t;
+                q.pad_ = 0;
             }
         HIPCHK(ctx, p->d_smp.ensure(smp.size() * sizeof(FnoSample)));
         HIPCHK(ctx, hipMemcpy(p->d_smp.p, smp.data(), smp.size() * sizeof(FnoSample), hipMemcpyHostToDevice));
@@ -747,11 +863,13 @@ nosdd_status solve_order(nosdd_problem *p, int n_rhs, int n_src, const int2 **or
         HIPCHK(p->ctx, hipMemcpy(ob.buf.p, ord.data(), ord.size() * sizeof(int2), hipMemcpyHostToDevice));
         ob.n_jobs = (int)ord.size();
         if (use_multi(p, n_src)) {
-            // one job per (tile, wavelength, group of sources), largest tiles first
-            const int ncol = bt_multi_cols(p->bmax);
+            // one job per (tile, wavelength, group of sources), largest tiles first;
+            // the group width follows the tile's block size
             std::vector<int4> mj;
-            for (const auto &g : groups)
+            for (const auto &g : groups) {
+                const int ncol = bt_multi_cols(p->tiles[g.first].b);
                 for (int s0 = 0; s0 < n_src; s0 += ncol) mj.push_back(make_int4(g.first, g.second, s0, std::min(ncol, n_src - s0)));
+            }
             HIPCHK(p->ctx, ob.mbuf.ensure(mj.size() * sizeof(int4)));
             HIPCHK(p->ctx, hipMemcpy(ob.mbuf.p, mj.data(), mj.size() * sizeof(int4), hipMemcpyHostToDevice));
             ob.n_mjobs = (int)mj.size();

@@ -134,10 +134,10 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, in
                      const int *active, int mode, int bmax, int max_cells, int depth = 0);
 void bt_solve_prepare(int bmax, int max_cells);
 // Many sources per wavelength: one workgroup per jobs[j] = (tile, wavelength,
-// first source, sources), bt_multi_cols(bmax) sources at most; the gathered
+// first source, sources), bt_multi_cols(tile block size) sources at most; the gathered
 // right-hand sides and intermediate blocks go through loc[n_rhs][LT] (packed
 // local layout, block-major within a tile).  Global input and core output.
-int bt_multi_cols(int bmax);
+int bt_multi_cols(int b);
 void launch_bt_solve_multi(hipStream_t s, const TileDesc *tiles, const int4 *jobs, int n_jobs, int n_src,
                            const float2 *dinv, long long dinv_wl_stride, const float2 *coef, const float2 *sc, int nx,
                            int ny, const float2 *vin, long long vin_stride, float2 *out, long long out_stride,
@@ -220,6 +220,8 @@ struct FnoSample {
     int lx, ly;
     long long cell_off;     // offset of the sample's cells in a sample-packed cell array
     long long aux_off;      // offset (cells) of its aux channels in [wl][7][loc_total]
+    int mod_idx;            // (wavelength, subdomain) index of its modulation tensors
+    int pad_;
 };
 
 // Network parameters on the device (C = 64, 16 modes, projection width 128).
@@ -233,11 +235,15 @@ struct FnoDevice {
     unsigned short *p1w = nullptr;                // [128][64] bf16
     float *p1b = nullptr, *p2w = nullptr, *p2b = nullptr;   // [128], [2][128], [2]
     float2 *tw = nullptr;                         // twiddle tables, FNO_TW_UNIT * L float2 per side L
+    // modulated network: mod[mod_idx][layer][mode] (complex) multiplies the
+    // spectral product of every block mode by mode; null for the plain network
+    const float2 *mod = nullptr;
 };
 // Twiddle tables of the truncated DFTs for side L, at tw + FNO_TW_UNIT L (L-1)/2:
 // forward kx [x][q] (L x 32), inverse kx [q][x] at FNO_TW_INV_X L, forward ky
 // [y][ky] (L x 16) at FNO_TW_FWD_Y L, inverse ky at FNO_TW_INV_Y L.
 constexpr int FNO_MAXL = 72;
+constexpr int FNO_MODES_TOTAL = 512;                          // 32 kx x 16 ky kept modes
 constexpr int FNO_TW_INV_X = 32, FNO_TW_FWD_Y = 64, FNO_TW_INV_Y = 80, FNO_TW_UNIT = 96;
 
 // Workspace of the batched inner NN-FGMRES (device pointers).
