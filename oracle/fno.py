@@ -1,8 +1,13 @@
 """NumPy forward pass of the subdomain Fourier neural operator (oracle).
 
-Test infrastructure only.  Architecture (Fig. 2 of the paper without the
-modulation path and low-rank R, which the plain 4-layer configuration does
-not use): lift (1x1) -> L Fourier blocks -> project (1x1, 1x1).
+Test infrastructure only.  Architecture (Fig. 2 of the paper): lift (1x1) ->
+L Fourier blocks -> project (1x1, 1x1).  Two variants share every convention
+below: the plain network (a dense complex R per block) and the modulated
+low-rank network of Fig. 2 (``modulation``/``lowrank`` below: R built from a
+low-dimensional tensor by a linear expansion over the kept modes, and the
+spectral product of every block multiplied mode by mode by a tensor that a
+small convolution / pooling / fully connected path computes from the
+auxiliary inputs alone).
 
 Each Fourier block computes  u <- act(W u + b + F^-1(R . F(u)))  where F is the
 2D DFT of each channel truncated to the low modes, R a complex channel mix per
@@ -80,8 +85,9 @@ def round_bf16(a):
     return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
 
 
-def fourier_block(u, R, W, bias, m, act=True, bf16=False):
-    """One block: act(W u + b + F^-1(R . F(u))).  R [2m][m][Cin][Cout] complex.
+def fourier_block(u, R, W, bias, m, act=True, bf16=False, mod=None):
+    """One block: act(W u + b + F^-1(mod . (R . F(u)))).  R [2m][m][Cin][Cout]
+    complex; mod [2m][m] complex (None: no modulation).
 
     bf16: the operands of the two channel mixes (the truncated spectrum X
     before R, the activations u before W) are rounded to bfloat16, as a
@@ -91,11 +97,61 @@ def fourier_block(u, R, W, bias, m, act=True, bf16=False):
     X = dft_truncated(u, m)
     if bf16:
         X = round_bf16(X)
+        R = round_bf16(R)              # a no-op for weights stored in bfloat16
     Y = np.einsum("ikq,kqio->okq", X, R)
+    if mod is not None:
+        Y = Y * mod[None]
     spec = idft_truncated(Y, Lx, Ly, m)
     pw = np.einsum("oi,iyx->oyx", W, round_bf16(u) if bf16 else u) + bias[:, None, None]
     out = pw + spec
     return leaky(out) if act else out
+
+
+def expand_lowrank(A, B):
+    """R[k][i][o] = sum_r A[k][r] B[r][i][o]: the linear layer A (rank r -> the
+    kept modes k, complex) applied to the low-dimensional tensor B (Fig. 2
+    caption; Sec. 2.1, low-rank parameterisation of R).  A [2m][m][r],
+    B [r][Cin][Cout] -> R [2m][m][Cin][Cout]."""
+    return np.einsum("xyr,rio->xyio", A, B)
+
+
+def adaptive_avg_pool(a, P):
+    """Average of a [C][Ly][Lx] over a P x P grid of bins; bin (p, q) covers
+    rows floor(p Ly / P) .. floor((p+1) Ly / P) - 1 and the same for columns."""
+    C, Ly, Lx = a.shape
+    out = np.zeros((C, P, P))
+    for p in range(P):
+        y0, y1 = (p * Ly) // P, ((p + 1) * Ly) // P
+        for q in range(P):
+            x0, x1 = (q * Lx) // P, ((q + 1) * Lx) // P
+            out[:, p, q] = a[:, y0:y1, x0:x1].mean(axis=(1, 2))
+    return out
+
+
+def conv3x3(a, w, b):
+    """Zero-padded 3 x 3 convolution (cross-correlation): a [Cin][Ly][Lx],
+    w [Cout][Cin][3][3], b [Cout] -> [Cout][Ly][Lx]."""
+    Cin, Ly, Lx = a.shape
+    ap = np.pad(a, ((0, 0), (1, 1), (1, 1)))
+    out = np.zeros((w.shape[0], Ly, Lx)) + b[:, None, None]
+    for dy in range(3):
+        for dx in range(3):
+            out += np.einsum("oi,iyx->oyx", w[:, :, dy, dx], ap[:, dy:dy + Ly, dx:dx + Lx])
+    return out
+
+
+def modulation(weights, aux):
+    """Modulation tensor of every block from the seven auxiliary channels
+    aux [7][Ly][Lx] (Fig. 2: convolution, pooling and fully connected layers):
+    leaky(conv3x3) -> P x P average pool -> leaky(FC) -> FC, read as
+    mod[l][kx][ky] = 1 + (o_re + i o_im) (identity when the path outputs 0)."""
+    w = weights
+    L, m = int(w["layers"]), int(w["modes"])
+    h = leaky(conv3x3(aux, w["mod_conv_w"], w["mod_conv_b"]))
+    p = adaptive_avg_pool(h, int(w["mod_pool"])).ravel()
+    f = leaky(w["mod_fc1_w"] @ p + w["mod_fc1_b"])
+    o = (w["mod_fc2_w"] @ f + w["mod_fc2_b"]).reshape(L, 2 * m, m, 2)
+    return 1.0 + o[..., 0] + 1j * o[..., 1]
 
 
 def build_inputs(v, eps, k0h, inv_sx, inv_sy, ring_mask):
@@ -127,9 +183,11 @@ def fno_forward(weights, v, eps, k0h, inv_sx, inv_sy, ring_mask, bf16=False):
     x, s = build_inputs(v, eps, k0h, inv_sx, inv_sy, ring_mask)
     if s == 0:
         return np.zeros_like(v, dtype=np.complex128)
+    mod = modulation(wt, x[2:]) if "mod_conv_w" in wt else None
     u = np.einsum("oi,iyx->oyx", wt["lift_w"], x) + wt["lift_b"][:, None, None]
     for l in range(nl):
-        u = fourier_block(u, wt[f"R{l}"], wt[f"W{l}"], wt[f"b{l}"], m, act=(l < nl - 1), bf16=bf16)
+        u = fourier_block(u, wt[f"R{l}"], wt[f"W{l}"], wt[f"b{l}"], m, act=(l < nl - 1), bf16=bf16,
+                          mod=None if mod is None else mod[l])
     p = leaky(np.einsum("oi,iyx->oyx", wt["proj1_w"], round_bf16(u) if bf16 else u)
               + wt["proj1_b"][:, None, None])
     o = np.einsum("oi,iyx->oyx", wt["proj2_w"], p) + wt["proj2_b"][:, None, None]
@@ -145,9 +203,13 @@ def load_weights(path):
     if raw[:8] != b"NOSDDFNO":
         raise ValueError("not a weights file")
     version, C, m, L, in_ch, hidden, dtype = struct.unpack("<7i", raw[8:36])
-    if version != 1 or dtype != 1:
+    if version not in (1, 2) or dtype != 1:
         raise ValueError("unsupported weights file version/dtype")
-    bits = np.frombuffer(raw[36:], dtype=np.uint16)
+    hdr = 36
+    if version == 2:
+        rank, mod_ch, mod_pool, mod_hidden = struct.unpack("<4i", raw[36:52])
+        hdr = 52
+    bits = np.frombuffer(raw[hdr:], dtype=np.uint16)
     vals = (bits.astype(np.uint32) << 16).view(np.float32)
     pos = [0]
 
@@ -158,15 +220,33 @@ def load_weights(path):
         return out
     w = {"modes": m, "layers": L, "lift_w": take(C, in_ch), "lift_b": take(C)}
     for l in range(L):
-        rr = take(2 * m, m, C, C)
-        ri = take(2 * m, m, C, C)
-        w[f"R{l}"] = rr.astype(np.float64) + 1j * ri.astype(np.float64)
+        if version == 1:
+            rr = take(2 * m, m, C, C)
+            ri = take(2 * m, m, C, C)
+            w[f"R{l}"] = rr.astype(np.float64) + 1j * ri.astype(np.float64)
+        else:
+            # low-rank R: the network's spectral weights are the expansion of the
+            # stored (bfloat16) factors; the BF16 emulation rounds it like any
+            # other matrix-core operand
+            Ar, Ai = take(2 * m, m, rank), take(2 * m, m, rank)
+            Br, Bi = take(rank, C, C), take(rank, C, C)
+            w[f"A{l}"] = Ar.astype(np.float64) + 1j * Ai.astype(np.float64)
+            w[f"B{l}"] = Br.astype(np.float64) + 1j * Bi.astype(np.float64)
+            w[f"R{l}"] = expand_lowrank(w[f"A{l}"], w[f"B{l}"])
         w[f"W{l}"] = take(C, C)
         w[f"b{l}"] = take(C)
     w["proj1_w"] = take(hidden, C)
     w["proj1_b"] = take(hidden)
     w["proj2_w"] = take(2, hidden)
     w["proj2_b"] = take(2)
+    if version == 2:
+        w["mod_pool"] = mod_pool
+        w["mod_conv_w"] = take(mod_ch, 7, 3, 3)
+        w["mod_conv_b"] = take(mod_ch)
+        w["mod_fc1_w"] = take(mod_hidden, mod_ch * mod_pool * mod_pool)
+        w["mod_fc1_b"] = take(mod_hidden)
+        w["mod_fc2_w"] = take(L * 2 * m * m * 2, mod_hidden)
+        w["mod_fc2_b"] = take(L * 2 * m * m * 2)
     if pos[0] != vals.size:
         raise ValueError("weights file size does not match its header")
     return w

@@ -282,9 +282,14 @@ __device__ __forceinline__ int mfma_row(int i) { return 8 * (i >> 2) + 4 * ((thr
 // ------------------------------------------------------------------ spectral mix (MFMA)
 // Y[mode][s][:] = X[mode][s][:] (1 x 128, Re/Im interleaved per channel) . Rb[mode] (128 x 128),
 // 64 samples per workgroup.
+// With mod (modulated network), output (o, Re/Im) pairs of sample s are
+// multiplied by mod[smp[s].mod_idx][layer][mode] (complex); the pair sits in
+// two adjacent lanes.
 __global__ __launch_bounds__(256) void fno_spectral_kernel(const float *__restrict__ X,
                                                            const unsigned short *__restrict__ Rb,
-                                                           float *__restrict__ Y, int S_tot) {
+                                                           float *__restrict__ Y, int S_tot,
+                                                           const FnoSample *__restrict__ smp,
+                                                           const float2 *__restrict__ mod, int layer, int n_layers) {
     __shared__ unsigned short As[64 * 128];
     __shared__ unsigned short Bs[128 * 128];
     const int mode = blockIdx.x, s0 = blockIdx.y * 64;
@@ -308,7 +313,15 @@ __global__ __launch_bounds__(256) void fno_spectral_kernel(const float *__restri
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int r = s0 + rb + mfma_row(i);
-            if (r < S_tot) Ym[(long long)r * 128 + col] = acc[i];
+            float v = acc[i];
+            if (mod) {                                       // uniform branch: every lane shuffles
+                const float partner = __shfl_xor(v, 1, 64);
+                const float2 md = mod[((long long)smp[r < S_tot ? r : S_tot - 1].mod_idx * n_layers + layer) *
+                                          FMODES + mode];
+                const float re = (col & 1) ? partner : v, im = (col & 1) ? v : partner;
+                v = (col & 1) ? md.x * im + md.y * re : md.x * re - md.y * im;
+            }
+            if (r < S_tot) Ym[(long long)r * 128 + col] = v;
         }
     }
 }
@@ -419,7 +432,7 @@ void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, con
         hipLaunchKernelGGL(fno_dft_x_fwd_kernel, dim3(FC * FM / 64, 1, S_tot), dim3(256), 0, st, smp, sact, spec, X,
                            S_tot, net.tw);
         hipLaunchKernelGGL(fno_spectral_kernel, dim3(FMODES, (S_tot + 63) / 64), dim3(256), 0, st, X,
-                           net.R + (long long)l * FMODES * 128 * 128, Y, S_tot);
+                           net.R + (long long)l * FMODES * 128 * 128, Y, S_tot, smp, net.mod, l, net.layers);
         hipLaunchKernelGGL(fno_dft_x_inv_kernel, dim3(FC * FM / 64, (2 * lmax + 63) / 64, S_tot), dim3(256), 0, st,
                            smp, sact, Y, nxt, S_tot, net.tw);
         hipLaunchKernelGGL(fno_dft_y_inv_kernel, dim3((FC * lmax + 127) / 128, (lmax + 31) / 32, S_tot), dim3(256), 0,

@@ -132,19 +132,57 @@ def aux_inputs(t, lam, eps_tile):
 
 
 # ----------------------------------------------------------------- model
-def build_model(C=64, modes=16, layers=4, hidden=HIDDEN):
+MOD_CH, MOD_POOL, MOD_HIDDEN = 8, 4, 64
+
+
+def pool_bins(a, P):
+    """Average of a [B][C][Ly][Lx] over a P x P grid of bins, bin (p, q) covering
+    rows floor(p Ly / P) .. floor((p+1) Ly / P) - 1 (and the same for columns)."""
+    import torch
+    Ly, Lx = a.shape[-2:]
+    rows = []
+    for p in range(P):
+        y0, y1 = (p * Ly) // P, ((p + 1) * Ly) // P
+        rows.append(torch.stack([a[..., y0:y1, (q * Lx) // P:((q + 1) * Lx) // P].mean(dim=(-1, -2))
+                                 for q in range(P)], dim=-1))
+    return torch.stack(rows, dim=-2)
+
+
+def build_model(C=64, modes=16, layers=4, hidden=HIDDEN, rank=0):
+    """rank = 0: the plain network (dense complex R per block).  rank > 0: the
+    modulated low-rank network of Fig. 2: R_l = sum_r A_l[k][r] B_l[r] (a
+    linear expansion over the kept modes of a rank-r tensor) and the spectral
+    product multiplied mode by mode by mod_l = 1 + (o_re + i o_im), where o
+    comes from the auxiliary channels through leaky(conv 3x3, MOD_CH
+    channels) -> MOD_POOL x MOD_POOL average pool -> leaky(FC, MOD_HIDDEN) -> FC."""
     import torch
     import torch.nn as nn
 
     class FNO(nn.Module):
         def __init__(self):
             super().__init__()
-            self.C, self.m, self.L = C, modes, layers
+            self.C, self.m, self.L, self.rank = C, modes, layers, rank
             g = 1.0 / math.sqrt(C)
             self.lift_w = nn.Parameter(torch.randn(C, IN_CH) / math.sqrt(IN_CH))
             self.lift_b = nn.Parameter(torch.zeros(C))
-            self.Rr = nn.ParameterList([nn.Parameter(torch.randn(2 * modes, modes, C, C) * g / C) for _ in range(layers)])
-            self.Ri = nn.ParameterList([nn.Parameter(torch.randn(2 * modes, modes, C, C) * g / C) for _ in range(layers)])
+            if rank == 0:
+                self.Rr = nn.ParameterList([nn.Parameter(torch.randn(2 * modes, modes, C, C) * g / C)
+                                            for _ in range(layers)])
+                self.Ri = nn.ParameterList([nn.Parameter(torch.randn(2 * modes, modes, C, C) * g / C)
+                                            for _ in range(layers)])
+            else:
+                a = 1.0 / math.sqrt(rank)
+                self.Ar = nn.ParameterList([nn.Parameter(torch.randn(2 * modes, modes, rank) * a) for _ in range(layers)])
+                self.Ai = nn.ParameterList([nn.Parameter(torch.randn(2 * modes, modes, rank) * a) for _ in range(layers)])
+                self.Br = nn.ParameterList([nn.Parameter(torch.randn(rank, C, C) * g / C) for _ in range(layers)])
+                self.Bi = nn.ParameterList([nn.Parameter(torch.randn(rank, C, C) * g / C) for _ in range(layers)])
+                nf = MOD_CH * MOD_POOL * MOD_POOL
+                self.mcw = nn.Parameter(torch.randn(MOD_CH, 7, 3, 3) / math.sqrt(63))
+                self.mcb = nn.Parameter(torch.zeros(MOD_CH))
+                self.mf1w = nn.Parameter(torch.randn(MOD_HIDDEN, nf) / math.sqrt(nf))
+                self.mf1b = nn.Parameter(torch.zeros(MOD_HIDDEN))
+                self.mf2w = nn.Parameter(torch.zeros(layers * 2 * modes * modes * 2, MOD_HIDDEN))
+                self.mf2b = nn.Parameter(torch.zeros(layers * 2 * modes * modes * 2))
             self.W = nn.ParameterList([nn.Parameter(torch.randn(C, C) * g) for _ in range(layers)])
             self.b = nn.ParameterList([nn.Parameter(torch.zeros(C)) for _ in range(layers)])
             self.p1w = nn.Parameter(torch.randn(hidden, C) * g)
@@ -152,15 +190,33 @@ def build_model(C=64, modes=16, layers=4, hidden=HIDDEN):
             self.p2w = nn.Parameter(torch.randn(2, hidden) / math.sqrt(hidden) * 0.1)
             self.p2b = nn.Parameter(torch.zeros(2))
 
-        def spectral(self, u, l):
+        def spectral_weights(self, l):
+            if self.rank == 0:
+                return torch.complex(self.Rr[l], self.Ri[l])      # [kx][ky][Cin][Cout]
+            A = torch.complex(self.Ar[l], self.Ai[l])
+            B = torch.complex(self.Br[l], self.Bi[l])
+            return torch.einsum("xyr,rio->xyio", A, B)
+
+        def modulation(self, aux):
+            """[B][L][2m][m] complex from the auxiliary channels aux [B][7][Ly][Lx]."""
+            import torch.nn.functional as Fn
+            h = Fn.leaky_relu(Fn.conv2d(aux, self.mcw, self.mcb, padding=1), 0.01)
+            p = pool_bins(h, MOD_POOL).flatten(1)
+            f = Fn.leaky_relu(p @ self.mf1w.t() + self.mf1b, 0.01)
+            o = (f @ self.mf2w.t() + self.mf2b).reshape(-1, self.L, 2 * self.m, self.m, 2)
+            return torch.complex(1.0 + o[..., 0], o[..., 1])
+
+        def spectral(self, u, l, mod=None):
             Bn, C, Ly, Lx = u.shape
             m = self.m
             F = torch.fft.rfftn(u, dim=(-1, -2))                 # [B][C][Ly/2+1][Lx], halved along y
             kx = torch.cat([torch.arange(m), torch.arange(Lx - m, Lx)]).to(u.device)
             X = F[:, :, :m, :][:, :, :, kx]                      # [B][C][ky][kx]
             X = X.permute(0, 3, 2, 1)                            # [B][kx][ky][C]
-            R = torch.complex(self.Rr[l], self.Ri[l])             # [kx][ky][Cin][Cout]
+            R = self.spectral_weights(l)                          # [kx][ky][Cin][Cout]
             Y = torch.einsum("bxyi,xyio->bxyo", X, R)
+            if mod is not None:
+                Y = Y * mod[:, l, :, :, None]
             full = torch.zeros(Bn, C, Ly // 2 + 1, Lx, dtype=F.dtype, device=u.device)
             full[:, :, :m, kx] = Y.permute(0, 3, 2, 1)
             return torch.fft.irfftn(full, s=(Lx, Ly), dim=(-1, -2))
@@ -171,10 +227,11 @@ def build_model(C=64, modes=16, layers=4, hidden=HIDDEN):
             s = torch.sqrt(torch.mean(torch.abs(v) ** 2, dim=(-1, -2), keepdim=True)).clamp_min(1e-30)
             vn = v / s
             x = torch.cat([vn.real[:, None], vn.imag[:, None], aux], dim=1)
+            mod = self.modulation(aux) if self.rank > 0 else None
             u = torch.einsum("oi,biyx->boyx", self.lift_w, x) + self.lift_b[None, :, None, None]
             for l in range(self.L):
                 pw = torch.einsum("oi,biyx->boyx", self.W[l], u) + self.b[l][None, :, None, None]
-                u = pw + self.spectral(u, l)
+                u = pw + self.spectral(u, l, mod)
                 if l < self.L - 1:
                     u = Fn.leaky_relu(u, 0.01)
             p = Fn.leaky_relu(torch.einsum("oi,biyx->boyx", self.p1w, u) + self.p1b[None, :, None, None], 0.01)
@@ -204,33 +261,50 @@ def bf16_bits(a):
     return rounded.astype(np.uint16)
 
 
+def _ordered_params(model):
+    """Parameters in weights-file order (version 1: plain; version 2: modulated low rank)."""
+    params = [model.lift_w, model.lift_b]
+    for l in range(model.L):
+        if model.rank == 0:
+            params += [model.Rr[l], model.Ri[l]]
+        else:
+            params += [model.Ar[l], model.Ai[l], model.Br[l], model.Bi[l]]
+        params += [model.W[l], model.b[l]]
+    params += [model.p1w, model.p1b, model.p2w, model.p2b]
+    if model.rank > 0:
+        params += [model.mcw, model.mcb, model.mf1w, model.mf1b, model.mf2w, model.mf2b]
+    return params
+
+
+def _header(model):
+    ver = 1 if model.rank == 0 else 2
+    h = struct.pack("<7i", ver, model.C, model.m, model.L, IN_CH, HIDDEN, 1)
+    if ver == 2:
+        h += struct.pack("<4i", model.rank, MOD_CH, MOD_POOL, MOD_HIDDEN)
+    return h
+
+
 def write_weights(model, path):
     t = lambda p: p.detach().float().cpu().numpy()
-    parts = [t(model.lift_w), t(model.lift_b)]
-    for l in range(model.L):
-        parts += [t(model.Rr[l]), t(model.Ri[l]), t(model.W[l]), t(model.b[l])]
-    parts += [t(model.p1w), t(model.p1b), t(model.p2w), t(model.p2b)]
     with open(path, "wb") as f:
         f.write(MAGIC)
-        f.write(struct.pack("<7i", 1, model.C, model.m, model.L, IN_CH, HIDDEN, 1))
-        for p in parts:
-            f.write(bf16_bits(p).tobytes())
+        f.write(_header(model))
+        for p in _ordered_params(model):
+            f.write(bf16_bits(t(p)).tobytes())
 
 
 def read_weights(model, path):
     """Load a weights file written by write_weights into a model of the same shape."""
     import torch
+    hdr = _header(model)
     with open(path, "rb") as f:
         if f.read(8) != MAGIC:
             raise ValueError(f"{path}: not a weights file")
-        ver, C, m, L, in_ch, hidden, dt = struct.unpack("<7i", f.read(28))
-        if (ver, C, m, L, in_ch, hidden, dt) != (1, model.C, model.m, model.L, IN_CH, HIDDEN, 1):
-            raise ValueError(f"{path}: header {(ver, C, m, L, in_ch, hidden, dt)} does not match the model")
+        got = f.read(len(hdr))
+        if got != hdr:
+            raise ValueError(f"{path}: header does not match the model")
         raw = np.frombuffer(f.read(), dtype=np.uint16)
-    params = [model.lift_w, model.lift_b]
-    for l in range(model.L):
-        params += [model.Rr[l], model.Ri[l], model.W[l], model.b[l]]
-    params += [model.p1w, model.p1b, model.p2w, model.p2b]
+    params = _ordered_params(model)
     off = 0
     with torch.no_grad():
         for p in params:
@@ -396,16 +470,17 @@ def evaluate(model, data, rng, steps=30, n=32):
     return float(np.median(res[0])), float(np.median(first)), res
 
 
-def evaluate_many(model, data, seed, batches=8, n=32, steps=30):
-    """evaluate() over several held-out batches drawn from a fixed seed, pooled:
-    median residual after 1, 2, 4, 8 and 16 NN-FGMRES steps, and the median
-    number of steps to 1e-3 and to 1e-5 (steps + 1 when not reached)."""
+def evaluate_many(model, data, seed, batches=16, n=32, steps=30):
+    """evaluate() over several held-out batches drawn from a fixed seed, pooled
+    (16 x 32 = 512 subdomains by default): median residual after 1, 2, 4, 8
+    and 16 NN-FGMRES steps, and the median number of steps to 1e-3, 1e-5 and
+    1e-6 (steps + 1 when not reached)."""
     rng = np.random.default_rng(seed)
     res = np.concatenate([evaluate(model, data, rng, steps, n)[2] for _ in range(batches)], axis=1)
     out = {"samples": res.shape[1]}
     for k in (1, 2, 4, 8, 16):
         out[f"res_after_{k}"] = float(np.median(res[k - 1]))
-    for t in (1e-3, 1e-5):
+    for t in (1e-3, 1e-5, 1e-6):
         below = res <= t
         out[f"steps_to_{t:g}"] = float(np.median(np.where(below.any(0), below.argmax(0) + 1, steps + 1)))
     return out
@@ -423,6 +498,8 @@ def main():
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--modes", type=int, default=16)
     ap.add_argument("--layers", type=int, default=4)
+    ap.add_argument("--rank", type=int, default=0,
+                    help="0: plain network; r > 0: modulated network with rank-r spectral weights (Fig. 2)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--scheme", choices=("fgmres", "fixed-point"), default="fgmres",
                     help="recurrent FGMRES training (Algorithm 1) or fixed-point training with clipping (Algorithm 2)")
@@ -437,12 +514,15 @@ def main():
     data = Data(a.data, dev)
     if a.eval:
         for path in a.eval:
-            model = build_model(a.width, a.modes, a.layers).to(dev)
+            model = build_model(a.width, a.modes, a.layers, rank=a.rank).to(dev)
             read_weights(model, path)
             ev = evaluate_many(model, data, seed=12345)
             print(f"[fno_train] eval {path}: " + ", ".join(f"{k} {v:.3g}" for k, v in ev.items()), flush=True)
         return
-    model = build_model(a.width, a.modes, a.layers).to(dev)
+    model = build_model(a.width, a.modes, a.layers, rank=a.rank).to(dev)
+    n_par = sum(p.numel() for p in model.parameters())
+    print(f"[fno_train] {'modulated rank-%d' % a.rank if a.rank else 'plain'} network, {n_par} weights",
+          flush=True)
     opt = torch.optim.Adam(model.parameters(), lr=a.lr)
     t0 = time.time()
     it = 0

@@ -33,3 +33,16 @@ def host(t):
     import torch
     torch.cuda.synchronize()
     return t.cpu().numpy()
+
+
+def oracle_fgmres_iterations(args):
+    """Outer iterations of the oracle's Schwarz-FGMRES to 1e-6 for one
+    (permittivity, wavelength, source) problem: a process-pool job, one BLAS
+    thread, no GPU."""
+    from threadpoolctl import threadpool_limits
+    from oracle.schwarz import SchwarzProblem
+    eps, lam, h, npml, core_x, core_y, overlap, k_coarse, k_trial, J = args
+    with threadpool_limits(1):
+        op = SchwarzProblem(eps, lam, h, npml, core_x, core_y, overlap, k_coarse=k_coarse, k_trial=k_trial)
+        xo, it_o, hist_o, res_o = op.solve(J, tol=1e-6)
+    return int(it_o)

@@ -137,3 +137,39 @@ def test_fixed_point_training_reduces_the_loss():
         last = ft.fixed_point_train_step(model, opt, coef, None, b, y, 3, th_clip=4.0)
     assert last[0] < 0.5 * first[0]
     assert abs(model.a.item() - 0.5) < abs(0.1 - 0.5)
+
+
+def test_modulated_lowrank_weights_roundtrip_and_forward_matches_oracle(tmp_path):
+    """The modulated low-rank network (Fig. 2: R from a rank-r factor pair,
+    mode-wise modulation from the auxiliary channels) written by the trainer
+    (weights file version 2) and read by the oracle gives the same output."""
+    torch.manual_seed(2)
+    model = ft.build_model(C=8, modes=4, layers=2, rank=3).double()
+    with torch.no_grad():
+        for p in model.parameters():
+            p.add_(0.05 * torch.randn_like(p))
+        model.mf2w.add_(0.3 * torch.randn_like(model.mf2w))     # a modulation far from 1
+    ft.round_model_to_bf16(model)
+    path = os.path.join(tmp_path, "w2.bin")
+    ft.write_weights(model, path)
+    other = ft.build_model(C=8, modes=4, layers=2, rank=3)
+    ft.read_weights(other, path)
+    for p, q in zip(model.parameters(), other.parameters()):
+        assert torch.equal(p.float(), q)
+    w = load_weights(path)
+    rng = np.random.default_rng(3)
+    for t, lam in ((4, 1.1), (0, 0.9), (5, 1.4)):
+        x0, x1, y0, y1, side = ft.tile_box(t)
+        eps = rng.uniform(1, 12, (y1 - y0, x1 - x0)).astype(np.float32)
+        aux = ft.aux_inputs(t, lam, eps)
+        v = (rng.standard_normal(eps.shape) + 1j * rng.standard_normal(eps.shape))
+        with torch.no_grad():
+            e_t = model(torch.from_numpy(v)[None], torch.from_numpy(aux.astype(np.float64))[None])[0].numpy()
+            mod_t = model.modulation(torch.from_numpy(aux.astype(np.float64))[None])[0].numpy()
+        from oracle.fno import modulation
+        np.testing.assert_allclose(modulation(w, aux.astype(np.float64)), mod_t, rtol=1e-12, atol=1e-12)
+        isx = aux[2, 0, :] + 1j * aux[3, 0, :]
+        isy = aux[4, :, 0] + 1j * aux[5, :, 0]
+        e_o = fno_forward(w, v, eps.astype(np.float64), 2 * np.pi / lam * ft.H, isx.astype(np.complex128),
+                          isy.astype(np.complex128), aux[6])
+        assert np.linalg.norm(e_t - e_o) <= 1e-5 * np.linalg.norm(e_o)

@@ -133,6 +133,7 @@ def test_two_level_preconditioner_matches_oracle(k_coarse, k_trial, tol):
     A, part, locs = oracle_parts(w, 1.1)
     cs = CoarseSpace(part, locs, A, w.eps.astype(np.float64), 1.1, w.h, k_coarse, k_trial)
     zr, Azr = two_level_apply(locs, A, cs, v.ravel())
+    print(f"k_coarse {k_coarse}: z {rel(z.ravel(), zr):.2e}, Az {rel(Az.ravel(), Azr):.2e}")
     assert rel(z.ravel(), zr) < tol
     assert rel(Az.ravel(), Azr) < tol
 
@@ -198,7 +199,10 @@ def test_batched_wavelengths_and_sources_two_level():
             if err_o <= 5e-6:
                 assert rel(E[wi, s].ravel(), xs) < 1e-5
             else:
-                assert rel(E[wi, s].ravel(), xo) < 1e-5 + err_o
+                # the oracle's own iterate misses x* at this tolerance: compare with
+                # its iterate after the GPU's iteration count
+                xk, _, _, _ = op.solve(w.J()[s], tol=1e-300, max_iters=int(iters[wi, s]))
+                assert rel(E[wi, s].ravel(), xk) < 1e-5, (rel(E[wi, s].ravel(), xk), err_o)
             assert abs(int(iters[wi, s]) - it_o) <= 1, (lam, s, iters[wi, s], it_o)
             assert fin[wi, s] <= 1e-6
 
