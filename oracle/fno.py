@@ -89,11 +89,13 @@ def fourier_block(u, R, W, bias, m, act=True, bf16=False, mod=None):
     """One block: act(W u + b + F^-1(mod . (R . F(u)))).  R [2m][m][Cin][Cout]
     complex; mod [2m][m] complex (None: no modulation).
 
-    bf16: the operands of the two channel mixes (the truncated spectrum X
-    before R, the activations u before W) are rounded to bfloat16, as a
-    matrix-core implementation with BF16 operands sees them; the transforms,
-    sums and bias stay exact."""
+    bf16: the block's input u is rounded to bfloat16 (activations stored in
+    bfloat16 between blocks), and so are the truncated spectrum X and R
+    before their product, as a matrix-core implementation with BF16 operands
+    sees them; the transforms, sums and bias stay exact."""
     C, Ly, Lx = u.shape
+    if bf16:
+        u = round_bf16(u)              # activations are stored in bfloat16 between blocks
     X = dft_truncated(u, m)
     if bf16:
         X = round_bf16(X)
@@ -171,11 +173,11 @@ def build_inputs(v, eps, k0h, inv_sx, inv_sy, ring_mask):
 def fno_forward(weights, v, eps, k0h, inv_sx, inv_sy, ring_mask, bf16=False):
     """Apply the network to one local residual v [Ly][Lx]; returns e [Ly][Lx] complex.
 
-    bf16=True is the emulation of a BF16 matrix-core forward pass: the
-    operands of every learned channel mix (spectral mix, 1x1 mix, first
-    projection) are rounded to bfloat16 before the product, everything else
-    is exact (the lift, the transforms and the last projection are not
-    matrix-core products)."""
+    bf16=True is the emulation of a BF16 matrix-core forward pass: every
+    activation tensor between blocks is rounded to bfloat16 (it is stored so),
+    and so are the operands of every learned channel mix (spectral mix, 1x1
+    mix, first projection); everything else is exact (the lift, the
+    transforms and the last projection are not matrix-core products)."""
     wt = {k: np.asarray(a, dtype=np.float64) if not np.iscomplexobj(a) else np.asarray(a, np.complex128)
           for k, a in weights.items()}
     m = int(weights["modes"])

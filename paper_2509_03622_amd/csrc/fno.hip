@@ -1,16 +1,22 @@
 // Subdomain Fourier neural operator, batched inference on gfx950.
 //
-// Network (Fig. 2 architecture, plain spectral form): 9 input channels
+// Network (Fig. 2 architecture): 9 input channels
 // [Re v/s, Im v/s, (eps-1)/11, k0 h sqrt(eps), Re/Im 1/s_x, Re/Im 1/s_y,
 // interface-ring mask] (s = rms of v over the subdomain), lift to C = 64,
 // L blocks u <- act(W u + b + F^-1(R . F u)) on the kept modes kx in
 // {0..15} U {Lx-16..Lx-1}, ky in {0..15} (512 modes), leaky ReLU 0.01
 // (identity after the last block), projection 64 -> 128 (leaky) -> 2,
-// output (o0 + i o1) s.
+// output (o0 + i o1) s.  The modulated low-rank form of Fig. 2 runs the same
+// kernels: its R = A B is expanded once when the weights are loaded, and its
+// per-mode modulation (a function of the auxiliary channels only) is formed
+// once per (subdomain, wavelength) at set-up and multiplies the spectral
+// product in fno_spectral_kernel.
 //
 // A "sample" is one (subdomain, RHS) pair; all samples of a sweep run in one
-// launch per stage.  Activations are FP32 [sample][C][cells] with the
-// subdomain's own (lx, ly).  The dense channel contractions -- the 1x1 mix W
+// launch per stage.  Activations are stored in BF16 [sample][C][cells] with
+// the subdomain's own (lx, ly) (every block reads its input rounded to BF16:
+// the transforms take it as FP32 values, the channel mixes as BF16 MFMA
+// operands); transform intermediates stay FP32.  The dense channel contractions -- the 1x1 mix W
 // and the per-mode complex mix R -- run on MFMA in BF16 with FP32
 // accumulation (v_mfma_f32_32x32x8_bf16): R is applied as the real 128 x 128
 // form of the complex 64 x 64 mix to (Re X_c, Im X_c) interleaved per
@@ -39,6 +45,7 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
     u += 0x7FFFu + ((u >> 16) & 1u);        // round to nearest even
     return (unsigned short)(u >> 16);
 }
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 __device__ __forceinline__ float leaky(float x) { return x >= 0.f ? x : LEAK * x; }
 
 // ------------------------------------------------------------------ lift
@@ -47,7 +54,7 @@ __global__ __launch_bounds__(256) void fno_lift_kernel(const FnoSample *__restri
                                                        const float2 *__restrict__ v, const float *__restrict__ vscale,
                                                        const float *__restrict__ aux, long long aux_ch_stride,
                                                        const float *__restrict__ lw, const float *__restrict__ lb,
-                                                       float *__restrict__ act) {
+                                                       unsigned short *__restrict__ act) {
     __shared__ float w[FC * FIN + FC];
     const int s = blockIdx.y;
     if (sact && !sact[s]) return;
@@ -65,13 +72,13 @@ __global__ __launch_bounds__(256) void fno_lift_kernel(const FnoSample *__restri
     x[1] = vv.y * sc;
 #pragma unroll
     for (int k = 0; k < 7; ++k) x[2 + k] = aux[S.aux_off + k * aux_ch_stride + c];
-    float *out = act + S.cell_off * FC + c;
+    unsigned short *out = act + S.cell_off * FC + c;
 #pragma unroll 4
     for (int o = 0; o < FC; ++o) {
         float a = w[FC * FIN + o];
 #pragma unroll
         for (int k = 0; k < FIN; ++k) a += w[o * FIN + k] * x[k];
-        out[(long long)o * n] = a;
+        out[(long long)o * n] = f2bf(a);
     }
 }
 
@@ -100,27 +107,43 @@ template <int WM, int WN, class AR, class LA, class LB, class SC>
 __device__ __forceinline__ void dft_gemm(int M, int N, int K, int m0, int n0, AR arow, LA la, LB lb, SC sink) {
     __shared__ float As[32 * WM][DG_KC + 1];
     __shared__ float Bs[DG_KC][32 * WN + 1];
-    constexpr int BM = 32 * WM, KSTEP = 256 / BM;
+    constexpr int BM = 32 * WM, KSTEP = 256 / BM, NA = DG_KC / KSTEP, NB = DG_KC * 32 * WN / 256;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = wv % WM, wn = wv / WM;
     const int r = threadIdx.x % BM, kq = threadIdx.x / BM;
     const bool rin = m0 + r < M;
     const auto actx = arow(rin ? m0 + r : m0);
+    // the next K chunk is loaded into registers while the current one is
+    // multiplied; addresses are clamped into range so every load is
+    // unconditional, and out-of-range values are zeroed when staged
+    float ra[NA], rb[NB];
+    auto load = [&](int kc) {
+#pragma unroll
+        for (int j = 0; j < NA; ++j) ra[j] = la(actx, min(kc + kq + j * KSTEP, K - 1));
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = threadIdx.x + j * 256;
+            rb[j] = lb(min(kc + i / (32 * WN), K - 1), min(n0 + i % (32 * WN), N - 1));
+        }
+    };
     f32x16v acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    load(0);
     for (int kc = 0; kc < K; kc += DG_KC) {
 #pragma unroll
-        for (int k = kq; k < DG_KC; k += KSTEP) {
-            const int kk = kc + k;
-            As[r][k] = (rin && kk < K) ? la(actx, kk) : 0.f;
+        for (int j = 0; j < NA; ++j) {
+            const int k = kq + j * KSTEP;
+            As[r][k] = (rin && kc + k < K) ? ra[j] : 0.f;
         }
-        for (int i = threadIdx.x; i < DG_KC * 32 * WN; i += 256) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = threadIdx.x + j * 256;
             const int c = i % (32 * WN), k = i / (32 * WN);
-            const int n = n0 + c, kk = kc + k;
-            Bs[k][c] = (n < N && kk < K) ? lb(kk, n) : 0.f;
+            Bs[k][c] = (n0 + c < N && kc + k < K) ? rb[j] : 0.f;
         }
         __syncthreads();
+        if (kc + DG_KC < K) load(kc + DG_KC);
 #pragma unroll
         for (int k = 0; k < DG_KC; k += 2) {
             const float av = As[wm * 32 + (lane & 31)][k + (lane >> 5)];
@@ -145,7 +168,7 @@ __device__ __forceinline__ const float2 *tw_side(const float2 *tw, int L) {
 // Grid (ceil(64 Lmax / 128), 1, S).  T1[c][x][2 ky + ri].
 __global__ __launch_bounds__(256) void fno_dft_y_fwd_kernel(const FnoSample *__restrict__ smp,
                                                             const int *__restrict__ sact,
-                                                            const float *__restrict__ act, float *__restrict__ T1,
+                                                            const unsigned short *__restrict__ act, float *__restrict__ T1,
                                                             const float2 *__restrict__ tw) {
     const int s = blockIdx.z;
     if (sact && !sact[s]) return;
@@ -153,20 +176,23 @@ __global__ __launch_bounds__(256) void fno_dft_y_fwd_kernel(const FnoSample *__r
     const int lx = S.lx, ly = S.ly, n = lx * ly;
     const int M = FC * lx, m0 = blockIdx.x * 128;
     if (m0 >= M) return;
-    const float *u = act + S.cell_off * FC;
+    const unsigned short *u = act + S.cell_off * FC;
     const float *ey = reinterpret_cast<const float *>(tw_side(tw, ly) + FNO_TW_FWD_Y * ly);   // [y][2 ky + ri]
     float *t1 = T1 + S.cell_off * FC;
     // output rows are 32 contiguous floats and the MFMA lanes run along them
     dft_gemm<4, 1>(
         M, 2 * FM, ly, m0, 0, [&](int m) { return u + (m / lx) * n + (m % lx); },
-        [&](const float *row, int k) { return row[k * lx]; }, [&](int k, int nn) { return ey[k * 2 * FM + nn]; },
+        [&](const unsigned short *row, int k) { return bf2f(row[k * lx]); },
+        [&](int k, int nn) { return ey[k * 2 * FM + nn]; },
         [&](int rr, int c, float v) {
             if (m0 + rr < M) t1[(long long)(m0 + rr) * 2 * FM + c] = v;
         });
 }
 
-// B: forward along x (complex): rows (ky, c) (all 64 channels of one ky per
-// block), K = (x, ri), N = (kx, ri).  Grid (16, 1, S).
+// B: forward along x (complex): rows (c, ky) with ky fastest (a block takes
+// 4 channels x all 16 ky, so consecutive lanes read consecutive (ky, Re/Im)
+// entries of a T1 row and every block reads its own channels only),
+// K = (x, ri), N = (kx, ri).  Grid (16, 1, S).
 // X[mode = kx * 16 + ky][s][2 c + ri].
 __global__ __launch_bounds__(256) void fno_dft_x_fwd_kernel(const FnoSample *__restrict__ smp,
                                                             const int *__restrict__ sact,
@@ -176,24 +202,29 @@ __global__ __launch_bounds__(256) void fno_dft_x_fwd_kernel(const FnoSample *__r
     const int s = blockIdx.z;
     if (sact && !sact[s]) return;
     const FnoSample S = smp[s];
-    const int lx = S.lx, ky = blockIdx.x;
+    const int lx = S.lx, m0 = blockIdx.x * 64;          // rows m = c * 16 + ky
     const float *t1 = T1 + S.cell_off * FC;
     const float2 *ex = tw_side(tw, lx);                  // [x][kx]
     dft_gemm<2, 2>(
-        FC, 4 * FM, 2 * lx, 0, 0, [&](int c) { return t1 + (long long)c * lx * 2 * FM + 2 * ky; },
+        FC * FM, 4 * FM, 2 * lx, m0, 0,
+        [&](int m) { return t1 + (long long)(m / FM) * lx * 2 * FM + 2 * (m % FM); },
         [&](const float *row, int k) { return row[(k >> 1) * 2 * FM + (k & 1)]; },
         [&](int k, int nn) { return cplx_entry(ex[(k >> 1) * 2 * FM + (nn >> 1)], k & 1, nn & 1); },
         [&](int rr, int c, float v) { Cs[rr][c] = v; });
     __syncthreads();
-    // for each kx: 64 channels x (Re, Im) = 128 contiguous floats
-    for (int i = threadIdx.x; i < 2 * FM * 2 * FC; i += 256) {
-        const int kx = i / (2 * FC), j = i % (2 * FC), c = j >> 1, ri = j & 1;
-        X[((long long)(kx * FM + ky) * S_tot + s) * (2 * FC) + j] = Cs[c][2 * kx + ri];
+    // for each (kx, ky): the block's 4 channels x (Re, Im) = 8 contiguous floats
+    const int c0 = m0 / FM;
+    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+        const int j = i & 7, rest = i >> 3;          // j = (channel, Re/Im) within the block
+        const int ky = rest % FM, kx = rest / FM;
+        const int cl = j >> 1, ri = j & 1;
+        X[((long long)(kx * FM + ky) * S_tot + s) * (2 * FC) + 2 * (c0 + cl) + ri] = Cs[cl * FM + ky][2 * kx + ri];
     }
 }
 
-// C: inverse along x (complex): rows (c, ky), K = (kx, ri), N = (x, ri).
-// Grid (16, ceil(2 Lmax / 64), S).  P[c][ky][2 x + ri].
+// C: inverse along x (complex): rows c (all 64 channels of one ky per block,
+// so consecutive lanes read consecutive channels of a Y row), K = (kx, ri),
+// N = (x, ri).  Grid (16, ceil(2 Lmax / 64), S).  P[c][ky][2 x + ri].
 __global__ __launch_bounds__(256) void fno_dft_x_inv_kernel(const FnoSample *__restrict__ smp,
                                                             const int *__restrict__ sact,
                                                             const float *__restrict__ Y, float *__restrict__ P,
@@ -203,22 +234,21 @@ __global__ __launch_bounds__(256) void fno_dft_x_inv_kernel(const FnoSample *__r
     if (sact && !sact[s]) return;
     const FnoSample S = smp[s];
     const int lx = S.lx;
-    const int N = 2 * lx, m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    const int N = 2 * lx, ky = blockIdx.x, n0 = blockIdx.y * 64;
     if (n0 >= N) return;
     float *pp = P + S.cell_off * FC;
     const float2 *ext = tw_side(tw, lx) + FNO_TW_INV_X * lx;     // [kx][x]
-    const float *Ys = Y + (long long)s * (2 * FC);
     const long long mode_stride = (long long)S_tot * (2 * FC);
+    const float *Ys = Y + (long long)s * (2 * FC) + (long long)ky * mode_stride;
     dft_gemm<2, 2>(
-        FC * FM, N, 4 * FM, m0, n0,
-        [&](int m) { return Ys + (long long)(m % FM) * mode_stride + 2 * (m / FM); },
+        FC, N, 4 * FM, 0, n0, [&](int c) { return Ys + 2 * c; },
         [&](const float *row, int k) { return row[(long long)(k >> 1) * FM * mode_stride + (k & 1)]; },
         [&](int k, int nn) { return cplx_entry(ext[(k >> 1) * lx + (nn >> 1)], k & 1, nn & 1); },
         [&](int rr, int c, float v) { Cs[rr][c] = v; });
     __syncthreads();
     for (int i = threadIdx.x; i < 64 * 64; i += 256) {
         const int rr = i / 64, c = i % 64;
-        if (n0 + c < N) pp[(long long)(m0 + rr) * N + n0 + c] = Cs[rr][c];
+        if (n0 + c < N) pp[(long long)(rr * FM + ky) * N + n0 + c] = Cs[rr][c];
     }
 }
 
@@ -327,50 +357,64 @@ __global__ __launch_bounds__(256) void fno_spectral_kernel(const float *__restri
 }
 
 // ------------------------------------------------------------------ pointwise (MFMA)
-// out[s][o][c] = act(sum_i W[o][i] u[s][i][c] + b[o] + spec[s][o][c]) on 64-cell tiles.
+// out[s][o][c] = act(sum_i W[o][i] u[s][i][c] + b[o] + spec[s][o][c]) on 64-cell
+// tiles, FNO_PW_TILES tiles per workgroup (W is staged in LDS once for all;
+// one tile per workgroup measured fastest: more workgroups in flight).
+constexpr int FNO_PW_TILES = 1, FNO_PROJ_TILES = 4;
 __global__ __launch_bounds__(256) void fno_pointwise_kernel(const FnoSample *__restrict__ smp,
-                                                            const int *__restrict__ sact, const float *__restrict__ u,
+                                                            const int *__restrict__ sact,
+                                                            const unsigned short *__restrict__ u,
                                                             const float *__restrict__ spec,
                                                             const unsigned short *__restrict__ Wb,
-                                                            const float *__restrict__ bias, float *__restrict__ out,
+                                                            const float *__restrict__ bias, unsigned short *__restrict__ out,
                                                             int apply_act) {
     __shared__ unsigned short As[FC * FC];
     __shared__ unsigned short Bs[FC * 64];
+    __shared__ float bs[FC];
     const int s = blockIdx.y;
     if (sact && !sact[s]) return;
     const FnoSample S = smp[s];
     const int n = S.lx * S.ly;
-    const int c0 = blockIdx.x * 64;
-    if (c0 >= n) return;
+    const int cbase = blockIdx.x * 64 * FNO_PW_TILES;
+    if (cbase >= n) return;
     for (int i = threadIdx.x; i < FC * FC; i += 256) As[i] = Wb[i];
-    const float *us = u + S.cell_off * FC;
-    for (int i = threadIdx.x; i < FC * 64; i += 256) {
-        const int k = i >> 6, c = i & 63;
-        Bs[i] = (c0 + c < n) ? f2bf(us[(long long)k * n + c0 + c]) : (unsigned short)0;
-    }
-    __syncthreads();
+    if (threadIdx.x < FC) bs[threadIdx.x] = bias[threadIdx.x];
+    const unsigned short *us = u + S.cell_off * FC;
+    const float *sp = spec + S.cell_off * FC;
+    unsigned short *os = out + S.cell_off * FC;
     const int wv = threadIdx.x >> 6;
     const int rb = (wv & 1) * 32, cb = (wv >> 1) * 32;
-    f32x16 acc;
+    for (int t = 0; t < FNO_PW_TILES; ++t) {
+        const int c0 = cbase + 64 * t;
+        if (c0 >= n) break;
+        __syncthreads();                              // previous tile's operands consumed
+        for (int i = threadIdx.x; i < FC * 64; i += 256) {
+            const int k = i >> 6, c = i & 63;
+            Bs[i] = (c0 + c < n) ? us[(long long)k * n + c0 + c] : (unsigned short)0;
+        }
+        __syncthreads();
+        f32x16 acc;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-    mfma_tile(As + rb * FC, FC, Bs + cb, 64, FC, acc);
-    const int c = c0 + cb + (threadIdx.x & 31);
-    if (c >= n) return;
-    const float *sp = spec + S.cell_off * FC;
-    float *os = out + S.cell_off * FC;
+        for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+        mfma_tile(As + rb * FC, FC, Bs + cb, 64, FC, acc);
+        const int c = c0 + cb + (threadIdx.x & 31);
+        if (c < n) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int o = rb + mfma_row(i);
-        float v = acc[i] + bias[o] + sp[(long long)o * n + c];
-        os[(long long)o * n + c] = apply_act ? leaky(v) : v;
+            for (int i = 0; i < 16; ++i) {
+                const int o = rb + mfma_row(i);
+                const float v = acc[i] + bs[o] + sp[(long long)o * n + c];
+                os[(long long)o * n + c] = f2bf(apply_act ? leaky(v) : v);
+            }
+        }
     }
 }
 
 // ------------------------------------------------------------------ projection
-// p = leaky(P1 u + b1) (MFMA, 128 x 64), o = P2 p + b2 (FP32), e = (o0 + i o1) * oscale.
+// p = leaky(P1 u + b1) (MFMA, 128 x 64), o = P2 p + b2 (FP32), e = (o0 + i o1) * oscale,
+// FNO_PROJ_TILES 64-cell tiles per workgroup; the 128-term sums of the last
+// projection are split in two halves over all 256 threads.
 __global__ __launch_bounds__(256) void fno_project_kernel(const FnoSample *__restrict__ smp, const int *__restrict__ sact,
-                                                          const float *__restrict__ u,
+                                                          const unsigned short *__restrict__ u,
                                                           const unsigned short *__restrict__ P1b,
                                                           const float *__restrict__ b1, const float *__restrict__ P2,
                                                           const float *__restrict__ b2,
@@ -378,41 +422,53 @@ __global__ __launch_bounds__(256) void fno_project_kernel(const FnoSample *__res
     __shared__ unsigned short As[FH * FC];
     __shared__ unsigned short Bs[FC * 64];
     __shared__ float Ps[FH * 64];
+    __shared__ float p2s[2 * FH], b1s[FH], red[2][2][64];
     const int s = blockIdx.y;
     if (sact && !sact[s]) return;
     const FnoSample S = smp[s];
     const int n = S.lx * S.ly;
-    const int c0 = blockIdx.x * 64;
-    if (c0 >= n) return;
+    const int cbase = blockIdx.x * 64 * FNO_PROJ_TILES;
+    if (cbase >= n) return;
     for (int i = threadIdx.x; i < FH * FC; i += 256) As[i] = P1b[i];
-    const float *us = u + S.cell_off * FC;
-    for (int i = threadIdx.x; i < FC * 64; i += 256) {
-        const int k = i >> 6, c = i & 63;
-        Bs[i] = (c0 + c < n) ? f2bf(us[(long long)k * n + c0 + c]) : (unsigned short)0;
-    }
-    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * FH; i += 256) p2s[i] = P2[i];
+    for (int i = threadIdx.x; i < FH; i += 256) b1s[i] = b1[i];
+    const unsigned short *us = u + S.cell_off * FC;
+    const float osc = oscale[s];
     const int wv = threadIdx.x >> 6;          // wave wv: rows 32 wv, both column halves
-    for (int t = 0; t < 2; ++t) {
-        f32x16 acc;
+    const int tc = threadIdx.x & 63, which = (threadIdx.x >> 6) & 1, half = threadIdx.x >> 7;
+    for (int tt = 0; tt < FNO_PROJ_TILES; ++tt) {
+        const int c0 = cbase + 64 * tt;
+        if (c0 >= n) break;
+        __syncthreads();                              // previous tile's Bs, Ps and red consumed
+        for (int i = threadIdx.x; i < FC * 64; i += 256) {
+            const int k = i >> 6, c = i & 63;
+            Bs[i] = (c0 + c < n) ? us[(long long)k * n + c0 + c] : (unsigned short)0;
+        }
+        __syncthreads();
+        for (int t = 0; t < 2; ++t) {
+            f32x16 acc;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-        mfma_tile(As + 32 * wv * FC, FC, Bs + 32 * t, 64, FC, acc);
-        const int c = 32 * t + (threadIdx.x & 31);
+            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+            mfma_tile(As + 32 * wv * FC, FC, Bs + 32 * t, 64, FC, acc);
+            const int c = 32 * t + (threadIdx.x & 31);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int o = 32 * wv + mfma_row(i);
-            Ps[o * 64 + c] = leaky(acc[i] + b1[o]);
+            for (int i = 0; i < 16; ++i) {
+                const int o = 32 * wv + mfma_row(i);
+                Ps[o * 64 + c] = leaky(acc[i] + b1s[o]);
+            }
+        }
+        __syncthreads();
+        float a = 0.f;
+#pragma unroll 8
+        for (int k = half * (FH / 2); k < (half + 1) * (FH / 2); ++k) a += p2s[which * FH + k] * Ps[k * 64 + tc];
+        red[half][which][tc] = a;
+        __syncthreads();
+        if (threadIdx.x < 128 && c0 + tc < n) {
+            // two threads per cell write re / im
+            float *eo = reinterpret_cast<float *>(e + S.cell_off + c0 + tc);
+            eo[which] = (b2[which] + red[0][which][tc] + red[1][which][tc]) * osc;
         }
     }
-    __syncthreads();
-    if (threadIdx.x >= 128) return;
-    const int c = threadIdx.x & 63, which = threadIdx.x >> 6;
-    if (c0 + c >= n) return;
-    float a = b2[which];
-    for (int k = 0; k < FH; ++k) a += P2[which * FH + k] * Ps[k * 64 + c];
-    // two threads per cell write re / im
-    float *eo = reinterpret_cast<float *>(e + S.cell_off + c0 + c);
-    eo[which] = a * oscale[s];
 }
 
 // ------------------------------------------------------------------ host side
@@ -420,15 +476,19 @@ void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, con
                  const float2 *v, const float *vscale, const float *oscale, const float *aux, long long aux_ch_stride,
                  float *act0, float *act1, float *spec, float *X, float *Y, float2 *e) {
     const int cblk = (max_cells + 255) / 256;
-    const int tblk = (max_cells + 63) / 64;
+    const int tblk = (max_cells + 64 * FNO_PW_TILES - 1) / (64 * FNO_PW_TILES);
+    const int pblk = (max_cells + 64 * FNO_PROJ_TILES - 1) / (64 * FNO_PROJ_TILES);
     const int lmax = FNO_MAXL;                 // longest subdomain side (blocks beyond a sample's size exit)
+    // activations are stored in BF16 [sample][channel][cell] between kernels;
+    // the same buffers hold the FP32 intermediates P (nxt) of a layer
+    auto bf = [](float *p) { return reinterpret_cast<unsigned short *>(p); };
     hipLaunchKernelGGL(fno_lift_kernel, dim3(cblk, S_tot), dim3(256), 0, st, smp, sact, v, vscale, aux, aux_ch_stride,
-                       net.lift_w, net.lift_b, act0);
+                       net.lift_w, net.lift_b, bf(act0));
     float *cur = act0, *nxt = act1;
     for (int l = 0; l < net.layers; ++l) {
         // T1 in spec, P in nxt: both are free until the pointwise step of this layer
         hipLaunchKernelGGL(fno_dft_y_fwd_kernel, dim3((FC * lmax + 127) / 128, 1, S_tot), dim3(256), 0, st, smp, sact,
-                           cur, spec, net.tw);
+                           bf(cur), spec, net.tw);
         hipLaunchKernelGGL(fno_dft_x_fwd_kernel, dim3(FC * FM / 64, 1, S_tot), dim3(256), 0, st, smp, sact, spec, X,
                            S_tot, net.tw);
         hipLaunchKernelGGL(fno_spectral_kernel, dim3(FMODES, (S_tot + 63) / 64), dim3(256), 0, st, X,
@@ -437,14 +497,14 @@ void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, con
                            smp, sact, Y, nxt, S_tot, net.tw);
         hipLaunchKernelGGL(fno_dft_y_inv_kernel, dim3((FC * lmax + 127) / 128, (lmax + 31) / 32, S_tot), dim3(256), 0,
                            st, smp, sact, nxt, spec, net.tw);
-        hipLaunchKernelGGL(fno_pointwise_kernel, dim3(tblk, S_tot), dim3(256), 0, st, smp, sact, cur, spec,
-                           net.W + (long long)l * FC * FC, net.b + (long long)l * FC, nxt,
+        hipLaunchKernelGGL(fno_pointwise_kernel, dim3(tblk, S_tot), dim3(256), 0, st, smp, sact, bf(cur), spec,
+                           net.W + (long long)l * FC * FC, net.b + (long long)l * FC, bf(nxt),
                            l < net.layers - 1 ? 1 : 0);
         float *t = cur;
         cur = nxt;
         nxt = t;
     }
-    hipLaunchKernelGGL(fno_project_kernel, dim3(tblk, S_tot), dim3(256), 0, st, smp, sact, cur, net.p1w, net.p1b,
+    hipLaunchKernelGGL(fno_project_kernel, dim3(pblk, S_tot), dim3(256), 0, st, smp, sact, bf(cur), net.p1w, net.p1b,
                        net.p2w, net.p2b, oscale, e);
 }
 
