@@ -682,9 +682,11 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, in
 // (both triangles), and the step's products for all sources, M_k (S_k Y) with
 // Y the b x NCOL operand, run as FP32 MFMA contractions (16 x 16 x 4):
 //   Re = M_r Y_r + M_i (-Y_i),  Im = M_r Y_i + M_i Y_r.
-// The recurrence then runs elementwise over (row, source).  The gathered
-// right-hand sides, w_k and u_k live block-major in a packed workspace
-// (loc[rhs][tile cells]); the core cells are scattered at the end.
+// The recurrence then runs elementwise over (row, source): the forward sweep
+// reads each block of the right-hand sides straight from the global vector
+// (the gather R_i v), keeps w_k block-major in a packed workspace
+// (loc[rhs][tile cells]) for the backward sweep, and the backward sweep
+// writes the core cells of u_k straight to the global output (the RAS scatter).
 // The group width follows the tile: 32 sources for blocks up to 80 cells,
 // 16 above (LDS), so one launch serves mixed tile sizes and the common
 // 72-wide tiles stream each factor block once per wavelength.
@@ -733,7 +735,7 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
         const int r = rfirst + tid;
         colr[tid] = (tid < ns && (!active || active[r])) ? r : -1;
     }
-    const int lx = t.x1 - t.x0, ly = t.y1 - t.y0;
+    
     const float2 *cf = coef + wl * coef_stride(nx, ny);
     const float2 *clo_a = t.tr ? cf : cf + 2 * nx;
     const float2 *chi_a = t.tr ? cf + nx : cf + 2 * nx + ny;
@@ -751,17 +753,6 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
     for (int e = tid; e < BP * LDM; e += BM_THREADS) M[e] = make_float2(0.f, 0.f);
     for (int e = tid; e < 3 * NCOL * LDK; e += BM_THREADS) Xr[e] = 0.f;
     __syncthreads();
-    // gather R_i v block-major: loc[r][loc_off + k b + i]
-    for (int c = 0; c < ns; ++c) {
-        const int r = colr[c];
-        if (r < 0) continue;
-        const float2 *vr = vin + r * vin_stride;
-        float2 *lr = loc + r * LT + t.loc_off;
-        for (int e = tid; e < lx * ly; e += BM_THREADS) {
-            const int yy = e / lx, xx = e - yy * lx;
-            lr[t.tr ? xx * b + yy : e] = vr[(long long)(t.y0 + yy) * nx + (t.x0 + xx)];
-        }
-    }
     // this thread's elements of a packed block: a clamped (always valid) load
     // index and the two LDS positions of the element (-1: nothing to store)
     const long long blk = bt_sym_block(b);
@@ -784,18 +775,30 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
         }
     }
     // this thread's (row, source) elements of the recurrence, fixed for all
-    // steps, and their workspace rows (clamped to a valid source when idle)
+    // steps: their workspace rows and their cells in the global input and
+    // output (clamped to a valid source when idle).  Cell (block k, row i)
+    // is (x0 + i, y0 + k) for row blocks and (x0 + k, y0 + i) for column blocks.
     int ri[RMAX], rc[RMAX];
-    const float2 *prow[RMAX];
+    float2 *prow[RMAX];
+    const float2 *vrow[RMAX];
+    long long orow[RMAX];
+    const long long kstep = t.tr ? 1 : nx;
 #pragma unroll
     for (int j = 0; j < RMAX; ++j) {
         const int e = tid + j * BM_THREADS;
         const bool valid = e < b * NCOL;
-        ri[j] = valid ? e % b : -1;
+        const int i = valid ? e % b : 0;
+        ri[j] = valid ? i : -1;
         rc[j] = valid ? e / b : 0;
-        const int r = colr[rc[j]];
-        prow[j] = loc + (long long)(r >= 0 ? r : rfirst) * LT + t.loc_off + (valid ? e % b : 0);
+        const int r = colr[rc[j]], rr = r >= 0 ? r : rfirst;
+        const long long cell0 = t.tr ? (long long)(t.y0 + i) * nx + t.x0 : (long long)t.y0 * nx + t.x0 + i;
+        prow[j] = loc + (long long)rr * LT + t.loc_off + i;
+        vrow[j] = vin + (long long)rr * vin_stride + cell0;
+        orow[j] = (long long)rr * out_stride + cell0;
     }
+    // core rows of the block direction and core range of the in-block index
+    const int kc0 = t.tr ? t.cx0 - t.x0 : t.cy0 - t.y0, kc1 = t.tr ? t.cx1 - t.x0 : t.cy1 - t.y0;
+    const int ic0 = t.tr ? t.cy0 - t.y0 : t.cx0 - t.x0, ic1 = t.tr ? t.cy1 - t.y0 : t.cx1 - t.x0;
     const int nsteps = 2 * nb - 1;
     auto blk_of = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
     auto fetch = [&](int s, float2(&dst)[EMAX]) {
@@ -811,15 +814,19 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
                 M[o2[j]] = src[j];
             }
     };
-    // v_{k+1} (forward) or w_k (backward) for step s
+    // v_{k+1} from the global input (forward) or w_k from the workspace (backward) for step s
     auto load_pre = [&](int s, float2(&dst)[RMAX]) {
         const int sc_ = s < nsteps ? s : nsteps - 1;
         const int k = blk_of(sc_);
-        const int kk = sc_ < nb ? (k + 1 < nb ? k + 1 : nb - 1) : k;
+        if (sc_ < nb) {
+            const int kk = k + 1 < nb ? k + 1 : nb - 1;
 #pragma unroll
-        for (int j = 0; j < RMAX; ++j) dst[j] = prow[j][(long long)kk * b];
+            for (int j = 0; j < RMAX; ++j) dst[j] = vrow[j][kk * kstep];
+        } else {
+#pragma unroll
+            for (int j = 0; j < RMAX; ++j) dst[j] = prow[j][(long long)k * b];
+        }
     };
-    __syncthreads();                                  // gathered data visible
     float2 ra[EMAX], rb[EMAX], pre_c[RMAX], pre_n[RMAX];
     fetch(0, ra);
     fetch(1, rb);
@@ -828,7 +835,9 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
     for (int e = tid; e < b * NCOL; e += BM_THREADS) {
         const int i = e % b, c = e / b, r = colr[c];
         float2 z = make_float2(0.f, 0.f);
-        if (r >= 0) z = cmul(cmul(si_s[i], so_s[0]), loc[r * LT + t.loc_off + i]);
+        if (r >= 0)
+            z = cmul(cmul(si_s[i], so_s[0]),
+                     vin[(long long)r * vin_stride + (t.tr ? (long long)(t.y0 + i) * nx + t.x0 : (long long)t.y0 * nx + t.x0 + i)]);
         Xr[c * LDK + i] = z.x;
         Xi[c * LDK + i] = z.y;
         Xn[c * LDK + i] = -z.y;
@@ -882,16 +891,16 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
             const int i = ri[j], c = rc[j], r = colr[c];
             float2 z = make_float2(0.f, 0.f);
             if (r >= 0) {
-                float2 *lr = loc + r * LT + t.loc_off;
                 const float2 a = make_float2(Cr[i * LDC + c], Ci[i * LDC + c]);
                 float2 y;
                 if (fwd) {
-                    lr[k * b + i] = a;                                              // w_k
+                    if (!turn) prow[j][(long long)k * b] = a;                       // w_k
                     y = turn ? a : cfms(pre_c[j], cc, a);                           // y_{k+1} or u_{nb-1}
                 } else {
                     y = cfms(pre_c[j], cc, a);                                      // u_k
-                    lr[k * b + i] = y;
                 }
+                // u_k (and u_{nb-1} at the turn): core cells to the output
+                if ((!fwd || turn) && k >= kc0 && k < kc1 && i >= ic0 && i < ic1) out[orow[j] + k * kstep] = y;
                 if (knext >= 0) z = cmul(cmul(si_s[i], so_s[knext]), y);
             }
             Xr[c * LDK + i] = z.x;
@@ -905,21 +914,6 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
     for (int s = 0; s < nsteps; s += 2) {
         step(s, ra, rb);
         if (s + 1 < nsteps) step(s + 1, rb, ra);
-    }
-    __syncthreads();
-    // core cells of u to the output
-    for (int c = 0; c < ns; ++c) {
-        const int r = colr[c];
-        if (r < 0) continue;
-        const float2 *lr = loc + r * LT + t.loc_off;
-        float2 *orr = out + r * out_stride;
-        const int cw = t.cx1 - t.cx0, chh = t.cy1 - t.cy0;
-        for (int e = tid; e < cw * chh; e += BM_THREADS) {
-            const int yy = e / cw, xx = e - yy * cw;
-            const int gx = t.cx0 + xx, gy = t.cy0 + yy;
-            const int lxx = gx - t.x0, lyy = gy - t.y0;
-            orr[(long long)gy * nx + gx] = lr[t.tr ? lxx * b + lyy : lyy * lx + lxx];
-        }
     }
 }
 

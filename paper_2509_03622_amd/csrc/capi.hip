@@ -1363,7 +1363,9 @@ nosdd_status autotune(nosdd_problem *p, int n_rhs, int n_src, int m, const Given
         }
         w.tuned = true;
     }
-    if (!p->bt_tuned && p->sub_solver == 0) {
+    // the prefetch depth belongs to the one-source kernel: nothing to tune when
+    // the sources of a wavelength are solved together
+    if (!p->bt_tuned && p->sub_solver == 0 && !use_multi(p, n_src)) {
         int depths[4];
         const int nd = bt_solve_depths(p->bmax, depths);
         const int2 *ord = nullptr;
