@@ -315,7 +315,13 @@ def main():
     ap.add_argument("--nn-compare", action="store_true",
                     help="instead of the default line: exact-LU against NN-FGMRES subdomain solves, time to 1e-6 "
                          "on the 1024 x 1024 workload (16 x 16 subdomains)")
-    ap.add_argument("--weights", default=NN_WEIGHTS, help="--nn-compare: network weights file")
+    ap.add_argument("--weights", default=NN_WEIGHTS, help="--nn-compare / --nn-apply: network weights file")
+    ap.add_argument("--coarse-sweep", default=None, metavar="K1,K2,...",
+                    help="instead of the default line: time to 1e-6 on --workload for each coarse size "
+                         "(k_trial = max(8, k))")
+    ap.add_argument("--nn-apply", action="store_true",
+                    help="instead of the default line: time one network application to the 256 subdomains of the "
+                         "1024 x 1024 workload (HIP events), with its algorithmic FLOPs")
     ap.add_argument("--nn-quick", action="store_true",
                     help="--nn-compare: only exact LU and two NN-FGMRES settings, all with one coarse function")
     a = ap.parse_args()
@@ -441,6 +447,84 @@ def main():
                           "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "overlap": w.overlap,
                                      "wavelengths": w.wavelengths, "k_coarse": w.k_coarse, "tol": 1e-6},
                           "rows": rows}), flush=True)
+        return
+    if a.coarse_sweep:
+        torch.cuda.init()
+        w = WORKLOADS[a.workload]()
+        J = torch.from_numpy(w.J()).cuda()
+        ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+        rows = []
+        for kc in [int(v) for v in a.coarse_sweep.split(",")]:
+            P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m,
+                              w.pml_lnR, cores=w.cores)
+            t0 = time.perf_counter()
+            P.setup(k_coarse=kc, k_trial=max(8, kc))
+            torch.cuda.synchronize()
+            setup_ms = 1e3 * (time.perf_counter() - t0)
+            E = torch.zeros((len(w.wavelengths), len(w.sources), w.ny, w.nx), dtype=torch.complex64, device="cuda")
+            P.solve_device(J, E, max_iters=2)                   # autotuning and graph capture
+            torch.cuda.synchronize()
+            E.zero_()
+            t0 = time.perf_counter()
+            hist, iters, fin, st = P.solve_device(J, E, max_iters=a.max_iters)
+            torch.cuda.synchronize()
+            rows.append({"k_coarse": kc, "k_trial": max(8, kc), "status": int(st),
+                         "time_to_tol_ms": round(1e3 * (time.perf_counter() - t0), 2),
+                         "setup_ms": round(setup_ms, 1), "iterations_per_rhs": iters.ravel().tolist()})
+            print(f"[bench] {rows[-1]}", file=sys.stderr, flush=True)
+            P.close()
+        print(json.dumps({"mode": "coarse_sweep", "metric": "time to 1e-6 residual per global solve by coarse size",
+                          "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "wavelengths": w.wavelengths,
+                                     "sources": len(w.sources)}, "rows": rows}), flush=True)
+        ctx.close()
+        return
+    if a.nn_apply:
+        torch.cuda.init()
+        from paper_2509_03622_amd.workloads import blocks_1024
+        w = blocks_1024()
+        ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+        P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m, w.pml_lnR)
+        P.setup(k_coarse=0, sub_solver=1, nn_weights=a.weights, inner_max=2, inner_tol=0.1)
+        nt, lc, ne, nc = P.sizes()
+        g = torch.Generator(device="cuda").manual_seed(0)
+        v = torch.randn((1, lc), dtype=torch.complex64, device="cuda", generator=g)
+        e = torch.empty_like(v)
+        for _ in range(3):
+            P.nn_apply(v, e)
+        torch.cuda.synchronize()
+        reps = max(a.steps, 5)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            P.nn_apply(v, e)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tiles = tile_geometry(w)
+        C, m, L, hid = 64, 16, 4, 128
+
+        def flops(lx, ly):
+            """Algorithmic FLOPs of one network application to one lx x ly subdomain."""
+            n = lx * ly
+            dft = 64 * lx * m * ly * 4 + 64 * m * 2 * m * lx * 8          # y then x transform (real input)
+            idft = 64 * m * lx * 2 * m * 8 + 64 * lx * ly * m * 4          # x then y inverse (real output)
+            mix = 2 * m * m * C * C * 8
+            layer = dft + idft + mix + 2 * C * C * n
+            return 2 * 9 * C * n + L * layer + (2 * C * hid + 2 * hid * 2) * n
+        bf16_part = sum(L * (2 * m * m * C * C * 8 + 2 * C * C * t[0] * t[1]) + 2 * C * hid * t[0] * t[1]
+                        for t in tiles)
+        total = sum(flops(t[0], t[1]) for t in tiles)
+        fp32_part = total - bf16_part
+        floor_us = 1e6 * max(bf16_part / 2.5e15 + fp32_part / FP32_MFMA_PEAK_TFS / 1e12, 0.0)
+        print(json.dumps({"mode": "nn_apply", "metric": "one network application to every subdomain",
+                          "config": {"workload": w.name, "subdomains": nt, "weights": os.path.basename(a.weights)},
+                          "ms_per_application": round(ms, 4), "reps": reps,
+                          "algorithmic_gflop": round(total / 1e9, 2),
+                          "bf16_mfma_gflop": round(bf16_part / 1e9, 2), "fp32_gflop": round(fp32_part / 1e9, 2),
+                          "achieved_tflops": round(total / (ms * 1e-3) / 1e12, 2),
+                          "mfma_floor_us": round(floor_us, 1)}), flush=True)
+        P.close()
+        ctx.close()
         return
     if a.nn_compare:
         torch.cuda.init()

@@ -46,3 +46,14 @@ def oracle_fgmres_iterations(args):
         op = SchwarzProblem(eps, lam, h, npml, core_x, core_y, overlap, k_coarse=k_coarse, k_trial=k_trial)
         xo, it_o, hist_o, res_o = op.solve(J, tol=1e-6)
     return int(it_o)
+
+
+def oracle_direct_field(args):
+    """The FP64 direct solution of one (permittivity, wavelength, source)
+    problem: a process-pool job (global sparse LU, one BLAS thread, no GPU)."""
+    from threadpoolctl import threadpool_limits
+    from oracle.fdfd import assemble_A, solve_direct, source_rhs
+    eps, lam, h, npml, pml_m, pml_lnR, J = args
+    with threadpool_limits(1):
+        A = assemble_A(eps, lam, h, npml, pml_m, pml_lnR)
+        return solve_direct(A, source_rhs(J, lam))

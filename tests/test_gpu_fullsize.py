@@ -15,6 +15,9 @@ parameters, per-step HIP graphs).
   field with the oracle's operator.  This problem is about 100 x 77 vacuum
   wavelengths with permittivity up to 12 on 16-cell blocks, and the one-level
   sweep needs about 2 400 - 2 800 outer iterations per right-hand side.
+* 1024 x 1024, 16 x 16 subdomains, one coarse basis function each, with the
+  trained BF16 network as the subdomain solver (NN-FGMRES, 4 inner steps to
+  1e-2): the field against the FP64 direct solution (1e-5 relative L2).
 """
 import time
 
@@ -24,7 +27,7 @@ import pytest
 from oracle.fdfd import assemble_A, solve_direct, source_rhs
 from oracle.partition import LocalProblem, Partition
 from oracle.schwarz import SchwarzProblem
-from paper_2509_03622_amd.workloads import blocks_512, uneven_2048x1536
+from paper_2509_03622_amd.workloads import blocks_512, blocks_1024, uneven_2048x1536
 
 from gpu_common import dev, host, rel
 
@@ -143,6 +146,45 @@ def test_blocks512_algorithm3_loop_full_size():
     np.testing.assert_allclose(hist[wi, 0, :60], h, rtol=1e-3)
     P.close()
     ctx.close()
+
+
+def test_blocks1024_nn_solve_full_size():
+    """The network path at its full size: NN-FGMRES with the trained network
+    (4 inner steps to 1e-2, the faster of the settings the NN-vs-LU comparison
+    runs) reaches 1e-6 without any exact-LU fallback, and the field lies within
+    1e-5 of the FP64 direct solution, computed meanwhile in a separate process."""
+    import multiprocessing as mp
+    import os
+    import torch
+    from paper_2509_03622_amd import nosdd
+    from gpu_common import oracle_direct_field
+    w = blocks_1024()
+    weights = os.path.join(os.path.dirname(nosdd.__file__), "weights", "fno_c64_m16_l4.bin")
+    lam = w.wavelengths[0]
+    job = (w.eps.astype(np.float64), lam, w.h, w.npml, w.pml_m, w.pml_lnR, w.J()[0])
+    with mp.get_context("spawn").Pool(1) as pool:
+        direct = pool.apply_async(oracle_direct_field, (job,))
+        ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+        P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths, w.pml_m,
+                          w.pml_lnR)
+        P.setup(k_coarse=w.k_coarse, k_trial=w.k_trial, sub_solver=1, nn_weights=weights, inner_max=4,
+                inner_tol=1e-2)
+        J = torch.from_numpy(w.J()).cuda()
+        E = torch.zeros((1, 1, w.ny, w.nx), dtype=torch.complex64, device="cuda")
+        t0 = time.perf_counter()
+        hist, iters, fin, st = P.solve_device(J, E, tol=1e-6, max_iters=3000)
+        torch.cuda.synchronize()
+        print(f"NN-FGMRES: {int(iters[0, 0])} outer iterations, {time.perf_counter() - t0:.1f} s, "
+              f"residual {float(fin[0, 0]):.2e}, fallbacks {P.fallback_count()}", flush=True)
+        assert st == 0 and fin[0, 0] <= 1e-6, (iters, fin)
+        assert P.fallback_count() == 0
+        Eh = host(E)
+        P.close()
+        ctx.close()
+        xs = direct.get(timeout=600)
+    err = rel(Eh[0, 0].ravel(), xs)
+    print(f"field error vs FP64 direct {err:.2e}")
+    assert err < 1e-5, err
 
 
 def test_uneven_2048x1536_64_rhs_full_size():
