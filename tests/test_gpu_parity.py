@@ -115,11 +115,16 @@ def test_robin_traces_match_oracle():
         assert rel(g[wi], ref) < 1e-6
 
 
-@pytest.mark.parametrize("k_coarse,k_trial,tol", [(4, 4, 3e-5), (1, 8, 3e-4)])
-def test_two_level_preconditioner_matches_oracle(k_coarse, k_trial, tol):
+@pytest.mark.parametrize("k_coarse,k_trial", [(4, 4), (1, 8)])
+def test_two_level_preconditioner_matches_oracle(k_coarse, k_trial):
     """With k_coarse = k_trial the coarse span is the whole probe span, so the
     correction does not depend on the Rayleigh-Ritz rotation; with k_coarse = 1
-    the selected direction must agree too (distinct singular values)."""
+    the selected direction must agree too.  The selected singular vector moves
+    by at most (trace error) x sigma_1 / (sigma_1 - sigma_2), and the smallest
+    relative gap on this problem is 0.039 (a factor 25 on the FP32 trace error
+    of about 1e-7 -- 1e-6); both cases measure 5e-7 (z) and 1e-6 (A z) and are
+    held to 1e-5."""
+    tol = 1e-5
     w = random_small(22, 192, 192, [64] * 3, [64] * 3, wavelengths=(1.1,), npml=12, block=16)
     w.k_coarse, w.k_trial = k_coarse, k_trial
     ctx, P = make_gpu_problem(w)
