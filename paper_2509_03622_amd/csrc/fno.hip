@@ -289,21 +289,39 @@ __global__ __launch_bounds__(256) void fno_dft_y_inv_kernel(const FnoSample *__r
 
 // ------------------------------------------------------------------ MFMA helpers
 // Wave-level 32x32 tile product with K in steps of 8 on BF16 operands in LDS.
-// A is [32][K] row-major (lda), B is [K][32] row-major (ldb); both unsigned short (bf16 bits).
-// Lane l holds A[l%32][4(l/32)..+3], B[4(l/32)..+3][l%32]; the result lane l holds
-// D[8(i/4) + 4(l/32) + i%4][l%32] in acc[i].
-__device__ __forceinline__ void mfma_tile(const unsigned short *A, int lda, const unsigned short *B, int ldb, int K,
+// A is [32][K] (row stride lda) and Bt is B transposed, [32][K] (row stride
+// ldb), both k-contiguous (unsigned short, bf16 bits), so lane l reads its
+// A[l%32][4(l/32)..+3] and B[4(l/32)..+3][l%32] as one 8-byte LDS load each.
+// Row strides of K + 4 elements put consecutive rows two banks apart, so a
+// wave's loads are conflict-free (a stride of K elements would put all 32
+// rows in one bank).  The result lane l holds D[8(i/4) + 4(l/32) + i%4][l%32]
+// in acc[i].
+constexpr int LDS_PAD = 4;
+__device__ __forceinline__ void mfma_tile(const unsigned short *A, int lda, const unsigned short *Bt, int ldb, int K,
                                           f32x16 &acc) {
     const int lane = threadIdx.x & 63;
     const int row = lane & 31, kq = (lane >> 5) * 4;
+    const unsigned short *ap = A + row * lda + kq, *bp = Bt + row * ldb + kq;
     for (int k0 = 0; k0 < K; k0 += 8) {
-        bf16x4 a, b;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            a[j] = (short)A[row * lda + k0 + kq + j];
-            b[j] = (short)B[(k0 + kq + j) * ldb + row];
-        }
+        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(ap + k0);
+        const bf16x4 b = *reinterpret_cast<const bf16x4 *>(bp + k0);
         acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+}
+
+// Stage a [K][64] block of BF16 values from global memory (element (k, c) at
+// src[k * stride + c], c < valid, zero beyond) into LDS transposed, Bt[c][k]
+// with row stride K + LDS_PAD: each thread gathers four consecutive k of one
+// c (coalesced over c across the wave) and stores them as one 8-byte word.
+template <int K>
+__device__ __forceinline__ void stage_transposed(unsigned short *Bt, const unsigned short *src, long long stride,
+                                                 int valid) {
+    for (int i = threadIdx.x; i < 64 * (K / 4); i += 256) {
+        const int c = i & 63, k4 = (i >> 6) * 4;
+        bf16x4 v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (short)(c < valid ? src[(long long)(k4 + j) * stride + c] : 0);
+        *reinterpret_cast<bf16x4 *>(Bt + c * (K + LDS_PAD) + k4) = v;
     }
 }
 
@@ -320,16 +338,20 @@ __global__ __launch_bounds__(256) void fno_spectral_kernel(const float *__restri
                                                            float *__restrict__ Y, int S_tot,
                                                            const FnoSample *__restrict__ smp,
                                                            const float2 *__restrict__ mod, int layer, int n_layers) {
-    __shared__ unsigned short As[64 * 128];
-    __shared__ unsigned short Bs[128 * 128];
+    constexpr int LD = 128 + LDS_PAD;
+    __shared__ __align__(16) unsigned short As[64 * LD];
+    __shared__ __align__(16) unsigned short Bt[128 * LD];      // R of this mode, transposed: [out][in]
     const int mode = blockIdx.x, s0 = blockIdx.y * 64;
     const float *Xm = X + (long long)mode * S_tot * 128;
-    for (int i = threadIdx.x; i < 64 * 128; i += 256) {
-        const int r = i >> 7, k = i & 127;
-        As[i] = (s0 + r < S_tot) ? f2bf(Xm[(long long)(s0 + r) * 128 + k]) : (unsigned short)0;
+    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+        const int r = i >> 6, k = 2 * (i & 63);
+        float2 x = make_float2(0.f, 0.f);
+        if (s0 + r < S_tot) x = *reinterpret_cast<const float2 *>(Xm + (long long)(s0 + r) * 128 + k);
+        *reinterpret_cast<unsigned *>(As + r * LD + k) = (unsigned)f2bf(x.x) | ((unsigned)f2bf(x.y) << 16);
     }
     const unsigned short *Rm = Rb + (long long)mode * 128 * 128;
-    for (int i = threadIdx.x; i < 128 * 128; i += 256) Bs[i] = Rm[i];
+    stage_transposed<128>(Bt, Rm, 128, 64);
+    stage_transposed<128>(Bt + 64 * LD, Rm + 64, 128, 64);
     __syncthreads();
     const int wv = threadIdx.x >> 6;          // 4 waves: rows (wv & 1) * 32, columns (wv >> 1) * 64
     const int rb = (wv & 1) * 32, cb = (wv >> 1) * 64;
@@ -338,7 +360,7 @@ __global__ __launch_bounds__(256) void fno_spectral_kernel(const float *__restri
         f32x16 acc;
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-        mfma_tile(As + rb * 128, 128, Bs + cb + 32 * t, 128, 128, acc);
+        mfma_tile(As + rb * LD, LD, Bt + (cb + 32 * t) * LD, LD, 128, acc);
         const int col = cb + 32 * t + (threadIdx.x & 31);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -368,8 +390,9 @@ __global__ __launch_bounds__(256) void fno_pointwise_kernel(const FnoSample *__r
                                                             const unsigned short *__restrict__ Wb,
                                                             const float *__restrict__ bias, unsigned short *__restrict__ out,
                                                             int apply_act) {
-    __shared__ unsigned short As[FC * FC];
-    __shared__ unsigned short Bs[FC * 64];
+    constexpr int LD = FC + LDS_PAD;
+    __shared__ __align__(16) unsigned short As[FC * LD];       // W [o][i]
+    __shared__ __align__(16) unsigned short Bt[64 * LD];       // u of the tile, transposed: [cell][i]
     __shared__ float bs[FC];
     const int s = blockIdx.y;
     if (sact && !sact[s]) return;
@@ -377,7 +400,7 @@ __global__ __launch_bounds__(256) void fno_pointwise_kernel(const FnoSample *__r
     const int n = S.lx * S.ly;
     const int cbase = blockIdx.x * 64 * FNO_PW_TILES;
     if (cbase >= n) return;
-    for (int i = threadIdx.x; i < FC * FC; i += 256) As[i] = Wb[i];
+    for (int i = threadIdx.x; i < FC * FC; i += 256) As[(i / FC) * LD + i % FC] = Wb[i];
     if (threadIdx.x < FC) bs[threadIdx.x] = bias[threadIdx.x];
     const unsigned short *us = u + S.cell_off * FC;
     const float *sp = spec + S.cell_off * FC;
@@ -388,15 +411,12 @@ __global__ __launch_bounds__(256) void fno_pointwise_kernel(const FnoSample *__r
         const int c0 = cbase + 64 * t;
         if (c0 >= n) break;
         __syncthreads();                              // previous tile's operands consumed
-        for (int i = threadIdx.x; i < FC * 64; i += 256) {
-            const int k = i >> 6, c = i & 63;
-            Bs[i] = (c0 + c < n) ? us[(long long)k * n + c0 + c] : (unsigned short)0;
-        }
+        stage_transposed<FC>(Bt, us + c0, n, n - c0);
         __syncthreads();
         f32x16 acc;
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-        mfma_tile(As + rb * FC, FC, Bs + cb, 64, FC, acc);
+        mfma_tile(As + rb * LD, LD, Bt + cb * LD, LD, FC, acc);
         const int c = c0 + cb + (threadIdx.x & 31);
         if (c < n) {
 #pragma unroll
@@ -419,8 +439,9 @@ __global__ __launch_bounds__(256) void fno_project_kernel(const FnoSample *__res
                                                           const float *__restrict__ b1, const float *__restrict__ P2,
                                                           const float *__restrict__ b2,
                                                           const float *__restrict__ oscale, float2 *__restrict__ e) {
-    __shared__ unsigned short As[FH * FC];
-    __shared__ unsigned short Bs[FC * 64];
+    constexpr int LD = FC + LDS_PAD;
+    __shared__ __align__(16) unsigned short As[FH * LD];       // P1 [h][c]
+    __shared__ __align__(16) unsigned short Bt[64 * LD];       // u of the tile, transposed: [cell][c]
     __shared__ float Ps[FH * 64];
     __shared__ float p2s[2 * FH], b1s[FH], red[2][2][64];
     const int s = blockIdx.y;
@@ -429,7 +450,7 @@ __global__ __launch_bounds__(256) void fno_project_kernel(const FnoSample *__res
     const int n = S.lx * S.ly;
     const int cbase = blockIdx.x * 64 * FNO_PROJ_TILES;
     if (cbase >= n) return;
-    for (int i = threadIdx.x; i < FH * FC; i += 256) As[i] = P1b[i];
+    for (int i = threadIdx.x; i < FH * FC; i += 256) As[(i / FC) * LD + i % FC] = P1b[i];
     for (int i = threadIdx.x; i < 2 * FH; i += 256) p2s[i] = P2[i];
     for (int i = threadIdx.x; i < FH; i += 256) b1s[i] = b1[i];
     const unsigned short *us = u + S.cell_off * FC;
@@ -439,17 +460,14 @@ __global__ __launch_bounds__(256) void fno_project_kernel(const FnoSample *__res
     for (int tt = 0; tt < FNO_PROJ_TILES; ++tt) {
         const int c0 = cbase + 64 * tt;
         if (c0 >= n) break;
-        __syncthreads();                              // previous tile's Bs, Ps and red consumed
-        for (int i = threadIdx.x; i < FC * 64; i += 256) {
-            const int k = i >> 6, c = i & 63;
-            Bs[i] = (c0 + c < n) ? us[(long long)k * n + c0 + c] : (unsigned short)0;
-        }
+        __syncthreads();                              // previous tile's Bt, Ps and red consumed
+        stage_transposed<FC>(Bt, us + c0, n, n - c0);
         __syncthreads();
         for (int t = 0; t < 2; ++t) {
             f32x16 acc;
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-            mfma_tile(As + 32 * wv * FC, FC, Bs + 32 * t, 64, FC, acc);
+            mfma_tile(As + 32 * wv * LD, LD, Bt + 32 * t * LD, LD, FC, acc);
             const int c = 32 * t + (threadIdx.x & 31);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
