@@ -92,7 +92,9 @@ def fourier_block(u, R, W, bias, m, act=True, bf16=False, mod=None):
     bf16: the block's input u is rounded to bfloat16 (activations stored in
     bfloat16 between blocks), and so are the truncated spectrum X and R
     before their product, as a matrix-core implementation with BF16 operands
-    sees them; the transforms, sums and bias stay exact."""
+    sees them, and the inverse-transform term before it joins the 1 x 1 mix
+    (it is stored in bfloat16 between the two stages); the transforms, sums
+    and bias stay exact."""
     C, Ly, Lx = u.shape
     if bf16:
         u = round_bf16(u)              # activations are stored in bfloat16 between blocks
@@ -104,6 +106,8 @@ def fourier_block(u, R, W, bias, m, act=True, bf16=False, mod=None):
     if mod is not None:
         Y = Y * mod[None]
     spec = idft_truncated(Y, Lx, Ly, m)
+    if bf16:
+        spec = round_bf16(spec)        # stored in bfloat16 for the pointwise stage
     pw = np.einsum("oi,iyx->oyx", W, round_bf16(u) if bf16 else u) + bias[:, None, None]
     out = pw + spec
     return leaky(out) if act else out

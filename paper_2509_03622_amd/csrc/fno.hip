@@ -16,7 +16,8 @@
 // launch per stage.  Activations are stored in BF16 [sample][C][cells] with
 // the subdomain's own (lx, ly) (every block reads its input rounded to BF16:
 // the transforms take it as FP32 values, the channel mixes as BF16 MFMA
-// operands); transform intermediates stay FP32.  The dense channel contractions -- the 1x1 mix W
+// operands); transform intermediates stay FP32 except the inverse-transform
+// term handed to the pointwise stage, which is stored in BF16.  The dense channel contractions -- the 1x1 mix W
 // and the per-mode complex mix R -- run on MFMA in BF16 with FP32
 // accumulation (v_mfma_f32_32x32x8_bf16): R is applied as the real 128 x 128
 // form of the complex 64 x 64 mix to (Re X_c, Im X_c) interleaved per
@@ -253,10 +254,12 @@ __global__ __launch_bounds__(256) void fno_dft_x_inv_kernel(const FnoSample *__r
 }
 
 // D: inverse along y, real part: rows (c, x), K = (ky, ri), N = y.
-// Grid (ceil(64 Lmax / 128), ceil(Lmax / 32), S).  spec[c][y][x].
+// Grid (ceil(64 Lmax / 128), ceil(Lmax / 32), S).  spec[c][y][x], stored in
+// BF16 (the pointwise stage adds it to its FP32 sum and rounds to BF16).
 __global__ __launch_bounds__(256) void fno_dft_y_inv_kernel(const FnoSample *__restrict__ smp,
                                                             const int *__restrict__ sact,
-                                                            const float *__restrict__ P, float *__restrict__ spec,
+                                                            const float *__restrict__ P,
+                                                            unsigned short *__restrict__ spec,
                                                             const float2 *__restrict__ tw) {
     __shared__ float Cs[128][33];
     const int s = blockIdx.z;
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(256) void fno_dft_y_inv_kernel(const FnoSample *__r
     const float *pp = P + S.cell_off * FC;
     const float2 *ey = tw_side(tw, ly) + FNO_TW_INV_Y * ly;       // [y][ky]
     const float norm = 1.f / (float)n;
-    float *sp = spec + S.cell_off * FC;
+    unsigned short *sp = spec + S.cell_off * FC;
     dft_gemm<4, 1>(
         M, ly, 2 * FM, m0, n0, [&](int m) { return pp + (m / lx) * FM * 2 * lx + 2 * (m % lx); },
         [&](const float *row, int k) { return row[(k >> 1) * 2 * lx + (k & 1)]; },
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(256) void fno_dft_y_inv_kernel(const FnoSample *__r
     for (int i = threadIdx.x; i < 128 * 32; i += 256) {
         const int rr = i % 128, c = i / 128;
         const int m = m0 + rr, y = n0 + c;
-        if (m < M && y < ly) sp[(m / lx) * n + y * lx + (m % lx)] = Cs[rr][c];
+        if (m < M && y < ly) sp[(m / lx) * n + y * lx + (m % lx)] = f2bf(Cs[rr][c]);
     }
 }
 
@@ -386,7 +389,7 @@ constexpr int FNO_PW_TILES = 1, FNO_PROJ_TILES = 4;
 __global__ __launch_bounds__(256) void fno_pointwise_kernel(const FnoSample *__restrict__ smp,
                                                             const int *__restrict__ sact,
                                                             const unsigned short *__restrict__ u,
-                                                            const float *__restrict__ spec,
+                                                            const unsigned short *__restrict__ spec,
                                                             const unsigned short *__restrict__ Wb,
                                                             const float *__restrict__ bias, unsigned short *__restrict__ out,
                                                             int apply_act) {
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(256) void fno_pointwise_kernel(const FnoSample *__r
     for (int i = threadIdx.x; i < FC * FC; i += 256) As[(i / FC) * LD + i % FC] = Wb[i];
     if (threadIdx.x < FC) bs[threadIdx.x] = bias[threadIdx.x];
     const unsigned short *us = u + S.cell_off * FC;
-    const float *sp = spec + S.cell_off * FC;
+    const unsigned short *sp = spec + S.cell_off * FC;
     unsigned short *os = out + S.cell_off * FC;
     const int wv = threadIdx.x >> 6;
     const int rb = (wv & 1) * 32, cb = (wv >> 1) * 32;
@@ -422,7 +425,7 @@ __global__ __launch_bounds__(256) void fno_pointwise_kernel(const FnoSample *__r
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int o = rb + mfma_row(i);
-                const float v = acc[i] + bs[o] + sp[(long long)o * n + c];
+                const float v = acc[i] + bs[o] + bf2f(sp[(long long)o * n + c]);
                 os[(long long)o * n + c] = f2bf(apply_act ? leaky(v) : v);
             }
         }
@@ -514,8 +517,8 @@ void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, con
         hipLaunchKernelGGL(fno_dft_x_inv_kernel, dim3(FC * FM / 64, (2 * lmax + 63) / 64, S_tot), dim3(256), 0, st,
                            smp, sact, Y, nxt, S_tot, net.tw);
         hipLaunchKernelGGL(fno_dft_y_inv_kernel, dim3((FC * lmax + 127) / 128, (lmax + 31) / 32, S_tot), dim3(256), 0,
-                           st, smp, sact, nxt, spec, net.tw);
-        hipLaunchKernelGGL(fno_pointwise_kernel, dim3(tblk, S_tot), dim3(256), 0, st, smp, sact, bf(cur), spec,
+                           st, smp, sact, nxt, bf(spec), net.tw);
+        hipLaunchKernelGGL(fno_pointwise_kernel, dim3(tblk, S_tot), dim3(256), 0, st, smp, sact, bf(cur), bf(spec),
                            net.W + (long long)l * FC * FC, net.b + (long long)l * FC, bf(nxt),
                            l < net.layers - 1 ? 1 : 0);
         float *t = cur;
