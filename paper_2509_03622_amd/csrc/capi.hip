@@ -1994,6 +1994,7 @@ nosdd_status nosdd_problem_setup(nosdd_problem *p, const nosdd_setup_opts *o) {
     }
     bt_solve_prepare(p->bmax, p->max_cells);
     if (p->bmax <= 112) bt_solve_multi_prepare(p->bmax);
+    fno_prepare();
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
     {

@@ -299,6 +299,8 @@ void nn_precond(hipStream_t st, const NnWork &nw, const TileDesc *tiles, int n_t
 void nn_rms_scales(hipStream_t st, const FnoSample *smp, int S, const float2 *v, float *vscale, float *oscale);
 
 // e = NN(v) for every active sample; v, e: sample-packed complex cells.
+// raises the dynamic-LDS limit of the network kernels that need more than 64 KB
+void fno_prepare();
 void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, const int *sact, int S_tot, int max_cells,
                  const float2 *v, const float *vscale, const float *oscale, const float *aux, long long aux_ch_stride,
                  float *act0, float *act1, float *spec, float *X, float *Y, float2 *e);

@@ -92,8 +92,8 @@ __global__ __launch_bounds__(256) void fno_lift_kernel(const FnoSample *__restri
 //            D: s[c][y][x]     = Re sum_ky w_ky P[c][ky][x] e^{+2pi i ky y/Ly} / (Lx Ly)   (M = 64 Lx, K = 32, N = Ly)
 // with w_0 = 1, w_ky = 2 (Hermitian completion along y).  Complex products
 // use the real 2 x 2 form of each complex entry (Re/Im interleaved in K and
-// N).  T1 lives in the spec buffer and P in the next-activation buffer of
-// the same sample, both free at that point of the layer.
+// N).  T1 lives in the spec buffer, free at that point of the layer; C and D
+// run in one kernel that keeps P in LDS.
 typedef float f32x16v __attribute__((ext_vector_type(16)));
 constexpr int DG_KC = 16;     // K chunk staged in LDS
 
@@ -223,70 +223,117 @@ __global__ __launch_bounds__(256) void fno_dft_x_fwd_kernel(const FnoSample *__r
     }
 }
 
-// C: inverse along x (complex): rows c (all 64 channels of one ky per block,
-// so consecutive lanes read consecutive channels of a Y row), K = (kx, ri),
-// N = (x, ri).  Grid (16, ceil(2 Lmax / 64), S).  P[c][ky][2 x + ri].
-__global__ __launch_bounds__(256) void fno_dft_x_inv_kernel(const FnoSample *__restrict__ smp,
-                                                            const int *__restrict__ sact,
-                                                            const float *__restrict__ Y, float *__restrict__ P,
-                                                            int S_tot, const float2 *__restrict__ tw) {
-    __shared__ float Cs[64][65];
-    const int s = blockIdx.z;
-    if (sact && !sact[s]) return;
-    const FnoSample S = smp[s];
-    const int lx = S.lx;
-    const int N = 2 * lx, ky = blockIdx.x, n0 = blockIdx.y * 64;
-    if (n0 >= N) return;
-    float *pp = P + S.cell_off * FC;
-    const float2 *ext = tw_side(tw, lx) + FNO_TW_INV_X * lx;     // [kx][x]
-    const long long mode_stride = (long long)S_tot * (2 * FC);
-    const float *Ys = Y + (long long)s * (2 * FC) + (long long)ky * mode_stride;
-    dft_gemm<2, 2>(
-        FC, N, 4 * FM, 0, n0, [&](int c) { return Ys + 2 * c; },
-        [&](const float *row, int k) { return row[(long long)(k >> 1) * FM * mode_stride + (k & 1)]; },
-        [&](int k, int nn) { return cplx_entry(ext[(k >> 1) * lx + (nn >> 1)], k & 1, nn & 1); },
-        [&](int rr, int c, float v) { Cs[rr][c] = v; });
-    __syncthreads();
-    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-        const int rr = i / 64, c = i % 64;
-        if (n0 + c < N) pp[(long long)(rr * FM + ky) * N + n0 + c] = Cs[rr][c];
-    }
-}
-
-// D: inverse along y, real part: rows (c, x), K = (ky, ri), N = y.
-// Grid (ceil(64 Lmax / 128), ceil(Lmax / 32), S).  spec[c][y][x], stored in
-// BF16 (the pointwise stage adds it to its FP32 sum and rounds to BF16).
-__global__ __launch_bounds__(256) void fno_dft_y_inv_kernel(const FnoSample *__restrict__ smp,
-                                                            const int *__restrict__ sact,
-                                                            const float *__restrict__ P,
-                                                            unsigned short *__restrict__ spec,
-                                                            const float2 *__restrict__ tw) {
-    __shared__ float Cs[128][33];
-    const int s = blockIdx.z;
+// C+D: both inverse transforms of FI_CB channels of one sample in one
+// workgroup, the x-transform's result kept in LDS:
+//   P[c][ky][x]  = sum_kx Y[kx][ky][c] e^{+2pi i kx x/Lx}             rows (c, ky), K = (kx, ri), N = (x, ri)
+//   s[c][y][x]   = Re sum_ky w_ky P[c][ky][x] e^{+2pi i ky y/Ly} / (Lx Ly)   rows y, K = (ky, ri), N = (c, x)
+// (w_0 = 1, w_ky = 2: Hermitian completion along y).  The second product
+// takes y as its rows so that lanes store x-contiguous runs of s (BF16).
+// Grid (64 / FI_CB, S), FI_THREADS threads, FI_LDS bytes of dynamic LDS:
+//   Yl [FI_CB 16][65] f32   the block's spectrum, rows (c, ky), k = (kx, ri)
+//   ex [32][Lx]      f2    inverse x twiddles
+//   Wl [32][72]      f32   real weights of the inverse y transform, [k = (ky, ri)][y]
+//   Pl [FI_CB Lx][33] f32  P, rows (c, x), k = (ky, ri)
+constexpr int FI_CB = 2, FI_THREADS = 512;
+constexpr int FI_LDY = 2 * 2 * FM + 1, FI_LDP = 2 * FM + 1;
+constexpr size_t FI_LDS = sizeof(float) * ((size_t)FI_CB * FM * FI_LDY + 2 * 2 * FM * FNO_MAXL +
+                                           2 * FM * FNO_MAXL + (size_t)FI_CB * FNO_MAXL * FI_LDP);
+__global__ __launch_bounds__(FI_THREADS) void fno_dft_inv_kernel(const FnoSample *__restrict__ smp,
+                                                                 const int *__restrict__ sact,
+                                                                 const float *__restrict__ Y,
+                                                                 unsigned short *__restrict__ spec, int S_tot,
+                                                                 const float2 *__restrict__ tw) {
+    extern __shared__ __align__(16) float fl[];
+    const int s = blockIdx.y;
     if (sact && !sact[s]) return;
     const FnoSample S = smp[s];
     const int lx = S.lx, ly = S.ly, n = lx * ly;
-    const int M = FC * lx, m0 = blockIdx.x * 128, n0 = blockIdx.y * 32;
-    if (m0 >= M || n0 >= ly) return;
-    const float *pp = P + S.cell_off * FC;
-    const float2 *ey = tw_side(tw, ly) + FNO_TW_INV_Y * ly;       // [y][ky]
+    const int c0 = blockIdx.x * FI_CB;
+    float *Yl = fl;
+    float2 *ex = reinterpret_cast<float2 *>(Yl + FI_CB * FM * FI_LDY);         // 4160 floats: 16-byte aligned
+    float *Wl = reinterpret_cast<float *>(ex + 2 * FM * FNO_MAXL);
+    float *Pl = Wl + 2 * FM * FNO_MAXL;
+    // the block's modes: 2 x FI_CB floats (channels c0.., Re/Im) per mode
+    const long long mstride = (long long)S_tot * (2 * FC);
+    for (int i = threadIdx.x; i < FMODES * (FI_CB / 2); i += FI_THREADS) {
+        const int mode = i / (FI_CB / 2), h = i % (FI_CB / 2);
+        const float4 v = *reinterpret_cast<const float4 *>(Y + mode * mstride + (long long)s * (2 * FC) + 2 * c0 + 4 * h);
+        const int kx = mode / FM, ky = mode % FM;
+        float *ra = Yl + ((2 * h) * FM + ky) * FI_LDY + 2 * kx, *rb = ra + FM * FI_LDY;
+        ra[0] = v.x;
+        ra[1] = v.y;
+        rb[0] = v.z;
+        rb[1] = v.w;
+    }
+    const float2 *ext = tw_side(tw, lx) + FNO_TW_INV_X * lx;                  // [q][x]
+    for (int i = threadIdx.x; i < 2 * FM * lx; i += FI_THREADS) ex[i] = ext[i];
+    const float2 *ey = tw_side(tw, ly) + FNO_TW_INV_Y * ly;                   // [y][ky]
     const float norm = 1.f / (float)n;
-    unsigned short *sp = spec + S.cell_off * FC;
-    dft_gemm<4, 1>(
-        M, ly, 2 * FM, m0, n0, [&](int m) { return pp + (m / lx) * FM * 2 * lx + 2 * (m % lx); },
-        [&](const float *row, int k) { return row[(k >> 1) * 2 * lx + (k & 1)]; },
-        [&](int k, int nn) {
-            const float2 e = ey[nn * FM + (k >> 1)];
-            const float w = ((k >> 1) == 0 ? 1.f : 2.f) * norm;
-            return (k & 1) ? -w * e.y : w * e.x;
-        },
-        [&](int rr, int c, float v) { Cs[rr][c] = v; });
+    for (int i = threadIdx.x; i < ly * FM; i += FI_THREADS) {
+        const int y = i / FM, ky = i % FM;
+        const float2 e = ey[i];
+        const float w = (ky == 0 ? 1.f : 2.f) * norm;
+        Wl[(2 * ky) * FNO_MAXL + y] = w * e.x;
+        Wl[(2 * ky + 1) * FNO_MAXL + y] = -w * e.y;
+    }
     __syncthreads();
-    // rows m = (c, x) with x fastest: lanes along m give contiguous x runs
-    for (int i = threadIdx.x; i < 128 * 32; i += 256) {
-        const int rr = i % 128, c = i / 128;
-        const int m = m0 + rr, y = n0 + c;
-        if (m < M && y < ly) sp[(m / lx) * n + y * lx + (m % lx)] = f2bf(Cs[rr][c]);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
+    constexpr int NW = FI_THREADS / 64;
+    // x-transform: rows (c, ky) (FI_CB 16), N = 2 Lx
+    {
+        const int N = 2 * lx, nct = (N + 31) / 32, ntile = (FI_CB * FM / 32) * nct;
+        for (int t = wv; t < ntile; t += NW) {
+            const int rt = t / nct, ct = t % nct;
+            const int nn = ct * 32 + lr, x = min(nn >> 1, lx - 1), ro = nn & 1;
+            const bool nin = nn < N;
+            const float *arow = Yl + (rt * 32 + lr) * FI_LDY + lk;
+            f32x16v acc;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll 4
+            for (int k0 = 0; k0 < 4 * FM; k0 += 2) {
+                const int k = k0 + lk;
+                const float bv = nin ? cplx_entry(ex[(k >> 1) * lx + x], k & 1, ro) : 0.f;
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[k0], bv, acc, 0, 0, 0);
+            }
+            if (nin) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int row = rt * 32 + 8 * (i >> 2) + 4 * lk + (i & 3);
+                    const int c = row / FM, ky = row % FM;
+                    Pl[(c * lx + x) * FI_LDP + 2 * ky + ro] = acc[i];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // y-transform: rows y, K = 2 FM, N = (c, x) (FI_CB Lx)
+    {
+        const int N = FI_CB * lx, nrt = (ly + 31) / 32, nct = (N + 31) / 32, ntile = nrt * nct;
+        unsigned short *sp = spec + S.cell_off * FC + (long long)c0 * n;
+        for (int t = wv; t < ntile; t += NW) {
+            const int rt = t / nct, ct = t % nct;
+            const int y = min(rt * 32 + lr, ly - 1), nn = ct * 32 + lr;
+            const bool yin = rt * 32 + lr < ly;
+            const int nc = min(nn, N - 1);
+            const float *bcol = Pl + nc * FI_LDP + lk;
+            f32x16v acc;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll 4
+            for (int k0 = 0; k0 < 2 * FM; k0 += 2) {
+                const float av = yin ? Wl[(k0 + lk) * FNO_MAXL + y] : 0.f;
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bcol[k0], acc, 0, 0, 0);
+            }
+            if (nn < N) {
+                const int c = nn / lx, x = nn % lx;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int yy = rt * 32 + 8 * (i >> 2) + 4 * lk + (i & 3);
+                    if (yy < ly) sp[(long long)c * n + yy * lx + x] = f2bf(acc[i]);
+                }
+            }
+        }
     }
 }
 
@@ -493,6 +540,11 @@ __global__ __launch_bounds__(256) void fno_project_kernel(const FnoSample *__res
 }
 
 // ------------------------------------------------------------------ host side
+void fno_prepare() {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fno_dft_inv_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)FI_LDS);
+}
+
 void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, const int *sact, int S_tot, int max_cells,
                  const float2 *v, const float *vscale, const float *oscale, const float *aux, long long aux_ch_stride,
                  float *act0, float *act1, float *spec, float *X, float *Y, float2 *e) {
@@ -500,24 +552,21 @@ void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, con
     const int tblk = (max_cells + 64 * FNO_PW_TILES - 1) / (64 * FNO_PW_TILES);
     const int pblk = (max_cells + 64 * FNO_PROJ_TILES - 1) / (64 * FNO_PROJ_TILES);
     const int lmax = FNO_MAXL;                 // longest subdomain side (blocks beyond a sample's size exit)
-    // activations are stored in BF16 [sample][channel][cell] between kernels;
-    // the same buffers hold the FP32 intermediates P (nxt) of a layer
+    // activations are stored in BF16 [sample][channel][cell] between kernels
     auto bf = [](float *p) { return reinterpret_cast<unsigned short *>(p); };
     hipLaunchKernelGGL(fno_lift_kernel, dim3(cblk, S_tot), dim3(256), 0, st, smp, sact, v, vscale, aux, aux_ch_stride,
                        net.lift_w, net.lift_b, bf(act0));
     float *cur = act0, *nxt = act1;
     for (int l = 0; l < net.layers; ++l) {
-        // T1 in spec, P in nxt: both are free until the pointwise step of this layer
+        // T1 lives in spec until the inverse transforms overwrite it with their BF16 result
         hipLaunchKernelGGL(fno_dft_y_fwd_kernel, dim3((FC * lmax + 127) / 128, 1, S_tot), dim3(256), 0, st, smp, sact,
                            bf(cur), spec, net.tw);
         hipLaunchKernelGGL(fno_dft_x_fwd_kernel, dim3(FC * FM / 64, 1, S_tot), dim3(256), 0, st, smp, sact, spec, X,
                            S_tot, net.tw);
         hipLaunchKernelGGL(fno_spectral_kernel, dim3(FMODES, (S_tot + 63) / 64), dim3(256), 0, st, X,
                            net.R + (long long)l * FMODES * 128 * 128, Y, S_tot, smp, net.mod, l, net.layers);
-        hipLaunchKernelGGL(fno_dft_x_inv_kernel, dim3(FC * FM / 64, (2 * lmax + 63) / 64, S_tot), dim3(256), 0, st,
-                           smp, sact, Y, nxt, S_tot, net.tw);
-        hipLaunchKernelGGL(fno_dft_y_inv_kernel, dim3((FC * lmax + 127) / 128, (lmax + 31) / 32, S_tot), dim3(256), 0,
-                           st, smp, sact, nxt, bf(spec), net.tw);
+        hipLaunchKernelGGL(fno_dft_inv_kernel, dim3(FC / FI_CB, S_tot), dim3(FI_THREADS), FI_LDS, st, smp, sact, Y,
+                           bf(spec), S_tot, net.tw);
         hipLaunchKernelGGL(fno_pointwise_kernel, dim3(tblk, S_tot), dim3(256), 0, st, smp, sact, bf(cur), bf(spec),
                            net.W + (long long)l * FC * FC, net.b + (long long)l * FC, bf(nxt),
                            l < net.layers - 1 ? 1 : 0);
