@@ -20,6 +20,7 @@
 
 #include "../../include/nosdd.h"
 #include "common.h"
+#include "hostla.h"
 
 using namespace nosdd;
 using cd = std::complex<double>;
@@ -261,40 +262,11 @@ void herm_eig(int n, std::vector<cd> A, std::vector<double> &w, std::vector<cd> 
     for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i].real();
 }
 
-// Explicit inverse of a Hermitian positive-definite matrix through its Cholesky factor.
+// Explicit inverse of a Hermitian positive-definite matrix through its
+// profile Cholesky factor (the coarse matrices are block-sparse: only
+// neighbouring subdomains couple), column solves spread over host threads.
 bool hpd_inverse(int n, const std::vector<cd> &G, std::vector<cd> &Ginv) {
-    std::vector<cd> L((size_t)n * n, cd(0, 0));
-    for (int j = 0; j < n; ++j) {
-        double d = G[(size_t)j * n + j].real();
-        for (int k = 0; k < j; ++k) d -= std::norm(L[(size_t)j * n + k]);
-        if (!(d > 0.0)) return false;
-        const double ljj = std::sqrt(d);
-        L[(size_t)j * n + j] = ljj;
-        for (int i = j + 1; i < n; ++i) {
-            cd s = G[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * std::conj(L[(size_t)j * n + k]);
-            L[(size_t)i * n + j] = s / ljj;
-        }
-    }
-    // Li = L^-1 (lower triangular)
-    std::vector<cd> Li((size_t)n * n, cd(0, 0));
-    for (int c = 0; c < n; ++c) {
-        Li[(size_t)c * n + c] = 1.0 / L[(size_t)c * n + c];
-        for (int i = c + 1; i < n; ++i) {
-            cd s = 0;
-            for (int k = c; k < i; ++k) s += L[(size_t)i * n + k] * Li[(size_t)k * n + c];
-            Li[(size_t)i * n + c] = -s / L[(size_t)i * n + i];
-        }
-    }
-    // Ginv = Li^H Li
-    Ginv.assign((size_t)n * n, cd(0, 0));
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-            cd s = 0;
-            for (int k = std::max(i, j); k < n; ++k) s += std::conj(Li[(size_t)k * n + i]) * Li[(size_t)k * n + j];
-            Ginv[(size_t)i * n + j] = s;
-        }
-    return true;
+    return hpd_inverse_profile(n, G, Ginv);
 }
 
 // ---------------------------------------------------------------- geometry helpers
