@@ -696,6 +696,7 @@ void launch_bt_solve(hipStream_t s, const TileDesc *tiles, const int2 *order, in
 // and a step waits only for the loads it consumes.
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 constexpr int BM_THREADS = 1024;
+typedef unsigned bm_u32x2 __attribute__((ext_vector_type(2)));
 constexpr int BM_NARROW = 80;                  // widest block of the 32-source form
 
 // LDS layout (b the tile's block size, padded to BP = 16 * ceil(b / 16) in rows and in k):
@@ -754,64 +755,84 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
     for (int e = tid; e < 3 * NCOL * LDK; e += BM_THREADS) Xr[e] = 0.f;
     __syncthreads();
     // this thread's elements of a packed block: a clamped (always valid) load
-    // index and the two LDS positions of the element (-1: nothing to store)
+    // index and the two LDS positions of the element, packed in 16 bits each
+    // (0xffff: nothing to store).  The per-thread state of this kernel is kept
+    // compact on purpose: at 1024 threads a wave has 128 registers, and a
+    // spill reloaded inside the step loop would make the compiler wait for
+    // every outstanding load there (vmcnt(0)), prefetched factor blocks included.
     const long long blk = bt_sym_block(b);
     const int nsub = (int)(blk >> 2);
     const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
-    int gi[EMAX], o1[EMAX], o2[EMAX];
+    // every global access goes through a buffer resource: the per-lane byte
+    // offset stays in one 32-bit register and the block step's offset in a
+    // scalar one, so no 64-bit address is formed per access (the host keeps
+    // each range below 2^31 bytes)
+    const __amdgpu_buffer_rsrc_t rsD = bt_rsrc(D, (unsigned)(nb * blk * (long long)sizeof(float2)));
+    const __amdgpu_buffer_rsrc_t rsV =
+        bt_rsrc(vin + (long long)rfirst * vin_stride, (unsigned)((long long)ns * vin_stride * sizeof(float2)));
+    const __amdgpu_buffer_rsrc_t rsL =
+        bt_rsrc(loc + (long long)rfirst * LT, (unsigned)((long long)ns * LT * sizeof(float2)));
+    const __amdgpu_buffer_rsrc_t rsO =
+        bt_rsrc(out + (long long)rfirst * out_stride, (unsigned)((long long)ns * out_stride * sizeof(float2)));
+    auto ld = [](__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+    };
+    auto st = [](__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, float2 v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bm_u32x2, v), rs, (int)voff, (int)soff, 0);
+    };
+    unsigned gi[EMAX];
+    unsigned opos[EMAX];
 #pragma unroll
     for (int j = 0; j < EMAX; ++j) {
         const int e = tid + j * BM_THREADS;
-        gi[j] = e < (int)blk ? e : (int)blk - 1;
-        o1[j] = -1;
-        o2[j] = -1;
+        gi[j] = (unsigned)(e < (int)blk ? e : (int)blk - 1) * (unsigned)sizeof(float2);
+        opos[j] = 0xffffffffu;
         if (e < (int)blk) {
             const int half = e >= 2 * nsub, sub = (e - half * 2 * nsub) >> 1, comp = (e & 1) | (half << 1);
             int bp, bq;
             bt_sym_pq(P, sub, bp, bq);
             const int rr = 2 * bp + (comp & 1), cc = 2 * bq + (comp >> 1);
-            o1[j] = rr * LDM + cc;
-            o2[j] = cc * LDM + rr;
+            opos[j] = (unsigned)(rr * LDM + cc) | ((unsigned)(cc * LDM + rr) << 16);
         }
     }
     // this thread's (row, source) elements of the recurrence, fixed for all
-    // steps: their workspace rows and their cells in the global input and
-    // output (clamped to a valid source when idle).  Cell (block k, row i)
-    // is (x0 + i, y0 + k) for row blocks and (x0 + k, y0 + i) for column blocks.
-    int ri[RMAX], rc[RMAX];
-    float2 *prow[RMAX];
-    const float2 *vrow[RMAX];
-    long long orow[RMAX];
-    const long long kstep = t.tr ? 1 : nx;
+    // steps: row and column packed (-1 when idle), and the byte offsets of
+    // their workspace row and of their cells in the global input and output,
+    // relative to the group's first source (clamped to it when idle).  Cell
+    // (block k, row i) is (x0 + i, y0 + k) for row blocks and (x0 + k, y0 + i)
+    // for column blocks.
+    int rcx[RMAX];
+    unsigned poff[RMAX], voff[RMAX], ooff[RMAX];
+    const unsigned kstep = (t.tr ? 1u : (unsigned)nx) * (unsigned)sizeof(float2);   // bytes per block step
 #pragma unroll
     for (int j = 0; j < RMAX; ++j) {
         const int e = tid + j * BM_THREADS;
         const bool valid = e < b * NCOL;
-        const int i = valid ? e % b : 0;
-        ri[j] = valid ? i : -1;
-        rc[j] = valid ? e / b : 0;
-        const int r = colr[rc[j]], rr = r >= 0 ? r : rfirst;
+        const int i = valid ? e % b : 0, c = valid ? e / b : 0;
+        rcx[j] = valid ? (i | (c << 16)) : -1;
+        const int r = colr[c], rl = r >= 0 ? r - rfirst : 0;
         const long long cell0 = t.tr ? (long long)(t.y0 + i) * nx + t.x0 : (long long)t.y0 * nx + t.x0 + i;
-        prow[j] = loc + (long long)rr * LT + t.loc_off + i;
-        vrow[j] = vin + (long long)rr * vin_stride + cell0;
-        orow[j] = (long long)rr * out_stride + cell0;
+        poff[j] = (unsigned)(((long long)rl * LT + t.loc_off + i) * (long long)sizeof(float2));
+        voff[j] = (unsigned)(((long long)rl * vin_stride + cell0) * (long long)sizeof(float2));
+        ooff[j] = (unsigned)(((long long)rl * out_stride + cell0) * (long long)sizeof(float2));
     }
+    const unsigned bstep = (unsigned)b * (unsigned)sizeof(float2);                   // workspace bytes per block
     // core rows of the block direction and core range of the in-block index
     const int kc0 = t.tr ? t.cx0 - t.x0 : t.cy0 - t.y0, kc1 = t.tr ? t.cx1 - t.x0 : t.cy1 - t.y0;
     const int ic0 = t.tr ? t.cy0 - t.y0 : t.cx0 - t.x0, ic1 = t.tr ? t.cy1 - t.y0 : t.cx1 - t.x0;
     const int nsteps = 2 * nb - 1;
     auto blk_of = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
     auto fetch = [&](int s, float2(&dst)[EMAX]) {
-        const float2 *Dk = D + (long long)blk_of(s < nsteps ? s : nsteps - 1) * blk;
+        const unsigned bo = (unsigned)(blk_of(s < nsteps ? s : nsteps - 1) * blk * (long long)sizeof(float2));
 #pragma unroll
-        for (int j = 0; j < EMAX; ++j) dst[j] = Dk[gi[j]];
+        for (int j = 0; j < EMAX; ++j) dst[j] = ld(rsD, gi[j], bo);
     };
     auto expand = [&](const float2(&src)[EMAX]) {
 #pragma unroll
         for (int j = 0; j < EMAX; ++j)
-            if (o1[j] >= 0) {
-                M[o1[j]] = src[j];
-                M[o2[j]] = src[j];
+            if (opos[j] != 0xffffffffu) {
+                M[opos[j] & 0xffffu] = src[j];
+                M[opos[j] >> 16] = src[j];
             }
     };
     // v_{k+1} from the global input (forward) or w_k from the workspace (backward) for step s
@@ -821,10 +842,10 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
         if (sc_ < nb) {
             const int kk = k + 1 < nb ? k + 1 : nb - 1;
 #pragma unroll
-            for (int j = 0; j < RMAX; ++j) dst[j] = vrow[j][kk * kstep];
+            for (int j = 0; j < RMAX; ++j) dst[j] = ld(rsV, voff[j], (unsigned)kk * kstep);
         } else {
 #pragma unroll
-            for (int j = 0; j < RMAX; ++j) dst[j] = prow[j][(long long)k * b];
+            for (int j = 0; j < RMAX; ++j) dst[j] = ld(rsL, poff[j], (unsigned)k * bstep);
         }
     };
     float2 ra[EMAX], rb[EMAX], pre_c[RMAX], pre_n[RMAX];
@@ -887,20 +908,21 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
         const float2 cc = fwd ? cl_s[min(k + 1, nb - 1)] : ch_s[k];
 #pragma unroll
         for (int j = 0; j < RMAX; ++j) {
-            if (ri[j] < 0) break;
-            const int i = ri[j], c = rc[j], r = colr[c];
+            if (rcx[j] < 0) break;
+            const int i = rcx[j] & 0xffff, c = rcx[j] >> 16, r = colr[c];
             float2 z = make_float2(0.f, 0.f);
             if (r >= 0) {
                 const float2 a = make_float2(Cr[i * LDC + c], Ci[i * LDC + c]);
                 float2 y;
                 if (fwd) {
-                    if (!turn) prow[j][(long long)k * b] = a;                       // w_k
+                    if (!turn) st(rsL, poff[j], (unsigned)k * bstep, a);           // w_k
                     y = turn ? a : cfms(pre_c[j], cc, a);                           // y_{k+1} or u_{nb-1}
                 } else {
                     y = cfms(pre_c[j], cc, a);                                      // u_k
                 }
                 // u_k (and u_{nb-1} at the turn): core cells to the output
-                if ((!fwd || turn) && k >= kc0 && k < kc1 && i >= ic0 && i < ic1) out[orow[j] + k * kstep] = y;
+                if ((!fwd || turn) && k >= kc0 && k < kc1 && i >= ic0 && i < ic1)
+                    st(rsO, ooff[j], (unsigned)k * kstep, y);
                 if (knext >= 0) z = cmul(cmul(si_s[i], so_s[knext]), y);
             }
             Xr[c * LDK + i] = z.x;

@@ -806,7 +806,13 @@ void nn_sweep(nosdd_problem *p, hipStream_t s, const float2 *v, float2 *z, int n
 // Sources that share a wavelength are solved together (one factor stream,
 // MFMA products) from 4 sources per wavelength on, for blocks up to 112 wide
 // (LDS of the expanded block and operands).
-bool use_multi(const nosdd_problem *p, int n_src) { return n_src >= 4 && p->bmax <= 112 && p->use_multi; }
+// The many-source kernel addresses the vectors of one group of sources (at
+// most 32) through buffer resources with 32-bit byte offsets: each group's
+// range must stay below 2^31 bytes (grids and workspaces up to 2^23 cells).
+bool use_multi(const nosdd_problem *p, int n_src) {
+    const long long span = 32LL * std::max((long long)p->nx * p->ny, (long long)p->loc_total) * 8;
+    return n_src >= 4 && p->bmax <= 112 && p->use_multi && span < (1LL << 31);
+}
 
 nosdd_status solve_order(nosdd_problem *p, int n_rhs, int n_src, const int2 **order, int *n_jobs) {
     auto key = std::make_pair(n_rhs, n_src);
