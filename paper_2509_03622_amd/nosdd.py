@@ -66,6 +66,12 @@ def load(path=LIBPATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2509_03622_amd.build`")
+    try:
+        # torch brings its own HIP runtime; loading it first makes the library
+        # bind to that one, so torch's streams and memory are valid in both
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     vp, i, ll = C.c_void_p, C.c_int, C.c_longlong
     sig = {
