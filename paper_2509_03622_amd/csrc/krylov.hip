@@ -237,7 +237,13 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float
 #pragma unroll
         for (int i = 0; i < NV; ++i) v = cfms(v, hs[i], vv[i]);
         v = cscale(v, sf);
-        dr[n] = v;
+        {
+            // the new basis vector (one per step, far larger than the last-level
+            // cache) goes out with streaming stores
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            const f32x2 t = {v.x, v.y};
+            __builtin_nontemporal_store(t, reinterpret_cast<f32x2 *>(dr + n));
+        }
         fn += cabs2(v);
 #pragma unroll
         for (int i = 0; i < NV; ++i) facc[i] = cfma_conj(facc[i], vv[i], v);
