@@ -73,14 +73,30 @@ inline bool hpd_inverse_profile(int n, const std::vector<std::complex<double>> &
     };
     int nt = threads > 0 ? threads : (int)std::thread::hardware_concurrency();
     nt = std::max(1, std::min({nt, 16, n}));
-    if (nt == 1) {
-        solve_columns(0, n);
-    } else {
-        std::vector<std::thread> pool;
-        for (int t = 0; t < nt; ++t) pool.emplace_back(solve_columns, (int)((long long)n * t / nt),
-                                                       (int)((long long)n * (t + 1) / nt));
-        for (auto &th : pool) th.join();
+    auto range = [&](int t, int &c0, int &c1) {
+        c0 = (int)((long long)n * t / nt);
+        c1 = (int)((long long)n * (t + 1) / nt);
+    };
+    std::vector<std::thread> pool;
+    int started = 0;
+    if (nt > 1) {
+        try {
+            for (int t = 0; t < nt; ++t) {
+                int c0, c1;
+                range(t, c0, c1);
+                pool.emplace_back(solve_columns, c0, c1);
+                started = t + 1;
+            }
+        } catch (...) {
+            // no more threads: the calling thread takes the remaining columns
+        }
     }
+    for (int t = started; t < nt; ++t) {
+        int c0, c1;
+        range(t, c0, c1);
+        solve_columns(c0, c1);
+    }
+    for (auto &th : pool) th.join();
     return true;
 }
 
