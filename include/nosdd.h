@@ -325,7 +325,9 @@ nosdd_status nosdd_tuning(const nosdd_problem *p, int out[6]);
  * by one.  Results are bit-identical in both modes. */
 nosdd_status nosdd_graphs(nosdd_problem *p, int enable);
 /* Subdomain solves of the FGMRES preconditioner when a wavelength has at
- * least 4 sources (and blocks are at most 112 cells wide): enabled (default),
+ * least 4 sources (blocks at most 112 cells wide, grid and packed subdomain
+ * vectors at most 2^23 cells, so that one group's vectors stay below 2^31
+ * bytes): enabled (default),
  * one workgroup per subdomain, wavelength and group of 32 (16 above 80-cell
  * blocks) sources reads each factor block once and forms the block's products
  * for the whole group as FP32 MFMA contractions; disabled, one workgroup per
