@@ -57,3 +57,14 @@ def oracle_direct_field(args):
     with threadpool_limits(1):
         A = assemble_A(eps, lam, h, npml, pml_m, pml_lnR)
         return solve_direct(A, source_rhs(J, lam))
+
+
+def oracle_fom_gradient_one(args):
+    """The oracle's figure of merit and its gradient (direct LU of A and A^T)
+    for one wavelength: a process-pool job, one BLAS thread, no GPU."""
+    from threadpoolctl import threadpool_limits
+    from oracle.adjoint import fom_and_gradient
+    eps, lam, J, focal, h, npml = args
+    with threadpool_limits(1):
+        fom, grad, _ = fom_and_gradient(eps, [lam], [J], focal, h, npml)
+    return fom, grad

@@ -2,7 +2,9 @@
 the C ABI) against the FP64 oracle: the figure of merit, the gradient over the
 whole grid (oracle: direct LU of A and A^T, no use of the S A symmetry), central
 finite differences of the oracle's FoM on 16 random design pixels, and the
-torch.autograd wrapper."""
+torch.autograd wrapper; and at the full size of the inverse-design workload
+(1024 x 1024, three wavelengths), the figure of merit and the design-region
+gradient against the oracle's, computed meanwhile in separate processes."""
 import numpy as np
 import pytest
 
@@ -86,3 +88,38 @@ def test_autograd_wrapper_raises_when_a_solve_stops_at_max_iters():
     e = torch.from_numpy(eps).cuda().requires_grad_(True)
     with pytest.raises(nosdd.NosddError, match="NOT_CONVERGED"):
         nosdd.figure_of_merit(e, torch.from_numpy(J).cuda(), focal, spec)
+
+
+def test_inverse_design_1024_full_size():
+    import multiprocessing as mp
+    import torch
+    from paper_2509_03622_amd import nosdd
+    from paper_2509_03622_amd.workloads import inverse_design_1024
+    from gpu_common import oracle_fom_gradient_one
+    w = inverse_design_1024()
+    J = w.J()
+    jobs = [(w.eps.astype(np.float64), lam, J[0].astype(np.complex128), w.focal, w.h, w.npml)
+            for lam in w.wavelengths]
+    with mp.get_context("spawn").Pool(len(jobs)) as pool:
+        oracle = pool.map_async(oracle_fom_gradient_one, jobs)
+        ctx = nosdd.Context(0, nosdd.torch_stream_handle())
+        P = nosdd.Problem(ctx, w.eps, w.h, w.npml, w.core_x, w.core_y, w.overlap, w.wavelengths)
+        P.setup(k_coarse=w.k_coarse, k_trial=8)
+        fom, grad, iters, st = P.fom_gradient(torch.from_numpy(J).cuda(), w.focal, max_iters=2000)
+        assert st == 0, iters
+        g = grad.cpu().numpy()
+        print(f"GPU: FoM {fom:.6e}, iterations forward {iters[0].ravel().tolist()}, "
+              f"adjoint {iters[1].ravel().tolist()}", flush=True)
+        P.close()
+        ctx.close()
+        res = oracle.get(timeout=900)
+    fom_o = sum(r[0] for r in res)
+    g_o = sum(r[1] for r in res)
+    x0, x1, y0, y1 = w.design
+    err_g = rel(g[y0:y1, x0:x1], g_o[y0:y1, x0:x1])
+    print(f"oracle FoM {fom_o:.6e}; FoM error {abs(fom - fom_o) / fom_o:.2e}, design gradient error {err_g:.2e}")
+    # measured 2e-7 and 1e-5 (forward and adjoint solves to 1e-6 in FP32 Krylov
+    # cycles around the FP64 iterate)
+    assert abs(fom - fom_o) <= 1e-5 * fom_o, (fom, fom_o)
+    assert err_g < 1e-4, err_g
+    assert rel(g, g_o) < 1e-4
