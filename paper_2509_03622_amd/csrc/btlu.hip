@@ -713,10 +713,7 @@ static size_t bm_lds_class(int b, int ncol) {
     return sizeof(float) * ((size_t)2 * BP * (BP + 2) + (size_t)3 * ncol * (BP + 4) + (size_t)2 * BP * (ncol + 1));
 }
 // dynamic LDS of a launch whose widest block is bmax (either group form may run)
-static size_t bm_lds_bytes(int bmax) {
-    if (bmax <= BM_NARROW) return bm_lds_class(bmax, 32);
-    return std::max(bm_lds_class(BM_NARROW, 32), bm_lds_class(bmax, 16));
-}
+static size_t bm_lds_bytes(int bmax);
 
 template <int NCOL, int EMAX, int RMAX>
 __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int ns, int n_src,
@@ -939,6 +936,244 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
     }
 }
 
+// The 32-source form (blocks up to 80 cells) with one barrier per block step.
+// M_k is complex symmetric, so the step's products are formed transposed,
+// C^T = Y^T M_k (rows: sources, columns: block rows), and the wave that forms
+// an output tile runs the recurrence of its 16 x 16 (source, row) elements
+// straight from its accumulators: each lane holds 4 sources of one block row,
+// so its global loads and stores are row-contiguous across lanes.  The waves
+// without a tile meanwhile expand the next factor block into the second of
+// two LDS buffers, and the operand of the next step goes to the second of two
+// operand buffers, so a step needs no second barrier and no product buffer.
+// Re C^T = Yr Mr - Yi Mi is accumulated as two sums (the operand is kept as
+// Re and Im only), Im C^T = Yr Mi + Yi Mr as one.
+constexpr int B32_EMAX = 9;                           // expand elements per lane: ceil(3280 / (6 * 64))
+__host__ __device__ __forceinline__ size_t b32_lds_bytes(int b) {
+    const int BP = bm_pad(b);
+    return sizeof(float) * ((size_t)2 * 2 * BP * (BP + 2) + (size_t)2 * 2 * 32 * (BP + 4));
+}
+__device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, int ns, int n_src,
+                                           const float2 *__restrict__ dinv, long long dinv_wl_stride,
+                                           const float2 *__restrict__ coef, const float2 *__restrict__ sc, int nx,
+                                           int ny, const float2 *__restrict__ vin, long long vin_stride,
+                                           float2 *__restrict__ out, long long out_stride,
+                                           const int *__restrict__ active, float2 *__restrict__ loc, long long LT,
+                                           float *lds, float2 *cl_s, float2 *ch_s, float2 *so_s, float2 *si_s,
+                                           int *colr) {
+    constexpr int NCOL = 32;
+    const int b = t.b, nb = t.nb, P = b >> 1, tid = threadIdx.x;
+    const int BP = bm_pad(b), LDM = BP + 2, LDK = BP + 4;
+    // buffers are addressed arithmetically (an array of pointers indexed at run
+    // time would live in scratch memory and lose the LDS address space)
+    auto MB = [&](int buf) { return reinterpret_cast<float2 *>(lds) + buf * BP * LDM; };
+    float *Xb = lds + 2 * 2 * BP * LDM;               // [buffer][Re, Im][NCOL][LDK]
+    auto XR = [&](int buf) { return Xb + (2 * buf) * NCOL * LDK; };
+    auto XI = [&](int buf) { return Xb + (2 * buf + 1) * NCOL * LDK; };
+    const int rfirst = wl * n_src + s0;
+    if (tid < NCOL) {
+        const int r = rfirst + tid;
+        colr[tid] = (tid < ns && (!active || active[r])) ? r : -1;
+    }
+    const float2 *cf = coef + wl * coef_stride(nx, ny);
+    const float2 *clo_a = t.tr ? cf : cf + 2 * nx;
+    const float2 *chi_a = t.tr ? cf + nx : cf + 2 * nx + ny;
+    const float2 *scw = sc + (long long)wl * (nx + ny);
+    const float2 *s_in = t.tr ? scw + nx + t.y0 : scw + t.x0;
+    const float2 *s_out = t.tr ? scw + t.x0 : scw + nx + t.y0;
+    const int base = t.tr ? t.x0 : t.y0;
+    for (int k = tid; k < nb; k += BM_THREADS) {
+        cl_s[k] = clo_a[base + k];
+        ch_s[k] = chi_a[base + k];
+        so_s[k] = s_out[k];
+    }
+    for (int i = tid; i < b; i += BM_THREADS) si_s[i] = s_in[i];
+    // zero both factor buffers and both operand buffers (padding rows and k >= b stay zero)
+    for (int e = tid; e < 2 * BP * LDM; e += BM_THREADS) MB(0)[e] = make_float2(0.f, 0.f);
+    for (int e = tid; e < 2 * 2 * NCOL * LDK; e += BM_THREADS) Xb[e] = 0.f;
+    __syncthreads();
+    const long long blk = bt_sym_block(b);
+    const int nsub = (int)(blk >> 2);
+    const float2 *D = dinv + wl * dinv_wl_stride + t.dinv_off;
+    const __amdgpu_buffer_rsrc_t rsD = bt_rsrc(D, (unsigned)(nb * blk * (long long)sizeof(float2)));
+    const __amdgpu_buffer_rsrc_t rsV =
+        bt_rsrc(vin + (long long)rfirst * vin_stride, (unsigned)((long long)ns * vin_stride * sizeof(float2)));
+    const __amdgpu_buffer_rsrc_t rsL =
+        bt_rsrc(loc + (long long)rfirst * LT, (unsigned)((long long)ns * LT * sizeof(float2)));
+    const __amdgpu_buffer_rsrc_t rsO =
+        bt_rsrc(out + (long long)rfirst * out_stride, (unsigned)((long long)ns * out_stride * sizeof(float2)));
+    auto ld = [](__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+    };
+    auto st = [](__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, float2 v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bm_u32x2, v), rs, (int)voff, (int)soff, 0);
+    };
+    const int wave = tid >> 6, lane = tid & 63;
+    const int RT = BP / 16, nT = 2 * RT, KQ = BP / 4;     // output tiles: 2 source tiles x RT row tiles
+    const bool prod = wave < nT;                           // wave-uniform role
+    const int nsteps = 2 * nb - 1;
+    auto blk_of = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
+    // ---- expand waves: element e of the packed block goes to lane e mod (their
+    // lane count); indices and LDS positions are recomputed each step (these
+    // waves wait for the products anyway), and one register slot holds the
+    // next block: it is expanded at the start of a step and refilled at once
+    const int ne_lanes = (BM_THREADS / 64 - nT) * 64, el = tid - nT * 64;
+    auto fetch = [&](int s, float2(&dst)[B32_EMAX]) {
+        const unsigned bo = (unsigned)(blk_of(s < nsteps ? s : nsteps - 1) * blk * (long long)sizeof(float2));
+#pragma unroll
+        for (int j = 0; j < B32_EMAX; ++j) {
+            const int e = min(el + j * ne_lanes, (int)blk - 1);
+            dst[j] = ld(rsD, (unsigned)e * (unsigned)sizeof(float2), bo);
+        }
+    };
+    auto expand = [&](const float2(&src)[B32_EMAX], float2 *M) {
+#pragma unroll
+        for (int j = 0; j < B32_EMAX; ++j) {
+            const int e = el + j * ne_lanes;
+            if (e < (int)blk) {
+                const int half = e >= 2 * nsub, sub = (e - half * 2 * nsub) >> 1, comp = (e & 1) | (half << 1);
+                int bp, bq;
+                bt_sym_pq(P, sub, bp, bq);
+                const int rr = 2 * bp + (comp & 1), cc = 2 * bq + (comp >> 1);
+                M[rr * LDM + cc] = src[j];
+                M[cc * LDM + rr] = src[j];
+            }
+        }
+    };
+    // ---- product waves: tile (source tile st, row tile it); lane: row i, sources c_q
+    const int tile = prod ? wave : 0, st_ = tile / RT, it = tile % RT;
+    const int i = it * 16 + (lane & 15);
+    const int cq0 = st_ * 16 + 4 * (lane >> 4);
+    const bool irow = prod && i < b;
+    const int ic = i < b ? i : 0;                          // clamped row for addresses
+    const long long cell0 = t.tr ? (long long)(t.y0 + ic) * nx + t.x0 : (long long)t.y0 * nx + t.x0 + ic;
+    const unsigned kstep = (t.tr ? 1u : (unsigned)nx) * (unsigned)sizeof(float2);
+    const unsigned bstep = (unsigned)b * (unsigned)sizeof(float2);
+    // byte offsets of element q: its source's vector (rl_q, packed 8 bits each)
+    // times a scalar stride plus the row's base, formed at each use
+    int live = 0;                                          // bit q: (c_q, i) is a live element
+    unsigned rlpk = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = cq0 + q, r = colr[c], rl = r >= 0 ? r - rfirst : 0;
+        if (irow && r >= 0) live |= 1 << q;
+        rlpk |= (unsigned)rl << (8 * q);
+    }
+    const unsigned lbase = (unsigned)((t.loc_off + ic) * (long long)sizeof(float2));
+    const unsigned cbase = (unsigned)(cell0 * (long long)sizeof(float2));
+    const unsigned LT8 = (unsigned)(LT * (long long)sizeof(float2));
+    const unsigned VS8 = (unsigned)(vin_stride * (long long)sizeof(float2));
+    const unsigned OS8 = (unsigned)(out_stride * (long long)sizeof(float2));
+    auto rl_of = [&](int q) { return (rlpk >> (8 * q)) & 0xffu; };
+    auto poff = [&](int q) { return rl_of(q) * LT8 + lbase; };
+    auto voff = [&](int q) { return rl_of(q) * VS8 + cbase; };
+    auto ooff = [&](int q) { return rl_of(q) * OS8 + cbase; };
+    const int kc0 = t.tr ? t.cx0 - t.x0 : t.cy0 - t.y0, kc1 = t.tr ? t.cx1 - t.x0 : t.cy1 - t.y0;
+    const int ic0 = t.tr ? t.cy0 - t.y0 : t.cx0 - t.x0, ic1 = t.tr ? t.cy1 - t.y0 : t.cx1 - t.x0;
+    const bool icore = i >= ic0 && i < ic1;
+    // v_{k+1} from the global input (forward) or w_k from the workspace (backward) for step s
+    auto load_pre = [&](int s, float2(&dst)[4]) {
+        const int sc_ = s < nsteps ? s : nsteps - 1;
+        const int k = blk_of(sc_);
+        if (sc_ < nb) {
+            const unsigned so = (unsigned)(k + 1 < nb ? k + 1 : nb - 1) * kstep;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = ld(rsV, voff(q), so);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = ld(rsL, poff(q), (unsigned)k * bstep);
+        }
+    };
+    float2 slot[B32_EMAX], pre[4];
+    if (prod) {
+        // operand of the first step: S_0 v_0, and v_1 for the first recurrence
+        float2 v0[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v0[q] = ld(rsV, voff(q), 0u);
+        load_pre(0, pre);
+        if (irow) {
+            const float2 f = cmul(si_s[i], so_s[0]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float2 z = (live >> q) & 1 ? cmul(f, v0[q]) : make_float2(0.f, 0.f);
+                XR(0)[(cq0 + q) * LDK + i] = z.x;
+                XI(0)[(cq0 + q) * LDK + i] = z.y;
+            }
+        }
+    } else {
+        fetch(0, slot);
+        expand(slot, MB(0));
+        fetch(1, slot);
+    }
+    __syncthreads();
+    // one block step s on buffers cur = s & 1; the expand waves expand block s + 1
+    // (waiting in the slot) into the other buffer and refill the slot with block s + 2
+    auto step = [&](int s) {
+        const int cur = s & 1, k = blk_of(s);
+        const bool fwd = s < nb, turn = s == nb - 1;
+        if (prod) {
+            f32x4v accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
+            const int k0 = (lane >> 4) * KQ;
+            const float2 *mrow = MB(cur) + (it * 16 + (lane & 15)) * LDM + k0;
+            const float *xr = XR(cur) + (st_ * 16 + (lane & 15)) * LDK + k0;
+            const float *xi = XI(cur) + (st_ * 16 + (lane & 15)) * LDK + k0;
+            for (int kk = 0; kk < KQ; kk += 4) {
+                const float4 m01 = *reinterpret_cast<const float4 *>(mrow + kk);
+                const float4 m23 = *reinterpret_cast<const float4 *>(mrow + kk + 2);
+                const float4 yr = *reinterpret_cast<const float4 *>(xr + kk);
+                const float4 yi = *reinterpret_cast<const float4 *>(xi + kk);
+                const float mr[4] = {m01.x, m01.z, m23.x, m23.z}, mi[4] = {m01.y, m01.w, m23.y, m23.w};
+                const float vr[4] = {yr.x, yr.y, yr.z, yr.w}, vi[4] = {yi.x, yi.y, yi.z, yi.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    accA = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[u], mr[u], accA, 0, 0, 0);
+                    accB = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[u], mi[u], accB, 0, 0, 0);
+                    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[u], mi[u], accI, 0, 0, 0);
+                    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[u], mr[u], accI, 0, 0, 0);
+                }
+            }
+            // recurrence of this lane's 4 (source, row) elements, straight from the accumulators
+            const int knext = fwd && !turn ? k + 1 : k - 1;
+            const float2 cc = fwd ? cl_s[min(k + 1, nb - 1)] : ch_s[k];
+            const float2 f = knext >= 0 && irow ? cmul(si_s[i], so_s[knext]) : make_float2(0.f, 0.f);
+            const bool kcore = k >= kc0 && k < kc1;
+            float *xrn = XR(cur ^ 1), *xin = XI(cur ^ 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float2 z = make_float2(0.f, 0.f);
+                if ((live >> q) & 1) {
+                    const float2 a = make_float2(accA[q] - accB[q], accI[q]);
+                    float2 y;
+                    if (fwd) {
+                        if (!turn) st(rsL, poff(q), (unsigned)k * bstep, a);          // w_k
+                        y = turn ? a : cfms(pre[q], cc, a);                            // y_{k+1} or u_{nb-1}
+                    } else {
+                        y = cfms(pre[q], cc, a);                                       // u_k
+                    }
+                    if ((!fwd || turn) && kcore && icore) st(rsO, ooff(q), (unsigned)k * kstep, y);
+                    z = cmul(f, y);
+                }
+                if (irow) {
+                    xrn[(cq0 + q) * LDK + i] = z.x;
+                    xin[(cq0 + q) * LDK + i] = z.y;
+                }
+            }
+            // the next step's v_{k+1} or w_k: in flight over the barrier and the next products
+            load_pre(s + 1, pre);
+        } else if (s + 1 < nsteps) {
+            expand(slot, MB(cur ^ 1));
+            fetch(s + 2, slot);
+        }
+        __syncthreads();                              // next factor block and operand in LDS
+    };
+    for (int s = 0; s < nsteps; ++s) step(s);
+}
+
+// dynamic LDS of a launch whose widest block is bmax (either group form may run)
+static size_t bm_lds_bytes(int bmax) {
+    if (bmax <= BM_NARROW) return b32_lds_bytes(bmax);
+    return std::max(b32_lds_bytes(BM_NARROW), bm_lds_class(bmax, 16));
+}
+
 // jobs[j] = (tile, wavelength, first source, sources), at most bm_cols(b) sources
 __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
     const TileDesc *__restrict__ tiles, const int4 *__restrict__ jobs, int n_src, const float2 *__restrict__ dinv,
@@ -952,8 +1187,8 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
     if (job.x < 0) return;
     const TileDesc t = tiles[job.x];
     if (t.b <= BM_NARROW)
-        bm_solve<32, 4, 3>(t, job.y, job.z, job.w, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride,
-                           out, out_stride, active, loc, LT, lds, cl_s, ch_s, so_s, si_s, colr);
+        bm_solve32(t, job.y, job.z, job.w, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride, out,
+                   out_stride, active, loc, LT, lds, cl_s, ch_s, so_s, si_s, colr);
     else
         bm_solve<16, 7, 2>(t, job.y, job.z, job.w, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride,
                            out, out_stride, active, loc, LT, lds, cl_s, ch_s, so_s, si_s, colr);
