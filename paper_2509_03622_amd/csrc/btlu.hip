@@ -1008,7 +1008,8 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bm_u32x2, v), rs, (int)voff, (int)soff, 0);
     };
     const int wave = tid >> 6, lane = tid & 63;
-    const int RT = BP / 16, nT = 2 * RT, KQ = BP / 4;     // output tiles: 2 source tiles x RT row tiles
+    const int RT = BP / 16, nT = 2 * RT;                  // output tiles: 2 source tiles x RT row tiles
+    const int KG = 2 * ((b + 7) >> 3);                    // k per MFMA lane group: 4 KG >= b, 4 KG <= BP
     const bool prod = wave < nT;                           // wave-uniform role
     const int nsteps = 2 * nb - 1;
     auto blk_of = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
@@ -1111,24 +1112,24 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
         const int cur = s & 1, k = blk_of(s);
         const bool fwd = s < nb, turn = s == nb - 1;
         if (prod) {
-            f32x4v accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f}, accI = {0.f, 0.f, 0.f, 0.f};
-            const int k0 = (lane >> 4) * KQ;
+            // three real products per complex one (Gauss): T1 = Yr Mr, T2 = Yi Mi,
+            // T3 = (Yr + Yi)(Mr + Mi); Re = T1 - T2, Im = T3 - T1 - T2
+            f32x4v accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f}, accS = {0.f, 0.f, 0.f, 0.f};
+            const int k0 = (lane >> 4) * KG;
             const float2 *mrow = MB(cur) + (it * 16 + (lane & 15)) * LDM + k0;
             const float *xr = XR(cur) + (st_ * 16 + (lane & 15)) * LDK + k0;
             const float *xi = XI(cur) + (st_ * 16 + (lane & 15)) * LDK + k0;
-            for (int kk = 0; kk < KQ; kk += 4) {
-                const float4 m01 = *reinterpret_cast<const float4 *>(mrow + kk);
-                const float4 m23 = *reinterpret_cast<const float4 *>(mrow + kk + 2);
-                const float4 yr = *reinterpret_cast<const float4 *>(xr + kk);
-                const float4 yi = *reinterpret_cast<const float4 *>(xi + kk);
-                const float mr[4] = {m01.x, m01.z, m23.x, m23.z}, mi[4] = {m01.y, m01.w, m23.y, m23.w};
-                const float vr[4] = {yr.x, yr.y, yr.z, yr.w}, vi[4] = {yi.x, yi.y, yi.z, yi.w};
+#pragma unroll 3
+            for (int kk = 0; kk < KG; kk += 2) {
+                const float4 m = *reinterpret_cast<const float4 *>(mrow + kk);
+                const float2 yr = *reinterpret_cast<const float2 *>(xr + kk);
+                const float2 yi = *reinterpret_cast<const float2 *>(xi + kk);
+                const float mr[2] = {m.x, m.z}, mi[2] = {m.y, m.w}, vr[2] = {yr.x, yr.y}, vi[2] = {yi.x, yi.y};
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 2; ++u) {
                     accA = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[u], mr[u], accA, 0, 0, 0);
                     accB = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[u], mi[u], accB, 0, 0, 0);
-                    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[u], mi[u], accI, 0, 0, 0);
-                    accI = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[u], mr[u], accI, 0, 0, 0);
+                    accS = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[u] + vi[u], mr[u] + mi[u], accS, 0, 0, 0);
                 }
             }
             // recurrence of this lane's 4 (source, row) elements, straight from the accumulators
@@ -1141,7 +1142,7 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
             for (int q = 0; q < 4; ++q) {
                 float2 z = make_float2(0.f, 0.f);
                 if ((live >> q) & 1) {
-                    const float2 a = make_float2(accA[q] - accB[q], accI[q]);
+                    const float2 a = make_float2(accA[q] - accB[q], accS[q] - accA[q] - accB[q]);
                     float2 y;
                     if (fwd) {
                         if (!turn) st(rsL, poff(q), (unsigned)k * bstep, a);          // w_k
