@@ -1014,10 +1014,24 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
     const int nsteps = 2 * nb - 1;
     auto blk_of = [&](int s) { return s < nb ? s : 2 * nb - 2 - s; };
     // ---- expand waves: element e of the packed block goes to lane e mod (their
-    // lane count); indices and LDS positions are recomputed each step (these
-    // waves wait for the products anyway), and one register slot holds the
-    // next block: it is expanded at the start of a step and refilled at once
+    // lane count); its two LDS positions (both triangles, 16 bits each) are
+    // formed once, since the index arithmetic of every step would compete for
+    // issue with the product waves on the same SIMDs; one register slot holds
+    // the next block: it is expanded at the start of a step and refilled at once
     const int ne_lanes = (BM_THREADS / 64 - nT) * 64, el = tid - nT * 64;
+    unsigned epos[B32_EMAX];
+#pragma unroll
+    for (int j = 0; j < B32_EMAX; ++j) {
+        const int e = el + j * ne_lanes;
+        epos[j] = 0xffffffffu;
+        if (!prod && e < (int)blk) {
+            const int half = e >= 2 * nsub, sub = (e - half * 2 * nsub) >> 1, comp = (e & 1) | (half << 1);
+            int bp, bq;
+            bt_sym_pq(P, sub, bp, bq);
+            const int rr = 2 * bp + (comp & 1), cc = 2 * bq + (comp >> 1);
+            epos[j] = (unsigned)(rr * LDM + cc) | ((unsigned)(cc * LDM + rr) << 16);
+        }
+    }
     auto fetch = [&](int s, float2(&dst)[B32_EMAX]) {
         const unsigned bo = (unsigned)(blk_of(s < nsteps ? s : nsteps - 1) * blk * (long long)sizeof(float2));
 #pragma unroll
@@ -1029,14 +1043,9 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
     auto expand = [&](const float2(&src)[B32_EMAX], float2 *M) {
 #pragma unroll
         for (int j = 0; j < B32_EMAX; ++j) {
-            const int e = el + j * ne_lanes;
-            if (e < (int)blk) {
-                const int half = e >= 2 * nsub, sub = (e - half * 2 * nsub) >> 1, comp = (e & 1) | (half << 1);
-                int bp, bq;
-                bt_sym_pq(P, sub, bp, bq);
-                const int rr = 2 * bp + (comp & 1), cc = 2 * bq + (comp >> 1);
-                M[rr * LDM + cc] = src[j];
-                M[cc * LDM + rr] = src[j];
+            if (epos[j] != 0xffffffffu) {
+                M[epos[j] & 0xffffu] = src[j];
+                M[epos[j] >> 16] = src[j];
             }
         }
     };
@@ -1132,7 +1141,11 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
                     accS = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[u] + vi[u], mr[u] + mi[u], accS, 0, 0, 0);
                 }
             }
-            // recurrence of this lane's 4 (source, row) elements, straight from the accumulators
+            // recurrence of this lane's 4 (source, row) elements, straight from the accumulators.
+            // Wait for every outstanding memory operation first: the counter retires in
+            // issue order, so once this step's stores are issued, the wait for the operand
+            // loaded in the previous step would also wait for those stores to complete.
+            __builtin_amdgcn_s_waitcnt(0x0F70);           // vmcnt(0); expcnt, lgkmcnt unconstrained
             const int knext = fwd && !turn ? k + 1 : k - 1;
             const float2 cc = fwd ? cl_s[min(k + 1, nb - 1)] : ch_s[k];
             const float2 f = knext >= 0 && irow ? cmul(si_s[i], so_s[knext]) : make_float2(0.f, 0.f);
