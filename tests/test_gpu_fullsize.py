@@ -9,16 +9,21 @@ parameters, per-step HIP graphs).
   against the oracle's sparse LU (2e-5).
 * 2048 x 1536, mixed 64/96 cores (100 x 100 corner, 100 x 72 edge, 72 x 72
   interior subdomains), 32 sources x 2 wavelengths = 64 right-hand sides in
-  one launch: a direct solve of the global problem takes minutes on the host,
-  so the checks are sampled subdomain solves against the oracle's sparse LU
-  and, for every right-hand side, the FP64 residual of the returned complex64
-  field with the oracle's operator.  This problem is about 100 x 77 vacuum
+  one launch: sampled subdomain solves against the oracle's sparse LU; for
+  every right-hand side, the FP64 residual of the returned complex64 field
+  with the oracle's operator; and two fields (wavelength 1.0, sources 0 and
+  17) against the oracle's direct solution at 4096 seeded grid points (1e-5
+  relative L2 over the samples).  The global direct solve takes about 5
+  minutes per wavelength on one host core, so its samples are stored in
+  tests/golden/uneven2048_reference.npz, written by the committed script
+  beside it from the oracle alone.  This problem is about 100 x 77 vacuum
   wavelengths with permittivity up to 12 on 16-cell blocks, and the one-level
   sweep needs about 2 400 - 2 800 outer iterations per right-hand side.
 * 1024 x 1024, 16 x 16 subdomains, one coarse basis function each, with the
   trained BF16 network as the subdomain solver (NN-FGMRES, 4 inner steps to
   1e-2): the field against the FP64 direct solution (1e-5 relative L2).
 """
+import os
 import time
 
 import numpy as np
@@ -228,5 +233,13 @@ def test_uneven_2048x1536_64_rhs_full_size():
             worst = max(worst, (res / bound, res))
             assert res <= bound, (wi, s, res, bound)
     print(f"FP64 residuals of the complex64 fields: worst {worst[1]:.2e}, at most {worst[0]:.2f} of the bound")
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "uneven2048_reference.npz"))
+    wi, idx = int(ref["wavelength_index"]), ref["index"]
+    for s in ref["sources"]:
+        x_ref = ref[f"x_{s}"]
+        err = float(np.linalg.norm(Eh[wi, s].ravel()[idx] - x_ref) / np.linalg.norm(x_ref))
+        print(f"wavelength {w.wavelengths[wi]}, source {s}: field against the direct solution at "
+              f"{len(idx)} points {err:.2e} (reference residual {float(ref[f'residual_{s}']):.1e})")
+        assert err < 1e-5, (s, err)
     P.close()
     ctx.close()
