@@ -206,7 +206,10 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_dots_kernel(const float2 *__re
 // First-pass update fused with the second pass's dots: dst = w - sum_i Hc_i V_i,
 // and, from the same loads of V, per-workgroup partials of V_i^H dst (slots
 // i < NV) and of ||dst||^2 (slot KR_MAXV).  The second pass then needs one
-// more read of V (its update) instead of two.
+// more read of V (its update) instead of two.  Laid out like the dots kernel:
+// the coefficients are uniform per workgroup (scalar registers), the vector
+// bases are scalars with 32-bit byte offsets, and the next cell's loads are
+// issued before the current cell's arithmetic.
 template <int NV>
 __global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float2 *__restrict__ V, long long vstride,
                                                                      const float2 *w, float2 *dst, long long N,
@@ -214,39 +217,59 @@ __global__ __launch_bounds__(KR_THREADS) void cgs_update_dots_kernel(const float
                                                                      const float2 *__restrict__ Hc, int m, int col,
                                                                      double2 *__restrict__ partial, int nblk,
                                                                      const float *__restrict__ scale) {
-    __shared__ float2 hs[NV > 0 ? NV : 1];
     __shared__ double2 red[(KR_THREADS / 64) * KR_SLOTS];
+    constexpr int NA = NV > 0 ? NV : 1;
     const int r = blockIdx.y;
     if (!gate[r]) return;
     const float sf = scale ? scale[r] : 1.f;
-    if (threadIdx.x < NV) hs[threadIdx.x] = Hc[((long long)r * (m + 1) + threadIdx.x) * m + col];
-    __syncthreads();
-    const float2 *wr = w + r * N;
-    float2 *dr = dst + r * N;
-    const float2 *Vr = V + r * N;
-    float2 facc[NV > 0 ? NV : 1];
+    float2 h[NA];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) h[i] = Hc[((long long)r * (m + 1) + i) * m + col];
+    const char *wb = reinterpret_cast<const char *>(w + r * N);
+    char *db = reinterpret_cast<char *>(dst + r * N);
+    const char *vb = reinterpret_cast<const char *>(V + r * N);
+    float2 facc[NA];
 #pragma unroll
     for (int i = 0; i < NV; ++i) facc[i] = make_float2(0.f, 0.f);
     float fn = 0.f;
-    const long long stride = (long long)gridDim.x * KR_THREADS;
-    for (long long n = (long long)blockIdx.x * KR_THREADS + threadIdx.x; n < N; n += stride) {
-        float2 vv[NV > 0 ? NV : 1];
-        float2 v = wr[n];
+    // cells past the end load as zeros and store nothing
+    auto load = [&](float2 &wv, float2 (&vv)[NA], long long n) {
+        if (n < N) {
+            const unsigned off = (unsigned)n * 8u;
+            wv = *reinterpret_cast<const float2 *>(wb + off);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) vv[i] = Vr[i * vstride + n];
+            for (int i = 0; i < NV; ++i) vv[i] = *reinterpret_cast<const float2 *>(vb + i * vstride * 8 + off);
+        } else {
+            wv = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v = cfms(v, hs[i], vv[i]);
+            for (int i = 0; i < NV; ++i) vv[i] = make_float2(0.f, 0.f);
+        }
+    };
+    auto use = [&](const float2 &wv, const float2 (&vv)[NA], long long n) {
+        float2 v = wv;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v = cfms(v, h[i], vv[i]);
         v = cscale(v, sf);
-        {
+        if (n < N) {
             // the new basis vector (one per step, far larger than the last-level
             // cache) goes out with streaming stores
             typedef float f32x2 __attribute__((ext_vector_type(2)));
             const f32x2 t = {v.x, v.y};
-            __builtin_nontemporal_store(t, reinterpret_cast<f32x2 *>(dr + n));
+            __builtin_nontemporal_store(t, reinterpret_cast<f32x2 *>(db + (unsigned)n * 8u));
         }
         fn += cabs2(v);
 #pragma unroll
         for (int i = 0; i < NV; ++i) facc[i] = cfma_conj(facc[i], vv[i], v);
+    };
+    const long long stride = (long long)gridDim.x * KR_THREADS;
+    long long n = (long long)blockIdx.x * KR_THREADS + threadIdx.x;
+    float2 wa, va[NA], wn, vn[NA];
+    load(wa, va, n);
+    for (; n < N; n += 2 * stride) {
+        load(wn, vn, n + stride);
+        use(wa, va, n);
+        load(wa, va, n + 2 * stride);
+        use(wn, vn, n + stride);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
