@@ -235,6 +235,10 @@ struct FnoDevice {
     unsigned short *p1w = nullptr;                // [128][64] bf16
     float *p1b = nullptr, *p2w = nullptr, *p2b = nullptr;   // [128], [2][128], [2]
     float2 *tw = nullptr;                         // twiddle tables, FNO_TW_UNIT * L float2 per side L
+    // inverse x-transform as the B operand of BF16 MFMA: per side L, at
+    // twb + 128 L (L-1), the real 2 x 2 form [n = (x, Re/Im out)][k = (kx, Re/Im in)]
+    // (2L x 64) as BF16 high parts, then the same as BF16 low parts (value - high)
+    unsigned short *twb = nullptr;
     // modulated network: mod[mod_idx][layer][mode] (complex) multiplies the
     // spectral product of every block mode by mode; null for the plain network
     const float2 *mod = nullptr;

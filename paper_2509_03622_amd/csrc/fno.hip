@@ -21,12 +21,13 @@
 // and the per-mode complex mix R -- run on MFMA in BF16 with FP32
 // accumulation (v_mfma_f32_32x32x8_bf16): R is applied as the real 128 x 128
 // form of the complex 64 x 64 mix to (Re X_c, Im X_c) interleaved per
-// channel.  The truncated DFTs are four batched FP32 MFMA contractions
-// (v_mfma_f32_32x32x2f32) against twiddle tables built on the host in FP64
-// per subdomain side: the y-transform first (it keeps 16 of the ly
-// frequencies), then the x-transform of those 16 rows, and the inverse in the
-// reverse order with the Hermitian weights of the real inverse folded into
-// its last table.
+// channel.  The truncated DFTs are four batched MFMA contractions against
+// twiddle tables built on the host in FP64 per subdomain side: the
+// y-transform first (it keeps 16 of the ly frequencies), then the x-transform
+// of those 16 rows, and the inverse in the reverse order with the Hermitian
+// weights of the real inverse folded into its last table.  The forward pair
+// runs in FP32 (v_mfma_f32_32x32x2f32); the inverse pair in BF16
+// (v_mfma_f32_32x32x16_bf16) on operands split into high and low BF16 parts.
 #include "common.h"
 
 namespace nosdd {
@@ -227,109 +228,144 @@ __global__ __launch_bounds__(256) void fno_dft_x_fwd_kernel(const FnoSample *__r
 // workgroup, the x-transform's result kept in LDS:
 //   P[c][ky][x]  = sum_kx Y[kx][ky][c] e^{+2pi i kx x/Lx}             rows (c, ky), K = (kx, ri), N = (x, ri)
 //   s[c][y][x]   = Re sum_ky w_ky P[c][ky][x] e^{+2pi i ky y/Ly} / (Lx Ly)   rows y, K = (ky, ri), N = (c, x)
-// (w_0 = 1, w_ky = 2: Hermitian completion along y).  The second product
-// takes y as its rows so that lanes store x-contiguous runs of s (BF16).
-// Grid (64 / FI_CB, S), FI_THREADS threads, FI_LDS bytes of dynamic LDS:
-//   Yl [FI_CB 16][65] f32   the block's spectrum, rows (c, ky), k = (kx, ri)
-//   ex [32][Lx]      f2    inverse x twiddles
-//   Wl [32][72]      f32   real weights of the inverse y transform, [k = (ky, ri)][y]
-//   Pl [FI_CB Lx][33] f32  P, rows (c, x), k = (ky, ri)
-constexpr int FI_CB = 2, FI_THREADS = 512;
-constexpr int FI_LDY = 2 * 2 * FM + 1, FI_LDP = 2 * FM + 1;
-constexpr size_t FI_LDS = sizeof(float) * ((size_t)FI_CB * FM * FI_LDY + 2 * 2 * FM * FNO_MAXL +
-                                           2 * FM * FNO_MAXL + (size_t)FI_CB * FNO_MAXL * FI_LDP);
+// (w_0 = 1, w_ky = 2: Hermitian completion along y).  Both run as BF16 MFMA
+// contractions (v_mfma_f32_32x32x16_bf16) with every FP32 operand split into
+// BF16 high and low parts, v = h + l with |v - h - l| <= 2^-16 |v|, and three
+// products per k step (h h, h l, l h; the l l term is below FP32 rounding of
+// the sum), so the transforms keep close to FP32 accuracy at the BF16 rate.
+// The x-transform's B operand is the host-built table twb (high and low parts
+// of the FP64 twiddles); its result goes to LDS already split, as the
+// y-transform's B operand.  A lane's eight k values of an operand are one
+// 16-byte load; the A and B operands use the same lane-to-k assignment, so the
+// contraction does not depend on the order of k inside a lane group.
+// Grid (64 / FI_CB, S), FI_THREADS threads, FI_LDS bytes of dynamic LDS (BF16):
+//   Ya [2][FI_CB 16][FI_KA]   the block's spectrum, rows (c, ky), k = (kx, ri)
+//   Pb [2][FI_CB 72][FI_KP]   P, rows n = (c, x), k = (ky, ri)
+//   Wa [2][96][FI_KP]         the inverse y weights, rows y, k = (ky, ri)
+constexpr int FI_CB = 4, FI_THREADS = 512;
+constexpr int FI_KA = 4 * FM + 8, FI_KP = 2 * FM + 8, FI_NP = FI_CB * FNO_MAXL, FI_YR = 96;
+constexpr size_t FI_LDS = 2 * ((size_t)2 * FI_CB * FM * FI_KA + (size_t)2 * FI_NP * FI_KP + (size_t)2 * FI_YR * FI_KP);
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf16x8v ld_bf8(const unsigned short *p) {
+    return __builtin_bit_cast(bf16x8v, *reinterpret_cast<const uint4 *>(p));
+}
+__device__ __forceinline__ void split_bf(float v, unsigned short &h, unsigned short &l) {
+    h = f2bf(v);
+    l = f2bf(v - bf2f(h));
+}
+__device__ __forceinline__ f32x16v mfma_hl(bf16x8v ah, bf16x8v al, bf16x8v bh, bf16x8v bl, f32x16v acc) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+    return acc;
+}
 __global__ __launch_bounds__(FI_THREADS) void fno_dft_inv_kernel(const FnoSample *__restrict__ smp,
                                                                  const int *__restrict__ sact,
                                                                  const float *__restrict__ Y,
                                                                  unsigned short *__restrict__ spec, int S_tot,
-                                                                 const float2 *__restrict__ tw) {
-    extern __shared__ __align__(16) float fl[];
+                                                                 const float2 *__restrict__ tw,
+                                                                 const unsigned short *__restrict__ twb) {
+    extern __shared__ __align__(16) unsigned short fb[];
     const int s = blockIdx.y;
     if (sact && !sact[s]) return;
     const FnoSample S = smp[s];
     const int lx = S.lx, ly = S.ly, n = lx * ly;
     const int c0 = blockIdx.x * FI_CB;
-    float *Yl = fl;
-    float2 *ex = reinterpret_cast<float2 *>(Yl + FI_CB * FM * FI_LDY);         // 4160 floats: 16-byte aligned
-    float *Wl = reinterpret_cast<float *>(ex + 2 * FM * FNO_MAXL);
-    float *Pl = Wl + 2 * FM * FNO_MAXL;
-    // the block's modes: 2 x FI_CB floats (channels c0.., Re/Im) per mode
+    unsigned short *Ya = fb;                                   // [hi, lo][FI_CB * FM][FI_KA]
+    unsigned short *Pb = Ya + 2 * FI_CB * FM * FI_KA;          // [hi, lo][FI_NP][FI_KP]
+    unsigned short *Wa = Pb + 2 * FI_NP * FI_KP;               // [hi, lo][FI_YR][FI_KP]
+    constexpr int YA_LO = FI_CB * FM * FI_KA, PB_LO = FI_NP * FI_KP, WA_LO = FI_YR * FI_KP;
+    // the block's modes: FI_CB channels x (Re, Im) per mode, as float4 pairs of channels
     const long long mstride = (long long)S_tot * (2 * FC);
     for (int i = threadIdx.x; i < FMODES * (FI_CB / 2); i += FI_THREADS) {
         const int mode = i / (FI_CB / 2), h = i % (FI_CB / 2);
         const float4 v = *reinterpret_cast<const float4 *>(Y + mode * mstride + (long long)s * (2 * FC) + 2 * c0 + 4 * h);
         const int kx = mode / FM, ky = mode % FM;
-        float *ra = Yl + ((2 * h) * FM + ky) * FI_LDY + 2 * kx, *rb = ra + FM * FI_LDY;
-        ra[0] = v.x;
-        ra[1] = v.y;
-        rb[0] = v.z;
-        rb[1] = v.w;
+        unsigned short *ra = Ya + ((2 * h) * FM + ky) * FI_KA + 2 * kx, *rb = ra + FM * FI_KA;
+        split_bf(v.x, ra[0], ra[YA_LO]);
+        split_bf(v.y, ra[1], ra[YA_LO + 1]);
+        split_bf(v.z, rb[0], rb[YA_LO]);
+        split_bf(v.w, rb[1], rb[YA_LO + 1]);
     }
-    const float2 *ext = tw_side(tw, lx) + FNO_TW_INV_X * lx;                  // [q][x]
-    for (int i = threadIdx.x; i < 2 * FM * lx; i += FI_THREADS) ex[i] = ext[i];
-    const float2 *ey = tw_side(tw, ly) + FNO_TW_INV_Y * ly;                   // [y][ky]
+    // inverse y weights (rows y >= ly are zero), and P's rows beyond the block's cells
+    const float2 *ey = tw_side(tw, ly) + FNO_TW_INV_Y * ly;     // [y][ky]
     const float norm = 1.f / (float)n;
-    for (int i = threadIdx.x; i < ly * FM; i += FI_THREADS) {
+    for (int i = threadIdx.x; i < FI_YR * FM; i += FI_THREADS) {
         const int y = i / FM, ky = i % FM;
-        const float2 e = ey[i];
-        const float w = (ky == 0 ? 1.f : 2.f) * norm;
-        Wl[(2 * ky) * FNO_MAXL + y] = w * e.x;
-        Wl[(2 * ky + 1) * FNO_MAXL + y] = -w * e.y;
+        float wr = 0.f, wi = 0.f;
+        if (y < ly) {
+            const float2 e = ey[y * FM + ky];
+            const float w = (ky == 0 ? 1.f : 2.f) * norm;
+            wr = w * e.x;
+            wi = -w * e.y;
+        }
+        unsigned short *wa = Wa + y * FI_KP + 2 * ky;
+        split_bf(wr, wa[0], wa[WA_LO]);
+        split_bf(wi, wa[1], wa[WA_LO + 1]);
+    }
+    for (int i = threadIdx.x; i < (FI_NP - FI_CB * lx) * 2 * FM; i += FI_THREADS) {
+        const int r = FI_CB * lx + i / (2 * FM), k = i % (2 * FM);
+        Pb[r * FI_KP + k] = 0;
+        Pb[PB_LO + r * FI_KP + k] = 0;
     }
     __syncthreads();
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 31, lk = lane >> 5;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 31, lk = 8 * (lane >> 5);
     constexpr int NW = FI_THREADS / 64;
-    // x-transform: rows (c, ky) (FI_CB 16), N = 2 Lx
+    // x-transform: rows (c, ky) in FI_CB / 2 tiles of 32, N = (x, ri) in tiles of 32, K = 64;
+    // a wave takes one column tile for every row tile, so its B fragments are loaded once
     {
-        const int N = 2 * lx, nct = (N + 31) / 32, ntile = (FI_CB * FM / 32) * nct;
-        for (int t = wv; t < ntile; t += NW) {
-            const int rt = t / nct, ct = t % nct;
-            const int nn = ct * 32 + lr, x = min(nn >> 1, lx - 1), ro = nn & 1;
-            const bool nin = nn < N;
-            const float *arow = Yl + (rt * 32 + lr) * FI_LDY + lk;
-            f32x16v acc;
+        const int N = 2 * lx, nct = (N + 31) / 32;
+        const unsigned short *tb = twb + (size_t)128 * lx * (lx - 1), *tbl = tb + (size_t)2 * lx * 64;
+        for (int ct = wv; ct < nct; ct += NW) {
+            const int nn = ct * 32 + lr, nr = min(nn, N - 1);
+            f32x16v acc[FI_CB / 2];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-#pragma unroll 4
-            for (int k0 = 0; k0 < 4 * FM; k0 += 2) {
-                const int k = k0 + lk;
-                const float bv = nin ? cplx_entry(ex[(k >> 1) * lx + x], k & 1, ro) : 0.f;
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[k0], bv, acc, 0, 0, 0);
-            }
-            if (nin) {
+            for (int rt = 0; rt < FI_CB / 2; ++rt)
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int row = rt * 32 + 8 * (i >> 2) + 4 * lk + (i & 3);
-                    const int c = row / FM, ky = row % FM;
-                    Pl[(c * lx + x) * FI_LDP + 2 * ky + ro] = acc[i];
+                for (int i = 0; i < 16; ++i) acc[rt][i] = 0.f;
+#pragma unroll
+            for (int k0 = 0; k0 < 4 * FM; k0 += 16) {
+                const bf16x8v bh = ld_bf8(tb + nr * 64 + k0 + lk), bl = ld_bf8(tbl + nr * 64 + k0 + lk);
+#pragma unroll
+                for (int rt = 0; rt < FI_CB / 2; ++rt) {
+                    const unsigned short *ar = Ya + (rt * 32 + lr) * FI_KA + k0 + lk;
+                    acc[rt] = mfma_hl(ld_bf8(ar), ld_bf8(ar + YA_LO), bh, bl, acc[rt]);
                 }
+            }
+            if (nn < N) {
+                const int x = nn >> 1, ro = nn & 1;
+#pragma unroll
+                for (int rt = 0; rt < FI_CB / 2; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int row = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+                        const int c = row / FM, ky = row % FM;
+                        unsigned short *pb = Pb + (c * lx + x) * FI_KP + 2 * ky + ro;
+                        split_bf(acc[rt][i], pb[0], pb[PB_LO]);
+                    }
             }
         }
     }
     __syncthreads();
-    // y-transform: rows y, K = 2 FM, N = (c, x) (FI_CB Lx)
+    // y-transform: rows y (3 tiles of 32), N = (c, x) (FI_CB Lx) in tiles of 32, K = 32
     {
         const int N = FI_CB * lx, nrt = (ly + 31) / 32, nct = (N + 31) / 32, ntile = nrt * nct;
         unsigned short *sp = spec + S.cell_off * FC + (long long)c0 * n;
         for (int t = wv; t < ntile; t += NW) {
             const int rt = t / nct, ct = t % nct;
-            const int y = min(rt * 32 + lr, ly - 1), nn = ct * 32 + lr;
-            const bool yin = rt * 32 + lr < ly;
-            const int nc = min(nn, N - 1);
-            const float *bcol = Pl + nc * FI_LDP + lk;
+            const int nn = ct * 32 + lr;
+            const unsigned short *ar = Wa + (rt * 32 + lr) * FI_KP + lk, *br = Pb + nn * FI_KP + lk;
             f32x16v acc;
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-#pragma unroll 4
-            for (int k0 = 0; k0 < 2 * FM; k0 += 2) {
-                const float av = yin ? Wl[(k0 + lk) * FNO_MAXL + y] : 0.f;
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bcol[k0], acc, 0, 0, 0);
-            }
+#pragma unroll
+            for (int k0 = 0; k0 < 2 * FM; k0 += 16)
+                acc = mfma_hl(ld_bf8(ar + k0), ld_bf8(ar + WA_LO + k0), ld_bf8(br + k0), ld_bf8(br + PB_LO + k0), acc);
             if (nn < N) {
                 const int c = nn / lx, x = nn % lx;
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
-                    const int yy = rt * 32 + 8 * (i >> 2) + 4 * lk + (i & 3);
+                    const int yy = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
                     if (yy < ly) sp[(long long)c * n + yy * lx + x] = f2bf(acc[i]);
                 }
             }
@@ -566,7 +602,7 @@ void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, con
         hipLaunchKernelGGL(fno_spectral_kernel, dim3(FMODES, (S_tot + 63) / 64), dim3(256), 0, st, X,
                            net.R + (long long)l * FMODES * 128 * 128, Y, S_tot, smp, net.mod, l, net.layers);
         hipLaunchKernelGGL(fno_dft_inv_kernel, dim3(FC / FI_CB, S_tot), dim3(FI_THREADS), FI_LDS, st, smp, sact, Y,
-                           bf(spec), S_tot, net.tw);
+                           bf(spec), S_tot, net.tw, net.twb);
         hipLaunchKernelGGL(fno_pointwise_kernel, dim3(tblk, S_tot), dim3(256), 0, st, smp, sact, bf(cur), bf(spec),
                            net.W + (long long)l * FC * FC, net.b + (long long)l * FC, bf(nxt),
                            l < net.layers - 1 ? 1 : 0);
