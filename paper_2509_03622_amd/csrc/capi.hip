@@ -585,9 +585,10 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
                 base[FNO_TW_INV_Y * L + i * m + q] = ph(q, i, 1.0);        // inverse, [y][ky]
             }
     }
-    // the inverse x-transform's real 2 x 2 form split into BF16 high and low parts
-    // (from the FP64 values), the B operand of its BF16 MFMA contraction
+    // the x-transforms' real 2 x 2 forms split into BF16 high and low parts
+    // (from the FP64 values), the B operands of their BF16 MFMA contractions
     std::vector<unsigned short> twb((size_t)128 * FNO_MAXL * (FNO_MAXL + 1));
+    std::vector<unsigned short> twf((size_t)2 * 64 * FNO_TWF_K * FNO_MAXL, 0);
     {
         auto bf = [](double v) {
             const float f = (float)v;
@@ -603,6 +604,22 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
             return (double)f;
         };
         for (int L = 1; L <= FNO_MAXL; ++L) {
+            // forward x: [n = (q, ro)][k = (x, ri)], e^{-2 pi i kx x / L}
+            unsigned short *fh = &twf[(size_t)2 * 64 * FNO_TWF_K * (L - 1)], *fl = fh + (size_t)64 * FNO_TWF_K;
+            for (int x = 0; x < L; ++x)
+                for (int q = 0; q < 2 * m; ++q) {
+                    const int k = q < m ? q : L - 2 * m + q;
+                    const double a = -2.0 * M_PI * (double)(((long long)k * x) % L) / (double)L;
+                    const double c = std::cos(a), sn = std::sin(a);
+                    const double e[2][2] = {{c, sn}, {-sn, c}};              // [Re/Im in][Re/Im out]
+                    for (int ri = 0; ri < 2; ++ri)
+                        for (int ro = 0; ro < 2; ++ro) {
+                            const size_t i = (size_t)(2 * q + ro) * FNO_TWF_K + 2 * x + ri;
+                            fh[i] = bf(e[ri][ro]);
+                            fl[i] = bf(e[ri][ro] - val(fh[i]));
+                        }
+                }
+            // inverse x: [n = (x, ro)][k = (q, ri)], e^{+2 pi i kx x / L}
             unsigned short *hi = &twb[(size_t)128 * L * (L - 1)], *lo = hi + (size_t)2 * L * 64;
             for (int x = 0; x < L; ++x)
                 for (int q = 0; q < 2 * m; ++q) {
@@ -622,7 +639,7 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
     // one device buffer, carved
     const size_t bytes = (lift_w.size() + lift_b.size() + bias.size() + p1b.size() + p2w.size() + p2b.size()) * 4 +
                          (R.size() + Wb.size() + p1w.size()) * 2 + tw.size() * sizeof(float2) + twb.size() * 2 +
-                         10 * 256;
+                         twf.size() * 2 + 11 * 256;
     HIPCHK(ctx, p->d_net.ensure(bytes));
     char *base = p->d_net.as<char>();
     size_t off = 0;
@@ -646,6 +663,7 @@ nosdd_status load_network(nosdd_problem *p, const char *path) {
     n.p2b = (float *)put(p2b.data(), p2b.size() * 4);
     n.tw = (float2 *)put(tw.data(), tw.size() * sizeof(float2));
     n.twb = (unsigned short *)put(twb.data(), twb.size() * 2);
+    n.twf = (unsigned short *)put(twf.data(), twf.size() * 2);
     HIPCHK(ctx, hipStreamSynchronize(st));
     return NOSDD_OK;
 }

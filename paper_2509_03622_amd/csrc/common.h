@@ -239,6 +239,10 @@ struct FnoDevice {
     // twb + 128 L (L-1), the real 2 x 2 form [n = (x, Re/Im out)][k = (kx, Re/Im in)]
     // (2L x 64) as BF16 high parts, then the same as BF16 low parts (value - high)
     unsigned short *twb = nullptr;
+    // forward x-transform as the B operand of BF16 MFMA: per side L, at
+    // twf + 2 * 64 * FNO_TWF_K * (L - 1), [n = (kx, Re/Im out)][k = (x, Re/Im in)]
+    // (64 x FNO_TWF_K, zero for k >= 2L) as BF16 high parts, then as low parts
+    unsigned short *twf = nullptr;
     // modulated network: mod[mod_idx][layer][mode] (complex) multiplies the
     // spectral product of every block mode by mode; null for the plain network
     const float2 *mod = nullptr;
@@ -249,6 +253,7 @@ struct FnoDevice {
 constexpr int FNO_MAXL = 72;
 constexpr int FNO_MODES_TOTAL = 512;                          // 32 kx x 16 ky kept modes
 constexpr int FNO_TW_INV_X = 32, FNO_TW_FWD_Y = 64, FNO_TW_INV_Y = 80, FNO_TW_UNIT = 96;
+constexpr int FNO_TWF_K = 2 * FNO_MAXL;                       // row length of the twf tables
 
 // Workspace of the batched inner NN-FGMRES (device pointers).
 struct NnWork {

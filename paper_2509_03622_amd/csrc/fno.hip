@@ -14,10 +14,11 @@
 //
 // A "sample" is one (subdomain, RHS) pair; all samples of a sweep run in one
 // launch per stage.  Activations are stored in BF16 [sample][C][cells] with
-// the subdomain's own (lx, ly) (every block reads its input rounded to BF16:
-// the transforms take it as FP32 values, the channel mixes as BF16 MFMA
-// operands); transform intermediates stay FP32 except the inverse-transform
-// term handed to the pointwise stage, which is stored in BF16.  The dense channel contractions -- the 1x1 mix W
+// the subdomain's own (lx, ly) (every block reads its input rounded to BF16,
+// the operand of both the forward transform and the channel mix); the
+// transforms' intermediates are split into BF16 high and low parts in LDS,
+// their spectra are FP32, and the inverse-transform term handed to the
+// pointwise stage is stored in BF16.  The dense channel contractions -- the 1x1 mix W
 // and the per-mode complex mix R -- run on MFMA in BF16 with FP32
 // accumulation (v_mfma_f32_32x32x8_bf16): R is applied as the real 128 x 128
 // form of the complex 64 x 64 mix to (Re X_c, Im X_c) interleaved per
@@ -25,9 +26,9 @@
 // twiddle tables built on the host in FP64 per subdomain side: the
 // y-transform first (it keeps 16 of the ly frequencies), then the x-transform
 // of those 16 rows, and the inverse in the reverse order with the Hermitian
-// weights of the real inverse folded into its last table.  The forward pair
-// runs in FP32 (v_mfma_f32_32x32x2f32); the inverse pair in BF16
-// (v_mfma_f32_32x32x16_bf16) on operands split into high and low BF16 parts.
+// weights of the real inverse folded into its last table.  Both pairs run
+// in BF16 (v_mfma_f32_32x32x16_bf16) on FP32 operands split into high and
+// low BF16 parts, which keeps them close to FP32 accuracy.
 #include "common.h"
 
 namespace nosdd {
@@ -86,142 +87,18 @@ __global__ __launch_bounds__(256) void fno_lift_kernel(const FnoSample *__restri
 
 // ------------------------------------------------------------------ truncated DFTs on MFMA
 // The truncated transforms of one subdomain are small dense contractions over
-// all 64 channels at once, computed as FP32 MFMA GEMMs (v_mfma_f32_32x32x2f32):
-//   forward  A: T1[c][x][ky]   = sum_y u[c][y][x] e^{-2pi i ky y/Ly}        (M = 64 Lx, K = Ly, N = 32)
-//            B: X[kx][ky][c]   = sum_x T1[c][x][ky] e^{-2pi i kx x/Lx}      (M = 64 x 16, K = 2 Lx, N = 64)
-//   inverse  C: P[c][ky][x]    = sum_kx Y[kx][ky][c] e^{+2pi i kx x/Lx}     (M = 64 x 16, K = 64, N = 2 Lx)
-//            D: s[c][y][x]     = Re sum_ky w_ky P[c][ky][x] e^{+2pi i ky y/Ly} / (Lx Ly)   (M = 64 Lx, K = 32, N = Ly)
+// a few channels at once, computed as BF16 MFMA GEMMs:
+//   forward  A: T1[c][x][ky]   = sum_y u[c][y][x] e^{-2pi i ky y/Ly}
+//            B: X[kx][ky][c]   = sum_x T1[c][x][ky] e^{-2pi i kx x/Lx}
+//   inverse  C: P[c][ky][x]    = sum_kx Y[kx][ky][c] e^{+2pi i kx x/Lx}
+//            D: s[c][y][x]     = Re sum_ky w_ky P[c][ky][x] e^{+2pi i ky y/Ly} / (Lx Ly)
 // with w_0 = 1, w_ky = 2 (Hermitian completion along y).  Complex products
 // use the real 2 x 2 form of each complex entry (Re/Im interleaved in K and
-// N).  T1 lives in the spec buffer, free at that point of the layer; C and D
-// run in one kernel that keeps P in LDS.
+// N).  A and B run in one kernel that keeps T1 in LDS, C and D in one that
+// keeps P in LDS.
 typedef float f32x16v __attribute__((ext_vector_type(16)));
-constexpr int DG_KC = 16;     // K chunk staged in LDS
-
-// Block tile (32 WM) x (32 WN), one 32 x 32 MFMA tile per wave (4 waves).
-// Staging: thread t owns tile row t % (32 WM) and a stride of K; arow(m)
-// precomputes whatever the A address needs for row m once per chunk, and
-// la(ctx, k) returns the operand; lb(k, n) returns B (zero outside M, N, K is
-// handled here).  sink(row, col, v) receives the tile (block-local row and
-// column): either a direct store or a write into an LDS tile that the caller
-// stores with its own coalesced mapping after a barrier.
-template <int WM, int WN, class AR, class LA, class LB, class SC>
-__device__ __forceinline__ void dft_gemm(int M, int N, int K, int m0, int n0, AR arow, LA la, LB lb, SC sink) {
-    __shared__ float As[32 * WM][DG_KC + 1];
-    __shared__ float Bs[DG_KC][32 * WN + 1];
-    constexpr int BM = 32 * WM, KSTEP = 256 / BM, NA = DG_KC / KSTEP, NB = DG_KC * 32 * WN / 256;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wm = wv % WM, wn = wv / WM;
-    const int r = threadIdx.x % BM, kq = threadIdx.x / BM;
-    const bool rin = m0 + r < M;
-    const auto actx = arow(rin ? m0 + r : m0);
-    // the next K chunk is loaded into registers while the current one is
-    // multiplied; addresses are clamped into range so every load is
-    // unconditional, and out-of-range values are zeroed when staged
-    float ra[NA], rb[NB];
-    auto load = [&](int kc) {
-#pragma unroll
-        for (int j = 0; j < NA; ++j) ra[j] = la(actx, min(kc + kq + j * KSTEP, K - 1));
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int i = threadIdx.x + j * 256;
-            rb[j] = lb(min(kc + i / (32 * WN), K - 1), min(n0 + i % (32 * WN), N - 1));
-        }
-    };
-    f32x16v acc;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-    load(0);
-    for (int kc = 0; kc < K; kc += DG_KC) {
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-            const int k = kq + j * KSTEP;
-            As[r][k] = (rin && kc + k < K) ? ra[j] : 0.f;
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int i = threadIdx.x + j * 256;
-            const int c = i % (32 * WN), k = i / (32 * WN);
-            Bs[k][c] = (n0 + c < N && kc + k < K) ? rb[j] : 0.f;
-        }
-        __syncthreads();
-        if (kc + DG_KC < K) load(kc + DG_KC);
-#pragma unroll
-        for (int k = 0; k < DG_KC; k += 2) {
-            const float av = As[wm * 32 + (lane & 31)][k + (lane >> 5)];
-            const float bv = Bs[k + (lane >> 5)][wn * 32 + (lane & 31)];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) sink(wm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3), wn * 32 + (lane & 31), acc[i]);
-}
-
-// real 2 x 2 form of the complex twiddle e (input Re/Im = rin, output = rout)
-__device__ __forceinline__ float cplx_entry(float2 e, int rin, int rout) {
-    return rin == 0 ? (rout == 0 ? e.x : e.y) : (rout == 0 ? -e.y : e.x);
-}
 __device__ __forceinline__ const float2 *tw_side(const float2 *tw, int L) {
     return tw + (long long)FNO_TW_UNIT * L * (L - 1) / 2;
-}
-
-// A: forward along y (real input): rows (c, x), K = y, N = (ky, ri).
-// Grid (ceil(64 Lmax / 128), 1, S).  T1[c][x][2 ky + ri].
-__global__ __launch_bounds__(256) void fno_dft_y_fwd_kernel(const FnoSample *__restrict__ smp,
-                                                            const int *__restrict__ sact,
-                                                            const unsigned short *__restrict__ act, float *__restrict__ T1,
-                                                            const float2 *__restrict__ tw) {
-    const int s = blockIdx.z;
-    if (sact && !sact[s]) return;
-    const FnoSample S = smp[s];
-    const int lx = S.lx, ly = S.ly, n = lx * ly;
-    const int M = FC * lx, m0 = blockIdx.x * 128;
-    if (m0 >= M) return;
-    const unsigned short *u = act + S.cell_off * FC;
-    const float *ey = reinterpret_cast<const float *>(tw_side(tw, ly) + FNO_TW_FWD_Y * ly);   // [y][2 ky + ri]
-    float *t1 = T1 + S.cell_off * FC;
-    // output rows are 32 contiguous floats and the MFMA lanes run along them
-    dft_gemm<4, 1>(
-        M, 2 * FM, ly, m0, 0, [&](int m) { return u + (m / lx) * n + (m % lx); },
-        [&](const unsigned short *row, int k) { return bf2f(row[k * lx]); },
-        [&](int k, int nn) { return ey[k * 2 * FM + nn]; },
-        [&](int rr, int c, float v) {
-            if (m0 + rr < M) t1[(long long)(m0 + rr) * 2 * FM + c] = v;
-        });
-}
-
-// B: forward along x (complex): rows (c, ky) with ky fastest (a block takes
-// 4 channels x all 16 ky, so consecutive lanes read consecutive (ky, Re/Im)
-// entries of a T1 row and every block reads its own channels only),
-// K = (x, ri), N = (kx, ri).  Grid (16, 1, S).
-// X[mode = kx * 16 + ky][s][2 c + ri].
-__global__ __launch_bounds__(256) void fno_dft_x_fwd_kernel(const FnoSample *__restrict__ smp,
-                                                            const int *__restrict__ sact,
-                                                            const float *__restrict__ T1, float *__restrict__ X,
-                                                            int S_tot, const float2 *__restrict__ tw) {
-    __shared__ float Cs[64][65];
-    const int s = blockIdx.z;
-    if (sact && !sact[s]) return;
-    const FnoSample S = smp[s];
-    const int lx = S.lx, m0 = blockIdx.x * 64;          // rows m = c * 16 + ky
-    const float *t1 = T1 + S.cell_off * FC;
-    const float2 *ex = tw_side(tw, lx);                  // [x][kx]
-    dft_gemm<2, 2>(
-        FC * FM, 4 * FM, 2 * lx, m0, 0,
-        [&](int m) { return t1 + (long long)(m / FM) * lx * 2 * FM + 2 * (m % FM); },
-        [&](const float *row, int k) { return row[(k >> 1) * 2 * FM + (k & 1)]; },
-        [&](int k, int nn) { return cplx_entry(ex[(k >> 1) * 2 * FM + (nn >> 1)], k & 1, nn & 1); },
-        [&](int rr, int c, float v) { Cs[rr][c] = v; });
-    __syncthreads();
-    // for each (kx, ky): the block's 4 channels x (Re, Im) = 8 contiguous floats
-    const int c0 = m0 / FM;
-    for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-        const int j = i & 7, rest = i >> 3;          // j = (channel, Re/Im) within the block
-        const int ky = rest % FM, kx = rest / FM;
-        const int cl = j >> 1, ri = j & 1;
-        X[((long long)(kx * FM + ky) * S_tot + s) * (2 * FC) + 2 * (c0 + cl) + ri] = Cs[cl * FM + ky][2 * kx + ri];
-    }
 }
 
 // C+D: both inverse transforms of FI_CB channels of one sample in one
@@ -370,6 +247,152 @@ __global__ __launch_bounds__(FI_THREADS) void fno_dft_inv_kernel(const FnoSample
                 }
             }
         }
+    }
+}
+
+// A+B: both forward transforms of FF_CB channels of one sample in one
+// workgroup, the y-transform's result kept in LDS (no T1 round trip):
+//   T1[c][x][ky] = sum_y u[c][y][x] e^{-2pi i ky y/Ly}       rows (ky, ri), K = y, N = (c, x)
+//   X[kx][ky][c] = sum_x T1[c][x][ky] e^{-2pi i kx x/Lx}     rows (c, ky), K = (x, ri), N = (kx, ri)
+// on BF16 MFMA (v_mfma_f32_32x32x16_bf16).  The activations are BF16 values
+// already, so the y-transform needs two products per k step (twiddle high and
+// low parts); T1 goes to LDS split into high and low parts and the
+// x-transform takes three (against the host-built table twf).
+// Grid (64 / FF_CB, S), FF_THREADS threads, FF_LDS bytes of dynamic LDS (BF16):
+//   Bu [FF_NU][FF_KY]          activations, rows n = (c, x), k = y (zero for y >= ly)
+//   Ey [2][32][FF_KY]          forward y twiddles, rows (ky, ri), k = y
+//   A2 [2][FF_CB 16][FF_K2]    T1, rows (c, ky), k = (x, ri) (zero for x >= lx)
+//   Xs (aliases Bu) [512][2 FF_CB] f32: the block's modes, for 16-byte stores
+constexpr int FF_CB = 2, FF_THREADS = 512;
+constexpr int FF_LPT = (FF_CB * FNO_MAXL * FNO_MAXL + FF_THREADS - 1) / FF_THREADS;   // activation loads per thread
+constexpr int FF_KY = 88, FF_NU = 5 * 32, FF_K2 = 2 * FNO_MAXL + 8;
+constexpr size_t FF_LDS = 2 * ((size_t)FF_NU * FF_KY + (size_t)2 * 32 * FF_KY + (size_t)2 * FF_CB * FM * FF_K2);
+static_assert(FF_CB * FNO_MAXL <= FF_NU && FNO_MAXL <= 80 && FNO_TWF_K % 16 == 0, "one sample's rows and k fit the buffers");
+static_assert(sizeof(float) * FMODES * 2 * FF_CB <= 2 * (size_t)FF_NU * FF_KY, "Xs fits in Bu");
+__global__ __launch_bounds__(FF_THREADS) void fno_dft_fwd_kernel(const FnoSample *__restrict__ smp,
+                                                                 const int *__restrict__ sact,
+                                                                 const unsigned short *__restrict__ act,
+                                                                 float *__restrict__ X, int S_tot,
+                                                                 const float2 *__restrict__ tw,
+                                                                 const unsigned short *__restrict__ twf) {
+    extern __shared__ __align__(16) unsigned short fb[];
+    const int s = blockIdx.y;
+    if (sact && !sact[s]) return;
+    const FnoSample S = smp[s];
+    const int lx = S.lx, ly = S.ly, n = lx * ly;
+    const int c0 = blockIdx.x * FF_CB;
+    unsigned short *Bu = fb;                                   // [FF_NU][FF_KY]
+    unsigned short *Ey = Bu + FF_NU * FF_KY;                   // [hi, lo][32][FF_KY]
+    unsigned short *A2 = Ey + 2 * 32 * FF_KY;                  // [hi, lo][FF_CB * FM][FF_K2]
+    constexpr int EY_LO = 32 * FF_KY, A2_LO = FF_CB * FM * FF_K2;
+    // activations, transposed to rows (c, x) with y contiguous: every load of the
+    // thread is issued before the first store, and the (c, y, x) of its elements
+    // advance by the thread stride without divisions.  The k padding y >= ly of
+    // those rows is zeroed (the twiddles are zero there too, but 0 x NaN is not
+    // zero); rows beyond FF_CB lx only feed output columns that are dropped.
+    const unsigned short *u = act + S.cell_off * FC + (long long)c0 * n;
+    {
+        unsigned short uv[FF_LPT];
+#pragma unroll
+        for (int j = 0; j < FF_LPT; ++j) {
+            const int i = threadIdx.x + j * FF_THREADS;
+            uv[j] = i < FF_CB * n ? u[i] : (unsigned short)0;
+        }
+        const int dy = FF_THREADS / lx, dx = FF_THREADS % lx;
+        int c = threadIdx.x / n, y = (threadIdx.x % n) / lx, x = threadIdx.x % lx;
+#pragma unroll
+        for (int j = 0; j < FF_LPT; ++j) {
+            if (c < FF_CB) Bu[(c * lx + x) * FF_KY + y] = uv[j];
+            x += dx;
+            y += dy;
+            if (x >= lx) {
+                x -= lx;
+                ++y;
+            }
+            while (y >= ly) {
+                y -= ly;
+                ++c;
+            }
+        }
+        const int npad = 80 - ly;
+        for (int i = threadIdx.x; i < FF_CB * lx * npad; i += FF_THREADS)
+            Bu[(i / npad) * FF_KY + ly + i % npad] = 0;
+    }
+    // forward y twiddles (FP32 table) split into high and low parts; k >= ly zero
+    const float2 *ey = tw_side(tw, ly) + FNO_TW_FWD_Y * ly;     // [y][ky]
+    for (int i = threadIdx.x; i < FM * FF_KY; i += FF_THREADS) {
+        const int ky = i / FF_KY, y = i % FF_KY;
+        const float2 e = y < ly ? ey[y * FM + ky] : make_float2(0.f, 0.f);
+        unsigned short *er = Ey + (2 * ky) * FF_KY + y;
+        split_bf(e.x, er[0], er[EY_LO]);
+        split_bf(e.y, er[FF_KY], er[EY_LO + FF_KY]);
+    }
+    // T1's k >= 2 lx (x beyond the sample) zero
+    for (int i = threadIdx.x; i < FF_CB * FM * (FF_K2 - 2 * lx); i += FF_THREADS) {
+        const int r = i / (FF_K2 - 2 * lx), k = 2 * lx + i % (FF_K2 - 2 * lx);
+        A2[r * FF_K2 + k] = 0;
+        A2[A2_LO + r * FF_K2 + k] = 0;
+    }
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 31, lk = 8 * (lane >> 5);
+    constexpr int NW = FF_THREADS / 64;
+    // y-transform: one row tile (ky, ri), N = (c, x) in tiles of 32, K = y (5 steps of 16)
+    {
+        const int N = FF_CB * lx, nct = (N + 31) / 32;
+        const unsigned short *ar = Ey + lr * FF_KY + lk;
+        for (int ct = wv; ct < nct; ct += NW) {
+            const int nn = ct * 32 + lr;
+            const unsigned short *br = Bu + nn * FF_KY + lk;
+            f32x16v acc;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll
+            for (int k0 = 0; k0 < 80; k0 += 16) {
+                const bf16x8v b = ld_bf8(br + k0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ld_bf8(ar + k0), b, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ld_bf8(ar + EY_LO + k0), b, acc, 0, 0, 0);
+            }
+            if (nn < N) {
+                const int c = nn / lx, x = nn % lx;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int row = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);     // (ky, ri)
+                    unsigned short *a2 = A2 + (c * FM + (row >> 1)) * FF_K2 + 2 * x + (row & 1);
+                    split_bf(acc[i], a2[0], a2[A2_LO]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // x-transform: one row tile (c, ky), N = (kx, ri) in 2 tiles, K = (x, ri) in steps of 16
+    float *Xs = reinterpret_cast<float *>(Bu);                 // [mode][2 FF_CB]
+    {
+        // all FNO_TWF_K / 16 steps: the table and T1 are zero for k >= 2 lx, and the
+        // fixed count lets every twiddle load be issued ahead of the products
+        const unsigned short *tf = twf + (size_t)2 * 64 * FNO_TWF_K * (lx - 1), *tfl = tf + (size_t)64 * FNO_TWF_K;
+        const unsigned short *ar = A2 + lr * FF_K2 + lk;
+        for (int ct = wv; ct < 2; ct += NW) {
+            const int nn = ct * 32 + lr;
+            const unsigned short *bh = tf + nn * FNO_TWF_K + lk, *bl = tfl + nn * FNO_TWF_K + lk;
+            f32x16v acc;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll
+            for (int ks = 0; ks < FNO_TWF_K / 16; ++ks)
+                acc = mfma_hl(ld_bf8(ar + 16 * ks), ld_bf8(ar + A2_LO + 16 * ks), ld_bf8(bh + 16 * ks),
+                              ld_bf8(bl + 16 * ks), acc);
+            const int q = nn >> 1, ro = nn & 1;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int row = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);         // (c, ky)
+                Xs[(q * FM + (row % FM)) * (2 * FF_CB) + 2 * (row / FM) + ro] = acc[i];
+            }
+        }
+    }
+    __syncthreads();
+    for (int mode = threadIdx.x; mode < FMODES; mode += FF_THREADS) {
+        const float4 v = *reinterpret_cast<const float4 *>(Xs + mode * (2 * FF_CB));
+        *reinterpret_cast<float4 *>(X + ((long long)mode * S_tot + s) * (2 * FC) + 2 * c0) = v;
     }
 }
 
@@ -579,6 +602,8 @@ __global__ __launch_bounds__(256) void fno_project_kernel(const FnoSample *__res
 void fno_prepare() {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fno_dft_inv_kernel),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)FI_LDS);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fno_dft_fwd_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)FF_LDS);
 }
 
 void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, const int *sact, int S_tot, int max_cells,
@@ -587,18 +612,14 @@ void fno_forward(hipStream_t st, const FnoDevice &net, const FnoSample *smp, con
     const int cblk = (max_cells + 255) / 256;
     const int tblk = (max_cells + 64 * FNO_PW_TILES - 1) / (64 * FNO_PW_TILES);
     const int pblk = (max_cells + 64 * FNO_PROJ_TILES - 1) / (64 * FNO_PROJ_TILES);
-    const int lmax = FNO_MAXL;                 // longest subdomain side (blocks beyond a sample's size exit)
     // activations are stored in BF16 [sample][channel][cell] between kernels
     auto bf = [](float *p) { return reinterpret_cast<unsigned short *>(p); };
     hipLaunchKernelGGL(fno_lift_kernel, dim3(cblk, S_tot), dim3(256), 0, st, smp, sact, v, vscale, aux, aux_ch_stride,
                        net.lift_w, net.lift_b, bf(act0));
     float *cur = act0, *nxt = act1;
     for (int l = 0; l < net.layers; ++l) {
-        // T1 lives in spec until the inverse transforms overwrite it with their BF16 result
-        hipLaunchKernelGGL(fno_dft_y_fwd_kernel, dim3((FC * lmax + 127) / 128, 1, S_tot), dim3(256), 0, st, smp, sact,
-                           bf(cur), spec, net.tw);
-        hipLaunchKernelGGL(fno_dft_x_fwd_kernel, dim3(FC * FM / 64, 1, S_tot), dim3(256), 0, st, smp, sact, spec, X,
-                           S_tot, net.tw);
+        hipLaunchKernelGGL(fno_dft_fwd_kernel, dim3(FC / FF_CB, S_tot), dim3(FF_THREADS), FF_LDS, st, smp, sact,
+                           bf(cur), X, S_tot, net.tw, net.twf);
         hipLaunchKernelGGL(fno_spectral_kernel, dim3(FMODES, (S_tot + 63) / 64), dim3(256), 0, st, X,
                            net.R + (long long)l * FMODES * 128 * 128, Y, S_tot, smp, net.mod, l, net.layers);
         hipLaunchKernelGGL(fno_dft_inv_kernel, dim3(FC / FI_CB, S_tot), dim3(FI_THREADS), FI_LDS, st, smp, sact, Y,
