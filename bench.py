@@ -503,24 +503,29 @@ def main():
         tiles = tile_geometry(w)
         C, m, L, hid = 64, 16, 4, 128
 
-        def flops(lx, ly):
-            """Algorithmic FLOPs of one network application to one lx x ly subdomain."""
+        def parts(lx, ly):
+            """Algorithmic FLOPs of one network application to one lx x ly subdomain:
+            (channel contractions on BF16 MFMA, truncated DFTs, DFT products executed on BF16
+            MFMA with high/low operand splits, other FP32 work)."""
             n = lx * ly
-            dft = 64 * lx * m * ly * 4 + 64 * m * 2 * m * lx * 8          # y then x transform (real input)
-            idft = 64 * m * lx * 2 * m * 8 + 64 * lx * ly * m * 4          # x then y inverse (real output)
+            fy, fx = 64 * lx * m * ly * 4, 64 * m * 2 * m * lx * 8          # forward y (real input), then x
+            ix, iy = 64 * m * lx * 2 * m * 8, 64 * lx * ly * m * 4          # inverse x, then y (real output)
             mix = 2 * m * m * C * C * 8
-            layer = dft + idft + mix + 2 * C * C * n
-            return 2 * 9 * C * n + L * layer + (2 * C * hid + 2 * hid * 2) * n
-        bf16_part = sum(L * (2 * m * m * C * C * 8 + 2 * C * C * t[0] * t[1]) + 2 * C * hid * t[0] * t[1]
-                        for t in tiles)
-        total = sum(flops(t[0], t[1]) for t in tiles)
-        fp32_part = total - bf16_part
-        floor_us = 1e6 * max(bf16_part / 2.5e15 + fp32_part / FP32_MFMA_PEAK_TFS / 1e12, 0.0)
+            bf16 = L * (mix + 2 * C * C * n) + 2 * C * hid * n
+            dft = L * (fy + fx + ix + iy)
+            dft_exec = L * (2 * fy + 3 * fx + 3 * ix + 3 * iy)             # products per k step: 2, 3, 3, 3
+            other = 2 * 9 * C * n + 2 * hid * 2 * n                        # lift, last projection layer
+            return bf16, dft, dft_exec, other
+        tot = [sum(parts(t[0], t[1])[i] for t in tiles) for i in range(4)]
+        bf16_part, dft_part, dft_exec, other = tot
+        total = bf16_part + dft_part + other
+        floor_us = 1e6 * ((bf16_part + dft_exec) / 2.5e15 + other / FP32_MFMA_PEAK_TFS / 1e12)
         print(json.dumps({"mode": "nn_apply", "metric": "one network application to every subdomain",
                           "config": {"workload": w.name, "subdomains": nt, "weights": os.path.basename(a.weights)},
                           "ms_per_application": round(ms, 4), "reps": reps,
                           "algorithmic_gflop": round(total / 1e9, 2),
-                          "bf16_mfma_gflop": round(bf16_part / 1e9, 2), "fp32_gflop": round(fp32_part / 1e9, 2),
+                          "bf16_mfma_gflop": round(bf16_part / 1e9, 2), "dft_gflop": round(dft_part / 1e9, 2),
+                          "dft_bf16_executed_gflop": round(dft_exec / 1e9, 2), "fp32_other_gflop": round(other / 1e9, 2),
                           "achieved_tflops": round(total / (ms * 1e-3) / 1e12, 2),
                           "mfma_floor_us": round(floor_us, 1)}), flush=True)
         P.close()
