@@ -250,7 +250,8 @@ nosdd_status nosdd_precond_apply_noalloc(nosdd_problem *p, const nosdd_c32 *v, n
  * differ; use nosdd_tile_info for offsets), one vector per (wl, tile). */
 nosdd_status nosdd_local_solve(nosdd_problem *p, const nosdd_c32 *rhs, nosdd_c32 *u);
 /* Apply the subdomain neural operator once to every subdomain-local vector
- * (Fig. 2 network as loaded at setup, BF16 MFMA channel mixes, FP32 DFTs):
+ * (Fig. 2 network as loaded at setup, BF16 MFMA channel mixes, truncated DFTs
+ * on BF16 MFMA with operands split into high and low parts, near FP32):
  * e = NN(v) for v, e laid out [n_wl][n_tiles][ly_t][lx_t] like
  * nosdd_local_solve.  Needs a problem set up with sub_solver = 1. */
 nosdd_status nosdd_nn_apply(nosdd_problem *p, const nosdd_c32 *v, nosdd_c32 *e);

@@ -180,8 +180,9 @@ def fno_forward(weights, v, eps, k0h, inv_sx, inv_sy, ring_mask, bf16=False):
     bf16=True is the emulation of a BF16 matrix-core forward pass: every
     activation tensor between blocks is rounded to bfloat16 (it is stored so),
     and so are the operands of every learned channel mix (spectral mix, 1x1
-    mix, first projection); everything else is exact (the lift, the
-    transforms and the last projection are not matrix-core products)."""
+    mix, first projection); everything else is exact (the lift and the last
+    projection are not matrix-core products; the transforms are, but on
+    operands split into two BF16 parts, within about 2^-16 of exact)."""
     wt = {k: np.asarray(a, dtype=np.float64) if not np.iscomplexobj(a) else np.asarray(a, np.complex128)
           for k, a in weights.items()}
     m = int(weights["modes"])
