@@ -936,7 +936,8 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
     }
 }
 
-// The 32-source form (blocks up to 80 cells) with one barrier per block step.
+// The 32-source form (blocks up to 80 cells), synchronised per step through LDS
+// counters instead of workgroup barriers (see the step below).
 // M_k is complex symmetric, so the step's products are formed transposed,
 // C^T = Y^T M_k (rows: sources, columns: block rows), and the wave that forms
 // an output tile runs the recurrence of its 16 x 16 (source, row) elements
@@ -944,7 +945,7 @@ __device__ __forceinline__ void bm_solve(const TileDesc &t, int wl, int s0, int 
 // so its global loads and stores are row-contiguous across lanes.  The waves
 // without a tile meanwhile expand the next factor block into the second of
 // two LDS buffers, and the operand of the next step goes to the second of two
-// operand buffers, so a step needs no second barrier and no product buffer.
+// operand buffers, so a step needs no product buffer.
 // Re C^T = Yr Mr - Yi Mi is accumulated as two sums (the operand is kept as
 // Re and Im only), Im C^T = Yr Mi + Yi Mr as one.
 constexpr int B32_EMAX = 9;                           // expand elements per lane: ceil(3280 / (6 * 64))
@@ -959,7 +960,7 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
                                            float2 *__restrict__ out, long long out_stride,
                                            const int *__restrict__ active, float2 *__restrict__ loc, long long LT,
                                            float *lds, float2 *cl_s, float2 *ch_s, float2 *so_s, float2 *si_s,
-                                           int *colr) {
+                                           int *colr, int *sync) {
     constexpr int NCOL = 32;
     const int b = t.b, nb = t.nb, P = b >> 1, tid = threadIdx.x;
     const int BP = bm_pad(b), LDM = BP + 2, LDK = BP + 4;
@@ -990,6 +991,7 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
     // zero both factor buffers and both operand buffers (padding rows and k >= b stay zero)
     for (int e = tid; e < 2 * BP * LDM; e += BM_THREADS) MB(0)[e] = make_float2(0.f, 0.f);
     for (int e = tid; e < 2 * 2 * NCOL * LDK; e += BM_THREADS) Xb[e] = 0.f;
+    if (tid < 5) sync[tid] = 0;
     __syncthreads();
     const long long blk = bt_sym_block(b);
     const int nsub = (int)(blk >> 2);
@@ -1117,10 +1119,45 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
     __syncthreads();
     // one block step s on buffers cur = s & 1; the expand waves expand block s + 1
     // (waiting in the slot) into the other buffer and refill the slot with block s + 2
+    // The two source tiles (halves) are independent recurrences that share only
+    // the factor block, so instead of a workgroup barrier per step the waves
+    // synchronise through LDS counters, and one half's recurrence can overlap the
+    // other half's products:
+    //   sync[h]      product phases of half h done (its reads of M finished): RT per step
+    //   sync[2]      expansions done: NE per step (block s + 1 during step s)
+    //   sync[3 + h]  recurrences of half h done (its next operand written): RT per step
+    // Products of step s wait for block s (sync[2] >= NE s) and for their half's
+    // operand (sync[3 + h] >= RT s); the expansion of block s + 1 into the buffer
+    // that step s - 1 read waits for the other expansion waves' previous block
+    // (sync[2] >= NE s) and for both halves' products of step s - 1 (sync[h] >= RT s).
+    // A count reaches k per wave only when every wave of its group has finished
+    // step k - 1: no wave of a group starts step k before its whole group has
+    // finished step k - 1, which each wait above ensures.  No wait depends on a
+    // later one, so the halves drift at most a step apart, which the double
+    // buffers cover.  Every wait is bounded (about 2^18 short sleeps, some
+    // thousand times the longest wait seen), so a wave always finishes; a wave
+    // whose wait ran out writes NaN instead of its values, which the outer
+    // solver reports as a non-finite result rather than a wrong one.
+    const int NE = BM_THREADS / 64 - nT, half = prod ? tile / RT : 0;
+    auto wait_ge = [&](int idx, int target) {
+        for (int spin = 0; spin < (1 << 18); ++spin) {
+            if (__hip_atomic_load(&sync[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) return true;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        return false;
+    };
+    const float qnan = __builtin_nanf("");
+    auto signal = [&](int idx) {
+        if (lane == 0) __hip_atomic_fetch_add(&sync[idx], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     auto step = [&](int s) {
         const int cur = s & 1, k = blk_of(s);
         const bool fwd = s < nb, turn = s == nb - 1;
         if (prod) {
+            const bool ok = wait_ge(2, NE * s) & wait_ge(3 + half, RT * s);
+            // the first half contracts at raised issue priority, so the halves fall out
+            // of step and one half's recurrence runs beside the other's products
+            if (half == 0) __builtin_amdgcn_s_setprio(2);
             // three real products per complex one (Gauss): T1 = Yr Mr, T2 = Yi Mi,
             // T3 = (Yr + Yi)(Mr + Mi); Re = T1 - T2, Im = T3 - T1 - T2
             f32x4v accA = {0.f, 0.f, 0.f, 0.f}, accB = {0.f, 0.f, 0.f, 0.f}, accS = {0.f, 0.f, 0.f, 0.f};
@@ -1141,6 +1178,8 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
                     accS = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[u] + vi[u], mr[u] + mi[u], accS, 0, 0, 0);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
+            signal(half);                                 // this step's reads of M and X done
             // recurrence of this lane's 4 (source, row) elements, straight from the accumulators.
             // Wait for every outstanding memory operation first: the counter retires in
             // issue order, so once this step's stores are issued, the wait for the operand
@@ -1155,7 +1194,8 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
             for (int q = 0; q < 4; ++q) {
                 float2 z = make_float2(0.f, 0.f);
                 if ((live >> q) & 1) {
-                    const float2 a = make_float2(accA[q] - accB[q], accS[q] - accA[q] - accB[q]);
+                    const float2 a = ok ? make_float2(accA[q] - accB[q], accS[q] - accA[q] - accB[q])
+                                        : make_float2(qnan, qnan);
                     float2 y;
                     if (fwd) {
                         if (!turn) st(rsL, poff(q), (unsigned)k * bstep, a);          // w_k
@@ -1171,13 +1211,19 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
                     xin[(cq0 + q) * LDK + i] = z.y;
                 }
             }
-            // the next step's v_{k+1} or w_k: in flight over the barrier and the next products
+            signal(3 + half);                             // the half's next operand written
+            // the next step's v_{k+1} or w_k: in flight over the next products
             load_pre(s + 1, pre);
         } else if (s + 1 < nsteps) {
+            // every expansion of block s done; step s - 1 no longer reads MB(cur ^ 1)
+            const bool ok = wait_ge(2, NE * s) & wait_ge(0, RT * s) & wait_ge(1, RT * s);
+            if (!ok)
+#pragma unroll
+                for (int j = 0; j < B32_EMAX; ++j) slot[j] = make_float2(qnan, qnan);
             expand(slot, MB(cur ^ 1));
+            signal(2);
             fetch(s + 2, slot);
         }
-        __syncthreads();                              // next factor block and operand in LDS
     };
     for (int s = 0; s < nsteps; ++s) step(s);
 }
@@ -1197,12 +1243,13 @@ __global__ __launch_bounds__(BM_THREADS) void bt_solve_multi_kernel(
     extern __shared__ __align__(16) float lds[];
     __shared__ float2 cl_s[BT_NBMAX], ch_s[BT_NBMAX], so_s[BT_NBMAX], si_s[BT_BMAX];
     __shared__ int colr[32];                          // RHS index of each column, -1 when idle
+    __shared__ int sync[5];                           // step counters of the 32-source form
     const int4 job = jobs[blockIdx.x];
     if (job.x < 0) return;
     const TileDesc t = tiles[job.x];
     if (t.b <= BM_NARROW)
         bm_solve32(t, job.y, job.z, job.w, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride, out,
-                   out_stride, active, loc, LT, lds, cl_s, ch_s, so_s, si_s, colr);
+                   out_stride, active, loc, LT, lds, cl_s, ch_s, so_s, si_s, colr, sync);
     else
         bm_solve<16, 7, 2>(t, job.y, job.z, job.w, n_src, dinv, dinv_wl_stride, coef, sc, nx, ny, vin, vin_stride,
                            out, out_stride, active, loc, LT, lds, cl_s, ch_s, so_s, si_s, colr);
