@@ -1134,8 +1134,8 @@ __device__ __forceinline__ void bm_solve32(const TileDesc &t, int wl, int s0, in
     // step k - 1: no wave of a group starts step k before its whole group has
     // finished step k - 1, which each wait above ensures.  No wait depends on a
     // later one, so the halves drift at most a step apart, which the double
-    // buffers cover.  Every wait is bounded (about 2^18 short sleeps, some
-    // thousand times the longest wait seen), so a wave always finishes; a wave
+    // buffers cover.  Every wait is bounded (2^18 short sleeps, milliseconds,
+    // where a block step takes a few microseconds), so a wave always finishes; a wave
     // whose wait ran out writes NaN instead of its values, which the outer
     // solver reports as a non-finite result rather than a wrong one.
     const int NE = BM_THREADS / 64 - nT, half = prod ? tile / RT : 0;
