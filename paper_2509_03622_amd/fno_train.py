@@ -36,7 +36,7 @@ lift_w[C][9], lift_b[C], per layer R_re[2m][m][C][C], R_im[2m][m][C][C],
 W[C][C], b[C], then proj1_w[128][C], proj1_b[128], proj2_w[2][128], proj2_b[2].
 
 Usage: python -m paper_2509_03622_amd.fno_train --data tiles.npz --out weights.bin [--minutes 15]
-       [--scheme fixed-point --clip 4]
+       [--scheme fixed-point --clip 4] [--init weights.bin (continue from a weights file)]
 """
 from __future__ import annotations
 
@@ -505,6 +505,8 @@ def main():
                     help="recurrent FGMRES training (Algorithm 1) or fixed-point training with clipping (Algorithm 2)")
     ap.add_argument("--clip", type=float, default=4.0,
                     help="fixed-point scheme: clip threshold th_clip, in units of rms(b) per sample")
+    ap.add_argument("--init", default=None, metavar="WEIGHTS",
+                    help="start from these weights (a file of the same network shape) instead of random ones")
     ap.add_argument("--eval", nargs="+", metavar="WEIGHTS",
                     help="only evaluate these weights files on the same held-out batches (no training)")
     a = ap.parse_args()
@@ -520,6 +522,8 @@ def main():
             print(f"[fno_train] eval {path}: " + ", ".join(f"{k} {v:.3g}" for k, v in ev.items()), flush=True)
         return
     model = build_model(a.width, a.modes, a.layers, rank=a.rank).to(dev)
+    if a.init:
+        read_weights(model, a.init)
     n_par = sum(p.numel() for p in model.parameters())
     print(f"[fno_train] {'modulated rank-%d' % a.rank if a.rank else 'plain'} network, {n_par} weights",
           flush=True)
